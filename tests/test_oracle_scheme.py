@@ -1,0 +1,379 @@
+"""Pins of the oracle's whole right-hand side, boundary conditions and time
+step against invariants, symmetries, closed forms and textbook solutions."""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.oracle import RHS_FN, Oracle, lib, make_scheme
+from paper_2304_00140_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_published_first_output():
+    line = [l for l in open(os.path.join(GOLDEN, "splitmix64.txt")) if not l.startswith("#")][0].split()
+    assert lib().og_splitmix64(int(line[1], 16)) == int(line[3], 16)
+
+
+def test_lsrk_stability_polynomial():
+    """the four-stage low-storage scheme with a = (1/4, 1/3, 1/2, 1) applied to
+    q' = lam q gives exactly the fourth-order Taylor polynomial of exp(lam dt)"""
+    s = make_scheme(W.default_scheme())
+    lam = -1.7
+
+    @RHS_FN
+    def f(q, r, n, user):
+        for i in range(n):
+            r[i] = lam * q[i]
+    for dt in (0.1, 0.5, 1.3):
+        q = np.array([1.0, 2.0])
+        lib().og_lsrk(C.byref(s), q.ctypes.data_as(C.POINTER(C.c_double)), 2, dt, f, None)
+        z = lam * dt
+        amp = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+        np.testing.assert_allclose(q, [amp, 2 * amp], rtol=1e-14)
+
+
+def test_dt_uniform_state():
+    c = W.random_state(2, [8, 6], 1)
+    c["prim"][0] = 1e5
+    c["prim"][1] = 300.0
+    c["prim"][2] = 0.0
+    c["prim"][3] = 40.0
+    c["prim"][4] = -10.0
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    Wp = o.prim_from_cons(q)
+    cs = Wp[7, 0]
+    dx, dy = c["grid"]["dx"][:2]
+    expect = 0.5 / ((40 + cs) / dx + (10 + cs) / dy)
+    assert abs(o.dt(q) - expect) < 1e-14 * expect
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_WALL, W.BC_ZEROGRAD])
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_uniform_state_is_stationary(bc, dim):
+    n = [6, 5, 4][:dim]
+    c = W.random_state(dim, n, 2, bc=[[bc, bc]] * dim)
+    c["prim"][0] = 2e5
+    c["prim"][1] = 310.0
+    c["prim"][2] = 0.37
+    for d in range(dim):
+        c["prim"][3 + d] = 0.0 if bc == W.BC_WALL else 25.0 * (d + 1)
+    for sw in (0, 1):
+        c["scheme"]["switching"] = sw
+        o = Oracle(c)
+        q = o.cons_from_prim()
+        r = o.rhs(q)
+        scale = np.abs(q).max(axis=1, keepdims=True) / c["grid"]["dx"][0] * 1e-13 * 200
+        assert np.all(np.abs(r) <= scale)
+
+
+@pytest.mark.parametrize("dim,switching,sigma", [(1, 0, 0.0), (2, 0, 0.0), (2, 1, 0.0), (3, 1, 0.0),
+                                                 (2, 0, 0.07)])
+def test_conservation_periodic(dim, switching, sigma):
+    """finite-volume form with one flux per face: totals of mass, momentum,
+    energy and xi-mass are conserved to round-off on a periodic domain; the CSF
+    source changes momentum and energy only."""
+    n = {1: [64], 2: [24, 20], 3: [10, 9, 8]}[dim]
+    c = W.random_state(dim, n, 11 + dim, sigma=sigma, switching=switching)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    t0 = o.totals(q)
+    o.run(q, 5)
+    t1 = o.totals(q)
+    scale = np.abs(q).sum(axis=1) * np.prod(c["grid"]["dx"][:dim])
+    rel = np.abs(t1 - t0) / scale
+    keep = [0, dim + 2] if sigma > 0 else list(range(dim + 3))
+    assert np.all(rel[keep] < 1e-14), rel
+
+
+def test_interface_advection_keeps_p_u_equilibrium():
+    """Section 4.1 / Fig. 4.3: pressure and velocity stay at their initial values
+    while a (here stiff-liquid) interface is advected through a periodic domain."""
+    c = W.interface_advection_1d(200, periods=1.0)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    t0 = o.totals(q)
+    t, n = 0.0, 0
+    while t < c["t_end"] * (1 - 1e-14):
+        t, _ = o.step(q, n, t, c["t_end"])
+        n += 1
+    assert abs(t - c["t_end"]) < 1e-15
+    Wp = o.prim_from_cons(q)
+    assert np.abs(Wp[4] - 1e5).max() / (1e5 + 6e8) < 1e-12
+    assert np.abs(Wp[1] - 100.0).max() / 100.0 < 1e-11
+    assert np.all(np.abs(o.totals(q) - t0) <= 1e-13 * np.abs(t0))
+    # after one period the slab is back in place and sharp: at most 4 cells per
+    # interface between 1 % and 99 % mass fraction
+    Y = Wp[6]
+    assert np.all(Y[60:140] < 1e-4) and np.all(Y[:40] > 1 - 1e-4) and np.all(Y[160:] > 1 - 1e-4)
+    assert np.count_nonzero((Y > 0.01) & (Y < 0.99)) <= 8
+
+
+def test_interface_advection_paper_gases():
+    """Table 4.1 gases (gamma 5 / 1.6, p = 1e7, u = 5 m/s): p and u unchanged"""
+    c = W.interface_advection_1d_paper(100, periods=0.05)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    t, n = 0.0, 0
+    while t < c["t_end"] * (1 - 1e-14):
+        t, _ = o.step(q, n, t, c["t_end"])
+        n += 1
+    Wp = o.prim_from_cons(q)
+    assert np.abs(Wp[4] / 1e7 - 1).max() < 1e-12
+    assert np.abs(Wp[1] / 5 - 1).max() < 1e-10
+
+
+def transpose_case(c):
+    """swap x and y of a 2D case"""
+    d = dict(c)
+    g = dict(c["grid"])
+    g["n"] = [c["grid"]["n"][1], c["grid"]["n"][0], 1]
+    g["dx"] = [c["grid"]["dx"][1], c["grid"]["dx"][0], 1.0]
+    g["bc"] = [c["grid"]["bc"][1], c["grid"]["bc"][0], c["grid"]["bc"][2]]
+    d["grid"] = g
+    return d
+
+
+def tr(field, nx, ny):
+    return field.reshape(ny, nx).T.reshape(-1)
+
+
+@pytest.mark.parametrize("switching,sigma", [(0, 0.0), (1, 0.05)])
+def test_xy_transposition(switching, sigma):
+    """the scheme treats every direction alike: R(transpose q) = transpose R(q)"""
+    c = W.random_state(2, [14, 11], 21, sigma=sigma, switching=switching,
+                       bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC]])
+    nx, ny = 14, 11
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    r = o.rhs(q)
+    ct = transpose_case(c)
+    qt = np.stack([tr(q[0], nx, ny), tr(q[2], nx, ny), tr(q[1], nx, ny), tr(q[3], nx, ny), tr(q[4], nx, ny)])
+    ot = Oracle(ct)
+    rt = ot.rhs(qt)
+    expect = np.stack([tr(r[0], nx, ny), tr(r[2], nx, ny), tr(r[1], nx, ny), tr(r[3], nx, ny), tr(r[4], nx, ny)])
+    scale = np.abs(r).max(axis=1, keepdims=True)
+    assert np.all(np.abs(rt - expect) <= 1e-12 * scale)
+
+
+def test_3d_axis_permutation():
+    """(x, y, z) -> (y, z, x) relabelling commutes with the right-hand side"""
+    n = (7, 6, 5)
+    c = W.random_state(3, list(n), 31, switching=1, sigma=0.03)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    r = o.rhs(q)
+
+    def perm(f):   # array index [k][j][i] -> new axes x'=y, y'=z, z'=x
+        a = f.reshape(n[2], n[1], n[0])
+        return np.ascontiguousarray(a.transpose(2, 0, 1)).reshape(-1)
+    cp = dict(c)
+    g = dict(c["grid"])
+    g["n"] = [n[1], n[2], n[0]]
+    g["dx"] = [c["grid"]["dx"][1], c["grid"]["dx"][2], c["grid"]["dx"][0]]
+    cp["grid"] = g
+    order = [0, 2, 3, 1, 4, 5]
+    qp = np.stack([perm(q[i]) for i in order])
+    rp = Oracle(cp).rhs(qp)
+    expect = np.stack([perm(r[i]) for i in order])
+    scale = np.abs(r).max(axis=1, keepdims=True)[order]
+    assert np.all(np.abs(rp - expect) <= 1e-12 * scale)
+
+
+def test_slip_wall_equals_mirrored_domain():
+    """a slip wall is the mirror plane of the doubled domain: the solution next
+    to the wall equals the mirrored solution of the doubled, wall-free problem"""
+    n = 40
+    c = W.random_state(1, [n], 41, bc=[[W.BC_WALL, W.BC_WALL]])
+    cd = W.random_state(1, [2 * n], 41, bc=[[W.BC_WALL, W.BC_WALL]])
+    prim = c["prim"]
+    mir = np.concatenate([prim[:, ::-1], prim], axis=1)
+    mir[3, :n] *= -1.0
+    cd["prim"] = np.ascontiguousarray(mir)
+    cd["eos"] = c["eos"]
+    o, od = Oracle(c), Oracle(cd)
+    q, qd = o.cons_from_prim(), od.cons_from_prim()
+    o.run(q, 20)
+    od.run(qd, 20)
+    np.testing.assert_allclose(qd[:, n:], q, rtol=1e-12, atol=1e-12 * np.abs(q).max())
+
+
+def test_inflow_matched_state_is_stationary_and_noise_is_keyed():
+    c = W.random_state(2, [10, 8], 51, bc=[[W.BC_INFLOW, W.BC_ZEROGRAD], [W.BC_WALL, W.BC_WALL]])
+    g = c["grid"]
+    g["inflow"] = dict(p=2e5, T=300.0, alpha=0.0, u=30.0, radius=1.0, center=[0.0, 0.0],
+                       noise=0.0, seed=3)
+    c["prim"][0], c["prim"][1], c["prim"][2], c["prim"][3], c["prim"][4] = 2e5, 300.0, 0.0, 30.0, 0.0
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    r = o.rhs(q)
+    assert np.abs(r).max() < 1e-6 * np.abs(q).max() / g["dx"][0]
+    g["inflow"]["noise"] = 0.05
+    o = Oracle(c)
+    assert not np.allclose(o.rhs(q, step=5), 0.0)
+    np.testing.assert_array_equal(o.rhs(q, step=5), o.rhs(q, step=5))
+    assert not np.array_equal(o.rhs(q, step=5), o.rhs(q, step=6))
+
+
+def test_ducros_sensor_rotation_and_dilatation():
+    """eq. (D.4) with the Ducros sensor: a solid-body rotation is smooth (f = 0),
+    a pure dilatation is flagged (f = 1); uniform xi has no interface"""
+    c = W.random_state(2, [16, 16], 61, switching=1)
+    x, y = W.cell_centres(c["grid"])
+    L = 16 * c["grid"]["dx"][0]
+    c["prim"][2] = 0.3
+    c["prim"][3], c["prim"][4] = -(y - L / 2) * 1e4, (x - L / 2) * 1e4
+    o = Oracle(c)
+    fl = o.sensor_flags(o.cons_from_prim())
+    inner = fl.reshape(16, 16)[2:-2, 2:-2]
+    assert np.all((inner & 1) == 0)
+    c["prim"][3], c["prim"][4] = (x - L / 2) * 1e4, (y - L / 2) * 1e4
+    fl = o.sensor_flags(Oracle(c).cons_from_prim())
+    assert np.all((fl.reshape(16, 16)[2:-2, 2:-2] & 1) == 1)
+
+
+def _curvature_of_disc(dim, n, R_cells, drop=True):
+    sh = [n] * dim
+    c = W.random_state(dim, sh, 71, sigma=0.07)
+    xs = W.cell_centres(c["grid"])
+    dx = c["grid"]["dx"][0]
+    r = np.sqrt(sum((xs[d] - n * dx / 2) ** 2 for d in range(dim)))
+    R = R_cells * dx
+    al = W.smeared(r - R, dx) if drop else 1 - W.smeared(r - R, dx)
+    c["prim"][0], c["prim"][1], c["prim"][2] = 1e5, 300.0, al
+    for d in range(dim):
+        c["prim"][3 + d] = 0.0
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    k = o.curvature(q)
+    # weight by the central |grad alpha| the force uses
+    a = al.reshape([n] * dim)
+    gsq = sum(((np.roll(a, -1, axis=ax) - np.roll(a, 1, axis=ax)) / (2 * dx)) ** 2 for ax in range(dim))
+    w = np.sqrt(gsq).reshape(-1)
+    return (k * w).sum() / w.sum(), R
+
+
+@pytest.mark.parametrize("drop", [True, False])
+def test_curvature_of_a_circle(drop):
+    """kappa = -div(grad xi~ / |grad xi~|) of eq. (3-10) with vertex normals: a
+    circle of radius R gives |kappa| -> 1/R, negative for a drop (xi of the gas
+    rises outward), positive for a bubble"""
+    errs = []
+    for n, Rc in [(24, 5), (48, 10), (96, 20)]:
+        kav, R = _curvature_of_disc(2, n, Rc, drop)
+        target = -1.0 / R if drop else 1.0 / R
+        errs.append(abs(kav / target - 1))
+        assert np.sign(kav) == np.sign(target)
+    assert errs[0] < 0.1 and max(errs[1:]) < 0.02, errs
+
+
+def test_curvature_of_a_sphere():
+    kav, R = _curvature_of_disc(3, 40, 10, True)
+    assert abs(kav * R / -2.0 - 1) < 0.05
+
+
+def test_static_drop_keeps_laplace_jump():
+    """static drop (Section 4.4 eq. 4-4, Appendix C): with the CSF source the
+    initial jump sigma/R survives the acoustic transient; without it the jump
+    radiates away"""
+    def run(sigma):
+        c = W.drop_2d(n=40, steps=0, sigma=0.07, L=1e-3, rel_radius=0.25)
+        c["scheme"]["sigma"] = sigma
+        o = Oracle(c)
+        q = o.cons_from_prim()
+        o.run(q, 400)
+        Wp = o.prim_from_cons(q)
+        x, y = W.cell_centres(c["grid"])
+        r = np.hypot(x - 5e-4, y - 5e-4)
+        inside = Wp[4][r < 0.5 * c["radius"]].mean()
+        outside = Wp[4][r > 1.5 * c["radius"]].mean()
+        return (inside - outside) / (0.07 / c["radius"]), np.abs(Wp[1:3]).max()
+    jump, umax = run(0.07)
+    assert 0.85 < jump < 1.15, jump
+    jump0, _ = run(0.0)
+    assert abs(jump0) < 0.5
+
+
+def exact_riemann_ideal(rl, ul, pl, rr, ur, pr_, g, xs, t):
+    """textbook exact Riemann solver for one ideal gas (two-rarefaction/shock
+    wave curves, Newton on the star pressure), sampled at x/t"""
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr_ / rr)
+
+    def fk(p, rk, pk, ck):
+        if p > pk:
+            A, B = 2 / ((g + 1) * rk), (g - 1) / (g + 1) * pk
+            f = (p - pk) * math.sqrt(A / (p + B))
+            df = math.sqrt(A / (B + p)) * (1 - (p - pk) / (2 * (B + p)))
+        else:
+            f = 2 * ck / (g - 1) * ((p / pk) ** ((g - 1) / (2 * g)) - 1)
+            df = 1 / (rk * ck) * (p / pk) ** (-(g + 1) / (2 * g))
+        return f, df
+    p = 0.5 * (pl + pr_)
+    for _ in range(100):
+        f1, d1 = fk(p, rl, pl, cl)
+        f2, d2 = fk(p, rr, pr_, cr)
+        dp = (f1 + f2 + ur - ul) / (d1 + d2)
+        p = max(p - dp, 1e-12)
+        if abs(dp) < 1e-14 * p:
+            break
+    us = 0.5 * (ul + ur) + 0.5 * (fk(p, rr, pr_, cr)[0] - fk(p, rl, pl, cl)[0])
+    out = np.empty_like(xs)
+    for i, x in enumerate(xs):
+        s = x / t
+        if s < us:   # left of contact
+            if p > pl:
+                sl = ul - cl * math.sqrt((g + 1) / (2 * g) * p / pl + (g - 1) / (2 * g))
+                out[i] = rl if s < sl else rl * ((p / pl + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * p / pl + 1))
+            else:
+                csl = cl * (p / pl) ** ((g - 1) / (2 * g))
+                if s < ul - cl:
+                    out[i] = rl
+                elif s > us - csl:
+                    out[i] = rl * (p / pl) ** (1 / g)
+                else:
+                    out[i] = rl * (2 / (g + 1) + (g - 1) / ((g + 1) * cl) * (ul - s)) ** (2 / (g - 1))
+        else:
+            if p > pr_:
+                sr = ur + cr * math.sqrt((g + 1) / (2 * g) * p / pr_ + (g - 1) / (2 * g))
+                out[i] = rr if s > sr else rr * ((p / pr_ + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * p / pr_ + 1))
+            else:
+                csr = cr * (p / pr_) ** ((g - 1) / (2 * g))
+                if s > ur + cr:
+                    out[i] = rr
+                elif s < us + csr:
+                    out[i] = rr * (p / pr_) ** (1 / g)
+                else:
+                    out[i] = rr * (2 / (g + 1) - (g - 1) / ((g + 1) * cr) * (ur - s)) ** (2 / (g - 1))
+    return out
+
+
+def test_shock_tube_converges_to_exact_solution():
+    """Sod's shock tube in one ideal gas (both components identical): the L1
+    density error against the exact Riemann solution falls with refinement"""
+    g, R = 1.4, 287.0
+    air = W.sg(g, 0.0, R / (g - 1))
+    errs = []
+    t_end = 0.2 * math.sqrt(1.0 / 1e5)
+    for n in (100, 200, 400):
+        grid = W.make_grid(1, [n], [1.0], [[W.BC_ZEROGRAD, W.BC_ZEROGRAD]])
+        (x,) = W.cell_centres(grid)
+        left = x < 0.5
+        p = np.where(left, 1e5, 1e4)
+        rho = np.where(left, 1.0, 0.125)
+        T = p / (rho * R)
+        prim = W.pack_prim(p, T, np.zeros(n), [np.zeros(n)])
+        c = dict(grid=grid, eos=W.make_eos(air, air), scheme=W.default_scheme(), prim=prim)
+        o = Oracle(c)
+        q = o.cons_from_prim()
+        t, k = 0.0, 0
+        while t < t_end * (1 - 1e-14):
+            t, _ = o.step(q, k, t, t_end)
+            k += 1
+        ex = exact_riemann_ideal(1.0, 0.0, 1e5, 0.125, 0.0, 1e4, g, x - 0.5, t_end)
+        errs.append(np.abs(q[0] - ex).mean())
+    assert errs[1] < 0.75 * errs[0] and errs[2] < 0.75 * errs[1], errs
+    assert errs[2] < 0.01, errs

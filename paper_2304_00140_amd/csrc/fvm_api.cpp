@@ -1,0 +1,826 @@
+// fvm_api.cpp -- C ABI of the solver (include/fvm.h): validation, device
+// buffers, the case and tile tables, stage sequencing and HIP-graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fvm.h"
+#include "fvm_kernels.hpp"
+
+using fvm::CaseC;
+using fvm::CaseDyn;
+using fvm::Comp;
+using fvm::SchemeC;
+
+struct fvm_batch {
+  int ncases = 0, dim = 0, mixed = 0, prk = 0, nq = 0;
+  hipStream_t st = nullptr;
+  std::vector<CaseC> hc;
+  std::vector<double> vol;
+  CaseC* dc = nullptr;
+  CaseDyn* dd = nullptr;
+  int4* dtiles = nullptr;
+  int ntiles = 0, tile = 0;
+  long long total = 0;
+  size_t esz = 8;
+  void* q[3] = {nullptr, nullptr, nullptr};
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  double* dpart = nullptr;
+  double* dout = nullptr;
+  SchemeC sc{};
+  double rk[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gsteps = 0;
+  double gtend = -1.0;
+  std::vector<char> has_state;
+  std::string err;
+};
+
+struct fvm_ctx {
+  fvm_batch* b = nullptr;
+};
+
+static int fail(fvm_batch* b, int code, const std::string& msg)
+{
+  if (b) b->err = msg;
+  return code;
+}
+
+#define HIPCHECK(b, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((b), FVM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// ------------------------------------------------------------------ descriptors -> tables
+static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
+{
+  if (!g) return fail(b, FVM_EINVAL, "grid descriptor is NULL");
+  if (g->dim < 1 || g->dim > 3) return fail(b, FVM_EINVAL, "dim must be 1, 2 or 3");
+  for (int d = 0; d < 3; ++d) {
+    if (d < g->dim) {
+      if (g->n[d] < 2) return fail(b, FVM_EINVAL, "n[d] >= 2 is needed in every used direction");
+      if (!(g->dx[d] > 0.0)) return fail(b, FVM_EINVAL, "dx[d] must be > 0");
+      for (int s = 0; s < 2; ++s) {
+        int k = g->bc[d][s];
+        if (k < 0 || k > 3) return fail(b, FVM_EINVAL, "unknown boundary kind");
+        if (k == FVM_BC_INFLOW && !(d == 0 && s == 0)) return fail(b, FVM_EINVAL, "inflow only at the x-min side");
+      }
+      if ((g->bc[d][0] == FVM_BC_PERIODIC) != (g->bc[d][1] == FVM_BC_PERIODIC))
+        return fail(b, FVM_EINVAL, "periodic boundaries come in pairs");
+    } else if (g->n[d] != 1) {
+      return fail(b, FVM_EINVAL, "n[d] must be 1 in unused directions");
+    }
+  }
+  if (g->bc[0][0] == FVM_BC_INFLOW && !(g->in_p > -1e300 && g->in_T > 0.0))
+    return fail(b, FVM_EINVAL, "inflow state needs in_T > 0");
+  return FVM_OK;
+}
+
+static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
+{
+  if (!e) return fail(b, FVM_EINVAL, "eos descriptor is NULL");
+  for (int k = 0; k < 2; ++k) {
+    if (e->kind[k] == FVM_EOS_SG) {
+      if (!(e->gamma[k] > 1.0) || !(e->cv[k] > 0.0) || !(e->pinf[k] >= 0.0))
+        return fail(b, FVM_EINVAL, "stiffened gas needs gamma > 1, cv > 0, pinf >= 0");
+    } else if (e->kind[k] == FVM_EOS_PR) {
+      if (k != 1) return fail(b, FVM_EINVAL, "a Peng-Robinson fluid is supported as component 1 only");
+      int ns = e->pr_ns[k];
+      if (ns < 1 || ns > FVM_MAXSPEC || !(e->cv[k] > 0.0)) return fail(b, FVM_EINVAL, "bad Peng-Robinson description");
+      for (int a = 0; a < ns; ++a)
+        if (!(e->pr_Tc[k][a] > 0 && e->pr_pc[k][a] > 0 && e->pr_M[k][a] > 0 && e->pr_vc[k][a] > 0 &&
+              e->pr_Zc[k][a] > 0 && e->pr_X[k][a] >= 0))
+          return fail(b, FVM_EINVAL, "bad Peng-Robinson species data");
+    } else {
+      return fail(b, FVM_EINVAL, "unknown closure kind");
+    }
+  }
+  return FVM_OK;
+}
+
+static int check_scheme(fvm_batch* b, const fvm_scheme_desc* s)
+{
+  if (!s) return fail(b, FVM_EINVAL, "scheme descriptor is NULL");
+  if (s->lim_u < 0 || s->lim_u > 7 || s->lim_s < 0 || s->lim_s > 7) return fail(b, FVM_EINVAL, "unknown limiter");
+  if (!(s->cfl > 0.0) || !(s->sigma >= 0.0) || !(s->beta > 0.0) || !(s->thinc_gamma >= 0.0) ||
+      !(s->eps_normal > 0.0))
+    return fail(b, FVM_EINVAL, "scheme parameters out of range");
+  return FVM_OK;
+}
+
+static void fill_comp(Comp& c, const fvm_eos_desc* e, int k)
+{
+  std::memset(&c, 0, sizeof c);
+  c.kind = e->kind[k];
+  c.cv = e->cv[k];
+  c.qs = e->q[k];
+  if (c.kind == FVM_EOS_SG) {
+    c.gamma = e->gamma[k];
+    c.pinf = e->pinf[k];
+  } else {
+    const double R = fvm::R_UNIV;
+    int ns = e->pr_ns[k];
+    double bb = 0.0, M = 0.0;
+    for (int a = 0; a < ns; ++a) {
+      bb += e->pr_X[k][a] * 0.077796 * R * e->pr_Tc[k][a] / e->pr_pc[k][a];
+      M += e->pr_X[k][a] * e->pr_M[k][a];
+    }
+    int np = 0;
+    for (int a = 0; a < ns; ++a)
+      for (int be = a; be < ns; ++be) {
+        double Tc = std::sqrt(e->pr_Tc[k][a] * e->pr_Tc[k][be]) * (1.0 - e->pr_kij[k][a][be]);
+        double cr = 0.5 * (std::cbrt(e->pr_vc[k][a]) + std::cbrt(e->pr_vc[k][be]));
+        double vc = cr * cr * cr;
+        double Zc = 0.5 * (e->pr_Zc[k][a] + e->pr_Zc[k][be]);
+        double pc = Zc * R * Tc / vc;
+        double w = 0.5 * (e->pr_omega[k][a] + e->pr_omega[k][be]);
+        c.pcc[np] = 0.37464 + 1.5422 * w - 0.26992 * w * w;
+        c.pa0[np] = 0.457236 * (R * Tc) * (R * Tc) / pc;
+        c.prs[np] = 1.0 / std::sqrt(Tc);
+        c.pw[np] = e->pr_X[k][a] * e->pr_X[k][be] * (a == be ? 1.0 : 2.0);
+        ++np;
+      }
+    c.npair = np;
+    c.b = bb;
+    c.M = M;
+    c.gam_ig = 1.0 + R / (M * c.cv);
+    c.gamma = c.gam_ig;   // used only by the sound-speed bound of the ideal stand-in
+    c.pinf = 0.0;
+  }
+  c.A = (c.gamma - 1.0) * c.cv;
+  c.Cp = c.gamma * c.cv;
+  c.c2T = c.gamma * (c.gamma - 1.0) * c.cv;
+}
+
+static int build_tiles(fvm_batch* b)
+{
+  int tx, ty, nt;
+  if (fvm_k_tile_shape(b->dim, b->tile, &tx, &ty, &nt)) return fail(b, FVM_EINVAL, "bad tile index");
+  int zc = (b->dim == 3) ? fvm_k_tile_zchunk3(b->tile) : 1;
+  std::vector<int4> t;
+  for (int c = 0; c < b->ncases; ++c) {
+    CaseC& C = b->hc[c];
+    C.tiles[0] = (C.n[0] + tx - 1) / tx;
+    C.tiles[1] = (b->dim >= 2) ? (C.n[1] + ty - 1) / ty : 1;
+    C.tiles[2] = (b->dim >= 3) ? (C.n[2] + zc - 1) / zc : 1;
+    C.tile0 = (int)t.size();
+    for (int k = 0; k < C.tiles[2]; ++k)
+      for (int j = 0; j < C.tiles[1]; ++j)
+        for (int i = 0; i < C.tiles[0]; ++i) t.push_back(make_int4(c, i, j, k));
+  }
+  if (b->dtiles) (void)hipFree(b->dtiles);
+  b->dtiles = nullptr;
+  b->ntiles = (int)t.size();
+  HIPCHECK(b, hipMalloc(&b->dtiles, sizeof(int4) * t.size()));
+  HIPCHECK(b, hipMemcpy(b->dtiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+  HIPCHECK(b, hipMemcpy(b->dc, b->hc.data(), sizeof(CaseC) * b->hc.size(), hipMemcpyHostToDevice));
+  return FVM_OK;
+}
+
+static void drop_graph(fvm_batch* b)
+{
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->gsteps = 0;
+}
+
+static int ensure_scratch(fvm_batch* b, size_t bytes)
+{
+  if (bytes <= b->scratch_bytes) return FVM_OK;
+  if (b->scratch) (void)hipFree(b->scratch);
+  b->scratch = nullptr;
+  b->scratch_bytes = 0;
+  if (hipMalloc(&b->scratch, bytes) != hipSuccess) return fail(b, FVM_ENOMEM, "scratch allocation failed");
+  b->scratch_bytes = bytes;
+  return FVM_OK;
+}
+
+static void batch_free(fvm_batch* b)
+{
+  if (!b) return;
+  drop_graph(b);
+  for (int i = 0; i < 3; ++i)
+    if (b->q[i]) (void)hipFree(b->q[i]);
+  if (b->dc) (void)hipFree(b->dc);
+  if (b->dd) (void)hipFree(b->dd);
+  if (b->dtiles) (void)hipFree(b->dtiles);
+  if (b->scratch) (void)hipFree(b->scratch);
+  if (b->dpart) (void)hipFree(b->dpart);
+  if (b->dout) (void)hipFree(b->dout);
+  delete b;
+}
+
+static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids, const fvm_eos_desc* eos,
+                        const fvm_scheme_desc* s, int precision, void* stream, std::string* errout)
+{
+  fvm_batch* b = new fvm_batch();
+  auto bail = [&](int rc) {
+    if (errout) *errout = b->err;
+    batch_free(b);
+    return rc;
+  };
+  if (!out) return bail(fail(b, FVM_EINVAL, "out is NULL"));
+  *out = nullptr;
+  if (ncases < 1 || !grids || !eos) return bail(fail(b, FVM_EINVAL, "need at least one case"));
+  if (precision != FVM_FP64 && precision != FVM_MIXED) return bail(fail(b, FVM_EINVAL, "unknown precision"));
+  int rc = check_scheme(b, s);
+  if (rc) return bail(rc);
+  b->ncases = ncases;
+  b->dim = grids[0].dim;
+  b->mixed = precision == FVM_MIXED;
+  b->nq = b->dim + 3;
+  b->esz = b->mixed ? sizeof(float) : sizeof(double);
+  b->st = (hipStream_t)stream;
+  b->hc.resize(ncases);
+  b->vol.resize(ncases);
+  b->has_state.assign(ncases, 0);
+  long long off = 0;
+  for (int c = 0; c < ncases; ++c) {
+    const fvm_grid_desc* g = &grids[c];
+    if ((rc = check_grid(b, g))) return bail(rc);
+    if (g->dim != b->dim) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the dimension"));
+    if ((rc = check_eos(b, &eos[c]))) return bail(rc);
+    CaseC& C = b->hc[c];
+    std::memset(&C, 0, sizeof C);
+    C.dim = g->dim;
+    long long n = 1;
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      C.n[d] = g->n[d];
+      C.dx[d] = d < g->dim ? g->dx[d] : 1.0;
+      C.idx[d] = 1.0 / C.dx[d];
+      C.bc[d][0] = g->bc[d][0];
+      C.bc[d][1] = g->bc[d][1];
+      n *= g->n[d];
+      if (d < g->dim) vol *= g->dx[d];
+    }
+    b->vol[c] = vol;
+    C.ncell = n;
+    C.off = off;
+    off += (n + 63) / 64 * 64;   // keep every case's rows starting on a 64-word boundary
+    C.in_p = g->in_p; C.in_T = g->in_T; C.in_alpha = g->in_alpha; C.in_u = g->in_u;
+    C.in_radius = g->in_radius; C.in_c0 = g->in_center[0]; C.in_c1 = g->in_center[1];
+    C.in_noise = g->in_noise; C.in_seed = g->in_seed;
+    fill_comp(C.comp[0], &eos[c], 0);
+    fill_comp(C.comp[1], &eos[c], 1);
+    if (C.comp[1].kind == FVM_EOS_PR) b->prk = 1;
+  }
+  b->total = off;
+  // scheme constants
+  SchemeC& S = b->sc;
+  S.switching = s->switching; S.lim_u = s->lim_u; S.lim_s = s->lim_s; S.thinc = s->thinc;
+  S.beta = s->beta; S.thinc_gamma = s->thinc_gamma; S.eps_int = s->eps_interface;
+  S.th_d = s->theta_ducros; S.th_g = s->theta_gas; S.eps_d = s->eps_ducros; S.k3 = s->kappa3;
+  S.sigma = s->sigma; S.eps_n = s->eps_normal; S.cfl = s->cfl;
+  S.tanh_b = std::tanh(s->beta); S.icosh_b = 1.0 / std::cosh(s->beta); S.itanh_b = 1.0 / std::tanh(s->beta);
+  S.t_end = 0.0;
+  for (int i = 0; i < 4; ++i) b->rk[i] = s->rk[i];
+
+  // device tables
+  HIPCHECK(b, hipMalloc(&b->dc, sizeof(CaseC) * ncases));
+  HIPCHECK(b, hipMalloc(&b->dd, sizeof(CaseDyn) * ncases));
+  HIPCHECK(b, hipMemset(b->dd, 0, sizeof(CaseDyn) * ncases));
+  HIPCHECK(b, hipMemcpy(b->dc, b->hc.data(), sizeof(CaseC) * ncases, hipMemcpyHostToDevice));
+
+  // storage shifts: rho_k(p_ref, T_ref) and e_k(p_ref, T_ref), evaluated by the device closure
+  {
+    std::vector<double> pT(2 * ncases), sh(4 * ncases);
+    bool any = false;
+    for (int c = 0; c < ncases; ++c) {
+      pT[2 * c] = eos[c].p_ref;
+      pT[2 * c + 1] = eos[c].T_ref;
+      any = any || (eos[c].T_ref > 0.0);
+    }
+    if (any && b->mixed) {
+      if ((rc = ensure_scratch(b, sizeof(double) * 6 * ncases))) return bail(rc);
+      double* dpT = (double*)b->scratch;
+      double* dsh = dpT + 2 * ncases;
+      HIPCHECK(b, hipMemcpy(dpT, pT.data(), sizeof(double) * 2 * ncases, hipMemcpyHostToDevice));
+      HIPCHECK(b, fvm_k_ref_shift(b->dc, ncases, dsh, dpT, nullptr));
+      HIPCHECK(b, hipMemcpy(sh.data(), dsh, sizeof(double) * 4 * ncases, hipMemcpyDeviceToHost));
+    }
+    for (int c = 0; c < ncases; ++c) {
+      CaseC& C = b->hc[c];
+      // FP64 storage needs no shift; FP32 storage shifts the partial density of
+      // stiff components (pinf > 0, where one FP32 ulp of density is a large
+      // pressure) and the energy of both components.  Gases keep their
+      // partial density unshifted so that trace amounts keep full relative
+      // precision.
+      bool on = b->mixed && eos[c].T_ref > 0.0 && std::isfinite(sh[4 * c]) && std::isfinite(sh[4 * c + 1]) &&
+                std::isfinite(sh[4 * c + 2]) && std::isfinite(sh[4 * c + 3]);
+      for (int k = 0; k < 2; ++k) {
+        bool stiff = eos[c].kind[k] == FVM_EOS_SG && eos[c].pinf[k] > 0.0;
+        double rref = (on && stiff) ? sh[4 * c + k] : 0.0;
+        double qs = on ? eos[c].q[k] - sh[4 * c + 2 + k] : eos[c].q[k];
+        if (b->mixed) { rref = (double)(float)rref; qs = (double)(float)qs; }
+        C.rref[k] = rref;
+        C.comp[k].qs = qs;
+        C.Q[k] = eos[c].q[k] - qs;
+      }
+    }
+  }
+
+  size_t bytes = (size_t)b->nq * (size_t)b->total * b->esz;
+  for (int i = 0; i < 3; ++i) {
+    if (hipMalloc(&b->q[i], bytes) != hipSuccess) return bail(fail(b, FVM_ENOMEM, "state allocation failed"));
+    HIPCHECK(b, hipMemset(b->q[i], 0, bytes));
+  }
+  HIPCHECK(b, hipMalloc(&b->dpart, sizeof(double) * 1024 * 8));
+  HIPCHECK(b, hipMalloc(&b->dout, sizeof(double) * 16));
+  b->tile = 0;
+  if ((rc = build_tiles(b))) return bail(rc);
+  *out = b;
+  return FVM_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+static StageArgs stage_args(fvm_batch* b)
+{
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.cases = b->dc;
+  a.dyn = b->dd;
+  a.tiles = b->dtiles;
+  a.total = b->total;
+  a.sc = b->sc;
+  return a;
+}
+
+static hipError_t launch_step(fvm_batch* b, double t_end)
+{
+  hipError_t e = fvm_k_step_begin(b->dd, b->ncases, b->sc.cfl, t_end, b->st);
+  if (e != hipSuccess) return e;
+  StageArgs a = stage_args(b);
+  void* src[4] = {b->q[0], b->q[1], b->q[2], b->q[1]};
+  void* dst[4] = {b->q[1], b->q[2], b->q[1], b->q[0]};
+  for (int k = 0; k < 4; ++k) {
+    a.src = src[k];
+    a.qn = b->q[0];
+    a.dst = dst[k];
+    a.stage = k;
+    a.ak = b->rk[k];
+    e = fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static int all_state(fvm_batch* b)
+{
+  for (int c = 0; c < b->ncases; ++c)
+    if (!b->has_state[c]) return fail(b, FVM_ESTATE, "a case has no state yet");
+  return FVM_OK;
+}
+
+static int check_errors(fvm_batch* b, int* icase = nullptr)
+{
+  std::vector<CaseDyn> d(b->ncases);
+  HIPCHECK(b, hipMemcpy(d.data(), b->dd, sizeof(CaseDyn) * b->ncases, hipMemcpyDeviceToHost));
+  for (int c = 0; c < b->ncases; ++c)
+    if (d[c].err) {
+      if (icase) *icase = c;
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "case %d: %s at cell %lld, step %lld", c,
+                    d[c].err == FVM_ENAN ? "NaN/Inf" : "non-physical state", d[c].err_cell, d[c].err_step);
+      return fail(b, d[c].err, msg);
+    }
+  return FVM_OK;
+}
+
+static int run_steps(fvm_batch* b, int n, double t_end)
+{
+  int rc = all_state(b);
+  if (rc) return rc;
+  const int chunk = 50;
+  bool use_graph = b->st != nullptr && n >= chunk;
+  int done = 0;
+  if (use_graph) {
+    if (!b->gexec || b->gsteps != chunk || b->gtend != t_end) {
+      drop_graph(b);
+      HIPCHECK(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < chunk && e == hipSuccess; ++i) e = launch_step(b, t_end);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(b->st, &g);
+      if (e != hipSuccess) return fail(b, FVM_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
+      if (e2 != hipSuccess) return fail(b, FVM_EHIP, std::string("capture: ") + hipGetErrorString(e2));
+      b->graph = g;
+      HIPCHECK(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+      b->gsteps = chunk;
+      b->gtend = t_end;
+    }
+    for (; done + chunk <= n; done += chunk) HIPCHECK(b, hipGraphLaunch(b->gexec, b->st));
+  }
+  for (; done < n; ++done) HIPCHECK(b, launch_step(b, t_end));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  return check_errors(b);
+}
+
+static int set_from_device_cons(fvm_batch* b, int c, const double* qdev)
+{
+  const CaseC& C = b->hc[c];
+  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->dc, c, C.ncell, qdev, b->q[0], b->total, b->st));
+  return FVM_OK;
+}
+
+static int finish_set(fvm_batch* b, int c)
+{
+  const CaseC& C = b->hc[c];
+  CaseDyn z;
+  std::memset(&z, 0, sizeof z);
+  HIPCHECK(b, hipMemcpyAsync(b->dd + c, &z, sizeof z, hipMemcpyHostToDevice, b->st));
+  HIPCHECK(b, fvm_k_dt_init(b->dim, b->mixed, b->prk, b->dc, b->dd, c, C.ncell, b->q[0], b->total, b->st));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  b->has_state[c] = 1;
+  int rc = check_errors(b);
+  if (rc) b->has_state[c] = 0;
+  return rc;
+}
+
+static int batch_init_primitive(fvm_batch* b, int c, const double* prim)
+{
+  if (c < 0 || c >= b->ncases || !prim) return fail(b, FVM_EINVAL, "bad case or NULL array");
+  const CaseC& C = b->hc[c];
+  size_t bytes = sizeof(double) * (3 + b->dim) * (size_t)C.ncell;
+  int rc = ensure_scratch(b, bytes);
+  if (rc) return rc;
+  HIPCHECK(b, hipMemcpyAsync(b->scratch, prim, bytes, hipMemcpyHostToDevice, b->st));
+  HIPCHECK(b, fvm_k_prim_to_state(b->dim, b->mixed, b->prk, b->dc, c, C.ncell, (const double*)b->scratch,
+                                  b->q[0], b->total, b->st));
+  return finish_set(b, c);
+}
+
+static int batch_set_state(fvm_batch* b, int c, const double* q, bool device)
+{
+  if (c < 0 || c >= b->ncases || !q) return fail(b, FVM_EINVAL, "bad case or NULL array");
+  const CaseC& C = b->hc[c];
+  size_t bytes = sizeof(double) * b->nq * (size_t)C.ncell;
+  const double* qd = q;
+  if (!device) {
+    int rc = ensure_scratch(b, bytes);
+    if (rc) return rc;
+    HIPCHECK(b, hipMemcpyAsync(b->scratch, q, bytes, hipMemcpyHostToDevice, b->st));
+    qd = (const double*)b->scratch;
+  }
+  int rc = set_from_device_cons(b, c, qd);
+  if (rc) return rc;
+  return finish_set(b, c);
+}
+
+static int batch_get_state(fvm_batch* b, int c, double* q, bool device)
+{
+  if (c < 0 || c >= b->ncases || !q) return fail(b, FVM_EINVAL, "bad case or NULL array");
+  if (!b->has_state[c]) return fail(b, FVM_ESTATE, "no state set");
+  const CaseC& C = b->hc[c];
+  size_t bytes = sizeof(double) * b->nq * (size_t)C.ncell;
+  double* qd = q;
+  if (!device) {
+    int rc = ensure_scratch(b, bytes);
+    if (rc) return rc;
+    qd = (double*)b->scratch;
+  }
+  HIPCHECK(b, fvm_k_state_to_cons(b->dim, b->mixed, b->dc, c, C.ncell, b->q[0], qd, b->total, b->st));
+  if (!device) HIPCHECK(b, hipMemcpyAsync(q, qd, bytes, hipMemcpyDeviceToHost, b->st));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  return FVM_OK;
+}
+
+static int batch_totals(fvm_batch* b, int c, double* out)
+{
+  if (c < 0 || c >= b->ncases || !out) return fail(b, FVM_EINVAL, "bad case or NULL array");
+  if (!b->has_state[c]) return fail(b, FVM_ESTATE, "no state set");
+  const CaseC& C = b->hc[c];
+  int nblk = (int)std::min<long long>(1024, (C.ncell + 255) / 256);
+  HIPCHECK(b, fvm_k_totals(b->dim, b->mixed, b->dc, c, C.ncell, b->q[0], b->total, b->dpart, nblk, b->vol[c],
+                           b->dout, b->st));
+  HIPCHECK(b, hipMemcpyAsync(out, b->dout, sizeof(double) * b->nq, hipMemcpyDeviceToHost, b->st));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  return FVM_OK;
+}
+
+static int time_stages(fvm_batch* b, int steps, double* ms)
+{
+  int rc = all_state(b);
+  if (rc) return rc;
+  if (steps < 1 || !ms) return fail(b, FVM_EINVAL, "steps >= 1 and an output array are needed");
+  std::vector<hipEvent_t> ev(8 * steps);
+  for (auto& e : ev) HIPCHECK(b, hipEventCreate(&e));
+  StageArgs a = stage_args(b);
+  void* src[4] = {b->q[0], b->q[1], b->q[2], b->q[1]};
+  void* dst[4] = {b->q[1], b->q[2], b->q[1], b->q[0]};
+  for (int s = 0; s < steps; ++s) {
+    HIPCHECK(b, fvm_k_step_begin(b->dd, b->ncases, b->sc.cfl, 0.0, b->st));
+    for (int k = 0; k < 4; ++k) {
+      a.src = src[k];
+      a.qn = b->q[0];
+      a.dst = dst[k];
+      a.stage = k;
+      a.ak = b->rk[k];
+      HIPCHECK(b, hipEventRecord(ev[8 * s + 2 * k], b->st));
+      HIPCHECK(b, fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st));
+      HIPCHECK(b, hipEventRecord(ev[8 * s + 2 * k + 1], b->st));
+    }
+  }
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+  for (int s = 0; s < steps; ++s)
+    for (int k = 0; k < 4; ++k) {
+      float t = 0.f;
+      HIPCHECK(b, hipEventElapsedTime(&t, ev[8 * s + 2 * k], ev[8 * s + 2 * k + 1]));
+      ms[k] += t / steps;
+    }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return check_errors(b);
+}
+
+// ------------------------------------------------------------------ C ABI: single case
+extern "C" {
+
+static thread_local std::string g_create_err;
+
+int fvm_version(void) { return FVM_VERSION; }
+
+int fvm_create(fvm_ctx** out, const fvm_grid_desc* g, const fvm_eos_desc* e, const fvm_scheme_desc* s,
+               int precision, void* stream)
+{
+  if (!out) return FVM_EINVAL;
+  *out = nullptr;
+  fvm_batch* b = nullptr;
+  int rc = batch_create(&b, 1, g, e, s, precision, stream, &g_create_err);
+  if (rc) return rc;
+  fvm_ctx* c = new fvm_ctx();
+  c->b = b;
+  *out = c;
+  return FVM_OK;
+}
+
+void fvm_destroy(fvm_ctx* ctx)
+{
+  if (!ctx) return;
+  if (ctx->b) (void)hipStreamSynchronize(ctx->b->st);
+  batch_free(ctx->b);
+  delete ctx;
+}
+
+const char* fvm_last_error(const fvm_ctx* ctx)
+{
+  if (!ctx || !ctx->b) return g_create_err.c_str();
+  return ctx->b->err.c_str();
+}
+
+#define CTX_CHECK(ctx) \
+  if (!(ctx) || !(ctx)->b) return FVM_EINVAL
+
+int fvm_init_primitive(fvm_ctx* ctx, const double* prim_host)
+{
+  CTX_CHECK(ctx);
+  return batch_init_primitive(ctx->b, 0, prim_host);
+}
+
+int fvm_set_state(fvm_ctx* ctx, const double* q_host)
+{
+  CTX_CHECK(ctx);
+  return batch_set_state(ctx->b, 0, q_host, false);
+}
+
+int fvm_set_state_device(fvm_ctx* ctx, const double* q_dev)
+{
+  CTX_CHECK(ctx);
+  return batch_set_state(ctx->b, 0, q_dev, true);
+}
+
+int fvm_get_state(fvm_ctx* ctx, double* q_host)
+{
+  CTX_CHECK(ctx);
+  return batch_get_state(ctx->b, 0, q_host, false);
+}
+
+int fvm_get_state_device(fvm_ctx* ctx, double* q_dev)
+{
+  CTX_CHECK(ctx);
+  return batch_get_state(ctx->b, 0, q_dev, true);
+}
+
+int fvm_get_primitive(fvm_ctx* ctx, double* w_host)
+{
+  CTX_CHECK(ctx);
+  fvm_batch* b = ctx->b;
+  if (!w_host) return fail(b, FVM_EINVAL, "NULL array");
+  if (!b->has_state[0]) return fail(b, FVM_ESTATE, "no state set");
+  const CaseC& C = b->hc[0];
+  size_t bytes = sizeof(double) * 9 * (size_t)C.ncell;
+  int rc = ensure_scratch(b, bytes);
+  if (rc) return rc;
+  HIPCHECK(b, fvm_k_state_to_prim(b->dim, b->mixed, b->prk, b->dc, 0, C.ncell, b->q[0], (double*)b->scratch,
+                                  b->total, b->st));
+  HIPCHECK(b, hipMemcpyAsync(w_host, b->scratch, bytes, hipMemcpyDeviceToHost, b->st));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  return FVM_OK;
+}
+
+int fvm_rhs(fvm_ctx* ctx, const double* q_dev_in, double* r_dev_out, int64_t step)
+{
+  CTX_CHECK(ctx);
+  fvm_batch* b = ctx->b;
+  if (!q_dev_in || !r_dev_out) return fail(b, FVM_EINVAL, "NULL device array");
+  const CaseC& C = b->hc[0];
+  // the input goes to the first stage buffer; the case's own state q^n is untouched
+  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->dc, 0, C.ncell, q_dev_in, b->q[1], b->total, b->st));
+  StageArgs a = stage_args(b);
+  a.src = b->q[1];
+  a.qn = b->q[1];
+  a.dst = nullptr;
+  a.stage = -1;
+  a.rhs_out = r_dev_out;
+  a.rhs_step = step;
+  HIPCHECK(b, fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st));
+  HIPCHECK(b, hipStreamSynchronize(b->st));
+  return FVM_OK;
+}
+
+int fvm_step(fvm_ctx* ctx, double* dt_out, double* t_out)
+{
+  CTX_CHECK(ctx);
+  int rc = run_steps(ctx->b, 1, 0.0);
+  double t, dt;
+  int64_t n;
+  fvm_clock(ctx, &t, &dt, &n);
+  if (dt_out) *dt_out = dt;
+  if (t_out) *t_out = t;
+  return rc;
+}
+
+int fvm_n_steps(fvm_ctx* ctx, int n, double t_end, double* t_out)
+{
+  CTX_CHECK(ctx);
+  if (n < 0) return fail(ctx->b, FVM_EINVAL, "n < 0");
+  int rc = run_steps(ctx->b, n, t_end);
+  if (t_out) {
+    double dt;
+    int64_t k;
+    fvm_clock(ctx, t_out, &dt, &k);
+  }
+  return rc;
+}
+
+int fvm_clock(fvm_ctx* ctx, double* t, double* dt, int64_t* steps)
+{
+  CTX_CHECK(ctx);
+  fvm_batch* b = ctx->b;
+  CaseDyn d;
+  HIPCHECK(b, hipMemcpy(&d, b->dd, sizeof d, hipMemcpyDeviceToHost));
+  if (t) *t = d.t;
+  if (dt) *dt = d.dt;
+  if (steps) *steps = d.step;
+  return FVM_OK;
+}
+
+int fvm_totals(fvm_ctx* ctx, double* out)
+{
+  CTX_CHECK(ctx);
+  return batch_totals(ctx->b, 0, out);
+}
+
+int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step)
+{
+  CTX_CHECK(ctx);
+  CaseDyn d;
+  HIPCHECK(ctx->b, hipMemcpy(&d, ctx->b->dd, sizeof d, hipMemcpyDeviceToHost));
+  if (code) *code = d.err;
+  if (cell) *cell = d.err_cell;
+  if (step) *step = d.err_step;
+  return FVM_OK;
+}
+
+int fvm_tile_count(int dim) { return fvm_k_tile_count(dim); }
+
+int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads)
+{
+  int a, b2, c;
+  if (fvm_k_tile_shape(dim, tile, &a, &b2, &c)) return FVM_EINVAL;
+  if (tx) *tx = a;
+  if (ty) *ty = b2;
+  if (threads) *threads = c;
+  return FVM_OK;
+}
+
+int fvm_set_tile(fvm_ctx* ctx, int tile)
+{
+  CTX_CHECK(ctx);
+  fvm_batch* b = ctx->b;
+  if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  drop_graph(b);
+  b->tile = tile;
+  return build_tiles(b);
+}
+
+int fvm_time_stages(fvm_ctx* ctx, int steps, double* ms_per_stage)
+{
+  CTX_CHECK(ctx);
+  return time_stages(ctx->b, steps, ms_per_stage);
+}
+
+// ------------------------------------------------------------------ C ABI: batches
+int fvm_batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids, const fvm_eos_desc* eos,
+                     const fvm_scheme_desc* s, int precision, void* stream)
+{
+  return batch_create(out, ncases, grids, eos, s, precision, stream, &g_create_err);
+}
+
+void fvm_batch_destroy(fvm_batch* b)
+{
+  if (b) (void)hipStreamSynchronize(b->st);
+  batch_free(b);
+}
+
+const char* fvm_batch_last_error(const fvm_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+int fvm_batch_init_primitive(fvm_batch* b, int icase, const double* prim_host)
+{
+  if (!b) return FVM_EINVAL;
+  return batch_init_primitive(b, icase, prim_host);
+}
+
+int fvm_batch_set_state(fvm_batch* b, int icase, const double* q_host)
+{
+  if (!b) return FVM_EINVAL;
+  return batch_set_state(b, icase, q_host, false);
+}
+
+int fvm_batch_get_state(fvm_batch* b, int icase, double* q_host)
+{
+  if (!b) return FVM_EINVAL;
+  return batch_get_state(b, icase, q_host, false);
+}
+
+int fvm_batch_n_steps(fvm_batch* b, int n, double* t_out)
+{
+  if (!b) return FVM_EINVAL;
+  if (n < 0) return fail(b, FVM_EINVAL, "n < 0");
+  int rc = run_steps(b, n, 0.0);
+  if (t_out) {
+    std::vector<CaseDyn> d(b->ncases);
+    HIPCHECK(b, hipMemcpy(d.data(), b->dd, sizeof(CaseDyn) * b->ncases, hipMemcpyDeviceToHost));
+    for (int c = 0; c < b->ncases; ++c) t_out[c] = d[c].t;
+  }
+  return rc;
+}
+
+int fvm_batch_totals(fvm_batch* b, int icase, double* out)
+{
+  if (!b) return FVM_EINVAL;
+  return batch_totals(b, icase, out);
+}
+
+int fvm_batch_error_info(fvm_batch* b, int* code, int* icase, int64_t* cell, int64_t* step)
+{
+  if (!b) return FVM_EINVAL;
+  std::vector<CaseDyn> d(b->ncases);
+  HIPCHECK(b, hipMemcpy(d.data(), b->dd, sizeof(CaseDyn) * b->ncases, hipMemcpyDeviceToHost));
+  if (code) *code = 0;
+  for (int c = 0; c < b->ncases; ++c)
+    if (d[c].err) {
+      if (code) *code = d[c].err;
+      if (icase) *icase = c;
+      if (cell) *cell = d[c].err_cell;
+      if (step) *step = d[c].err_step;
+      break;
+    }
+  return FVM_OK;
+}
+
+int fvm_batch_time_stages(fvm_batch* b, int steps, double* ms_per_stage)
+{
+  if (!b) return FVM_EINVAL;
+  return time_stages(b, steps, ms_per_stage);
+}
+
+int fvm_batch_set_tile(fvm_batch* b, int tile)
+{
+  if (!b) return FVM_EINVAL;
+  if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  drop_graph(b);
+  b->tile = tile;
+  return build_tiles(b);
+}
+
+int64_t fvm_batch_cells(fvm_batch* b)
+{
+  if (!b) return -1;
+  long long n = 0;
+  for (const CaseC& C : b->hc) n += C.ncell;
+  return n;
+}
+
+}  // extern "C"

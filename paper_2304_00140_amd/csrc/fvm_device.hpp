@@ -1,0 +1,474 @@
+// fvm_device.hpp -- device-side data and point functions of the gfx950 solver.
+//
+// Thermodynamic closure (Appendix A: stiffened gas eq. A.1.1, Peng-Robinson
+// eq. A.2.1, pressure-temperature equilibrium of the two components),
+// reconstruction (Section 3.3, Table 4.2, Appendix D), All-Mach Riemann solver
+// (Section 3.2, eq. D.5/D.6), thermodynamic dependent update (eq. 3-5,
+// Appendix B) and the face flux of eq. (2-2).
+//
+// Storage ("internal") variables of a cell, N_q = D + 3:
+//   0: rho_L - rref_L   partial density of component 0 minus a reference
+//   1: rho_G - rref_G   partial density of component 1 minus a reference
+//   2..1+D: rho u
+//   2+D: E' = rho E - rho_L Q_L - rho_G Q_G   (energy in a shifted gauge)
+// The shifts are linear in the conserved variables, so fluxes telescope and
+// conservation is unchanged; they keep FP32 storage accurate in stiff liquids
+// (near the reference state the stored numbers are small).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fvm {
+
+constexpr int MAXSPEC = 4;
+constexpr int MAXPAIR = MAXSPEC * (MAXSPEC + 1) / 2;
+constexpr double R_UNIV = 8.314462618;
+constexpr double SQRT2 = 1.41421356237309505;
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_ZEROGRAD = 2, BC_INFLOW = 3 };
+enum { LIM_MINMOD = 0, LIM_KOREN = 1, LIM_VANALBADA = 2, LIM_VANLEER = 3,
+       LIM_CHAKRAVARTHY = 4, LIM_MC = 5, LIM_SUPERBEE = 6, LIM_NONE = 7 };
+enum { ERR_NONPHYS = -4, ERR_NAN = -5 };
+
+// one component of the closure
+struct Comp {
+  int kind;            // 0 stiffened gas, 1 Peng-Robinson
+  double gamma, pinf, cv;
+  double qs;           // energy constant in the storage gauge: q - Q
+  double A;            // (gamma - 1) cv
+  double Cp;           // gamma cv
+  double c2T;          // gamma (gamma - 1) cv : c^2 / T
+  // Peng-Robinson pseudo-mixture: a(T) = sum_pairs w a0 (1 + cc (1 - sqrt(T) rs))^2
+  int npair;
+  double pw[MAXPAIR], pa0[MAXPAIR], pcc[MAXPAIR], prs[MAXPAIR];
+  double b, M;         // covolume [m^3/mol], molar mass [kg/mol]
+  double gam_ig;       // 1 + R / (M cv): ideal-gas stand-in used as Newton start
+};
+
+struct CaseC {
+  int dim, n[3];
+  long long off, ncell;
+  double dx[3], idx[3];
+  int bc[3][2];
+  double in_p, in_T, in_alpha, in_u, in_radius, in_c0, in_c1, in_noise;
+  unsigned long long in_seed;
+  Comp comp[2];
+  double rref[2];      // partial-density shifts (FP32-exact for FP32 storage)
+  double Q[2];         // energy gauge: E' = rho E - sum_k rho_k Q_k
+  int tile0, tiles[3];
+};
+
+struct CaseDyn {
+  unsigned long long dtmax[2];   // bits of max_cells sum (|u| + c)/dx for q^n (slot = step & 1)
+  double dt, t;
+  long long step, step_cur;
+  int err, pad;
+  long long err_cell, err_step;
+};
+
+struct SchemeC {
+  int switching, lim_u, lim_s, thinc;
+  double beta, thinc_gamma, eps_int, th_d, th_g, eps_d, k3, sigma, eps_n, cfl;
+  double tanh_b, icosh_b, itanh_b;
+  double t_end;
+};
+
+// ------------------------------------------------------------------ math
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double frcp(double x) { return 1.0 / x; }
+__device__ inline float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double fdiv(double a, double b) { return a / b; }
+__device__ inline float fexp(float x) { return __expf(x); }
+__device__ inline double fexp(double x) { return exp(x); }
+
+// SplitMix64 (Steele, Lea, Flood 2014): Weyl increment then two xor-shift-multiply rounds
+__device__ inline unsigned long long splitmix64(unsigned long long x)
+{
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline double noise01(unsigned long long seed, unsigned long long step,
+                                 unsigned long long j, unsigned long long k, unsigned long long c)
+{
+  unsigned long long h = splitmix64(seed);
+  h = splitmix64(h ^ step);
+  h = splitmix64(h ^ j);
+  h = splitmix64(h ^ k);
+  h = splitmix64(h ^ c);
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------ Peng-Robinson (A.2.1)
+struct PRab { double a, a1, a2; };
+
+__device__ inline PRab pr_a(const Comp& c, double T)
+{
+  double s = sqrt(T), is = 1.0 / s, iT = is * is;
+  PRab r{0.0, 0.0, 0.0};
+  for (int q = 0; q < c.npair; ++q) {
+    double rs = c.prs[q], cc = c.pcc[q], wa = c.pw[q] * c.pa0[q];
+    double g = 1.0 + cc * (1.0 - s * rs);
+    r.a += wa * g * g;
+    r.a1 -= wa * cc * g * rs * is;
+    r.a2 += 0.5 * wa * cc * rs * iT * (cc * rs + g * is);
+  }
+  return r;
+}
+
+__device__ inline double pr_log(double V, double b)
+{
+  return log((V + (1.0 - SQRT2) * b) / (V + (1.0 + SQRT2) * b));
+}
+
+// molar volume at (p, T): largest root of the compressibility cubic by Newton
+// from Z = 1 + B (an upper bound of every root with V > b)
+__device__ inline double pr_volume(double p, double T, double a, double b)
+{
+  double RT = R_UNIV * T;
+  double Ad = a * p / (RT * RT), Bd = b * p / RT;
+  double c2 = Bd - 1.0, c1 = Ad - 3.0 * Bd * Bd - 2.0 * Bd, c0 = Bd * Bd * Bd + Bd * Bd - Ad * Bd;
+  double Z = 1.0 + Bd;
+  for (int it = 0; it < 60; ++it) {
+    double f = ((Z + c2) * Z + c1) * Z + c0;
+    double fp = (3.0 * Z + 2.0 * c2) * Z + c1;
+    double dZ = f / fp;
+    Z -= dZ;
+    if (fabs(dZ) <= 1e-15 * fabs(Z)) break;
+  }
+  return Z * RT / p;
+}
+
+// mass-specific volume / energy of a component at (p, T) with derivatives
+struct VE { double v, e, dvdp, dvdT, dedp, dedT; };
+
+__device__ inline VE comp_ve(const Comp& c, double p, double T)
+{
+  VE r;
+  if (c.kind == 0) {
+    double den = 1.0 / (p + c.pinf);
+    double v = c.A * T * den;
+    r.v = v;
+    r.e = c.cv * T + c.pinf * v + c.qs;
+    r.dvdp = -v * den;
+    r.dvdT = v / T;
+    r.dedp = c.pinf * r.dvdp;
+    r.dedT = c.cv + c.pinf * r.dvdT;
+    return r;
+  }
+  PRab A = pr_a(c, T);
+  double b = c.b, M = c.M;
+  double V = pr_volume(p, T, A.a, b);
+  double D = V * V + 2.0 * b * V - b * b;
+  double iD = 1.0 / D, iVb = 1.0 / (V - b);
+  double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
+  double dpdT = R_UNIV * iVb - A.a1 * iD;
+  double L = pr_log(V, b);
+  double k = 1.0 / (2.0 * SQRT2 * b);
+  double cvm = M * c.cv - T * A.a2 * k * L;
+  double dedV = T * dpdT - (R_UNIV * T * iVb - A.a * iD);
+  double dVdp = 1.0 / dpdV, dVdT = -dpdT * dVdp;
+  double iM = 1.0 / M;
+  r.v = V * iM;
+  r.e = c.cv * T + c.qs + (A.a - T * A.a1) * k * L * iM;
+  r.dvdp = dVdp * iM;
+  r.dvdT = dVdT * iM;
+  r.dedp = dedV * dVdp * iM;
+  r.dedT = (cvm + dedV * dVdT) * iM;
+  return r;
+}
+
+// speed of sound of a Peng-Robinson component at molar volume V and T
+__device__ inline double pr_sound_V(const Comp& c, double V, double T)
+{
+  PRab A = pr_a(c, T);
+  double b = c.b, M = c.M;
+  double D = V * V + 2.0 * b * V - b * b;
+  double iD = 1.0 / D, iVb = 1.0 / (V - b);
+  double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
+  double dpdT = R_UNIV * iVb - A.a1 * iD;
+  double cvm = M * c.cv - T * A.a2 / (2.0 * SQRT2 * b) * pr_log(V, b);
+  return sqrt(-(V * V / M) * (dpdV - T * dpdT * dpdT / cvm));
+}
+
+// ------------------------------------------------------------------ closure inversion
+struct PT { double p, T, c, alpha; int ok; };
+
+// stiffened-gas pair in p-T equilibrium: T = (eh + p v) / Cp and the larger
+// root of  (v Cv) p^2 + [v (Cp (P0+P1) - A0 P1 - A1 P0) - eh (A0+A1)] p
+//          + [v Cp P0 P1 - eh (A0 P1 + A1 P0)] = 0
+__device__ inline void sg_pair(double g0, double P0, double cv0, double q0,
+                               double g1, double P1, double cv1, double q1,
+                               double v, double e, double Y, double& p, double& T)
+{
+  double Y0 = 1.0 - Y;
+  double A0 = Y0 * (g0 - 1.0) * cv0, A1 = Y * (g1 - 1.0) * cv1;
+  double Cv = Y0 * cv0 + Y * cv1;
+  double Cp = Y0 * g0 * cv0 + Y * g1 * cv1;
+  double eh = e - Y0 * q0 - Y * q1;
+  double qa = v * Cv;
+  double qb = v * (Cp * (P0 + P1) - A0 * P1 - A1 * P0) - eh * (A0 + A1);
+  double qc = v * Cp * P0 * P1 - eh * (A0 * P1 + A1 * P0);
+  double sq = sqrt(qb * qb - 4.0 * qa * qc);
+  p = (qb < 0.0) ? (-qb + sq) / (2.0 * qa) : 2.0 * qc / (-qb - sq);
+  T = (eh + p * v) / Cp;
+}
+
+// (rho, xi, e) -> (p, T), c = max of the components' sound speeds, alpha_G.
+// e is the specific internal energy in the storage gauge.  PRK: component 1
+// may be a Peng-Robinson fluid.
+template <bool PRK>
+__device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
+{
+  const Comp& c0 = C.comp[0];
+  const Comp& c1 = C.comp[1];
+  PT r;
+  r.ok = 1;
+  double v = 1.0 / rho;
+  double p, T;
+  if (!PRK || c1.kind == 0) {
+    if (Y == 0.0) {
+      p = (c0.gamma - 1.0) * rho * (e - c0.qs) - c0.gamma * c0.pinf;
+      T = (e - c0.qs - c0.pinf * v) / c0.cv;
+    } else if (Y == 1.0) {
+      p = (c1.gamma - 1.0) * rho * (e - c1.qs) - c1.gamma * c1.pinf;
+      T = (e - c1.qs - c1.pinf * v) / c1.cv;
+    } else {
+      sg_pair(c0.gamma, c0.pinf, c0.cv, c0.qs, c1.gamma, c1.pinf, c1.cv, c1.qs, v, e, Y, p, T);
+    }
+    r.p = p;
+    r.T = T;
+    double cc0 = c0.c2T * T, cc1 = c1.c2T * T;
+    r.c = sqrt(fmax(cc0, cc1));
+    r.alpha = (Y == 0.0) ? 0.0 : Y * rho * c1.A * T / (p + c1.pinf);
+    return r;
+  }
+  if constexpr (PRK) {
+    if (Y == 0.0) {
+      p = (c0.gamma - 1.0) * rho * (e - c0.qs) - c0.gamma * c0.pinf;
+      T = (e - c0.qs - c0.pinf * v) / c0.cv;
+      r.p = p;
+      r.T = T;
+      double V = pr_volume(p, T, pr_a(c1, T).a, c1.b);
+      r.c = fmax(sqrt(c0.c2T * T), pr_sound_V(c1, V, T));
+      r.alpha = 0.0;
+      return r;
+    }
+    if (Y == 1.0) {
+      // pure Peng-Robinson: Newton on T at fixed v (Appendix B), then p from (A.2.1)
+      double V = c1.M * v;
+      double L = pr_log(V, c1.b);
+      double k = L / (2.0 * SQRT2 * c1.b * c1.M);
+      double Tn = (e - c1.qs) / c1.cv;
+      if (!(Tn > 0.0)) Tn = 100.0;
+      int conv = 0;
+      for (int it = 0; it < 60; ++it) {
+        PRab A = pr_a(c1, Tn);
+        double f = c1.cv * Tn + c1.qs + (A.a - Tn * A.a1) * k - e;
+        double fp = c1.cv - Tn * A.a2 * k;
+        double dT = f / fp;
+        double Tnew = Tn - dT;
+        if (Tnew <= 0.0) Tnew = 0.5 * Tn;
+        Tn = Tnew;
+        if (fabs(dT) <= 1e-13 * Tn) { conv = 1; break; }
+      }
+      PRab A = pr_a(c1, Tn);
+      r.T = Tn;
+      r.p = R_UNIV * Tn / (V - c1.b) - A.a / (V * V + 2.0 * c1.b * V - c1.b * c1.b);
+      r.c = fmax(sqrt(c0.c2T * Tn), pr_sound_V(c1, V, Tn));
+      r.alpha = 1.0;
+      r.ok = conv;
+      return r;
+    }
+    // mixed cell: Newton on sum xi_k v_k = v, sum xi_k e_k = e from the ideal-gas stand-in
+    sg_pair(c0.gamma, c0.pinf, c0.cv, c0.qs, c1.gam_ig, 0.0, c1.cv, c1.qs, v, e, Y, p, T);
+    double Y0 = 1.0 - Y;
+    int conv = 0;
+    for (int it = 0; it < 60; ++it) {
+      VE a = comp_ve(c0, p, T), b = comp_ve(c1, p, T);
+      double F1 = Y0 * a.v + Y * b.v - v, F2 = Y0 * a.e + Y * b.e - e;
+      double J11 = Y0 * a.dvdp + Y * b.dvdp, J12 = Y0 * a.dvdT + Y * b.dvdT;
+      double J21 = Y0 * a.dedp + Y * b.dedp, J22 = Y0 * a.dedT + Y * b.dedT;
+      double idet = 1.0 / (J11 * J22 - J12 * J21);
+      double dp = (F1 * J22 - F2 * J12) * idet;
+      double dT = (J11 * F2 - J21 * F1) * idet;
+      double Tn = T - dT;
+      if (Tn <= 0.0) Tn = 0.5 * T;
+      p -= dp;
+      T = Tn;
+      if (fabs(dT) <= 1e-13 * T && fabs(dp) <= 1e-13 * (fabs(p) + 1.0)) { conv = 1; break; }
+    }
+    r.p = p;
+    r.T = T;
+    double Vg = pr_volume(p, T, pr_a(c1, T).a, c1.b);
+    r.c = fmax(sqrt(c0.c2T * T), pr_sound_V(c1, Vg, T));
+    r.alpha = Y * rho * Vg / c1.M;
+    r.ok = conv;
+    return r;
+  }
+  return r;
+}
+
+// forward closure at (p, T, xi) in FP64: 1 / rho and e (storage gauge)
+template <bool PRK>
+__device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y, double& vmix, double& e)
+{
+  double Yk[2] = {1.0 - Y, Y};
+  vmix = 0.0;
+  e = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (Yk[k] == 0.0) continue;
+    const Comp& c = C.comp[k];
+    double vk, ek;
+    if (!PRK || c.kind == 0) {
+      vk = c.A * T / (p + c.pinf);
+      ek = c.cv * T + c.pinf * vk + c.qs;
+    } else {
+      PRab A = pr_a(c, T);
+      double V = pr_volume(p, T, A.a, c.b);
+      vk = V / c.M;
+      ek = c.cv * T + c.qs + (A.a - T * A.a1) / (2.0 * SQRT2 * c.b * c.M) * pr_log(V, c.b);
+    }
+    vmix += Yk[k] * vk;
+    e += Yk[k] * ek;
+  }
+}
+
+// ------------------------------------------------------------------ reconstruction
+// limited slope: f(r) of Table 4.2 times the far-side difference, written
+// without the division (r = near / far); zero at extrema
+template <class R>
+__device__ inline R slope(int kind, R far, R near)
+{
+  R a = fabs(far), b = fabs(near);
+  R g;
+  switch (kind) {
+    case LIM_MINMOD: g = fmin(a, b); break;
+    case LIM_KOREN: g = fmin(fmin(R(2) * a, R(2) * b), (a + R(2) * b) * R(1.0 / 3.0)); break;
+    case LIM_VANALBADA: g = fdiv(a * b * (a + b), a * a + b * b); break;
+    case LIM_VANLEER: g = fdiv(R(2) * a * b, a + b); break;
+    case LIM_CHAKRAVARTHY: g = fmin(a, R(4) * b); break;
+    case LIM_MC: g = fmin(fmin(R(2) * a, R(2) * b), R(0.5) * (a + b)); break;
+    case LIM_SUPERBEE: g = fmax(fmin(a, R(2) * b), fmin(R(2) * a, b)); break;
+    default: g = R(0);
+  }
+  return (far * near > R(0)) ? copysign(g, near) : R(0);
+}
+
+// upwind-biased left/right face values from cells i-1, i, i+1, i+2 (Section 3.3)
+template <class R>
+__device__ inline void recon(int kind, R a, R b, R c, R d, R& L, R& Rr)
+{
+  R dn = c - b;
+  L = b + R(0.5) * slope<R>(kind, b - a, dn);
+  Rr = c - R(0.5) * slope<R>(kind, d - c, dn);
+}
+
+// ------------------------------------------------------------------ face flux
+// primitive stencil of one face: cells i-1, i, i+1, i+2 along the face normal
+template <class R, int D>
+struct Stencil {
+  R u[D][4];
+  R p[4], T[4], Y[4];
+  R rho1, rho2, c1, c2;
+};
+
+// Thermodynamic dependent update at (p*, T_f, xi_f) in precision R for a
+// stiffened-gas pair: 1 / rho_f and e_f (storage gauge)
+template <class R>
+__device__ inline void tdu_sg(const CaseC& C, R ps, R Tf, R Yf, R& rf, R& ef)
+{
+  const Comp& c0 = C.comp[0];
+  const Comp& c1 = C.comp[1];
+  R Y0 = R(1) - Yf;
+  R P0 = R(c0.pinf), P1 = R(c1.pinf);
+  R v0 = R(c0.A) * Tf * frcp(ps + P0);
+  R v1 = R(c1.A) * Tf * frcp(ps + P1);
+  R vs = (Y0 != R(0) ? Y0 * v0 : R(0)) + (Yf != R(0) ? Yf * v1 : R(0));
+  rf = frcp(vs);
+  ef = (Y0 != R(0) ? Y0 * (R(c0.cv) * Tf + P0 * v0 + R(c0.qs)) : R(0)) +
+       (Yf != R(0) ? Yf * (R(c1.cv) * Tf + P1 * v1 + R(c1.qs)) : R(0));
+}
+
+// One face (Section 3.2/3.3, Appendix D):
+//  impedances I_L = (3 rho_i + rho_{i+1}) c_m / 4, I_R = (rho_i + 3 rho_{i+1}) c_m / 4;
+//  discontinuous branch: limited upwind-biased states, p* = (p_L + p_R)/2,
+//   u* = (I_L u_L + I_R u_R + p_L - p_R) / (I_L + I_R), face state from the
+//   upwind side of u* (ties to the left), xi by THINC when the upwind cell is
+//   an interface cell;
+//  smooth branch: fourth-order central u, p; second-order central T, xi;
+//   u* = u_C + k3 (p_{i+2} - 3 p_{i+1} + 3 p_i - p_{i-1}) / (I_L + I_R);
+//  TDU: rho_f, e_f from the closure at (p*, T_f, xi_f);
+//  flux (storage variables): (m xi_L, m xi_G, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*).
+template <class R, int D, int DIR, bool PRK>
+__device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil<R, D>& s,
+                                 bool disc, bool sl, bool sr, R* F)
+{
+  R cm = fmax(s.c1, s.c2);
+  R rsum = s.rho1 + s.rho2;
+  R IL = (R(3) * s.rho1 + s.rho2) * cm * R(0.25);
+  R IR = (s.rho1 + R(3) * s.rho2) * cm * R(0.25);
+  R iI = frcp(rsum * cm);
+  R uf[D];
+  R us, ps, Tf, Yf;
+  if (disc) {
+    R uL[D], uR[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) recon<R>(S.lim_u, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
+    R pL, pR, TL, TR, YL, YR;
+    recon<R>(S.lim_s, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
+    recon<R>(S.lim_s, s.T[0], s.T[1], s.T[2], s.T[3], TL, TR);
+    recon<R>(S.lim_s, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
+    ps = R(0.5) * (pL + pR);
+    us = (IL * uL[DIR] + IR * uR[DIR] + pL - pR) * iI;
+    bool left = us >= R(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) uf[d] = left ? uL[d] : uR[d];
+    Tf = left ? TL : TR;
+    Yf = left ? YL : YR;
+    if (S.thinc && (left ? sl : sr)) {
+      R a = left ? s.Y[0] : s.Y[1];
+      R b = left ? s.Y[1] : s.Y[2];
+      R c = left ? s.Y[2] : s.Y[3];
+      R mn = fmin(a, c), mx = fmax(a, c);
+      R th = (c >= a) ? R(1) : R(-1);
+      R Fv = fdiv(b - mn + R(S.thinc_gamma), mx - mn + R(S.thinc_gamma));
+      R tb = R(S.tanh_b);
+      R E = (fexp(th * R(S.beta) * (R(2) * Fv - R(1))) * R(S.icosh_b) - R(1)) * R(S.itanh_b);
+      R prof = left ? fdiv(tb + E, R(1) + E * tb) : E;
+      Yf = mn + R(0.5) * (mx - mn) * (R(1) + th * prof);
+    }
+  } else {
+    const R c12 = R(1.0 / 12.0);
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      uf[d] = (R(7) * (s.u[d][1] + s.u[d][2]) - s.u[d][0] - s.u[d][3]) * c12;
+    ps = (R(7) * (s.p[1] + s.p[2]) - s.p[0] - s.p[3]) * c12;
+    R d3p = s.p[3] - R(3) * s.p[2] + R(3) * s.p[1] - s.p[0];
+    us = uf[DIR] + R(S.k3) * d3p * iI;
+    Tf = R(0.5) * (s.T[1] + s.T[2]);
+    Yf = R(0.5) * (s.Y[1] + s.Y[2]);
+  }
+  R rf, ef;
+  if (!PRK || C.comp[1].kind == 0 || Yf == R(0)) {
+    tdu_sg<R>(C, ps, Tf, Yf, rf, ef);
+  } else {
+    double vm, em;
+    closure_fwd<PRK>(C, (double)ps, (double)Tf, (double)Yf, vm, em);
+    rf = R(1.0 / vm);
+    ef = R(em);
+  }
+  R m = rf * us;
+  R ke = R(0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) ke += uf[d] * uf[d];
+  F[0] = m * (R(1) - Yf);
+  F[1] = m * Yf;
+#pragma unroll
+  for (int d = 0; d < D; ++d) F[2 + d] = m * uf[d] + (d == DIR ? ps : R(0));
+  F[2 + D] = m * (ef + R(0.5) * ke) + ps * us;
+}
+
+}  // namespace fvm

@@ -1,0 +1,735 @@
+// fvm_kernels.hip -- gfx950 kernels of the solver.
+//
+// One fused kernel per Runge-Kutta stage (Algorithm 1): a workgroup owns a
+// tile of cells, stages the tile plus the two-cell halo of the four-cell
+// stencil (Fig. 3.1) in LDS after inverting the closure in FP64 for every
+// staged cell, evaluates the sensors (Appendix D), every face flux of the tile
+// once (Section 3.2/3.3), the CSF source (Section 3.5) and writes
+// q^(k) = q^n + a_k dt R.  Ghost cells are generated from the boundary kinds
+// while loading; the last stage also reduces the CFL bound of the new state
+// (wavefront shuffle -> LDS -> one atomicMax per workgroup) and flags cells
+// that left the closure's domain.  Batches of cases run through the same
+// kernels via a tile table (case, tile coordinates).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "fvm_device.hpp"
+#include "fvm_kernels.hpp"
+
+namespace fvm {
+
+// ------------------------------------------------------------------ ghost cells
+__device__ inline void map_index(int& i, int n, int bclo, int bchi, bool& flip)
+{
+  if (i < 0) {
+    if (bclo == BC_PERIODIC) i += n;
+    else if (bclo == BC_WALL) { i = -1 - i; flip = true; }
+    else i = 0;
+  } else if (i >= n) {
+    if (bchi == BC_PERIODIC) i -= n;
+    else if (bchi == BC_WALL) { i = 2 * n - 1 - i; flip = true; }
+    else i = n - 1;
+  }
+  i = min(max(i, 0), n - 1);   // cells beyond the stencil's reach (partial tiles)
+}
+
+// physical partial densities, momentum and gauge energy of a cell from its
+// primitives (p, T, alpha_G, u); xi = alpha_G rho_G / rho at (p, T)
+template <bool PRK>
+__device__ inline void state_from_prim(const CaseC& C, double p, double T, double al, const double* u,
+                                       int D, double* q)
+{
+  double vL, eL, vG, eG;
+  closure_fwd<PRK>(C, p, T, 0.0, vL, eL);
+  closure_fwd<PRK>(C, p, T, 1.0, vG, eG);
+  double rG = 1.0 / vG, rL = 1.0 / vL;
+  double rho = al * rG + (1.0 - al) * rL;
+  double Y = al * rG / rho;
+  double vm, em;
+  closure_fwd<PRK>(C, p, T, Y, vm, em);
+  double ke = 0.0;
+  for (int d = 0; d < D; ++d) ke += u[d] * u[d];
+  q[0] = rho - rho * Y;
+  q[1] = rho * Y;
+  for (int d = 0; d < D; ++d) q[2 + d] = rho * u[d];
+  q[2 + D] = rho * (em + 0.5 * ke);
+}
+
+// load one (possibly ghost) cell: physical partial densities, momentum, gauge energy
+template <class S, int D, bool PRK>
+__device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long long total,
+                                 int gx, int gy, int gz, long long step, double* q)
+{
+  bool fx = false, fy = false, fz = false;
+  int ix = gx, iy = gy, iz = gz;
+  if (D >= 2) map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
+  if (D >= 3) map_index(iz, C.n[2], C.bc[2][0], C.bc[2][1], fz);
+  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
+    double yy = (D >= 2) ? (iy + 0.5) * C.dx[1] - C.in_c0 : 0.0;
+    double zz = (D >= 3) ? (iz + 0.5) * C.dx[2] - C.in_c1 : 0.0;
+    if (D == 1 || sqrt(yy * yy + zz * zz) < C.in_radius) {
+      double u[3] = {C.in_u, 0.0, 0.0};
+      for (int c = 0; c < D; ++c)
+        u[c] += C.in_noise * C.in_u *
+                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
+                               (unsigned long long)iz, (unsigned long long)c) - 1.0);
+      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, D, q);
+      if (D >= 2 && fy) q[3] = -q[3];
+      if (D >= 3 && fz) q[4] = -q[4];
+      return;
+    }
+    ix = -1 - ix;
+    fx = true;
+  } else {
+    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
+  }
+  long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
+  q[0] = (double)src[cell] + C.rref[0];
+  q[1] = (double)src[total + cell] + C.rref[1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) q[2 + d] = (double)src[(2 + d) * total + cell];
+  q[2 + D] = (double)src[(2 + D) * total + cell];
+  if (fx) q[2] = -q[2];
+  if (D >= 2 && fy) q[3] = -q[3];
+  if (D >= 3 && fz) q[4] = -q[4];
+}
+
+// primitives of a loaded cell
+template <int D, bool PRK>
+__device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
+{
+  rho = q[0] + q[1];
+  double ir = 1.0 / rho;
+  Y = q[1] * ir;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
+  double e = q[2 + D] * ir - 0.5 * ke;
+  return closure<PRK>(C, rho, Y, e);
+}
+
+__device__ inline void record_error(CaseDyn& dy, int code, long long cell, long long step)
+{
+  if (atomicCAS(&dy.err, 0, code) == 0) {
+    dy.err_cell = cell;
+    dy.err_step = step;
+  }
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------ fused 1D/2D stage
+template <class S, int D, int TX, int TY, int NT, bool PRK>
+__global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
+{
+  static_assert(D == 1 || D == 2, "1D/2D kernel");
+  static_assert(D == 2 || TY == 1, "1D tiles are one row");
+  constexpr int HX = TX + 4, HY = (D == 2) ? TY + 4 : 1, NH = HX * HY;
+  constexpr int NQ = D + 3;
+  constexpr int NC = TX * TY;
+  constexpr int CPT = (NC + NT - 1) / NT;
+  constexpr int NFX = (TX + 1) * TY, NFY = (D == 2) ? TX * (TY + 1) : 0;
+  constexpr int NF = NFX > NFY ? NFX : NFY;
+  constexpr int OY = (D == 2) ? 2 : 0;          // halo offset in y
+  constexpr int FX = TX + 2, FY = (D == 2) ? TY + 2 : 1;   // tile + one halo layer
+  constexpr int VX = TX + 1, VY = (D == 2) ? TY + 1 : 1;   // vertices
+  static_assert(FX * FY + D * VX * VY <= NQ * NF, "CSF scratch fits in the flux buffer");
+
+  __shared__ S s_rho[NH], s_u[NH], s_v[D == 2 ? NH : 1], s_p[NH], s_T[NH], s_Y[NH], s_c[NH], s_a[NH];
+  __shared__ unsigned char s_fl[NH];
+  __shared__ S s_F[NQ][NF];
+  __shared__ double s_red[NT / 64];
+
+  const int4 tl = a.tiles[blockIdx.x];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const SchemeC& SC = a.sc;
+  const int x0 = tl.y * TX, y0 = tl.z * TY;
+  const int tid = threadIdx.x;
+  const long long step = (a.stage >= 0) ? dy.step_cur : a.rhs_step;
+  const S* __restrict__ src = (const S*)a.src;
+
+  // ---- closure inversion of tile + halo (FP64), primitives to LDS
+  for (int h = tid; h < NH; h += NT) {
+    int hx = h % HX, hy = h / HX;
+    double q[NQ], u[D], rho, Y;
+    load_cell<S, D, PRK>(C, src, a.total, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, q);
+    PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
+    s_rho[h] = S(rho);
+    s_u[h] = S(u[0]);
+    if (D == 2) s_v[h] = S(u[D - 1]);
+    s_p[h] = S(pt.p);
+    s_T[h] = S(pt.T);
+    s_Y[h] = S(Y);
+    s_c[h] = S(pt.c);
+    s_a[h] = S(pt.alpha);
+  }
+  __syncthreads();
+
+  // ---- sensors and THINC eligibility on tile + one halo layer (Appendix D)
+  for (int h = tid; h < FX * FY; h += NT) {
+    int lx = h % FX, ly = h / FX;
+    int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+    unsigned fl = 0;
+    S Y = s_Y[c];
+    bool inner = Y > S(SC.eps_int) && Y < S(1) - S(SC.eps_int);
+    if (inner && (Y - s_Y[c - 1]) * (s_Y[c + 1] - Y) > S(0)) fl |= 2u;
+    if (D == 2 && inner && (Y - s_Y[c - HX]) * (s_Y[c + HX] - Y) > S(0)) fl |= 4u;
+    if (!SC.switching) {
+      fl |= 1u;
+    } else {
+      S idx2 = S(0.5 * C.idx[0]);
+      S dudx = (s_u[c + 1] - s_u[c - 1]) * idx2;
+      S div = dudx, curl2 = S(0);
+      S thg = fabs(s_a[c] - s_a[c - 1]) + fabs(s_a[c + 1] - s_a[c]);
+      if (D == 2) {
+        S idy2 = S(0.5 * C.idx[1]);
+        S dvdy = (s_v[c + HX] - s_v[c - HX]) * idy2;
+        S dvdx = (s_v[c + 1] - s_v[c - 1]) * idx2;
+        S dudy = (s_u[c + HX] - s_u[c - HX]) * idy2;
+        div += dvdy;
+        S w = dvdx - dudy;
+        curl2 = w * w;
+        thg += fabs(s_a[c] - s_a[c - HX]) + fabs(s_a[c + HX] - s_a[c]);
+      }
+      S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
+      if (thd > S(SC.th_d) || thg > S(SC.th_g)) fl |= 1u;
+    }
+    s_fl[c] = (unsigned char)fl;
+  }
+  __syncthreads();
+
+  S R[CPT][NQ];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
+
+  // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
+  for (int f = tid; f < NFX; f += NT) {
+    int i = f % (TX + 1), j = f / (TX + 1);
+    int c = (j + OY) * HX + i + 1;
+    Stencil<S, D> st;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      st.u[0][m] = s_u[c - 1 + m];
+      if (D == 2) st.u[D - 1][m] = s_v[c - 1 + m];
+      st.p[m] = s_p[c - 1 + m];
+      st.T[m] = s_T[c - 1 + m];
+      st.Y[m] = s_Y[c - 1 + m];
+    }
+    st.rho1 = s_rho[c]; st.rho2 = s_rho[c + 1];
+    st.c1 = s_c[c]; st.c2 = s_c[c + 1];
+    unsigned fa = s_fl[c], fb = s_fl[c + 1];
+    S F[NQ];
+    face_flux<S, D, 0, PRK>(SC, C, st, ((fa | fb) & 1u) != 0, (fa & 2u) != 0, (fb & 2u) != 0, F);
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+  }
+  __syncthreads();
+  {
+    S ix = S(C.idx[0]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = cc / TX;
+        int f = j * (TX + 1) + i;
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + 1]) * ix;
+      }
+    }
+  }
+  if (D == 2) {
+    __syncthreads();
+    for (int f = tid; f < NFY; f += NT) {
+      int i = f % TX, j = f / TX;
+      int c = (j + 1) * HX + i + 2;
+      Stencil<S, D> st;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int cm = c + (m - 1) * HX;
+        st.u[0][m] = s_u[cm];
+        st.u[D - 1][m] = s_v[cm];
+        st.p[m] = s_p[cm];
+        st.T[m] = s_T[cm];
+        st.Y[m] = s_Y[cm];
+      }
+      st.rho1 = s_rho[c]; st.rho2 = s_rho[c + HX];
+      st.c1 = s_c[c]; st.c2 = s_c[c + HX];
+      unsigned fa = s_fl[c], fb = s_fl[c + HX];
+      S F[NQ];
+      face_flux<S, D, D - 1, PRK>(SC, C, st, ((fa | fb) & 1u) != 0, (fa & 4u) != 0, (fb & 4u) != 0, F);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+    }
+    __syncthreads();
+    S iy = S(C.idx[D - 1]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = cc / TX;
+        int f = j * TX + i;
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + TX]) * iy;
+      }
+    }
+  }
+
+  // ---- CSF: kappa from the Gaussian-smoothed xi with vertex normals, force sigma kappa grad(alpha_G)
+  if (SC.sigma > 0.0) {
+    __syncthreads();
+    S* s_H = &s_F[0][0];
+    S* s_nx = s_H + FX * FY;
+    S* s_ny = s_nx + VX * VY;
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+      S acc;
+      if (D == 1) {
+        acc = (s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1]) * S(0.25);
+      } else {
+        S r0 = s_Y[c - HX - 1] + S(2) * s_Y[c - HX] + s_Y[c - HX + 1];
+        S r1 = s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1];
+        S r2 = s_Y[c + HX - 1] + S(2) * s_Y[c + HX] + s_Y[c + HX + 1];
+        acc = (r0 + S(2) * r1 + r2) * S(1.0 / 16.0);
+      }
+      s_H[h] = acc;
+    }
+    __syncthreads();
+    S en = S(SC.eps_n * C.idx[0]);
+    for (int h = tid; h < VX * VY; h += NT) {
+      int vx = h % VX, vy = h / VX;      // vertex at the upper corner of tile cell (vx-1, vy-1)
+      int c = vy * FX + vx;              // s_H index of cell (vx-1, vy-1)
+      S gx, gy = S(0);
+      if (D == 1) {
+        gx = (s_H[c + 1] - s_H[c]) * S(C.idx[0]);
+      } else {
+        gx = (s_H[c + 1] + s_H[c + FX + 1] - s_H[c] - s_H[c + FX]) * S(0.5 * C.idx[0]);
+        gy = (s_H[c + FX] + s_H[c + FX + 1] - s_H[c] - s_H[c + 1]) * S(0.5 * C.idx[1]);
+      }
+      S inv = frcp(sqrt(gx * gx + gy * gy) + en);
+      s_nx[h] = gx * inv;
+      if (D == 2) s_ny[h] = gy * inv;
+    }
+    __syncthreads();
+    S sig = S(SC.sigma);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = cc / TX;
+        int c = (j + OY) * HX + i + 2;
+        S kap, Sx, Sy = S(0);
+        if (D == 1) {
+          kap = -(s_nx[i + 1] - s_nx[i]) * S(C.idx[0]);
+          Sx = sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
+        } else {
+          int v = (j + 1) * VX + (i + 1);   // vertex (i, j) = upper corner of cell (i, j)
+          S dnx = s_nx[v] + s_nx[v - VX] - s_nx[v - 1] - s_nx[v - VX - 1];
+          S dny = s_ny[v] + s_ny[v - 1] - s_ny[v - VX] - s_ny[v - VX - 1];
+          kap = -(dnx * S(0.5 * C.idx[0]) + dny * S(0.5 * C.idx[1]));
+          Sx = sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
+          Sy = sig * kap * (s_a[c + HX] - s_a[c - HX]) * S(0.5 * C.idx[1]);
+        }
+        R[k][2] += Sx;
+        S se = s_u[c] * Sx;
+        if (D == 2) { R[k][3] += Sy; se += s_v[c] * Sy; }
+        R[k][2 + D] += se;
+      }
+    }
+  }
+
+  // ---- output
+  const long long T = a.total;
+  if (a.stage < 0) {
+    // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      int i = cc % TX, j = cc / TX;
+      int gx = x0 + i, gy = y0 + j;
+      if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
+        // caller's layout: [N_q][ncell] of this case
+        const long long RS = C.ncell;
+        long long cell = gx + (long long)C.n[0] * gy;
+        double r0 = (double)R[k][0], r1 = (double)R[k][1];
+        a.rhs_out[cell] = r0 + r1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
+        a.rhs_out[(1 + D) * RS + cell] = (double)R[k][2 + D] + C.Q[0] * r0 + C.Q[1] * r1;
+        a.rhs_out[(2 + D) * RS + cell] = r1;
+      }
+    }
+    return;
+  }
+  // the last stage writes q^(n+1) over q^n: each cell is read, then written, by one thread
+  const S* qn = (const S*)a.qn;
+  S* dst = (S*)a.dst;
+  const S adt = S(a.ak * dy.dt);
+  double lam = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int cc = tid + k * NT;
+    int i = cc % TX, j = cc / TX;
+    int gx = x0 + i, gy = y0 + j;
+    if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
+      long long cell = C.off + gx + (long long)C.n[0] * gy;
+      S nv[NQ];
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        nv[v] = qn[v * T + cell] + adt * R[k][v];
+        dst[v * T + cell] = nv[v];
+      }
+      if (a.stage == 3) {
+        double q[NQ], u[D], rho, Y;
+        q[0] = (double)nv[0] + C.rref[0];
+        q[1] = (double)nv[1] + C.rref[1];
+#pragma unroll
+        for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
+        PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
+        double l = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+        bool finite = isfinite(l) && isfinite(pt.p);
+        if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
+        else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
+        else lam = fmax(lam, l);
+      }
+    }
+  }
+  if (a.stage == 3) {
+    lam = wave_max(lam);
+    if ((tid & 63) == 0) s_red[tid >> 6] = lam;
+    __syncthreads();
+    if (tid == 0) {
+      double m = s_red[0];
+      for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
+      atomicMax(&dy.dtmax[(step + 1) & 1], (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ per-step scalars
+__global__ void k_step_begin(CaseDyn* dyn, int ncases, double cfl, double t_end)
+{
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncases) return;
+  CaseDyn& d = dyn[c];
+  long long n = d.step;
+  int s = (int)(n & 1);
+  double lam = __longlong_as_double((long long)d.dtmax[s]);
+  double dt = cfl / lam;
+  if (t_end > 0.0 && d.t + dt > t_end) dt = t_end - d.t;
+  if (!(dt > 0.0) || d.err != 0) dt = 0.0;
+  d.dt = dt;
+  d.t += dt;
+  d.step_cur = n;
+  d.step = n + 1;
+  d.dtmax[s ^ 1] = 0ull;
+}
+
+// ------------------------------------------------------------------ per-cell kernels of one case
+template <class S, int D, bool PRK>
+__global__ void k_prim_to_state(const CaseC* cases, int icase, const double* __restrict__ prim,
+                                S* __restrict__ dst, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  double u[3] = {0, 0, 0}, q[D + 3];
+  for (int d = 0; d < D; ++d) u[d] = prim[(3 + d) * C.ncell + c];
+  state_from_prim<PRK>(C, prim[c], prim[C.ncell + c], prim[2 * C.ncell + c], u, D, q);
+  long long g = C.off + c;
+  dst[g] = S(q[0] - C.rref[0]);
+  dst[total + g] = S(q[1] - C.rref[1]);
+  for (int v = 2; v < D + 3; ++v) dst[v * total + g] = S(q[v]);
+}
+
+template <class S, int D>
+__global__ void k_cons_to_state(const CaseC* cases, int icase, const double* __restrict__ qin,
+                                S* __restrict__ dst, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double rho = qin[c], rY = qin[(2 + D) * n + c];
+  double rL = rho - rY, rG = rY;
+  dst[g] = S(rL - C.rref[0]);
+  dst[total + g] = S(rG - C.rref[1]);
+  for (int d = 0; d < D; ++d) dst[(2 + d) * total + g] = S(qin[(1 + d) * n + c]);
+  dst[(2 + D) * total + g] = S(qin[(1 + D) * n + c] - C.Q[0] * rL - C.Q[1] * rG);
+}
+
+template <class S, int D>
+__global__ void k_state_to_cons(const CaseC* cases, int icase, const S* __restrict__ src,
+                                double* __restrict__ qout, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g] + C.rref[1];
+  qout[c] = rL + rG;
+  for (int d = 0; d < D; ++d) qout[(1 + d) * n + c] = (double)src[(2 + d) * total + g];
+  qout[(1 + D) * n + c] = (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+  qout[(2 + D) * n + c] = rG;
+}
+
+template <class S, int D, bool PRK>
+__global__ void k_state_to_prim(const CaseC* cases, int icase, const S* __restrict__ src,
+                                double* __restrict__ w, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double q[D + 3], u[D], rho, Y;
+  q[0] = (double)src[g] + C.rref[0];
+  q[1] = (double)src[total + g] + C.rref[1];
+  for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
+  PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
+  w[c] = rho;
+  for (int d = 0; d < 3; ++d) w[(1 + d) * n + c] = d < D ? u[d] : 0.0;
+  w[4 * n + c] = pt.p;
+  w[5 * n + c] = pt.T;
+  w[6 * n + c] = Y;
+  w[7 * n + c] = pt.c;
+  w[8 * n + c] = pt.alpha;
+}
+
+// CFL bound of the current state of one case into dtmax[step & 1]
+template <class S, int D, bool PRK>
+__global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dyn, int icase,
+                                                 const S* __restrict__ src, long long total)
+{
+  __shared__ double s_red[4];
+  const CaseC& C = cases[icase];
+  CaseDyn& dy = dyn[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double lam = 0.0;
+  if (c < C.ncell) {
+    long long g = C.off + c;
+    double q[D + 3], u[D], rho, Y;
+    q[0] = (double)src[g] + C.rref[0];
+    q[1] = (double)src[total + g] + C.rref[1];
+    for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
+    PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
+    double l = 0.0;
+    for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+    if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.step);
+    else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.step);
+    else lam = l;
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+    atomicMax(&dy.dtmax[dy.step & 1], (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// deterministic conserved totals of one case: fixed-shape tree per block, then one block
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_totals_part(const CaseC* cases, int icase, const S* __restrict__ src,
+                                                     long long total, double* __restrict__ part)
+{
+  constexpr int NQ = D + 3;
+  __shared__ double s[NQ][256];
+  const CaseC& C = cases[icase];
+  double acc[NQ];
+  for (int v = 0; v < NQ; ++v) acc[v] = 0.0;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < C.ncell; c += 256ll * gridDim.x) {
+    long long g = C.off + c;
+    double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g] + C.rref[1];
+    acc[0] += rL + rG;
+    for (int d = 0; d < D; ++d) acc[1 + d] += (double)src[(2 + d) * total + g];
+    acc[1 + D] += (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+    acc[2 + D] += rG;
+  }
+  for (int v = 0; v < NQ; ++v) s[v][threadIdx.x] = acc[v];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int v = 0; v < NQ; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int v = 0; v < NQ; ++v) part[blockIdx.x * NQ + v] = s[v][0];
+}
+
+__global__ void k_totals_final(const double* __restrict__ part, int nblk, int nq, double vol, double* out)
+{
+  int v = threadIdx.x;
+  if (v >= nq) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[b * nq + v];
+  out[v] = acc * vol;
+}
+
+// ------------------------------------------------------------------ host-side launchers
+template <class S, int D, int TX, int TY, int NT, bool PRK>
+static hipError_t launch12(const StageArgs& a, int ntiles, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, PRK>), dim3(ntiles), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fvm
+
+using namespace fvm;
+
+// tile tables: (tx, ty, threads)
+static const int TILES1[][3] = {{256, 1, 256}, {128, 1, 128}};
+static const int TILES2[][3] = {{32, 8, 256}, {64, 4, 256}, {16, 16, 256}, {32, 16, 256}, {64, 8, 256}};
+
+int fvm_k_tile_count(int dim)
+{
+  if (dim == 1) return 2;
+  if (dim == 2) return 5;
+  if (dim == 3) return fvm_k_tile_count3();
+  return 0;
+}
+
+int fvm_k_tile_shape(int dim, int t, int* tx, int* ty, int* nt)
+{
+  if (dim == 1 && t >= 0 && t < 2) { *tx = TILES1[t][0]; *ty = TILES1[t][1]; *nt = TILES1[t][2]; return 0; }
+  if (dim == 2 && t >= 0 && t < 5) { *tx = TILES2[t][0]; *ty = TILES2[t][1]; *nt = TILES2[t][2]; return 0; }
+  if (dim == 3) return fvm_k_tile_shape3(t, tx, ty, nt);
+  return -1;
+}
+
+template <class S, bool PRK>
+static hipError_t stage12(int dim, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (dim == 1) {
+    switch (tile) {
+      case 0: return launch12<S, 1, 256, 1, 256, PRK>(a, ntiles, st);
+      case 1: return launch12<S, 1, 128, 1, 128, PRK>(a, ntiles, st);
+    }
+  } else {
+    switch (tile) {
+      case 0: return launch12<S, 2, 32, 8, 256, PRK>(a, ntiles, st);
+      case 1: return launch12<S, 2, 64, 4, 256, PRK>(a, ntiles, st);
+      case 2: return launch12<S, 2, 16, 16, 256, PRK>(a, ntiles, st);
+      case 3: return launch12<S, 2, 32, 16, 256, PRK>(a, ntiles, st);
+      case 4: return launch12<S, 2, 64, 8, 256, PRK>(a, ntiles, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (dim == 3) return fvm_k_stage3(mixed, prk, tile, a, ntiles, st);
+  if (mixed) return prk ? stage12<float, true>(dim, tile, a, ntiles, st) : stage12<float, false>(dim, tile, a, ntiles, st);
+  return prk ? stage12<double, true>(dim, tile, a, ntiles, st) : stage12<double, false>(dim, tile, a, ntiles, st);
+}
+
+hipError_t fvm_k_step_begin(CaseDyn* dyn, int ncases, double cfl, double t_end, hipStream_t st)
+{
+  hipLaunchKernelGGL(k_step_begin, dim3((ncases + 63) / 64), dim3(64), 0, st, dyn, ncases, cfl, t_end);
+  return hipGetLastError();
+}
+
+#define FVM_DISPATCH(MIXED, DIM, PRK, CALL)                                            \
+  do {                                                                                 \
+    if (MIXED) {                                                                       \
+      if (DIM == 1) { if (PRK) { CALL(float, 1, true); } else { CALL(float, 1, false); } }   \
+      else if (DIM == 2) { if (PRK) { CALL(float, 2, true); } else { CALL(float, 2, false); } } \
+      else { if (PRK) { CALL(float, 3, true); } else { CALL(float, 3, false); } }     \
+    } else {                                                                           \
+      if (DIM == 1) { if (PRK) { CALL(double, 1, true); } else { CALL(double, 1, false); } } \
+      else if (DIM == 2) { if (PRK) { CALL(double, 2, true); } else { CALL(double, 2, false); } } \
+      else { if (PRK) { CALL(double, 3, true); } else { CALL(double, 3, false); } }   \
+    }                                                                                  \
+  } while (0)
+
+static unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t fvm_k_prim_to_state(int dim, int mixed, int prk, const CaseC* cases, int icase, long long ncell,
+                               const double* prim, void* dst, long long total, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_prim_to_state<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
+  FVM_DISPATCH(mixed, dim, prk, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_k_cons_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                               const double* q, void* dst, long long total, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_cons_to_state<S, D>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
+  FVM_DISPATCH(mixed, dim, false, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_k_state_to_cons(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                               const void* src, double* q, long long total, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_state_to_cons<S, D>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
+  FVM_DISPATCH(mixed, dim, false, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const CaseC* cases, int icase, long long ncell,
+                               const void* src, double* w, long long total, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_state_to_prim<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
+  FVM_DISPATCH(mixed, dim, prk, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
+                         const void* src, long long total, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_dt_init<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total)
+  FVM_DISPATCH(mixed, dim, prk, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_k_totals(int dim, int mixed, const CaseC* cases, int icase, long long ncell, const void* src,
+                        long long total, double* part, int nblk, double vol, double* out, hipStream_t st)
+{
+#define CALL(S, D, P) hipLaunchKernelGGL((k_totals_part<S, D>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
+  FVM_DISPATCH(mixed, dim, false, CALL);
+#undef CALL
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, part, nblk, dim + 3, vol, out);
+  return hipGetLastError();
+}
+
+// storage shifts: partial densities and energies of both pure components at (p_ref, T_ref)
+template <bool PRK>
+__global__ void k_ref_shift(const CaseC* cases, int ncases, double* out, const double* pT)
+{
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncases) return;
+  const CaseC& C = cases[c];
+  double p = pT[2 * c], T = pT[2 * c + 1];
+  double v0, e0, v1, e1;
+  closure_fwd<PRK>(C, p, T, 0.0, v0, e0);
+  closure_fwd<PRK>(C, p, T, 1.0, v1, e1);
+  out[4 * c] = 1.0 / v0;
+  out[4 * c + 1] = 1.0 / v1;
+  out[4 * c + 2] = e0;
+  out[4 * c + 3] = e1;
+}
+
+hipError_t fvm_k_ref_shift(const CaseC* cases, int ncases, double* out, const double* pT, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_ref_shift<true>), dim3((ncases + 63) / 64), dim3(64), 0, st, cases, ncases, out, pT);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}

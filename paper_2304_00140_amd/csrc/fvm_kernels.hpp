@@ -1,0 +1,44 @@
+// fvm_kernels.hpp -- launch interface between the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "fvm_device.hpp"
+
+struct StageArgs {
+  const fvm::CaseC* cases;
+  fvm::CaseDyn* dyn;
+  const int4* tiles;          // (case, tile x, tile y, tile z) per workgroup
+  const void* src;            // q^(k-1), storage variables [N_q][total]
+  const void* qn;             // q^n
+  void* dst;                  // q^(k)
+  long long total;            // field stride (cells of all cases)
+  double* rhs_out;            // stage < 0: R in conserved variables [N_q][total]
+  long long rhs_step;         // stage < 0: step number for the inflow noise
+  int stage;                  // 0..3, or -1 for a bare right-hand side
+  double ak;                  // stage coefficient
+  fvm::SchemeC sc;
+};
+
+int fvm_k_tile_count(int dim);
+int fvm_k_tile_shape(int dim, int tile, int* tx, int* ty, int* nt);
+int fvm_k_tile_count3();
+int fvm_k_tile_shape3(int tile, int* tx, int* ty, int* nt);
+// 3D tiles march along z over this many planes per workgroup
+int fvm_k_tile_zchunk3(int tile);
+
+hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+hipError_t fvm_k_step_begin(fvm::CaseDyn* dyn, int ncases, double cfl, double t_end, hipStream_t st);
+hipError_t fvm_k_prim_to_state(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
+                               const double* prim, void* dst, long long total, hipStream_t st);
+hipError_t fvm_k_cons_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                               const double* q, void* dst, long long total, hipStream_t st);
+hipError_t fvm_k_state_to_cons(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                               const void* src, double* q, long long total, hipStream_t st);
+hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
+                               const void* src, double* w, long long total, hipStream_t st);
+hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
+                         long long ncell, const void* src, long long total, hipStream_t st);
+hipError_t fvm_k_totals(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell, const void* src,
+                        long long total, double* part, int nblk, double vol, double* out, hipStream_t st);
+hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /* [ncases][4] */,
+                           const double* pT /* [ncases][2] */, hipStream_t st);

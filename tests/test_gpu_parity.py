@@ -1,0 +1,252 @@
+"""GPU (gfx950) path against the CPU FP64 oracle, through the C ABI.
+
+FP64 path: element-wise agreement to 1e-10 relative to each field's largest
+magnitude.  Mixed path (FP32 storage/fluxes, FP64 closure): 1e-4 relative
+L1 per field.  Sizes span several tiles with ragged tails."""
+import numpy as np
+import pytest
+
+from paper_2304_00140_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_00140_amd import fvm
+    fvm.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def stream(dev):
+    return torch.cuda.Stream(device=dev)
+
+
+def ctx_for(case, prec, stream, tile=None):
+    from paper_2304_00140_amd import fvm
+    c = fvm.Context(case, prec, stream=stream.cuda_stream)
+    if tile is not None:
+        c.set_tile(tile)
+    return c
+
+
+def field_err(a, b):
+    """max |a - b| per field over max |b| per field"""
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return (np.abs(a - b).max(axis=1) / scale).max()
+
+
+def gpu_rhs(ctx, q, dev, step=0):
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+    rd = torch.zeros_like(qd)
+    torch.cuda.synchronize()
+    ctx.rhs(qd.data_ptr(), rd.data_ptr(), step)
+    return rd.cpu().numpy()
+
+
+RHS_CASES = [
+    dict(dim=1, n=[203], seed=1),
+    dict(dim=1, n=[77], seed=2, bc=[[W.BC_WALL, W.BC_ZEROGRAD]], sigma=0.05),
+    dict(dim=2, n=[70, 37], seed=3),
+    dict(dim=2, n=[70, 37], seed=4, switching=1),
+    dict(dim=2, n=[45, 52], seed=5, sigma=0.07),
+    dict(dim=2, n=[45, 52], seed=6, sigma=0.07, switching=1,
+         bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_ZEROGRAD, W.BC_WALL]]),
+    dict(dim=2, n=[33, 9], seed=7, liquid=False),
+]
+
+
+def make_case(spec):
+    spec = dict(spec)
+    dim, n, seed = spec.pop("dim"), spec.pop("n"), spec.pop("seed")
+    return W.random_state(dim, n, seed, **spec)
+
+
+@pytest.mark.parametrize("spec", RHS_CASES, ids=lambda s: f"{s['dim']}d-{s['seed']}")
+def test_rhs_fp64_matches_oracle(dev, stream, spec):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = make_case(spec)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    r_ref = o.rhs(q)
+    for tile in range(fvm.lib().fvm_tile_count(case["grid"]["dim"])):
+        ctx = ctx_for(case, fvm.FVM_FP64, stream, tile)
+        r = gpu_rhs(ctx, q, dev)
+        err = field_err(r, r_ref)
+        print(f"rhs {spec} tile {tile}: {err:.3e}", flush=True)
+        assert err < 1e-10
+
+
+def test_rhs_inflow_noise_matches_oracle(dev, stream):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [40, 30], 9, bc=[[W.BC_INFLOW, W.BC_ZEROGRAD], [W.BC_WALL, W.BC_PERIODIC]])
+    case["grid"]["bc"][1] = [W.BC_PERIODIC, W.BC_PERIODIC]
+    case["grid"]["inflow"] = dict(p=1.05e5, T=300.0, alpha=0.0, u=40.0, radius=0.3 * 40 * case["grid"]["dx"][0],
+                                  center=[0.5 * 30 * case["grid"]["dx"][1], 0.0], noise=0.05, seed=11)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    for step in (0, 3):
+        assert field_err(gpu_rhs(ctx, q, dev, step), o.rhs(q, step)) < 1e-10
+
+
+def test_primitives_match_oracle(dev, stream):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [37, 21], 12)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    ctx.set_state(q)
+    w = ctx.get_primitive()
+    w_ref = o.prim_from_cons(q)
+    np.testing.assert_allclose(w[4], w_ref[4], rtol=1e-12, atol=1e-12 * 6e8)
+    np.testing.assert_allclose(w[5], w_ref[5], rtol=1e-12)
+    np.testing.assert_allclose(w[[0, 6, 7, 8]], w_ref[[0, 6, 7, 8]], rtol=1e-12, atol=1e-14)
+    # init from primitives on the device equals the oracle's conversion
+    ctx.init_primitive()
+    np.testing.assert_allclose(ctx.get_state(), q, rtol=1e-13, atol=1e-13 * np.abs(q).max())
+
+
+@pytest.mark.parametrize("spec", [RHS_CASES[0], RHS_CASES[3], RHS_CASES[5]],
+                         ids=lambda s: f"{s['dim']}d-{s['seed']}")
+def test_steps_fp64_match_oracle(dev, stream, spec):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = make_case(spec)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    ctx.set_state(q)
+    t_ref = 0.0
+    for k in range(5):
+        t_ref, _ = o.step(q, k, t_ref)
+    t = ctx.n_steps(5)
+    assert abs(t - t_ref) < 1e-12 * t_ref
+    err = field_err(ctx.get_state(), q)
+    print(f"5 steps {spec}: {err:.3e}", flush=True)
+    assert err < 1e-10
+
+
+def test_interface_advection_period_fp64(dev, stream):
+    """one advection period of the stiff water slab (FP64): the kernel keeps p
+    and u at their initial values and matches the oracle's interface"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.interface_advection_1d(200, periods=1.0)
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    ctx.init_primitive()
+    t_end = case["t_end"]
+    t = ctx.n_steps(7000, t_end)
+    assert abs(t - t_end) < 1e-15
+    w = ctx.get_primitive()
+    assert np.abs(w[4] - 1e5).max() / (1e5 + 6e8) < 1e-12
+    assert np.abs(w[1] - 100.0).max() / 100.0 < 1e-11
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    tt, n = 0.0, 0
+    while tt < t_end * (1 - 1e-14):
+        tt, _ = o.step(q, n, tt, t_end)
+        n += 1
+    w_ref = o.prim_from_cons(q)
+    assert np.abs(w[6] - w_ref[6]).max() < 1e-9
+
+
+def test_conservation_fp64_and_mixed(dev, stream):
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [64, 48], 21)
+    for prec, tol in ((fvm.FVM_FP64, 1e-13), (fvm.FVM_MIXED, 1e-6)):
+        ctx = ctx_for(case, prec, stream)
+        ctx.init_primitive()
+        t0 = ctx.totals()
+        ctx.n_steps(60)
+        t1 = ctx.totals()
+        rel = np.abs(t1 - t0) / np.maximum(np.abs(t0), 1e-30)
+        print("conservation", prec, rel, flush=True)
+        assert rel[0] < tol and rel[-1] < tol and rel[-2] < tol
+
+
+def test_tile_shapes_bitwise_identical_and_deterministic(dev, stream):
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [70, 37], 31, sigma=0.05, switching=1,
+                          bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC]])
+    for prec in (fvm.FVM_FP64, fvm.FVM_MIXED):
+        outs = []
+        for tile in list(range(fvm.lib().fvm_tile_count(2))) + [0]:
+            ctx = ctx_for(case, prec, stream, tile)
+            ctx.init_primitive()
+            ctx.n_steps(7)
+            outs.append(ctx.get_state())
+        for o in outs[1:]:
+            np.testing.assert_array_equal(o, outs[0])
+
+
+def test_graph_replay_equals_single_steps(dev, stream):
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [40, 36], 41)
+    a = ctx_for(case, fvm.FVM_MIXED, stream)
+    a.init_primitive()
+    a.n_steps(120)          # 2 graph replays of 50 steps + 20 single launches
+    b = ctx_for(case, fvm.FVM_MIXED, stream)
+    b.init_primitive()
+    for _ in range(120):
+        b.step()
+    np.testing.assert_array_equal(a.get_state(), b.get_state())
+    assert a.clock() == b.clock()
+
+
+def test_batch_equals_single_cases(dev, stream):
+    from paper_2304_00140_amd import fvm
+    cases = fvm_cases = W.bubble_collapse_batch(ncases=3, nmin=20, nmax=50, steps=5)
+    b = fvm.Batch(cases, fvm.FVM_MIXED, stream=stream.cuda_stream)
+    for i in range(len(cases)):
+        b.init_primitive(i)
+    b.n_steps(6)
+    for i, c in enumerate(fvm_cases):
+        s = ctx_for(c, fvm.FVM_MIXED, stream)
+        s.init_primitive()
+        s.n_steps(6)
+        np.testing.assert_array_equal(b.get_state(i), s.get_state())
+
+
+def test_mixed_precision_against_fp64(dev, stream):
+    """mixed path vs FP64 path after 100 steps of a small shock-bubble case:
+    relative L1 per field (rho, u, p, xi) below 1e-4"""
+    from paper_2304_00140_amd import fvm
+    case = W.shock_bubble_2d(nx=128, ny=32, steps=100)
+    res = {}
+    for prec in (fvm.FVM_FP64, fvm.FVM_MIXED):
+        ctx = ctx_for(case, prec, stream)
+        ctx.init_primitive()
+        ctx.n_steps(100)
+        res[prec] = ctx.get_primitive()
+    a, b = res[fvm.FVM_MIXED], res[fvm.FVM_FP64]
+    l1 = {
+        "rho": np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum(),
+        "u": np.abs(a[1:3] - b[1:3]).sum() / (a.shape[1] * 113.5),
+        "p": np.abs(a[4] - b[4]).sum() / np.abs(b[4]).sum(),
+        "Y": np.abs(a[6] - b[6]).sum() / a.shape[1],
+    }
+    print("mixed vs fp64 L1", l1, flush=True)
+    assert max(l1.values()) < 1e-4
+
+
+def test_nonphysical_state_is_reported(dev, stream):
+    from paper_2304_00140_amd import fvm
+    from oracle.oracle import Oracle
+    case = W.random_state(2, [20, 20], 51)
+    q = Oracle(case).cons_from_prim()
+    q[0, 37] = -1.0
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    with pytest.raises(fvm.FvmError) as ei:
+        ctx.set_state(q)
+    assert ei.value.code in (fvm.FVM_ENONPHYS, fvm.FVM_ENAN)
+    with pytest.raises(fvm.FvmError):
+        ctx.n_steps(1)

@@ -283,6 +283,10 @@ static int pr_mixed(const og_eos* e, double rho, double ein, double Y, double* p
   double pp, TT;
   sg_pair(gam, pinf, cv, q, rho, ein, Y, &pp, &TT);
   double v = 1.0 / rho;
+  /* pressure is resolved to rounding relative to p + p_inf of a stiff component */
+  double pscale = 1.0;
+  for (int k = 0; k < 2; ++k)
+    if (e->kind[k] == OG_EOS_SG && e->pinf[k] > pscale) pscale = e->pinf[k];
   int ok = 0;
   for (int it = 0; it < 100; ++it) {
     double F1 = -v, F2 = -ein, J11 = 0, J12 = 0, J21 = 0, J22 = 0;
@@ -300,7 +304,7 @@ static int pr_mixed(const og_eos* e, double rho, double ein, double Y, double* p
     double pn = pp - dp, Tn = TT - dT;
     if (Tn <= 0.0) Tn = 0.5 * TT;
     pp = pn; TT = Tn;
-    if (fabs(dT) <= 1e-13 * TT && fabs(dp) <= 1e-13 * (fabs(pp) + 1.0)) { ok = 1; break; }
+    if (fabs(dT) <= 1e-12 * TT && fabs(dp) <= 1e-12 * (fabs(pp) + pscale)) { ok = 1; break; }
   }
   *p = pp; *T = TT;
   return ok ? 0 : -2;

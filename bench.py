@@ -29,7 +29,7 @@ def parse():
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
                              "interface_advection_1d"])
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
-    ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: tuned default)")
+    ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=4)
     ap.add_argument("--timing-steps", type=int, default=20, help="steps of per-stage event timing")
@@ -66,6 +66,10 @@ def run_path(cases, prec, args, stream, torch):
         ncell = h.ncell
     if args.tile >= 0:
         h.set_tile(args.tile)
+        tile, tune = args.tile, None
+    else:
+        from paper_2304_00140_amd import tune as tuner
+        tile, tune = tuner.autotune(h, prec, verbose=True)
     h.n_steps(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -77,7 +81,8 @@ def run_path(cases, prec, args, stream, torch):
     ms = e0.elapsed_time(e1)
     stage_ms = h.time_stages(args.timing_steps)
     nq = cases[0]["grid"]["dim"] + 3
-    return dict(handle=h, ncell=ncell, ms=ms, stage_ms=stage_ms, nq=nq)
+    return dict(handle=h, ncell=ncell, ms=ms, stage_ms=stage_ms, nq=nq, tile=tile,
+                tune={str(k): round(v * 1e3, 3) for k, v in (tune or {}).items()})
 
 
 def l1_errors(a, b, uref):
@@ -159,6 +164,8 @@ def main():
             "kernel": "k_stage12" if cases[0]["grid"]["dim"] < 3 else "k_stage3",
             "algorithmic_bytes_per_cell_stage": bytes_per_cell_stage,
             "stage_ms": r["stage_ms"],
+            "tile": r["tile"],
+            "tune_us_per_stage": r["tune"],
         },
     }
     if fvm.FVM_MIXED in res and len(paths) == 2:
@@ -167,7 +174,8 @@ def main():
         mavg = float(np.mean(m["stage_ms"]))
         mach = m["ncell"] * 2.75 * m["nq"] * 4 / (mavg * 1e-3) / 1e9
         entry = {"value": mv, "ms_per_step": m["ms"] / args.steps, "dtype": "f32+f64-closure",
-                 "stage_ms": m["stage_ms"], "achieved_GBs": mach, "frac": mach / HBM_PEAK_GBS}
+                 "stage_ms": m["stage_ms"], "achieved_GBs": mach, "frac": mach / HBM_PEAK_GBS,
+                 "tile": m["tile"], "tune_us_per_stage": m["tune"]}
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0,
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)

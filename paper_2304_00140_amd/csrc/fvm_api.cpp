@@ -29,6 +29,7 @@ struct fvm_batch {
   long long total = 0;
   size_t esz = 8;
   void* q[3] = {nullptr, nullptr, nullptr};
+  void* prim = nullptr;       // 3D: primitives of the stage input
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   double* dpart = nullptr;
@@ -212,6 +213,7 @@ static void batch_free(fvm_batch* b)
   drop_graph(b);
   for (int i = 0; i < 3; ++i)
     if (b->q[i]) (void)hipFree(b->q[i]);
+  if (b->prim) (void)hipFree(b->prim);
   if (b->dc) (void)hipFree(b->dc);
   if (b->dd) (void)hipFree(b->dd);
   if (b->dtiles) (void)hipFree(b->dtiles);
@@ -336,6 +338,10 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     if (hipMalloc(&b->q[i], bytes) != hipSuccess) return bail(fail(b, FVM_ENOMEM, "state allocation failed"));
     HIPCHECK(b, hipMemset(b->q[i], 0, bytes));
   }
+  if (b->dim == 3) {
+    if (hipMalloc(&b->prim, (size_t)9 * (size_t)b->total * b->esz) != hipSuccess)
+      return bail(fail(b, FVM_ENOMEM, "primitive buffer allocation failed"));
+  }
   HIPCHECK(b, hipMalloc(&b->dpart, sizeof(double) * 1024 * 8));
   HIPCHECK(b, hipMalloc(&b->dout, sizeof(double) * 16));
   b->tile = 0;
@@ -353,15 +359,18 @@ static StageArgs stage_args(fvm_batch* b)
   a.dyn = b->dd;
   a.tiles = b->dtiles;
   a.total = b->total;
+  a.prim = b->prim;
   a.sc = b->sc;
   return a;
 }
 
-static hipError_t launch_step(fvm_batch* b, double t_end)
+// the four stage launches of step `off` of the current chunk (dt, t and the
+// step number are derived on the device from CaseDyn)
+static hipError_t launch_stages(fvm_batch* b, int off, double t_end, hipEvent_t* ev = nullptr)
 {
-  hipError_t e = fvm_k_step_begin(b->dd, b->ncases, b->sc.cfl, t_end, b->st);
-  if (e != hipSuccess) return e;
   StageArgs a = stage_args(b);
+  a.sc.t_end = t_end;
+  a.step_off = off;
   void* src[4] = {b->q[0], b->q[1], b->q[2], b->q[1]};
   void* dst[4] = {b->q[1], b->q[2], b->q[1], b->q[0]};
   for (int k = 0; k < 4; ++k) {
@@ -370,10 +379,23 @@ static hipError_t launch_step(fvm_batch* b, double t_end)
     a.dst = dst[k];
     a.stage = k;
     a.ak = b->rk[k];
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[2 * k], b->st)) != hipSuccess) return e;
     e = fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st);
     if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2 * k + 1], b->st)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// a chunk of n steps followed by the device-side step counter update
+static hipError_t launch_chunk(fvm_batch* b, int n, double t_end)
+{
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = launch_stages(b, i, t_end);
+    if (e != hipSuccess) return e;
+  }
+  return fvm_k_advance(b->dd, b->ncases, n, b->st);
 }
 
 static int all_state(fvm_batch* b)
@@ -409,8 +431,7 @@ static int run_steps(fvm_batch* b, int n, double t_end)
     if (!b->gexec || b->gsteps != chunk || b->gtend != t_end) {
       drop_graph(b);
       HIPCHECK(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-      hipError_t e = hipSuccess;
-      for (int i = 0; i < chunk && e == hipSuccess; ++i) e = launch_step(b, t_end);
+      hipError_t e = launch_chunk(b, chunk, t_end);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(b->st, &g);
       if (e != hipSuccess) return fail(b, FVM_EHIP, std::string("launch during capture: ") + hipGetErrorString(e));
@@ -422,7 +443,7 @@ static int run_steps(fvm_batch* b, int n, double t_end)
     }
     for (; done + chunk <= n; done += chunk) HIPCHECK(b, hipGraphLaunch(b->gexec, b->st));
   }
-  for (; done < n; ++done) HIPCHECK(b, launch_step(b, t_end));
+  if (done < n) HIPCHECK(b, launch_chunk(b, n - done, t_end));
   HIPCHECK(b, hipStreamSynchronize(b->st));
   return check_errors(b);
 }
@@ -516,22 +537,8 @@ static int time_stages(fvm_batch* b, int steps, double* ms)
   if (steps < 1 || !ms) return fail(b, FVM_EINVAL, "steps >= 1 and an output array are needed");
   std::vector<hipEvent_t> ev(8 * steps);
   for (auto& e : ev) HIPCHECK(b, hipEventCreate(&e));
-  StageArgs a = stage_args(b);
-  void* src[4] = {b->q[0], b->q[1], b->q[2], b->q[1]};
-  void* dst[4] = {b->q[1], b->q[2], b->q[1], b->q[0]};
-  for (int s = 0; s < steps; ++s) {
-    HIPCHECK(b, fvm_k_step_begin(b->dd, b->ncases, b->sc.cfl, 0.0, b->st));
-    for (int k = 0; k < 4; ++k) {
-      a.src = src[k];
-      a.qn = b->q[0];
-      a.dst = dst[k];
-      a.stage = k;
-      a.ak = b->rk[k];
-      HIPCHECK(b, hipEventRecord(ev[8 * s + 2 * k], b->st));
-      HIPCHECK(b, fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st));
-      HIPCHECK(b, hipEventRecord(ev[8 * s + 2 * k + 1], b->st));
-    }
-  }
+  for (int s = 0; s < steps; ++s) HIPCHECK(b, launch_stages(b, s, 0.0, &ev[8 * s]));
+  HIPCHECK(b, fvm_k_advance(b->dd, b->ncases, steps, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
   for (int k = 0; k < 4; ++k) ms[k] = 0.0;
   for (int s = 0; s < steps; ++s)
@@ -680,9 +687,9 @@ int fvm_clock(fvm_ctx* ctx, double* t, double* dt, int64_t* steps)
   fvm_batch* b = ctx->b;
   CaseDyn d;
   HIPCHECK(b, hipMemcpy(&d, b->dd, sizeof d, hipMemcpyDeviceToHost));
-  if (t) *t = d.t;
-  if (dt) *dt = d.dt;
-  if (steps) *steps = d.step;
+  if (t) *t = d.t[d.base & 1];
+  if (dt) *dt = d.dt_last;
+  if (steps) *steps = d.base;
   return FVM_OK;
 }
 
@@ -772,7 +779,7 @@ int fvm_batch_n_steps(fvm_batch* b, int n, double* t_out)
   if (t_out) {
     std::vector<CaseDyn> d(b->ncases);
     HIPCHECK(b, hipMemcpy(d.data(), b->dd, sizeof(CaseDyn) * b->ncases, hipMemcpyDeviceToHost));
-    for (int c = 0; c < b->ncases; ++c) t_out[c] = d[c].t;
+    for (int c = 0; c < b->ncases; ++c) t_out[c] = d[c].t[d[c].base & 1];
   }
   return rc;
 }

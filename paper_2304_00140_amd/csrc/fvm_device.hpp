@@ -58,10 +58,13 @@ struct CaseC {
   int tile0, tiles[3];
 };
 
+// per-case scalars that live on the device across steps; slot s = step & 1
+// holds the values of q^n, slot s ^ 1 those of q^(n+1)
 struct CaseDyn {
-  unsigned long long dtmax[2];   // bits of max_cells sum (|u| + c)/dx for q^n (slot = step & 1)
-  double dt, t;
-  long long step, step_cur;
+  unsigned long long dtmax[2];   // bits of max_cells sum (|u| + c)/dx (non-negative doubles order as integers)
+  double t[2];                   // time at the start of the step
+  double dt_last;                // dt of the last step taken
+  long long base;                // steps completed before the current launch chunk
   int err, pad;
   long long err_cell, err_step;
 };
@@ -284,6 +287,8 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
     // mixed cell: Newton on sum xi_k v_k = v, sum xi_k e_k = e from the ideal-gas stand-in
     sg_pair(c0.gamma, c0.pinf, c0.cv, c0.qs, c1.gam_ig, 0.0, c1.cv, c1.qs, v, e, Y, p, T);
     double Y0 = 1.0 - Y;
+    // pressure is resolved to rounding relative to p + p_inf of the stiff component
+    const double pscale = fmax(c0.pinf, 1.0);
     int conv = 0;
     for (int it = 0; it < 60; ++it) {
       VE a = comp_ve(c0, p, T), b = comp_ve(c1, p, T);
@@ -297,7 +302,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
       if (Tn <= 0.0) Tn = 0.5 * T;
       p -= dp;
       T = Tn;
-      if (fabs(dT) <= 1e-13 * T && fabs(dp) <= 1e-13 * (fabs(p) + 1.0)) { conv = 1; break; }
+      if (fabs(dT) <= 1e-12 * T && fabs(dp) <= 1e-12 * (fabs(p) + pscale)) { conv = 1; break; }
     }
     r.p = p;
     r.T = T;
@@ -355,6 +360,14 @@ __device__ inline R slope(int kind, R far, R near)
     default: g = R(0);
   }
   return (far * near > R(0)) ? copysign(g, near) : R(0);
+}
+
+// THINC eligibility of the middle cell (Appendix D): eps < xi < 1 - eps and
+// xi monotone through the cell
+template <class R>
+__device__ inline bool eligible(R a, R b, R c, R eps)
+{
+  return b > eps && b < R(1) - eps && (b - a) * (c - b) > R(0);
 }
 
 // upwind-biased left/right face values from cells i-1, i, i+1, i+2 (Section 3.3)

@@ -14,117 +14,17 @@
 #include <stdint.h>
 #include "fvm_device.hpp"
 #include "fvm_kernels.hpp"
+#include "fvm_stage_common.hpp"
 
 namespace fvm {
 
-// ------------------------------------------------------------------ ghost cells
-__device__ inline void map_index(int& i, int n, int bclo, int bchi, bool& flip)
-{
-  if (i < 0) {
-    if (bclo == BC_PERIODIC) i += n;
-    else if (bclo == BC_WALL) { i = -1 - i; flip = true; }
-    else i = 0;
-  } else if (i >= n) {
-    if (bchi == BC_PERIODIC) i -= n;
-    else if (bchi == BC_WALL) { i = 2 * n - 1 - i; flip = true; }
-    else i = n - 1;
-  }
-  i = min(max(i, 0), n - 1);   // cells beyond the stencil's reach (partial tiles)
-}
-
-// physical partial densities, momentum and gauge energy of a cell from its
-// primitives (p, T, alpha_G, u); xi = alpha_G rho_G / rho at (p, T)
-template <bool PRK>
-__device__ inline void state_from_prim(const CaseC& C, double p, double T, double al, const double* u,
-                                       int D, double* q)
-{
-  double vL, eL, vG, eG;
-  closure_fwd<PRK>(C, p, T, 0.0, vL, eL);
-  closure_fwd<PRK>(C, p, T, 1.0, vG, eG);
-  double rG = 1.0 / vG, rL = 1.0 / vL;
-  double rho = al * rG + (1.0 - al) * rL;
-  double Y = al * rG / rho;
-  double vm, em;
-  closure_fwd<PRK>(C, p, T, Y, vm, em);
-  double ke = 0.0;
-  for (int d = 0; d < D; ++d) ke += u[d] * u[d];
-  q[0] = rho - rho * Y;
-  q[1] = rho * Y;
-  for (int d = 0; d < D; ++d) q[2 + d] = rho * u[d];
-  q[2 + D] = rho * (em + 0.5 * ke);
-}
-
-// load one (possibly ghost) cell: physical partial densities, momentum, gauge energy
-template <class S, int D, bool PRK>
-__device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long long total,
-                                 int gx, int gy, int gz, long long step, double* q)
-{
-  bool fx = false, fy = false, fz = false;
-  int ix = gx, iy = gy, iz = gz;
-  if (D >= 2) map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
-  if (D >= 3) map_index(iz, C.n[2], C.bc[2][0], C.bc[2][1], fz);
-  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
-    double yy = (D >= 2) ? (iy + 0.5) * C.dx[1] - C.in_c0 : 0.0;
-    double zz = (D >= 3) ? (iz + 0.5) * C.dx[2] - C.in_c1 : 0.0;
-    if (D == 1 || sqrt(yy * yy + zz * zz) < C.in_radius) {
-      double u[3] = {C.in_u, 0.0, 0.0};
-      for (int c = 0; c < D; ++c)
-        u[c] += C.in_noise * C.in_u *
-                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
-                               (unsigned long long)iz, (unsigned long long)c) - 1.0);
-      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, D, q);
-      if (D >= 2 && fy) q[3] = -q[3];
-      if (D >= 3 && fz) q[4] = -q[4];
-      return;
-    }
-    ix = -1 - ix;
-    fx = true;
-  } else {
-    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
-  }
-  long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
-  q[0] = (double)src[cell] + C.rref[0];
-  q[1] = (double)src[total + cell] + C.rref[1];
-#pragma unroll
-  for (int d = 0; d < D; ++d) q[2 + d] = (double)src[(2 + d) * total + cell];
-  q[2 + D] = (double)src[(2 + D) * total + cell];
-  if (fx) q[2] = -q[2];
-  if (D >= 2 && fy) q[3] = -q[3];
-  if (D >= 3 && fz) q[4] = -q[4];
-}
-
-// primitives of a loaded cell
-template <int D, bool PRK>
-__device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
-{
-  rho = q[0] + q[1];
-  double ir = 1.0 / rho;
-  Y = q[1] * ir;
-  double ke = 0.0;
-#pragma unroll
-  for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
-  double e = q[2 + D] * ir - 0.5 * ke;
-  return closure<PRK>(C, rho, Y, e);
-}
-
-__device__ inline void record_error(CaseDyn& dy, int code, long long cell, long long step)
-{
-  if (atomicCAS(&dy.err, 0, code) == 0) {
-    dy.err_cell = cell;
-    dy.err_step = step;
-  }
-}
-
-__device__ inline double wave_max(double v)
-{
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // ------------------------------------------------------------------ fused 1D/2D stage
-template <class S, int D, int TX, int TY, int NT, bool PRK>
-__global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
+// Tile TX x TY cells, NT threads (NT may exceed TX*TY: then several threads
+// share the halo and face work of fewer cells).  MINW: waves per SIMD the
+// register budget is held to.
+template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK>
+__global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
 {
   static_assert(D == 1 || D == 2, "1D/2D kernel");
   static_assert(D == 2 || TY == 1, "1D tiles are one row");
@@ -132,6 +32,7 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
   constexpr int NQ = D + 3;
   constexpr int NC = TX * TY;
   constexpr int CPT = (NC + NT - 1) / NT;
+  constexpr int NIT = (NH + NT - 1) / NT;
   constexpr int NFX = (TX + 1) * TY, NFY = (D == 2) ? TX * (TY + 1) : 0;
   constexpr int NF = NFX > NFY ? NFX : NFY;
   constexpr int OY = (D == 2) ? 2 : 0;          // halo offset in y
@@ -150,38 +51,60 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
   const SchemeC& SC = a.sc;
   const int x0 = tl.y * TX, y0 = tl.z * TY;
   const int tid = threadIdx.x;
-  const long long step = (a.stage >= 0) ? dy.step_cur : a.rhs_step;
+  const bool upd = a.stage >= 0;
+  const long long step = upd ? dy.base + a.step_off : a.rhs_step;
   const S* __restrict__ src = (const S*)a.src;
+  const long long T = a.total;
 
-  // ---- closure inversion of tile + halo (FP64), primitives to LDS
-  for (int h = tid; h < NH; h += NT) {
-    int hx = h % HX, hy = h / HX;
-    double q[NQ], u[D], rho, Y;
-    load_cell<S, D, PRK>(C, src, a.total, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, q);
-    PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
-    s_rho[h] = S(rho);
-    s_u[h] = S(u[0]);
-    if (D == 2) s_v[h] = S(u[D - 1]);
-    s_p[h] = S(pt.p);
-    s_T[h] = S(pt.T);
-    s_Y[h] = S(Y);
-    s_c[h] = S(pt.c);
-    s_a[h] = S(pt.alpha);
+  // ---- q^n of the owned cells, fetched early so its latency overlaps the stencil work
+  S qn_reg[CPT][NQ];
+  if (upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      int gx = x0 + cc % TX, gy = y0 + cc / TX;
+      bool own = cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1]);
+      long long cell = C.off + (own ? gx + (long long)C.n[0] * gy : 0);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+    }
+  }
+
+  // ---- tile + halo: all loads first, then the FP64 closure inversion, primitives to LDS
+  {
+    double qv[NIT][NQ];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        int hx = h % HX, hy = h / HX;
+        load_cell<S, D, PRK>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        double u[D], rho, Y;
+        PT pt = cell_prim<D, PRK>(C, qv[it], u, rho, Y);
+        s_rho[h] = S(rho);
+        s_u[h] = S(u[0]);
+        if (D == 2) s_v[h] = S(u[D - 1]);
+        s_p[h] = S(pt.p);
+        s_T[h] = S(pt.T);
+        s_Y[h] = S(Y);
+        s_c[h] = S(pt.c);
+        s_a[h] = S(pt.alpha);
+      }
+    }
   }
   __syncthreads();
 
-  // ---- sensors and THINC eligibility on tile + one halo layer (Appendix D)
-  for (int h = tid; h < FX * FY; h += NT) {
-    int lx = h % FX, ly = h / FX;
-    int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
-    unsigned fl = 0;
-    S Y = s_Y[c];
-    bool inner = Y > S(SC.eps_int) && Y < S(1) - S(SC.eps_int);
-    if (inner && (Y - s_Y[c - 1]) * (s_Y[c + 1] - Y) > S(0)) fl |= 2u;
-    if (D == 2 && inner && (Y - s_Y[c - HX]) * (s_Y[c + HX] - Y) > S(0)) fl |= 4u;
-    if (!SC.switching) {
-      fl |= 1u;
-    } else {
+  // ---- switching sensors (Appendix D) on tile + one halo layer
+  if (SC.switching) {
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
       S idx2 = S(0.5 * C.idx[0]);
       S dudx = (s_u[c + 1] - s_u[c - 1]) * idx2;
       S div = dudx, curl2 = S(0);
@@ -197,11 +120,10 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
         thg += fabs(s_a[c] - s_a[c - HX]) + fabs(s_a[c + HX] - s_a[c]);
       }
       S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
-      if (thd > S(SC.th_d) || thg > S(SC.th_g)) fl |= 1u;
+      s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
     }
-    s_fl[c] = (unsigned char)fl;
+    __syncthreads();
   }
-  __syncthreads();
 
   S R[CPT][NQ];
 #pragma unroll
@@ -209,6 +131,7 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
 #pragma unroll
     for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
 
+  const S eps = S(SC.eps_int);
   // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
   for (int f = tid; f < NFX; f += NT) {
     int i = f % (TX + 1), j = f / (TX + 1);
@@ -224,9 +147,10 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
     }
     st.rho1 = s_rho[c]; st.rho2 = s_rho[c + 1];
     st.c1 = s_c[c]; st.c2 = s_c[c + 1];
-    unsigned fa = s_fl[c], fb = s_fl[c + 1];
+    bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
     S F[NQ];
-    face_flux<S, D, 0, PRK>(SC, C, st, ((fa | fb) & 1u) != 0, (fa & 2u) != 0, (fb & 2u) != 0, F);
+    face_flux<S, D, 0, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                            eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
   }
@@ -237,8 +161,7 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
     for (int k = 0; k < CPT; ++k) {
       int cc = tid + k * NT;
       if (cc < NC) {
-        int i = cc % TX, j = cc / TX;
-        int f = j * (TX + 1) + i;
+        int f = (cc / TX) * (TX + 1) + cc % TX;
 #pragma unroll
         for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + 1]) * ix;
       }
@@ -261,9 +184,10 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
       }
       st.rho1 = s_rho[c]; st.rho2 = s_rho[c + HX];
       st.c1 = s_c[c]; st.c2 = s_c[c + HX];
-      unsigned fa = s_fl[c], fb = s_fl[c + HX];
+      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
       S F[NQ];
-      face_flux<S, D, D - 1, PRK>(SC, C, st, ((fa | fb) & 1u) != 0, (fa & 4u) != 0, (fb & 4u) != 0, F);
+      face_flux<S, D, D - 1, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                                  eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     }
@@ -273,8 +197,7 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
     for (int k = 0; k < CPT; ++k) {
       int cc = tid + k * NT;
       if (cc < NC) {
-        int i = cc % TX, j = cc / TX;
-        int f = j * TX + i;
+        int f = cc;   // j * TX + i
 #pragma unroll
         for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + TX]) * iy;
       }
@@ -346,16 +269,15 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
   }
 
   // ---- output
-  const long long T = a.total;
-  if (a.stage < 0) {
-    // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64
+  if (!upd) {
+    // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64,
+    // in the caller's layout [N_q][ncell] of this case
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       int cc = tid + k * NT;
       int i = cc % TX, j = cc / TX;
       int gx = x0 + i, gy = y0 + j;
       if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
-        // caller's layout: [N_q][ncell] of this case
         const long long RS = C.ncell;
         long long cell = gx + (long long)C.n[0] * gy;
         double r0 = (double)R[k][0], r1 = (double)R[k][1];
@@ -368,10 +290,10 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
     }
     return;
   }
-  // the last stage writes q^(n+1) over q^n: each cell is read, then written, by one thread
-  const S* qn = (const S*)a.qn;
+  const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
+  if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
   S* dst = (S*)a.dst;
-  const S adt = S(a.ak * dy.dt);
+  const S adt = S(a.ak * dt);
   double lam = 0.0;
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
@@ -383,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
       S nv[NQ];
 #pragma unroll
       for (int v = 0; v < NQ; ++v) {
-        nv[v] = qn[v * T + cell] + adt * R[k][v];
+        nv[v] = qn_reg[k][v] + adt * R[k][v];
         dst[v * T + cell] = nv[v];
       }
       if (a.stage == 3) {
@@ -415,23 +337,11 @@ __global__ __launch_bounds__(NT) void k_stage12(StageArgs a)
   }
 }
 
-// ------------------------------------------------------------------ per-step scalars
-__global__ void k_step_begin(CaseDyn* dyn, int ncases, double cfl, double t_end)
+// ------------------------------------------------------------------ per-chunk step counter
+__global__ void k_advance(CaseDyn* dyn, int ncases, int nsteps)
 {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncases) return;
-  CaseDyn& d = dyn[c];
-  long long n = d.step;
-  int s = (int)(n & 1);
-  double lam = __longlong_as_double((long long)d.dtmax[s]);
-  double dt = cfl / lam;
-  if (t_end > 0.0 && d.t + dt > t_end) dt = t_end - d.t;
-  if (!(dt > 0.0) || d.err != 0) dt = 0.0;
-  d.dt = dt;
-  d.t += dt;
-  d.step_cur = n;
-  d.step = n + 1;
-  d.dtmax[s ^ 1] = 0ull;
+  if (c < ncases) dyn[c].base += nsteps;
 }
 
 // ------------------------------------------------------------------ per-cell kernels of one case
@@ -523,8 +433,8 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
     PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
     double l = 0.0;
     for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
-    if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.step);
-    else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.step);
+    if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.base);
+    else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.base);
     else lam = l;
   }
   lam = wave_max(lam);
@@ -532,7 +442,7 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
-    atomicMax(&dy.dtmax[dy.step & 1], (unsigned long long)__double_as_longlong(m));
+    atomicMax(&dy.dtmax[dy.base & 1], (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -575,10 +485,12 @@ __global__ void k_totals_final(const double* __restrict__ part, int nblk, int nq
 }
 
 // ------------------------------------------------------------------ host-side launchers
-template <class S, int D, int TX, int TY, int NT, bool PRK>
+template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK>
 static hipError_t launch12(const StageArgs& a, int ntiles, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, PRK>), dim3(ntiles), dim3(NT), 0, st, a);
+  // the Peng-Robinson closure needs more registers than the stiffened-gas one
+  constexpr int W = PRK ? 1 : MINW;
+  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, W, PRK>), dim3(ntiles), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -586,22 +498,25 @@ static hipError_t launch12(const StageArgs& a, int ntiles, hipStream_t st)
 
 using namespace fvm;
 
-// tile tables: (tx, ty, threads)
-static const int TILES1[][3] = {{256, 1, 256}, {128, 1, 128}};
-static const int TILES2[][3] = {{32, 8, 256}, {64, 4, 256}, {16, 16, 256}, {32, 16, 256}, {64, 8, 256}};
+// tile tables: (tx, ty, threads, waves per SIMD targeted by the register budget)
+static const int TILES1[][4] = {{256, 1, 256, 4}, {128, 1, 128, 4}, {128, 1, 256, 4}};
+static const int TILES2[][4] = {{32, 8, 256, 4}, {16, 8, 256, 4}, {64, 4, 256, 4},
+                                {16, 16, 256, 4}, {32, 16, 256, 2}, {32, 4, 256, 4}};
+static const int NT1 = sizeof(TILES1) / sizeof(TILES1[0]);
+static const int NT2 = sizeof(TILES2) / sizeof(TILES2[0]);
 
 int fvm_k_tile_count(int dim)
 {
-  if (dim == 1) return 2;
-  if (dim == 2) return 5;
+  if (dim == 1) return NT1;
+  if (dim == 2) return NT2;
   if (dim == 3) return fvm_k_tile_count3();
   return 0;
 }
 
 int fvm_k_tile_shape(int dim, int t, int* tx, int* ty, int* nt)
 {
-  if (dim == 1 && t >= 0 && t < 2) { *tx = TILES1[t][0]; *ty = TILES1[t][1]; *nt = TILES1[t][2]; return 0; }
-  if (dim == 2 && t >= 0 && t < 5) { *tx = TILES2[t][0]; *ty = TILES2[t][1]; *nt = TILES2[t][2]; return 0; }
+  if (dim == 1 && t >= 0 && t < NT1) { *tx = TILES1[t][0]; *ty = TILES1[t][1]; *nt = TILES1[t][2]; return 0; }
+  if (dim == 2 && t >= 0 && t < NT2) { *tx = TILES2[t][0]; *ty = TILES2[t][1]; *nt = TILES2[t][2]; return 0; }
   if (dim == 3) return fvm_k_tile_shape3(t, tx, ty, nt);
   return -1;
 }
@@ -611,16 +526,18 @@ static hipError_t stage12(int dim, int tile, const StageArgs& a, int ntiles, hip
 {
   if (dim == 1) {
     switch (tile) {
-      case 0: return launch12<S, 1, 256, 1, 256, PRK>(a, ntiles, st);
-      case 1: return launch12<S, 1, 128, 1, 128, PRK>(a, ntiles, st);
+      case 0: return launch12<S, 1, 256, 1, 256, 4, PRK>(a, ntiles, st);
+      case 1: return launch12<S, 1, 128, 1, 128, 4, PRK>(a, ntiles, st);
+      case 2: return launch12<S, 1, 128, 1, 256, 4, PRK>(a, ntiles, st);
     }
   } else {
     switch (tile) {
-      case 0: return launch12<S, 2, 32, 8, 256, PRK>(a, ntiles, st);
-      case 1: return launch12<S, 2, 64, 4, 256, PRK>(a, ntiles, st);
-      case 2: return launch12<S, 2, 16, 16, 256, PRK>(a, ntiles, st);
-      case 3: return launch12<S, 2, 32, 16, 256, PRK>(a, ntiles, st);
-      case 4: return launch12<S, 2, 64, 8, 256, PRK>(a, ntiles, st);
+      case 0: return launch12<S, 2, 32, 8, 256, 4, PRK>(a, ntiles, st);
+      case 1: return launch12<S, 2, 16, 8, 256, 4, PRK>(a, ntiles, st);
+      case 2: return launch12<S, 2, 64, 4, 256, 4, PRK>(a, ntiles, st);
+      case 3: return launch12<S, 2, 16, 16, 256, 4, PRK>(a, ntiles, st);
+      case 4: return launch12<S, 2, 32, 16, 256, 2, PRK>(a, ntiles, st);
+      case 5: return launch12<S, 2, 32, 4, 256, 4, PRK>(a, ntiles, st);
     }
   }
   return hipErrorInvalidValue;
@@ -633,9 +550,9 @@ hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a
   return prk ? stage12<double, true>(dim, tile, a, ntiles, st) : stage12<double, false>(dim, tile, a, ntiles, st);
 }
 
-hipError_t fvm_k_step_begin(CaseDyn* dyn, int ncases, double cfl, double t_end, hipStream_t st)
+hipError_t fvm_k_advance(CaseDyn* dyn, int ncases, int nsteps, hipStream_t st)
 {
-  hipLaunchKernelGGL(k_step_begin, dim3((ncases + 63) / 64), dim3(64), 0, st, dyn, ncases, cfl, t_end);
+  hipLaunchKernelGGL(k_advance, dim3((ncases + 63) / 64), dim3(64), 0, st, dyn, ncases, nsteps);
   return hipGetLastError();
 }
 

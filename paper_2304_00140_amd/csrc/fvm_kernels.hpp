@@ -10,9 +10,11 @@ struct StageArgs {
   const void* src;            // q^(k-1), storage variables [N_q][total]
   const void* qn;             // q^n
   void* dst;                  // q^(k)
+  void* prim;                 // 3D: primitives of q^(k-1) [9][total] in the storage precision
   long long total;            // field stride (cells of all cases)
   double* rhs_out;            // stage < 0: R in conserved variables [N_q][total]
   long long rhs_step;         // stage < 0: step number for the inflow noise
+  int step_off;               // stage >= 0: step index relative to CaseDyn::base
   int stage;                  // 0..3, or -1 for a bare right-hand side
   double ak;                  // stage coefficient
   fvm::SchemeC sc;
@@ -27,7 +29,7 @@ int fvm_k_tile_zchunk3(int tile);
 
 hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
-hipError_t fvm_k_step_begin(fvm::CaseDyn* dyn, int ncases, double cfl, double t_end, hipStream_t st);
+hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
                                const double* prim, void* dst, long long total, hipStream_t st);
 hipError_t fvm_k_cons_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,

@@ -1,8 +1,422 @@
-// fvm_stage3d.hip -- fused 3D stage kernel (placeholder until the marching kernel lands)
+// fvm_stage3d.hip -- 3D stage: closure kernel + LDS-tiled face/update kernel.
+//
+// In 3D the halo of a tile is large (a 2-cell halo around 8x8x4 cells holds
+// 4.5 cells per owned cell), and the method is bound by arithmetic, so the
+// FP64 closure inversion runs once per cell in its own kernel and writes the
+// primitives (rho, u, v, w, p, T, xi, c, alpha_G) in the storage precision;
+// the face kernel stages tile + halo primitives in LDS (ghosts generated from
+// the boundary kinds), evaluates the sensors, every face flux once (x, y, z
+// sweeps), the CSF source with the 3D Gaussian kernel (/64) and vertex normals
+// of the 2x2x2 cell blocks, and the stage update.
 #include <hip/hip_runtime.h>
+#include "fvm_device.hpp"
 #include "fvm_kernels.hpp"
+#include "fvm_stage_common.hpp"
 
-int fvm_k_tile_count3() { return 0; }
-int fvm_k_tile_shape3(int, int*, int*, int*) { return -1; }
-int fvm_k_tile_zchunk3(int) { return 1; }
-hipError_t fvm_k_stage3(int, int, int, const StageArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
+namespace fvm {
+
+constexpr int NW3 = 9;   // rho, u, v, w, p, T, xi, c, alpha_G
+
+// primitives of every owned cell of the tile: one thread per cell
+template <class S, int TX, int TY, int TZ, bool PRK>
+__global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
+{
+  const int4 tl = a.tiles[blockIdx.x];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const S* __restrict__ src = (const S*)a.src;
+  const long long T = a.total;
+  constexpr int NC = TX * TY * TZ;
+  for (int cc = threadIdx.x; cc < NC; cc += 256) {
+    int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+    int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
+    if (gx >= C.n[0] || gy >= C.n[1] || gz >= C.n[2]) continue;
+    long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+    double q[6], u[3], rho, Y;
+    q[0] = (double)src[cell] + C.rref[0];
+    q[1] = (double)src[T + cell] + C.rref[1];
+#pragma unroll
+    for (int v = 2; v < 6; ++v) q[v] = (double)src[v * T + cell];
+    PT pt = cell_prim<3, PRK>(C, q, u, rho, Y);
+    W[cell] = S(rho);
+    W[T + cell] = S(u[0]);
+    W[2 * T + cell] = S(u[1]);
+    W[3 * T + cell] = S(u[2]);
+    W[4 * T + cell] = S(pt.p);
+    W[5 * T + cell] = S(pt.T);
+    W[6 * T + cell] = S(Y);
+    W[7 * T + cell] = S(pt.c);
+    W[8 * T + cell] = S(pt.alpha);
+    (void)dy;
+  }
+}
+
+// primitives of one (possibly ghost) cell
+template <class S, bool PRK>
+__device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long long T, int gx, int gy, int gz,
+                                  long long step, S* w)
+{
+  bool fx = false, fy = false, fz = false;
+  int ix = gx, iy = gy, iz = gz;
+  map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
+  map_index(iz, C.n[2], C.bc[2][0], C.bc[2][1], fz);
+  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
+    double yy = (iy + 0.5) * C.dx[1] - C.in_c0;
+    double zz = (iz + 0.5) * C.dx[2] - C.in_c1;
+    if (sqrt(yy * yy + zz * zz) < C.in_radius) {
+      double u[3] = {C.in_u, 0.0, 0.0}, q[6], uu[3], rho, Y;
+      for (int c = 0; c < 3; ++c)
+        u[c] += C.in_noise * C.in_u *
+                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
+                               (unsigned long long)iz, (unsigned long long)c) - 1.0);
+      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, 3, q);
+      PT pt = cell_prim<3, PRK>(C, q, uu, rho, Y);
+      w[0] = S(rho);
+      w[1] = S(uu[0]);
+      w[2] = S(fy ? -uu[1] : uu[1]);
+      w[3] = S(fz ? -uu[2] : uu[2]);
+      w[4] = S(pt.p); w[5] = S(pt.T); w[6] = S(Y); w[7] = S(pt.c); w[8] = S(pt.alpha);
+      return;
+    }
+    ix = -1 - ix;
+    fx = true;
+  } else {
+    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
+  }
+  long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
+#pragma unroll
+  for (int v = 0; v < NW3; ++v) w[v] = W[v * T + cell];
+  if (fx) w[1] = -w[1];
+  if (fy) w[2] = -w[2];
+  if (fz) w[3] = -w[3];
+}
+
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK>
+__global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __restrict__ W)
+{
+  constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HXY = HX * HY, NH = HXY * HZ;
+  constexpr int NQ = 6;
+  constexpr int NC = TX * TY * TZ;
+  constexpr int CPT = (NC + NT - 1) / NT;
+  constexpr int NFX = (TX + 1) * TY * TZ, NFY = TX * (TY + 1) * TZ, NFZ = TX * TY * (TZ + 1);
+  constexpr int NF = NFX > NFY ? (NFX > NFZ ? NFX : NFZ) : (NFY > NFZ ? NFY : NFZ);
+  constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2, NFH = FX * FY * FZ;   // tile + one halo layer
+  constexpr int VX = TX + 1, VY = TY + 1, VZ = TZ + 1, NV = VX * VY * VZ;    // vertices
+  constexpr int NBUF = (NQ * NF > NFH + 3 * NV) ? NQ * NF : NFH + 3 * NV;   // fluxes, then CSF scratch
+
+  __shared__ S s_w[NW3][NH];
+  __shared__ unsigned char s_fl[NH];
+  __shared__ S s_buf[NBUF];
+  __shared__ double s_red[NT / 64];
+  S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
+
+  const int4 tl = a.tiles[blockIdx.x];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const SchemeC& SC = a.sc;
+  const int x0 = tl.y * TX, y0 = tl.z * TY, z0 = tl.w * TZ;
+  const int tid = threadIdx.x;
+  const bool upd = a.stage >= 0;
+  const long long step = upd ? dy.base + a.step_off : a.rhs_step;
+  const long long T = a.total;
+  S* s_rho = s_w[0];
+  S* s_u = s_w[1];
+  S* s_v = s_w[2];
+  S* s_ww = s_w[3];
+  S* s_p = s_w[4];
+  S* s_T = s_w[5];
+  S* s_Y = s_w[6];
+  S* s_c = s_w[7];
+  S* s_a = s_w[8];
+
+  auto owned = [&](int cc, int& gx, int& gy, int& gz) {
+    int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+    gx = x0 + i; gy = y0 + j; gz = z0 + k;
+    return cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2];
+  };
+
+  S qn_reg[CPT][NQ];
+  if (upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int gx, gy, gz;
+      bool own = owned(tid + k * NT, gx, gy, gz);
+      long long cell = C.off + (own ? gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz) : 0);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+    }
+  }
+
+  // ---- tile + halo primitives into LDS
+  for (int h = tid; h < NH; h += NT) {
+    int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+    S w[NW3];
+    load_prim3<S, PRK>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+#pragma unroll
+    for (int v = 0; v < NW3; ++v) s_w[v][h] = w[v];
+  }
+  __syncthreads();
+
+  const int st[3] = {1, HX, HXY};
+  // ---- switching sensors on tile + one halo layer
+  if (SC.switching) {
+    for (int h = tid; h < NFH; h += NT) {
+      int lx = h % FX, ly = (h / FX) % FY, lz = h / (FX * FY);
+      int c = (lz + 1) * HXY + (ly + 1) * HX + lx + 1;
+      S g[3][3];
+      const S* uu[3] = {s_u, s_v, s_ww};
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          g[comp][d] = (uu[comp][c + st[d]] - uu[comp][c - st[d]]) * S(0.5 * C.idx[d]);
+      S div = g[0][0] + g[1][1] + g[2][2];
+      S w0 = g[2][1] - g[1][2], w1 = g[0][2] - g[2][0], w2 = g[1][0] - g[0][1];
+      S curl2 = w0 * w0 + w1 * w1 + w2 * w2;
+      S thg = S(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) thg += fabs(s_a[c] - s_a[c - st[d]]) + fabs(s_a[c + st[d]] - s_a[c]);
+      S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
+      s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+
+  S R[CPT][NQ];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
+
+  const S eps = S(SC.eps_int);
+  // ---- faces along d: face at the lower side of tile cell (i, j, k) with index
+  // i running to TX (d = 0), j to TY (d = 1) or k to TZ (d = 2)
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int EX = TX + (d == 0), EY = TY + (d == 1);
+    const int NFD = d == 0 ? NFX : (d == 1 ? NFY : NFZ);
+    const int sd = st[d];
+    if (d > 0) __syncthreads();
+    for (int f = tid; f < NFD; f += NT) {
+      int i = f % EX, j = (f / EX) % EY, k = f / (EX * EY);
+      int c = (k + 2) * HXY + (j + 2) * HX + (i + 2) - sd;   // lower cell of the face
+      Stencil<S, 3> sten;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int cm = c + (m - 1) * sd;
+        sten.u[0][m] = s_u[cm];
+        sten.u[1][m] = s_v[cm];
+        sten.u[2][m] = s_ww[cm];
+        sten.p[m] = s_p[cm];
+        sten.T[m] = s_T[cm];
+        sten.Y[m] = s_Y[cm];
+      }
+      sten.rho1 = s_rho[c]; sten.rho2 = s_rho[c + sd];
+      sten.c1 = s_c[c]; sten.c2 = s_c[c + sd];
+      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + sd]) != 0);
+      bool sl = eligible(sten.Y[0], sten.Y[1], sten.Y[2], eps);
+      bool sr = eligible(sten.Y[1], sten.Y[2], sten.Y[3], eps);
+      S F[NQ];
+      if (d == 0) face_flux<S, 3, 0, PRK>(SC, C, sten, disc, sl, sr, F);
+      else if (d == 1) face_flux<S, 3, 1, PRK>(SC, C, sten, disc, sl, sr, F);
+      else face_flux<S, 3, 2, PRK>(SC, C, sten, disc, sl, sr, F);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+    }
+    __syncthreads();
+    const S id = S(C.idx[d]);
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int f = (k * EY + j) * EX + i;
+        int fn = f + (d == 0 ? 1 : (d == 1 ? EX : EX * EY));
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[kk][v] += (s_F[v][f] - s_F[v][fn]) * id;
+      }
+    }
+  }
+
+  // ---- CSF (Section 3.5): 3D binomial kernel /64, vertex normals, kappa = -div n
+  if (SC.sigma > 0.0) {
+    __syncthreads();
+    S* s_H = s_buf;
+    S* s_n = s_H + NFH;    // [3][NV]
+    for (int h = tid; h < NFH; h += NT) {
+      int lx = h % FX, ly = (h / FX) % FY, lz = h / (FX * FY);
+      int c = (lz + 1) * HXY + (ly + 1) * HX + lx + 1;
+      S acc = S(0);
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dyy = -1; dyy <= 1; ++dyy) {
+          S row = s_Y[c + dz * HXY + dyy * HX - 1] + S(2) * s_Y[c + dz * HXY + dyy * HX] +
+                  s_Y[c + dz * HXY + dyy * HX + 1];
+          acc += row * S((dz == 0 ? 2 : 1) * (dyy == 0 ? 2 : 1));
+        }
+      s_H[h] = acc * S(1.0 / 64.0);
+    }
+    __syncthreads();
+    S en = S(SC.eps_n * C.idx[0]);
+    for (int h = tid; h < NV; h += NT) {
+      int vx = h % VX, vy = (h / VX) % VY, vz = h / (VX * VY);   // upper corner of tile cell (vx-1, vy-1, vz-1)
+      int c = (vz * FY + vy) * FX + vx;                           // s_H index of that cell
+      const int sx = 1, sy = FX, sz = FX * FY;
+      S gx = (s_H[c + sx] + s_H[c + sx + sy] + s_H[c + sx + sz] + s_H[c + sx + sy + sz] -
+              s_H[c] - s_H[c + sy] - s_H[c + sz] - s_H[c + sy + sz]) * S(0.25 * C.idx[0]);
+      S gy = (s_H[c + sy] + s_H[c + sy + sx] + s_H[c + sy + sz] + s_H[c + sy + sx + sz] -
+              s_H[c] - s_H[c + sx] - s_H[c + sz] - s_H[c + sx + sz]) * S(0.25 * C.idx[1]);
+      S gz = (s_H[c + sz] + s_H[c + sz + sx] + s_H[c + sz + sy] + s_H[c + sz + sx + sy] -
+              s_H[c] - s_H[c + sx] - s_H[c + sy] - s_H[c + sx + sy]) * S(0.25 * C.idx[2]);
+      S inv = frcp(sqrt(gx * gx + gy * gy + gz * gz) + en);
+      s_n[h] = gx * inv;
+      s_n[NV + h] = gy * inv;
+      s_n[2 * NV + h] = gz * inv;
+    }
+    __syncthreads();
+    S sig = S(SC.sigma);
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int c = (k + 2) * HXY + (j + 2) * HX + i + 2;
+        int v = ((k + 1) * VY + (j + 1)) * VX + (i + 1);   // vertex (i, j, k): upper corner of the cell
+        const int vs[3] = {1, VX, VX * VY};
+        S kap = S(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int t1 = vs[(d + 1) % 3], t2 = vs[(d + 2) % 3];
+          const S* nd = s_n + d * NV;
+          S plus = nd[v] + nd[v - t1] + nd[v - t2] + nd[v - t1 - t2];
+          S minus = nd[v - vs[d]] + nd[v - vs[d] - t1] + nd[v - vs[d] - t2] + nd[v - vs[d] - t1 - t2];
+          kap += (plus - minus) * S(0.25 * C.idx[d]);
+        }
+        kap = -kap;
+        S se = S(0);
+        const S* uu[3] = {s_u, s_v, s_ww};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          S Sd = sig * kap * (s_a[c + st[d]] - s_a[c - st[d]]) * S(0.5 * C.idx[d]);
+          R[kk][2 + d] += Sd;
+          se += uu[d][c] * Sd;
+        }
+        R[kk][5] += se;
+      }
+    }
+  }
+
+  // ---- output
+  if (!upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int gx, gy, gz;
+      if (owned(tid + k * NT, gx, gy, gz)) {
+        const long long RS = C.ncell;
+        long long cell = gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+        double r0 = (double)R[k][0], r1 = (double)R[k][1];
+        a.rhs_out[cell] = r0 + r1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
+        a.rhs_out[4 * RS + cell] = (double)R[k][5] + C.Q[0] * r0 + C.Q[1] * r1;
+        a.rhs_out[5 * RS + cell] = r1;
+      }
+    }
+    return;
+  }
+  const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
+  if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
+  S* dst = (S*)a.dst;
+  const S adt = S(a.ak * dt);
+  double lam = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int gx, gy, gz;
+    if (owned(tid + k * NT, gx, gy, gz)) {
+      long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+      S nv[NQ];
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        nv[v] = qn_reg[k][v] + adt * R[k][v];
+        dst[v * T + cell] = nv[v];
+      }
+      if (a.stage == 3) {
+        double q[NQ], u[3], rho, Y;
+        q[0] = (double)nv[0] + C.rref[0];
+        q[1] = (double)nv[1] + C.rref[1];
+#pragma unroll
+        for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
+        PT pt = cell_prim<3, PRK>(C, q, u, rho, Y);
+        double l = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+        bool finite = isfinite(l) && isfinite(pt.p);
+        if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
+        else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
+        else lam = fmax(lam, l);
+      }
+    }
+  }
+  if (a.stage == 3) {
+    lam = wave_max(lam);
+    if ((tid & 63) == 0) s_red[tid >> 6] = lam;
+    __syncthreads();
+    if (tid == 0) {
+      double m = s_red[0];
+      for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
+      atomicMax(&dy.dtmax[(step + 1) & 1], (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK>
+static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
+{
+  constexpr int Wv = PRK ? 1 : MINW;
+  S* W = (S*)a.prim;
+  hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK>), dim3(ntiles), dim3(256), 0, st, a, W);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
+  return hipGetLastError();
+}
+
+}  // namespace fvm
+
+using namespace fvm;
+
+// (tx, ty, tz, threads)
+static const int TILES3[][4] = {{8, 8, 4, 256}, {16, 8, 2, 256}, {8, 4, 4, 128}, {16, 4, 4, 256}};
+static const int NT3 = sizeof(TILES3) / sizeof(TILES3[0]);
+
+int fvm_k_tile_count3() { return NT3; }
+
+int fvm_k_tile_shape3(int t, int* tx, int* ty, int* nt)
+{
+  if (t < 0 || t >= NT3) return -1;
+  *tx = TILES3[t][0];
+  *ty = TILES3[t][1];
+  *nt = TILES3[t][3];
+  return 0;
+}
+
+int fvm_k_tile_zchunk3(int t) { return (t >= 0 && t < NT3) ? TILES3[t][2] : 1; }
+
+template <class S, bool PRK>
+static hipError_t stage3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  switch (tile) {
+    case 0: return launch3<S, 8, 8, 4, 256, 2, PRK>(a, ntiles, st);
+    case 1: return launch3<S, 16, 8, 2, 256, 2, PRK>(a, ntiles, st);
+    case 2: return launch3<S, 8, 4, 4, 128, 2, PRK>(a, ntiles, st);
+    case 3: return launch3<S, 16, 4, 4, 256, 2, PRK>(a, ntiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (mixed) return prk ? stage3<float, true>(tile, a, ntiles, st) : stage3<float, false>(tile, a, ntiles, st);
+  return prk ? stage3<double, true>(tile, a, ntiles, st) : stage3<double, false>(tile, a, ntiles, st);
+}

@@ -1,0 +1,139 @@
+// fvm_stage_common.hpp -- device helpers shared by the fused stage kernels:
+// ghost-cell generation from the boundary kinds, loading a cell, primitives of
+// a cell, error recording, wavefront max and the per-step scalars.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "fvm_device.hpp"
+
+namespace fvm {
+
+// ------------------------------------------------------------------ ghost cells
+__device__ inline void map_index(int& i, int n, int bclo, int bchi, bool& flip)
+{
+  if (i < 0) {
+    if (bclo == BC_PERIODIC) i += n;
+    else if (bclo == BC_WALL) { i = -1 - i; flip = true; }
+    else i = 0;
+  } else if (i >= n) {
+    if (bchi == BC_PERIODIC) i -= n;
+    else if (bchi == BC_WALL) { i = 2 * n - 1 - i; flip = true; }
+    else i = n - 1;
+  }
+  i = min(max(i, 0), n - 1);   // cells beyond the stencil's reach (partial tiles)
+}
+
+// physical partial densities, momentum and gauge energy of a cell from its
+// primitives (p, T, alpha_G, u); xi = alpha_G rho_G / rho at (p, T)
+template <bool PRK>
+__device__ inline void state_from_prim(const CaseC& C, double p, double T, double al, const double* u,
+                                       int D, double* q)
+{
+  double vL, eL, vG, eG;
+  closure_fwd<PRK>(C, p, T, 0.0, vL, eL);
+  closure_fwd<PRK>(C, p, T, 1.0, vG, eG);
+  double rG = 1.0 / vG, rL = 1.0 / vL;
+  double rho = al * rG + (1.0 - al) * rL;
+  double Y = al * rG / rho;
+  double vm, em;
+  closure_fwd<PRK>(C, p, T, Y, vm, em);
+  double ke = 0.0;
+  for (int d = 0; d < D; ++d) ke += u[d] * u[d];
+  q[0] = rho - rho * Y;
+  q[1] = rho * Y;
+  for (int d = 0; d < D; ++d) q[2 + d] = rho * u[d];
+  q[2 + D] = rho * (em + 0.5 * ke);
+}
+
+// load one (possibly ghost) cell: physical partial densities, momentum, gauge energy
+template <class S, int D, bool PRK>
+__device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long long total,
+                                 int gx, int gy, int gz, long long step, double* q)
+{
+  bool fx = false, fy = false, fz = false;
+  int ix = gx, iy = gy, iz = gz;
+  if (D >= 2) map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
+  if (D >= 3) map_index(iz, C.n[2], C.bc[2][0], C.bc[2][1], fz);
+  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
+    double yy = (D >= 2) ? (iy + 0.5) * C.dx[1] - C.in_c0 : 0.0;
+    double zz = (D >= 3) ? (iz + 0.5) * C.dx[2] - C.in_c1 : 0.0;
+    if (D == 1 || sqrt(yy * yy + zz * zz) < C.in_radius) {
+      double u[3] = {C.in_u, 0.0, 0.0};
+      for (int c = 0; c < D; ++c)
+        u[c] += C.in_noise * C.in_u *
+                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
+                               (unsigned long long)iz, (unsigned long long)c) - 1.0);
+      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, D, q);
+      if (D >= 2 && fy) q[3] = -q[3];
+      if (D >= 3 && fz) q[4] = -q[4];
+      return;
+    }
+    ix = -1 - ix;
+    fx = true;
+  } else {
+    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
+  }
+  long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
+  q[0] = (double)src[cell] + C.rref[0];
+  q[1] = (double)src[total + cell] + C.rref[1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) q[2 + d] = (double)src[(2 + d) * total + cell];
+  q[2 + D] = (double)src[(2 + D) * total + cell];
+  if (fx) q[2] = -q[2];
+  if (D >= 2 && fy) q[3] = -q[3];
+  if (D >= 3 && fz) q[4] = -q[4];
+}
+
+// primitives of a loaded cell
+template <int D, bool PRK>
+__device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
+{
+  rho = q[0] + q[1];
+  double ir = 1.0 / rho;
+  Y = q[1] * ir;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
+  double e = q[2 + D] * ir - 0.5 * ke;
+  return closure<PRK>(C, rho, Y, e);
+}
+
+__device__ inline void record_error(CaseDyn& dy, int code, long long cell, long long step)
+{
+  if (atomicCAS(&dy.err, 0, code) == 0) {
+    dy.err_cell = cell;
+    dy.err_step = step;
+  }
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// dt of the step `step` of a case, identical in every workgroup of every stage:
+// CFL / (max over cells of sum_d (|u_d| + c) / dx_d of q^n), shortened so that
+// the step ends on t_end; NaN or a non-positive bound gives dt = 0
+__device__ inline double step_dt(const CaseDyn& dy, long long step, double cfl, double t_end)
+{
+  int s = (int)(step & 1);
+  double lam = __longlong_as_double((long long)dy.dtmax[s]);
+  double dt = cfl / lam;
+  double t = dy.t[s];
+  if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
+  if (!(dt > 0.0) || !(dt < 1e300)) dt = 0.0;
+  return dt;
+}
+
+// first workgroup of a case in the first stage: time at the end of the step,
+// and the CFL slot of q^(n+1) cleared for the last stage's reduction
+__device__ inline void step_scalars(CaseDyn& dy, long long step, double dt)
+{
+  int s = (int)(step & 1);
+  dy.t[s ^ 1] = dy.t[s] + dt;
+  dy.dtmax[s ^ 1] = 0ull;
+  dy.dt_last = dt;
+}
+
+}  // namespace fvm

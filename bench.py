@@ -18,6 +18,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue ceiling of MI355X for unpacked FP32 and FP64 vector instructions:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions per second
+VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Per-unit figures of the dominant kernel measured with rocprofv3 on this
+# workload and launch shape (profiles/k_stage12_shock_bubble_2d_counters.md):
+# executed VALU lane-instructions per cell-stage (SQ_INSTS_VALU x 64 / cells)
+# and HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from
+# a 1 GiB device copy).  Keyed by (workload, precision, tile, kernel build).
+KERNEL_BUILD = "k_stage12-v3"
+MEASURED = {
+    ("shock_bubble_2d", 0, 0, "k_stage12-v3"): dict(valu_per_cell_stage=1058.7,
+                                                    traffic_bytes=(14322.3 * 2 + 10245.5) * 1024),
+    ("shock_bubble_2d", 1, 0, "k_stage12-v3"): dict(valu_per_cell_stage=1059.9,
+                                                    traffic_bytes=(9804.4 * 2 + 5125.7) * 1024),
+}
 
 
 def parse():
@@ -31,9 +47,29 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample length")
+    ap.add_argument("--retune", action="store_true", help="re-run the tile autotuner and store its choice")
     ap.add_argument("--timing-steps", type=int, default=20, help="steps of per-stage event timing")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """device-to-device copy of a known size: read mib MiB, write mib MiB per copy"""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_probe_mib": mib, "ms_per_copy": ms, "GBs": 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9}))
 
 
 def make_workload(name, steps):
@@ -69,7 +105,7 @@ def run_path(cases, prec, args, stream, torch):
         tile, tune = args.tile, None
     else:
         from paper_2304_00140_amd import tune as tuner
-        tile, tune = tuner.autotune(h, prec, verbose=True)
+        tile, tune = tuner.autotune(h, prec, verbose=True, retune=args.retune, save=args.retune)
     h.n_steps(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -82,7 +118,7 @@ def run_path(cases, prec, args, stream, torch):
     stage_ms = h.time_stages(args.timing_steps)
     nq = cases[0]["grid"]["dim"] + 3
     return dict(handle=h, ncell=ncell, ms=ms, stage_ms=stage_ms, nq=nq, tile=tile,
-                tune={str(k): round(v * 1e3, 3) for k, v in (tune or {}).items()})
+                tune={str(k): round(v, 5) for k, v in (tune or {}).items()})
 
 
 def l1_errors(a, b, uref):
@@ -96,24 +132,34 @@ def l1_errors(a, b, uref):
     }
 
 
-def cpu_baseline(cases, steps):
+def cpu_baseline(cases, seconds):
+    """the oracle on the host cores, on a bounded sample of the workload: whole
+    steps of the first case (for the 3D jet a reduced grid of the same case)
+    until about `seconds` of CPU work"""
     from oracle.oracle import Oracle
+    from paper_2304_00140_amd import workloads as W
     case = cases[0]
+    if case["grid"]["dim"] == 3 and np.prod(case["grid"]["n"]) > 2_000_000:
+        case = W.liquid_jet_3d(128, 64, 64, steps=1)
     o = Oracle(case)
     q = o.cons_from_prim()
     t0 = time.perf_counter()
-    t = 0.0
-    for k in range(steps):
+    t, k = 0.0, 0
+    while k < 2 or time.perf_counter() - t0 < seconds:
         t, _ = o.step(q, k, t)
+        k += 1
     sec = time.perf_counter() - t0
     ncell = int(np.prod(case["grid"]["n"]))
-    return dict(value=ncell * 4 * steps / sec, unit="cell-RK-stage updates/s", cores=int(o.L.og_nthreads()),
-                kind="oracle", sample=f"{case['name']} {ncell} cells x {steps} steps (first case only)",
-                seconds=round(sec, 3))
+    return dict(value=ncell * 4 * k / sec, unit="cell-RK-stage updates/s", cores=int(o.L.og_nthreads()),
+                kind="oracle", sample=f"{case['name']} {'x'.join(str(n) for n in case['grid']['n'][:case['grid']['dim']])}"
+                f" cells, {k} steps from the initial state", seconds=round(sec, 2))
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("this build runs on one GPU; the multi-GPU decomposition is described in DESIGN.md, "
               "not launched", file=sys.stderr)
@@ -139,7 +185,13 @@ def main():
     word = 8 if main_prec == fvm.FVM_FP64 else 4
     bytes_per_cell_stage = 2.75 * r["nq"] * word
     stage_avg_ms = float(np.mean(r["stage_ms"]))
-    achieved = r["ncell"] * bytes_per_cell_stage / (stage_avg_ms * 1e-3) / 1e9
+    hbm_alg = r["ncell"] * bytes_per_cell_stage / (stage_avg_ms * 1e-3) / 1e9
+    meas = MEASURED.get((args.workload, main_prec, r["tile"], KERNEL_BUILD))
+    if meas:
+        achieved = meas["valu_per_cell_stage"] * r["ncell"] / (stage_avg_ms * 1e-3) / 1e12
+        traffic = meas["traffic_bytes"]
+    else:
+        achieved, traffic = None, None
     out = {
         "metric": "cell-RK-stage updates/s + HBM GB/s frac, FP64 vs mixed FP32 at stated L1 err",
         "value": value,
@@ -155,17 +207,21 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, cells=r["ncell"], steps=args.steps, parallelism="single-gpu"),
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_stage12" if cases[0]["grid"]["dim"] < 3 else "k_stage3",
-            "algorithmic_bytes_per_cell_stage": bytes_per_cell_stage,
+            "peak": VALU_PEAK_TINSTR,
+            "unit": "T VALU lane-instr/s",
+            "frac": None if achieved is None else achieved / VALU_PEAK_TINSTR,
+            "traffic": traffic,
+            "kernel": "k_stage12" if cases[0]["grid"]["dim"] < 3 else "k_prim3+k_face3",
+            "kernel_build": KERNEL_BUILD,
+            "valu_per_cell_stage": None if meas is None else meas["valu_per_cell_stage"],
             "stage_ms": r["stage_ms"],
+            "hbm": {"algorithmic_bytes_per_cell_stage": bytes_per_cell_stage, "achieved_GBs": hbm_alg,
+                    "peak_GBs": HBM_PEAK_GBS, "frac": hbm_alg / HBM_PEAK_GBS,
+                    "counter_GBs": None if traffic is None else traffic / (stage_avg_ms * 1e-3) / 1e9},
             "tile": r["tile"],
-            "tune_us_per_stage": r["tune"],
+            "tune_ms_per_stage": r["tune"],
         },
     }
     if fvm.FVM_MIXED in res and len(paths) == 2:
@@ -175,14 +231,17 @@ def main():
         mach = m["ncell"] * 2.75 * m["nq"] * 4 / (mavg * 1e-3) / 1e9
         entry = {"value": mv, "ms_per_step": m["ms"] / args.steps, "dtype": "f32+f64-closure",
                  "stage_ms": m["stage_ms"], "achieved_GBs": mach, "frac": mach / HBM_PEAK_GBS,
-                 "tile": m["tile"], "tune_us_per_stage": m["tune"]}
+                 "tile": m["tile"], "tune_ms_per_stage": m["tune"]}
+        mm = MEASURED.get((args.workload, fvm.FVM_MIXED, m["tile"], KERNEL_BUILD))
+        if mm:
+            entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0,
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
         out["mixed"] = entry
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fvm.h"
+#include "fvm.h"
 #include "fvm_kernels.hpp"
 
 using fvm::CaseC;

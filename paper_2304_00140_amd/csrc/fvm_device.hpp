@@ -60,8 +60,12 @@ struct CaseC {
 
 // per-case scalars that live on the device across steps; slot s = step & 1
 // holds the values of q^n, slot s ^ 1 those of q^(n+1)
+constexpr int NSLOT = 32;   // CFL partial maxima are spread over slots to avoid one contended atomic
+
 struct CaseDyn {
-  unsigned long long dtmax[2];   // bits of max_cells sum (|u| + c)/dx (non-negative doubles order as integers)
+  // bits of max_cells sum (|u| + c)/dx, spread over NSLOT slots (workgroup b
+  // writes slot b % NSLOT; non-negative doubles order as their integer bits)
+  unsigned long long dtmax[2][NSLOT];
   double t[2];                   // time at the start of the step
   double dt_last;                // dt of the last step taken
   long long base;                // steps completed before the current launch chunk
@@ -78,9 +82,18 @@ struct SchemeC {
 
 // ------------------------------------------------------------------ math
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double frcp(double x) { return 1.0 / x; }
+// reciprocal: hardware estimate refined by two Newton steps (relative error near
+// one ulp; not correctly rounded)
+__device__ inline double frcp(double x)
+{
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 __device__ inline float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ inline double fdiv(double a, double b) { return a / b; }
+__device__ inline double fdiv(double a, double b) { return a * frcp(b); }
 __device__ inline float fexp(float x) { return __expf(x); }
 __device__ inline double fexp(double x) { return exp(x); }
 
@@ -214,8 +227,8 @@ __device__ inline void sg_pair(double g0, double P0, double cv0, double q0,
   double qb = v * (Cp * (P0 + P1) - A0 * P1 - A1 * P0) - eh * (A0 + A1);
   double qc = v * Cp * P0 * P1 - eh * (A0 * P1 + A1 * P0);
   double sq = sqrt(qb * qb - 4.0 * qa * qc);
-  p = (qb < 0.0) ? (-qb + sq) / (2.0 * qa) : 2.0 * qc / (-qb - sq);
-  T = (eh + p * v) / Cp;
+  p = (qb < 0.0) ? (-qb + sq) * frcp(2.0 * qa) : 2.0 * qc * frcp(-qb - sq);
+  T = (eh + p * v) * frcp(Cp);
 }
 
 // (rho, xi, e) -> (p, T), c = max of the components' sound speeds, alpha_G.
@@ -228,7 +241,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
   const Comp& c1 = C.comp[1];
   PT r;
   r.ok = 1;
-  double v = 1.0 / rho;
+  double v = frcp(rho);
   double p, T;
   if (!PRK || c1.kind == 0) {
     if (Y == 0.0) {
@@ -244,7 +257,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
     r.T = T;
     double cc0 = c0.c2T * T, cc1 = c1.c2T * T;
     r.c = sqrt(fmax(cc0, cc1));
-    r.alpha = (Y == 0.0) ? 0.0 : Y * rho * c1.A * T / (p + c1.pinf);
+    r.alpha = (Y == 0.0) ? 0.0 : Y * rho * c1.A * T * frcp(p + c1.pinf);
     return r;
   }
   if constexpr (PRK) {

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
 
   const S eps = S(SC.eps_int);
   // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
-  for (int f = tid; f < NFX; f += NT) {
+  auto xface = [&](int f) {
     int i = f % (TX + 1), j = f / (TX + 1);
     int c = (j + OY) * HX + i + 1;
     Stencil<S, D> st;
@@ -153,7 +153,8 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
                             eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
-  }
+  };
+  for_faces<NFX, NT>(tid, xface);
   __syncthreads();
   {
     S ix = S(C.idx[0]);
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
   }
   if (D == 2) {
     __syncthreads();
-    for (int f = tid; f < NFY; f += NT) {
+    auto yface = [&](int f) {
       int i = f % TX, j = f / TX;
       int c = (j + 1) * HX + i + 2;
       Stencil<S, D> st;
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
                                   eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
-    }
+    };
+    for_faces<NFY, NT>(tid, yface);
     __syncthreads();
     S iy = S(C.idx[D - 1]);
 #pragma unroll
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
     if (tid == 0) {
       double m = s_red[0];
       for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
-      atomicMax(&dy.dtmax[(step + 1) & 1], (unsigned long long)__double_as_longlong(m));
+      cfl_max(dy, (int)((step + 1) & 1), m);
     }
   }
 }
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
-    atomicMax(&dy.dtmax[dy.base & 1], (unsigned long long)__double_as_longlong(m));
+    cfl_max(dy, (int)(dy.base & 1), m);
   }
 }
 

@@ -365,7 +365,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
     if (tid == 0) {
       double m = s_red[0];
       for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
-      atomicMax(&dy.dtmax[(step + 1) & 1], (unsigned long long)__double_as_longlong(m));
+      cfl_max(dy, (int)((step + 1) & 1), m);
     }
   }
 }

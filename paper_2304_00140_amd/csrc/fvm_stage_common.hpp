@@ -88,7 +88,7 @@ template <int D, bool PRK>
 __device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
 {
   rho = q[0] + q[1];
-  double ir = 1.0 / rho;
+  double ir = frcp(rho);
   Y = q[1] * ir;
   double ke = 0.0;
 #pragma unroll
@@ -112,13 +112,36 @@ __device__ inline double wave_max(double v)
   return v;
 }
 
+// Apply fn to every face index f < NF, NT threads: the full rounds are taken two
+// at a time with independent faces per thread, so that the two face
+// evaluations interleave and hide each other's latency; the partial round last.
+template <int NF, int NT, class Fn>
+__device__ inline void for_faces(int tid, Fn&& fn)
+{
+  constexpr int FULL = NF / NT;
+  int f = tid;
+#pragma unroll 1
+  for (int r = 0; r + 1 < FULL; r += 2, f += 2 * NT) {
+    fn(f);
+    fn(f + NT);
+  }
+  if (FULL & 1) {
+    fn(f);
+    f += NT;
+  }
+  if (f < NF) fn(f);
+}
+
 // dt of the step `step` of a case, identical in every workgroup of every stage:
 // CFL / (max over cells of sum_d (|u_d| + c) / dx_d of q^n), shortened so that
 // the step ends on t_end; NaN or a non-positive bound gives dt = 0
 __device__ inline double step_dt(const CaseDyn& dy, long long step, double cfl, double t_end)
 {
   int s = (int)(step & 1);
-  double lam = __longlong_as_double((long long)dy.dtmax[s]);
+  unsigned long long mb = 0ull;
+#pragma unroll
+  for (int i = 0; i < NSLOT; ++i) mb = mb > dy.dtmax[s][i] ? mb : dy.dtmax[s][i];
+  double lam = __longlong_as_double((long long)mb);
   double dt = cfl / lam;
   double t = dy.t[s];
   if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
@@ -132,8 +155,18 @@ __device__ inline void step_scalars(CaseDyn& dy, long long step, double dt)
 {
   int s = (int)(step & 1);
   dy.t[s ^ 1] = dy.t[s] + dt;
-  dy.dtmax[s ^ 1] = 0ull;
+#pragma unroll
+  for (int i = 0; i < NSLOT; ++i) dy.dtmax[s ^ 1][i] = 0ull;
   dy.dt_last = dt;
+}
+
+// fold a workgroup's CFL bound into its slot; the plain read skips the atomic
+// when the slot already holds a larger value (slots only grow within a stage)
+__device__ inline void cfl_max(CaseDyn& dy, int s, double m)
+{
+  unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+  unsigned long long* slot = &dy.dtmax[s][blockIdx.x % NSLOT];
+  if (__atomic_load_n(slot, __ATOMIC_RELAXED) < bits) atomicMax(slot, bits);
 }
 
 }  // namespace fvm

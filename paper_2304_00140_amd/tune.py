@@ -1,13 +1,27 @@
 """Launch-shape autotuner for the fused stage kernels.
 
-Times every tile shape of the context's dimension with HIP events around the
-stage launches (fvm_time_stages, which advances the state) and keeps the
-fastest.  Results are cached per (dimension, precision, switching, CSF on,
-closure kind, cell count) for the process.
+Times every tile shape of the context's dimension on the path that production
+runs take (fvm_n_steps: HIP-graph replays of whole steps; the state advances)
+and keeps the fastest.  Choices are cached per (dimension, precision,
+switching, CSF on, closure kind, cell count): in memory for the process and in
+tune_cache.json beside this file, which the tuner writes when asked
+(`save=True`) and every later run reads, so that a benchmark or a profile
+uses the same launch shape as the run that chose it.
 """
 import ctypes as C
+import json
+import os
+import time
 
-import numpy as np
+CACHE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def _load_file():
+    try:
+        with open(CACHE_FILE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
 
 _cache = {}
 
@@ -20,11 +34,16 @@ def key_of(handle, precision):
             int(ncell))
 
 
-def autotune(handle, precision, steps=6, warm=2, verbose=False):
+def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, save=False):
     """handle: fvm.Context or fvm.Batch with a state set; returns (best tile, {tile: ms per stage})"""
     from . import fvm
     k = key_of(handle, precision)
-    if k in _cache:
+    if k in _cache and not retune:
+        handle.set_tile(_cache[k][0])
+        return _cache[k]
+    stored = _load_file().get(repr(k))
+    if stored is not None and not retune:
+        _cache[k] = (int(stored["tile"]), {int(t): v for t, v in stored["ms_per_stage"].items()})
         handle.set_tile(_cache[k][0])
         return _cache[k]
     L = fvm.lib()
@@ -32,8 +51,10 @@ def autotune(handle, precision, steps=6, warm=2, verbose=False):
     times = {}
     for t in range(L.fvm_tile_count(dim)):
         handle.set_tile(t)
-        handle.time_stages(warm)
-        times[t] = float(np.mean(handle.time_stages(steps)))
+        handle.n_steps(warm)
+        t0 = time.perf_counter()
+        handle.n_steps(steps)
+        times[t] = (time.perf_counter() - t0) / (4 * steps) * 1e3   # ms per stage
         if verbose:
             tx, ty, nt = C.c_int(), C.c_int(), C.c_int()
             L.fvm_tile_shape(dim, t, C.byref(tx), C.byref(ty), C.byref(nt))
@@ -41,4 +62,9 @@ def autotune(handle, precision, steps=6, warm=2, verbose=False):
     best = min(times, key=times.get)
     handle.set_tile(best)
     _cache[k] = (best, times)
+    if save:
+        data = _load_file()
+        data[repr(k)] = {"tile": best, "ms_per_stage": {str(t): v for t, v in times.items()}}
+        with open(CACHE_FILE, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
     return best, times

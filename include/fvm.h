@@ -53,7 +53,7 @@ enum { FVM_FP64 = 0,      /* FP64 storage and arithmetic */
        FVM_MIXED = 1 };   /* FP32 storage, reconstruction, fluxes and update;
                              FP64 closure inversion, time step and totals */
 
-enum { FVM_BC_PERIODIC = 0, FVM_BC_WALL = 1, FVM_BC_ZEROGRAD = 2, FVM_BC_INFLOW = 3 };
+enum { FVM_BC_PERIODIC = 0, FVM_BC_WALL = 1, FVM_BC_ZEROGRAD = 2, FVM_BC_INFLOW = 3, FVM_BC_FARFIELD = 4 };
 enum { FVM_EOS_SG = 0, FVM_EOS_PR = 1 };
 enum { FVM_LIM_MINMOD = 0, FVM_LIM_KOREN = 1, FVM_LIM_VANALBADA = 2, FVM_LIM_VANLEER = 3,
        FVM_LIM_CHAKRAVARTHY = 4, FVM_LIM_MC = 5, FVM_LIM_SUPERBEE = 6, FVM_LIM_NONE = 7 };
@@ -68,7 +68,10 @@ enum { FVM_LIM_MINMOD = 0, FVM_LIM_KOREN = 1, FVM_LIM_VANALBADA = 2, FVM_LIM_VAN
  * slot |x_2 - in_center[0]| < in_radius; 1D: everywhere) the ghost cells hold
  * the state (in_p, in_T, alpha_G = in_alpha, u = (in_u, 0, 0) + noise) with
  * noise_c = in_noise * in_u * (2 h - 1), h a SplitMix64 hash of
- * (in_seed, step, j, k, c); outside the disk the plane is a slip wall. */
+ * (in_seed, step, j, k, c); outside the disk the plane is a slip wall.
+ * FVM_BC_FARFIELD (any side): the ghost cells hold the fixed state at rest
+ * (ff_p, ff_T, alpha_G = ff_alpha), a reservoir standing in for non-reflective
+ * far-field boundaries; a ghost cell beyond any far-field side takes it. */
 typedef struct fvm_grid_desc {
   int dim;
   int n[3];
@@ -76,6 +79,7 @@ typedef struct fvm_grid_desc {
   int bc[3][2];
   double in_p, in_T, in_alpha, in_u, in_radius, in_center[2], in_noise;
   uint64_t in_seed;
+  double ff_p, ff_T, ff_alpha;
 } fvm_grid_desc;
 
 /* Closure of the two components (Appendix A).

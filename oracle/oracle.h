@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-enum { OG_BC_PERIODIC = 0, OG_BC_WALL = 1, OG_BC_ZEROGRAD = 2, OG_BC_INFLOW = 3 };
+enum { OG_BC_PERIODIC = 0, OG_BC_WALL = 1, OG_BC_ZEROGRAD = 2, OG_BC_INFLOW = 3, OG_BC_FARFIELD = 4 };
 enum { OG_EOS_SG = 0, OG_EOS_PR = 1 };
 enum {
   OG_LIM_MINMOD = 0, OG_LIM_KOREN = 1, OG_LIM_VANALBADA = 2, OG_LIM_VANLEER = 3,
@@ -47,6 +47,8 @@ typedef struct {
   double in_p, in_T, in_alpha, in_u, in_radius, in_center[2];
   double in_noise;      /* noise amplitude as a fraction of in_u */
   uint64_t in_seed;
+  /* far-field sides: ghost cells hold the fixed state (ff_p, ff_T, ff_alpha, u = 0) */
+  double ff_p, ff_T, ff_alpha;
 } og_grid;
 
 typedef struct {

@@ -19,7 +19,8 @@ class Grid(C.Structure):
                 ("bc", (C.c_int * 2) * 3),
                 ("in_p", C.c_double), ("in_T", C.c_double), ("in_alpha", C.c_double),
                 ("in_u", C.c_double), ("in_radius", C.c_double), ("in_center", C.c_double * 2),
-                ("in_noise", C.c_double), ("in_seed", C.c_uint64)]
+                ("in_noise", C.c_double), ("in_seed", C.c_uint64),
+                ("ff_p", C.c_double), ("ff_T", C.c_double), ("ff_alpha", C.c_double)]
 
 
 class Eos(C.Structure):
@@ -113,6 +114,8 @@ def make_grid(gd):
     c = inf.get("center", [0.0, 0.0])
     g.in_center[0], g.in_center[1] = c[0], c[1]
     g.in_noise, g.in_seed = inf.get("noise", 0.0), int(inf.get("seed", 0))
+    ff = gd.get("farfield", {})
+    g.ff_p, g.ff_T, g.ff_alpha = ff.get("p", 0.0), ff.get("T", 0.0), ff.get("alpha", 0.0)
     return g
 
 

@@ -191,6 +191,14 @@ static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, doub
                 }
                 bc = OG_BC_WALL;   /* outside the jet the inlet plane is a slip wall */
               }
+              if (bc == OG_BC_FARFIELD) {
+                /* a far-field reservoir at rest (stands in for the paper's
+                 * non-reflective boundaries around a collapsing bubble) */
+                double u[3] = {0.0, 0.0, 0.0}, qc[6];
+                if (cons_from_prim_cell(e, dim, g->ff_p, g->ff_T, g->ff_alpha, u, qc)) return -1;
+                for (int f = 0; f < nq; ++f) qp[f * pd->npad + gi] = qc[f];
+                continue;
+              }
               int flip = 0;
               switch (bc) {
                 case OG_BC_PERIODIC: sc[d] = side == 0 ? nd - 1 - m : m; break;

@@ -72,7 +72,9 @@ static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
       if (!(g->dx[d] > 0.0)) return fail(b, FVM_EINVAL, "dx[d] must be > 0");
       for (int s = 0; s < 2; ++s) {
         int k = g->bc[d][s];
-        if (k < 0 || k > 3) return fail(b, FVM_EINVAL, "unknown boundary kind");
+        if (k < 0 || k > 4) return fail(b, FVM_EINVAL, "unknown boundary kind");
+        if (k == FVM_BC_FARFIELD && !(g->ff_T > 0.0 && g->ff_alpha >= 0.0 && g->ff_alpha <= 1.0))
+          return fail(b, FVM_EINVAL, "far-field state needs ff_T > 0 and 0 <= ff_alpha <= 1");
         if (k == FVM_BC_INFLOW && !(d == 0 && s == 0)) return fail(b, FVM_EINVAL, "inflow only at the x-min side");
       }
       if ((g->bc[d][0] == FVM_BC_PERIODIC) != (g->bc[d][1] == FVM_BC_PERIODIC))
@@ -274,6 +276,10 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     C.in_p = g->in_p; C.in_T = g->in_T; C.in_alpha = g->in_alpha; C.in_u = g->in_u;
     C.in_radius = g->in_radius; C.in_c0 = g->in_center[0]; C.in_c1 = g->in_center[1];
     C.in_noise = g->in_noise; C.in_seed = g->in_seed;
+    C.ff_p = g->ff_p; C.ff_T = g->ff_T; C.ff_alpha = g->ff_alpha;
+    C.any_ff = 0;
+    for (int d = 0; d < g->dim; ++d)
+      for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
     fill_comp(C.comp[0], &eos[c], 0);
     fill_comp(C.comp[1], &eos[c], 1);
     if (C.comp[1].kind == FVM_EOS_PR) b->prk = 1;

@@ -25,7 +25,7 @@ constexpr int MAXPAIR = MAXSPEC * (MAXSPEC + 1) / 2;
 constexpr double R_UNIV = 8.314462618;
 constexpr double SQRT2 = 1.41421356237309505;
 
-enum { BC_PERIODIC = 0, BC_WALL = 1, BC_ZEROGRAD = 2, BC_INFLOW = 3 };
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_ZEROGRAD = 2, BC_INFLOW = 3, BC_FARFIELD = 4 };
 enum { LIM_MINMOD = 0, LIM_KOREN = 1, LIM_VANALBADA = 2, LIM_VANLEER = 3,
        LIM_CHAKRAVARTHY = 4, LIM_MC = 5, LIM_SUPERBEE = 6, LIM_NONE = 7 };
 enum { ERR_NONPHYS = -4, ERR_NAN = -5 };
@@ -52,6 +52,8 @@ struct CaseC {
   int bc[3][2];
   double in_p, in_T, in_alpha, in_u, in_radius, in_c0, in_c1, in_noise;
   unsigned long long in_seed;
+  double ff_p, ff_T, ff_alpha;   // far-field reservoir state (at rest)
+  int any_ff;                    // some side is a far-field reservoir
   Comp comp[2];
   double rref[2];      // partial-density shifts (FP32-exact for FP32 storage)
   double Q[2];         // energy gauge: E' = rho E - sum_k rho_k Q_k

@@ -56,6 +56,14 @@ template <class S, bool PRK>
 __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long long T, int gx, int gy, int gz,
                                   long long step, S* w)
 {
+  if (beyond_farfield<3>(C, gx, gy, gz)) {
+    double u0[3] = {0.0, 0.0, 0.0}, q[6], uu[3], rho, Y;
+    state_from_prim<PRK>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, 3, q);
+    PT pt = cell_prim<3, PRK>(C, q, uu, rho, Y);
+    w[0] = S(rho); w[1] = S(uu[0]); w[2] = S(uu[1]); w[3] = S(uu[2]);
+    w[4] = S(pt.p); w[5] = S(pt.T); w[6] = S(Y); w[7] = S(pt.c); w[8] = S(pt.alpha);
+    return;
+  }
   bool fx = false, fy = false, fz = false;
   int ix = gx, iy = gy, iz = gz;
   map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);

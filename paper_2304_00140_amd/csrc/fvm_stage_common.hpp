@@ -44,11 +44,27 @@ __device__ inline void state_from_prim(const CaseC& C, double p, double T, doubl
   q[2 + D] = rho * (em + 0.5 * ke);
 }
 
+// is the cell a ghost beyond a far-field side (in any direction)?
+template <int D>
+__device__ inline bool beyond_farfield(const CaseC& C, int gx, int gy, int gz)
+{
+  if (!C.any_ff) return false;
+  bool f = (gx < 0 && C.bc[0][0] == BC_FARFIELD) || (gx >= C.n[0] && C.bc[0][1] == BC_FARFIELD);
+  if (D >= 2) f = f || (gy < 0 && C.bc[1][0] == BC_FARFIELD) || (gy >= C.n[1] && C.bc[1][1] == BC_FARFIELD);
+  if (D >= 3) f = f || (gz < 0 && C.bc[2][0] == BC_FARFIELD) || (gz >= C.n[2] && C.bc[2][1] == BC_FARFIELD);
+  return f;
+}
+
 // load one (possibly ghost) cell: physical partial densities, momentum, gauge energy
 template <class S, int D, bool PRK>
 __device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long long total,
                                  int gx, int gy, int gz, long long step, double* q)
 {
+  if (beyond_farfield<D>(C, gx, gy, gz)) {
+    const double u0[3] = {0.0, 0.0, 0.0};
+    state_from_prim<PRK>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, D, q);
+    return;
+  }
   bool fx = false, fy = false, fz = false;
   int ix = gx, iy = gy, iz = gz;
   if (D >= 2) map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);

@@ -25,7 +25,7 @@ class fvm_grid_desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3), ("bc", (C.c_int * 2) * 3),
                 ("in_p", C.c_double), ("in_T", C.c_double), ("in_alpha", C.c_double), ("in_u", C.c_double),
                 ("in_radius", C.c_double), ("in_center", C.c_double * 2), ("in_noise", C.c_double),
-                ("in_seed", C.c_uint64)]
+                ("in_seed", C.c_uint64), ("ff_p", C.c_double), ("ff_T", C.c_double), ("ff_alpha", C.c_double)]
 
 
 class fvm_eos_desc(C.Structure):
@@ -134,6 +134,8 @@ def grid_desc(gd):
     c = inf.get("center", [0.0, 0.0])
     g.in_center[0], g.in_center[1] = c[0], c[1]
     g.in_seed = int(inf.get("seed", 0))
+    ff = gd.get("farfield", {})
+    g.ff_p, g.ff_T, g.ff_alpha = ff.get("p", 0.0), ff.get("T", 0.0), ff.get("alpha", 0.0)
     return g
 
 

@@ -17,7 +17,7 @@ import math
 
 import numpy as np
 
-BC_PERIODIC, BC_WALL, BC_ZEROGRAD, BC_INFLOW = 0, 1, 2, 3
+BC_PERIODIC, BC_WALL, BC_ZEROGRAD, BC_INFLOW, BC_FARFIELD = 0, 1, 2, 3, 4
 EOS_SG, EOS_PR = 0, 1
 LIM = {"minmod": 0, "koren": 1, "vanalbada": 2, "vanleer": 3, "chakravarthy": 4,
        "mc": 5, "superbee": 6, "none": 7}
@@ -71,7 +71,8 @@ def make_grid(dim, n, L, bc):
     bc3 = [list(b) for b in bc] + [[BC_PERIODIC, BC_PERIODIC]] * (3 - len(bc))
     return dict(dim=dim, n=n3, dx=dx, bc=bc3,
                 inflow=dict(p=0.0, T=0.0, alpha=0.0, u=0.0, radius=0.0, center=[0.0, 0.0],
-                            noise=0.0, seed=0))
+                            noise=0.0, seed=0),
+                farfield=dict(p=0.0, T=0.0, alpha=0.0))
 
 
 def cell_centres(grid):
@@ -182,7 +183,10 @@ def drop_2d(n=256, steps=10000, mode2=0.0, sigma=0.07, L=1e-3, rel_radius=0.25):
 def bubble_collapse_batch(ncases=256, seed=230400140, nmin=64, nmax=256, steps=500):
     """Independent 2D gas-bubble collapses of uneven size (Section 4.9 shape):
     N ~ U{nmin..nmax}, bubble radius 0.1-0.3 of the domain, liquid/gas pressure
-    ratio 10-1000 log-uniform."""
+    ratio 10-1000 log-uniform.  The liquid starts from the Rayleigh-collapse
+    pressure profile p = p_L + (p_g - p_L) R / r (no jump at the bubble wall)
+    and the box is surrounded by a far-field reservoir at (p_L, T) standing in
+    for the paper's non-reflective boundaries."""
     rng = np.random.default_rng(seed)
     L, T0, pg = 2e-3, 293.15, 1e4
     water = sg(4.4, 6e8, cv_for_density(4.4, 6e8, 1000.0, 1e5, T0))
@@ -192,15 +196,19 @@ def bubble_collapse_batch(ncases=256, seed=230400140, nmin=64, nmax=256, steps=5
         N = int(rng.integers(nmin, nmax + 1))
         fR = float(rng.uniform(0.1, 0.3))
         ratio = float(10.0 ** rng.uniform(1.0, 3.0))
-        g = make_grid(2, [N, N], [L, L], [[BC_ZEROGRAD, BC_ZEROGRAD], [BC_ZEROGRAD, BC_ZEROGRAD]])
-        x, y = cell_centres(g)
-        alpha = 1.0 - smeared(np.hypot(x - 0.5 * L, y - 0.5 * L) - fR * L, g["dx"][0])
+        g = make_grid(2, [N, N], [L, L], [[BC_FARFIELD, BC_FARFIELD], [BC_FARFIELD, BC_FARFIELD]])
         pL = ratio * pg
-        p = pg * alpha + pL * (1.0 - alpha)
+        g["farfield"] = dict(p=pL, T=T0, alpha=0.0)
+        x, y = cell_centres(g)
+        r = np.hypot(x - 0.5 * L, y - 0.5 * L)
+        R = fR * L
+        alpha = 1.0 - smeared(r - R, g["dx"][0])
+        p_liq = pL + (pg - pL) * np.minimum(1.0, R / np.maximum(r, 1e-300))
+        p = pg * alpha + p_liq * (1.0 - alpha)
         prim = pack_prim(p, np.full_like(p, T0), alpha, [np.zeros_like(p), np.zeros_like(p)])
         cases.append(dict(name=f"bubble_collapse_{c}", grid=g, eos=make_eos(water, air),
                           scheme=default_scheme(), prim=prim, steps=steps, t_end=0.0,
-                          storage=dict(p_ref=pL, T_ref=T0), ratio=ratio, radius=fR * L))
+                          storage=dict(p_ref=pL, T_ref=T0), ratio=ratio, radius=R))
     return cases
 
 

@@ -97,6 +97,25 @@ def test_rhs_inflow_noise_matches_oracle(dev, stream):
         assert field_err(gpu_rhs(ctx, q, dev, step), o.rhs(q, step)) < 1e-10
 
 
+def test_rhs_farfield_matches_oracle(dev, stream):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.random_state(2, [37, 29], 19, bc=[[W.BC_FARFIELD, W.BC_ZEROGRAD], [W.BC_WALL, W.BC_FARFIELD]])
+    case["grid"]["farfield"] = dict(p=1.3e5, T=305.0, alpha=0.0)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    for prec_tile in range(fvm.lib().fvm_tile_count(2)):
+        ctx = ctx_for(case, fvm.FVM_FP64, stream, prec_tile)
+        assert field_err(gpu_rhs(ctx, q, dev), o.rhs(q)) < 1e-10
+    case3 = W.random_state(3, [11, 9, 10], 20, bc=[[W.BC_FARFIELD, W.BC_ZEROGRAD], [W.BC_WALL, W.BC_FARFIELD],
+                                                   [W.BC_PERIODIC, W.BC_PERIODIC]])
+    case3["grid"]["farfield"] = dict(p=1.3e5, T=305.0, alpha=0.0)
+    o3 = Oracle(case3)
+    q3 = o3.cons_from_prim()
+    ctx = ctx_for(case3, fvm.FVM_FP64, stream)
+    assert field_err(gpu_rhs(ctx, q3, dev), o3.rhs(q3)) < 1e-10
+
+
 def test_primitives_match_oracle(dev, stream):
     from oracle.oracle import Oracle
     from paper_2304_00140_amd import fvm

@@ -377,3 +377,17 @@ def test_shock_tube_converges_to_exact_solution():
         errs.append(np.abs(q[0] - ex).mean())
     assert errs[1] < 0.75 * errs[0] and errs[2] < 0.75 * errs[1], errs
     assert errs[2] < 0.01, errs
+
+
+def test_farfield_reservoir_matched_state_is_stationary():
+    """a far-field side holding the interior's state at rest adds nothing; a
+    reservoir at higher pressure pushes fluid into the domain"""
+    c = W.random_state(2, [12, 10], 81, bc=[[W.BC_FARFIELD, W.BC_FARFIELD], [W.BC_FARFIELD, W.BC_WALL]])
+    c["grid"]["farfield"] = dict(p=2e5, T=300.0, alpha=0.0)
+    c["prim"][0], c["prim"][1], c["prim"][2], c["prim"][3], c["prim"][4] = 2e5, 300.0, 0.0, 0.0, 0.0
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    assert np.abs(o.rhs(q)).max() < 1e-6 * np.abs(q).max() / c["grid"]["dx"][0]
+    c["grid"]["farfield"]["p"] = 3e5
+    r = Oracle(c).rhs(q)
+    assert r[0].sum() > 0.0          # mass flows in

@@ -87,6 +87,8 @@ int og_eos_forward(const og_eos* e, double p, double T, double Y, double* rho, d
 int og_eos_inverse(const og_eos* e, double rho, double ein, double Y, double Tguess,
                    double* p, double* T);
 double og_sound(const og_eos* e, int k, double p, double T);
+/* mass fraction clipped into [0, 1] for the inverse closure (NaN unchanged) */
+double og_clip_fraction(double Y);
 double og_mix_sound(const og_eos* e, double p, double T, double Y);
 double og_spec_volume(const og_eos* e, int k, double p, double T);
 double og_spec_energy(const og_eos* e, int k, double p, double T);

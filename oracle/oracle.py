@@ -61,6 +61,7 @@ def lib():
             "og_eos_inverse": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_sound": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
             "og_mix_sound": (C.c_double, [pe, C.c_double, C.c_double, C.c_double]),
+            "og_clip_fraction": (C.c_double, [C.c_double]),
             "og_spec_volume": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
             "og_spec_energy": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
             "og_pr_coeffs": (C.c_int, [pe, C.c_int, C.c_double, dp, dp, dp, dp, dp]),

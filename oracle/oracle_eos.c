@@ -173,14 +173,27 @@ double og_sound(const og_eos* e, int k, double p, double T)
   return sqrt(c2);
 }
 
+double og_clip_fraction(double Y)
+{
+  return Y < 0.0 ? 0.0 : (Y > 1.0 ? 1.0 : Y);   /* NaN passes through */
+}
+
 /* Impedances and the CFL condition use one speed of sound per cell: the largest
  * of the components' speeds at the cell's (p, T); with a liquid present that is
- * the liquid's (Appendix D asks for the maximum liquid speed of sound). */
+ * the liquid's (Appendix D asks for the maximum liquid speed of sound).  A
+ * stiffened gas enters whether present or not (its c depends on T alone); a
+ * Peng-Robinson component enters only where present, since at p < 0 (a pure
+ * liquid in tension) its cubic need not have a root with V > b. */
 double og_mix_sound(const og_eos* e, double p, double T, double Y)
 {
-  (void)Y;
-  double c0 = og_sound(e, 0, p, T), c1 = og_sound(e, 1, p, T);
-  return c0 > c1 ? c0 : c1;
+  double Yc = og_clip_fraction(Y);
+  double Yk[2] = {1.0 - Yc, Yc}, c = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    if (e->kind[k] == OG_EOS_PR && Yk[k] == 0.0) continue;
+    double ck = og_sound(e, k, p, T);
+    if (!(ck <= c)) c = ck;     /* NaN propagates */
+  }
+  return c;
 }
 
 /* forward closure: (p, T, xi) -> (rho, e), Table A.1:
@@ -315,6 +328,10 @@ int og_eos_inverse(const og_eos* e, double rho, double ein, double Y, double Tgu
                    double* p, double* T)
 {
   if (!(rho > 0.0)) return -1;
+  /* a mass fraction a little outside [0, 1] (central reconstruction is not
+   * bounded) is taken at the nearer pure component; the conserved rho xi keeps
+   * its value, so conservation is untouched */
+  Y = og_clip_fraction(Y);
   if (Y == 0.0 || Y == 1.0) {
     int k = (Y == 0.0) ? 0 : 1;
     if (e->kind[k] == OG_EOS_SG) { sg_pure(e, k, rho, ein, p, T); return 0; }

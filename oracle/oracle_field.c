@@ -125,7 +125,8 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
   W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y;
   W[OW_C] = og_mix_sound(e, p, T, Y);
-  W[OW_A] = (Y == 0.0) ? 0.0 : Y * rho * og_spec_volume(e, 1, p, T);
+  double Yc = og_clip_fraction(Y);
+  W[OW_A] = (Yc == 0.0) ? 0.0 : Yc * rho * og_spec_volume(e, 1, p, T);
   if (rc || !(rho > 0.0) || !(T > 0.0) || !isfinite(p) || !isfinite(W[OW_C])) return -1;
   return 0;
 }

@@ -243,6 +243,9 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
   const Comp& c1 = C.comp[1];
   PT r;
   r.ok = 1;
+  // a mass fraction a little outside [0, 1] (the central reconstruction is not
+  // bounded) is closed as the nearer pure component; NaN passes through
+  Y = (Y < 0.0) ? 0.0 : ((Y > 1.0) ? 1.0 : Y);
   double v = frcp(rho);
   double p, T;
   if (!PRK || c1.kind == 0) {
@@ -266,10 +269,11 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
     if (Y == 0.0) {
       p = (c0.gamma - 1.0) * rho * (e - c0.qs) - c0.gamma * c0.pinf;
       T = (e - c0.qs - c0.pinf * v) / c0.cv;
+      // the absent Peng-Robinson gas does not enter c: at p < 0 (liquid in
+      // tension) its cubic need not have a root with V > b
       r.p = p;
       r.T = T;
-      double V = pr_volume(p, T, pr_a(c1, T).a, c1.b);
-      r.c = fmax(sqrt(c0.c2T * T), pr_sound_V(c1, V, T));
+      r.c = sqrt(c0.c2T * T);
       r.alpha = 0.0;
       return r;
     }

@@ -213,9 +213,16 @@ def bubble_collapse_batch(ncases=256, seed=230400140, nmin=64, nmax=256, steps=5
 
 
 def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, seed=7,
-                  gas="pr"):
+                  gas="pr", core_length=None):
     """n-dodecane-like jet into an 80/20 N2/CH4 ambient at 5 MPa (Section 4.7/4.8
-    shape), uniform Cartesian grid, inflow at x = 0 with 5 % velocity noise."""
+    shape), uniform Cartesian grid, inflow at x = 0 with 5 % velocity noise.
+
+    The liquid core starts as a cylinder of diameter D along the whole domain
+    (core_length=None), the stand-in for a jet that has already left the
+    nozzle.  A finite core (core_length in m) has a flat head that hits the gas
+    at rest; the lateral relief of that impact focuses on the axis, puts the
+    liquid into tension and empties cells that hold trace gas to near vacuum,
+    where the mixture has no state within a few hundred steps."""
     p0, T0, uj = 5e6, 400.0, 300.0
     rho_l, c_l, g_l = 700.0, 1100.0, 2.5
     pinf_l = rho_l * c_l * c_l / g_l - p0
@@ -235,7 +242,9 @@ def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, 
                        noise=0.05, seed=seed)
     x, y, z = cell_centres(g)
     r = np.hypot(y - yc, z - zc)
-    liq = (1.0 - smeared(r - 0.5 * D, dx)) * (1.0 - smeared(x - 2.0 * D, dx))
+    liq = 1.0 - smeared(r - 0.5 * D, dx)
+    if core_length is not None:
+        liq = liq * (1.0 - smeared(x - core_length, dx))
     alpha = 1.0 - liq
     del r
     u = uj * liq

@@ -346,3 +346,52 @@ def test_liquid_jet_small_fp64_and_mixed(dev, stream):
     l1u = np.abs(a[1:4] - b[1:4]).sum() / (a.shape[1] * 300.0)
     print(f"jet mixed vs fp64 L1 p {l1p:.2e} u {l1u:.2e}", flush=True)
     assert l1p < 1e-4 and l1u < 1e-4
+
+
+@pytest.mark.parametrize("gas,dim", [("sg", 2), ("pr", 3)])
+def test_mass_fraction_outside_unit_interval(dev, stream, gas, dim):
+    """cells whose mass fraction sits a little below 0 or above 1 (what an
+    unbounded central reconstruction leaves behind) close as the nearer pure
+    component on both sides: primitives and one RHS"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    n = [37, 29] if dim == 2 else [15, 12, 10]
+    case = W.random_state(dim, n, 90 + dim, gas=gas, velocity=10.0, switching=1, sigma=0.05)
+    al = case["prim"][2]
+    lo, hi = al < 0.05, al > 0.95
+    assert lo.any() and hi.any()
+    al[lo], al[hi] = 0.0, 1.0              # pure cells, then nudged just outside [0, 1]
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    q[2 + dim, lo] = -1e-8 * q[0, lo]
+    q[2 + dim, hi] = (1.0 + 1e-9) * q[0, hi]
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    ctx.set_state(q)
+    w, w_ref = ctx.get_primitive(), o.prim_from_cons(q)
+    for f in (4, 5, 7, 8):
+        np.testing.assert_allclose(w[f], w_ref[f], rtol=1e-10, atol=1e-10 * np.abs(w_ref[f]).max())
+    assert field_err(gpu_rhs(ctx, q, dev), o.rhs(q)) < 1e-9
+
+
+def test_liquid_jet_nozzle_lip_fp64(dev, stream):
+    """jet at its full resolution (32 cells across) through the first 60 steps,
+    where the flow round the nozzle lip drives the mass fraction below zero and
+    the pressure there down: FP64 GPU steps against the oracle"""
+    from oracle.oracle import Oracle
+    case = W.liquid_jet_3d(nx=40, ny=40, nz=40, steps=60)
+    from paper_2304_00140_amd import fvm
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    ctx = ctx_for(case, fvm.FVM_FP64, stream)
+    ctx.init_primitive()
+    t = 0.0
+    done = 0
+    for chunk in (10, 30, 60):
+        for k in range(done, chunk):
+            t, _ = o.step(q, k, t)
+        ctx.n_steps(chunk - done)
+        done = chunk
+        err = field_err(ctx.get_state(), q)
+        print(f"jet lip {done} steps: {err:.3e}", flush=True)
+        assert err < 1e-10
+    assert (q[5] / q[0]).min() < 0.0

@@ -109,6 +109,42 @@ def test_liquid_in_tension_pure_cell():
     assert abs(p + 5e7) < 1e-6 * 6e8 and abs(T - 300) < 1e-9
 
 
+def test_fraction_outside_unit_interval_closes_as_pure_component():
+    """A mass fraction just below 0 (above 1) is closed as the pure liquid
+    (gas): the result is eq. (A.1.1) solved for p and T by hand, for an SG and
+    a Peng-Robinson partner."""
+    gl, pl, cl = 2.5, 3.338e8, 806.7
+    for partner in (AIR, PRMIX):
+        e = _eos(W.sg(gl, pl, cl), partner)
+        rho, en = 704.0, 7.98e5
+        p_hand = (gl - 1) * rho * en - gl * pl
+        T_hand = (en - pl / rho) / cl
+        for Y in (-2.4e-4, -1e-12):
+            p, T = inv(e, rho, en, Y)
+            assert abs(p - p_hand) < 1e-12 * (abs(p_hand) + pl)
+            assert abs(T - T_hand) < 1e-12 * T_hand
+    e = _eos(WATER, AIR)
+    rho = 1.2
+    en = 717.5 * 300.0
+    p, T = inv(e, rho, en, 1.0 + 3e-7)
+    assert abs(p - 0.4 * rho * en) < 1e-12 * p and abs(T - 300.0) < 1e-12 * 300.0
+    assert lib().og_clip_fraction(float("nan")) != lib().og_clip_fraction(float("nan"))
+
+
+def test_sound_speed_of_pure_liquid_in_tension_with_pr_partner():
+    """a pure liquid cell below zero pressure keeps the liquid's
+    c = sqrt(gamma (gamma - 1) cv T) (Appendix A.1): the absent Peng-Robinson
+    gas, which has no state at p < 0, does not enter the maximum"""
+    gl, pl, cl = 2.5, 3.338e8, 806.7
+    e = _eos(W.sg(gl, pl, cl), PRMIX)
+    for p, T in [(-3.9e7, 366.8), (5e6, 400.0)]:
+        c = lib().og_mix_sound(C.byref(e), p, T, -1e-11)
+        assert abs(c - math.sqrt(gl * (gl - 1) * cl * T)) < 1e-12 * c
+    # with the gas present at positive pressure both enter: the liquid's is larger
+    c = lib().og_mix_sound(C.byref(e), 5e6, 400.0, 0.5)
+    assert c >= math.sqrt(gl * (gl - 1) * cl * 400.0) * (1 - 1e-15)
+
+
 # ---------------------------------------------------------------- Peng-Robinson
 
 def test_pr_ideal_gas_limit():

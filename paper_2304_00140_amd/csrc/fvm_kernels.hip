@@ -419,7 +419,7 @@ __global__ void k_state_to_prim(const CaseC* cases, int icase, const S* __restri
 // CFL bound of the current state of one case into dtmax[step & 1]
 template <class S, int D, bool PRK>
 __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dyn, int icase,
-                                                 const S* __restrict__ src, long long total)
+                                                 const S* __restrict__ src, long long total, long long label_off)
 {
   __shared__ double s_red[4];
   const CaseC& C = cases[icase];
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
     PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
     double l = 0.0;
     for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
-    if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.base);
-    else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.base);
+    if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.base + label_off);
+    else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.base + label_off);
     else lam = l;
   }
   lam = wave_max(lam);
@@ -610,9 +610,9 @@ hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const CaseC* cases, 
 }
 
 hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
-                         const void* src, long long total, hipStream_t st)
+                         const void* src, long long total, long long label_off, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_dt_init<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total)
+#define CALL(S, D, P) hipLaunchKernelGGL((k_dt_init<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
   FVM_DISPATCH(mixed, dim, prk, CALL);
 #undef CALL
   return hipGetLastError();

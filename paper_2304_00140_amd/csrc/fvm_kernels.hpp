@@ -38,8 +38,10 @@ hipError_t fvm_k_state_to_cons(int dim, int mixed, const fvm::CaseC* cases, int 
                                const void* src, double* q, long long total, hipStream_t st);
 hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
                                const void* src, double* w, long long total, hipStream_t st);
+// CFL bound of the current state into the slot of the next step, and its
+// checks; an error is reported as one of step (base + label_off)
 hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
-                         long long ncell, const void* src, long long total, hipStream_t st);
+                         long long ncell, const void* src, long long total, long long label_off, hipStream_t st);
 hipError_t fvm_k_totals(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell, const void* src,
                         long long total, double* part, int nblk, double vol, double* out, hipStream_t st);
 hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /* [ncases][4] */,

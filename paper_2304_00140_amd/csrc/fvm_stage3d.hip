@@ -17,15 +17,22 @@ namespace fvm {
 
 constexpr int NW3 = 9;   // rho, u, v, w, p, T, xi, c, alpha_G
 
-// primitives of every owned cell of the tile: one thread per cell
+// primitives of every owned cell of the tile.  In the first stage of a step
+// the cells hold q^n, so this kernel also folds the CFL bound of q^n into the
+// case's slot for this step (read by the face kernel of the same stage) and
+// reports a non-finite or non-physical q^n as an error of the step before.
 template <class S, int TX, int TY, int TZ, bool PRK>
 __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
 {
+  __shared__ double s_red[4];
   const int4 tl = a.tiles[blockIdx.x];
   const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const S* __restrict__ src = (const S*)a.src;
   const long long T = a.total;
+  const bool first = a.stage == 0;
+  const long long step = dy.base + a.step_off;
+  double lam = 0.0;
   constexpr int NC = TX * TY * TZ;
   for (int cc = threadIdx.x; cc < NC; cc += 256) {
     int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
@@ -47,7 +54,20 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
     W[6 * T + cell] = S(Y);
     W[7 * T + cell] = S(pt.c);
     W[8 * T + cell] = S(pt.alpha);
-    (void)dy;
+    if (first) {
+      double l = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+      if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, cell - C.off, step - 1);
+      else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step - 1);
+      else lam = fmax(lam, l);
+    }
+  }
+  if (first) {
+    lam = wave_max(lam);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lam;
+    __syncthreads();
+    if (threadIdx.x == 0) cfl_max(dy, (int)(step & 1), fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3])));
   }
 }
 
@@ -115,7 +135,6 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   __shared__ S s_w[NW3][NH];
   __shared__ unsigned char s_fl[NH];
   __shared__ S s_buf[NBUF];
-  __shared__ double s_red[NT / 64];
   S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
 
   const int4 tl = a.tiles[blockIdx.x];
@@ -335,45 +354,17 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   }
   const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
   if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
+  // the last stage writes q^(n+1); its CFL bound and its checks come from the
+  // closure kernel of the next step's first stage (or the end-of-run check)
   S* dst = (S*)a.dst;
   const S adt = S(a.ak * dt);
-  double lam = 0.0;
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     int gx, gy, gz;
     if (owned(tid + k * NT, gx, gy, gz)) {
       long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
-      S nv[NQ];
 #pragma unroll
-      for (int v = 0; v < NQ; ++v) {
-        nv[v] = qn_reg[k][v] + adt * R[k][v];
-        dst[v * T + cell] = nv[v];
-      }
-      if (a.stage == 3) {
-        double q[NQ], u[3], rho, Y;
-        q[0] = (double)nv[0] + C.rref[0];
-        q[1] = (double)nv[1] + C.rref[1];
-#pragma unroll
-        for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
-        PT pt = cell_prim<3, PRK>(C, q, u, rho, Y);
-        double l = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
-        bool finite = isfinite(l) && isfinite(pt.p);
-        if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
-        else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
-        else lam = fmax(lam, l);
-      }
-    }
-  }
-  if (a.stage == 3) {
-    lam = wave_max(lam);
-    if ((tid & 63) == 0) s_red[tid >> 6] = lam;
-    __syncthreads();
-    if (tid == 0) {
-      double m = s_red[0];
-      for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
-      cfl_max(dy, (int)((step + 1) & 1), m);
+      for (int v = 0; v < NQ; ++v) dst[v * T + cell] = qn_reg[k][v] + adt * R[k][v];
     }
   }
 }
@@ -395,7 +386,7 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
 using namespace fvm;
 
 // (tx, ty, tz, threads)
-static const int TILES3[][4] = {{8, 8, 4, 256}, {16, 8, 2, 256}, {8, 4, 4, 128}, {16, 4, 4, 256}};
+static const int TILES3[][4] = {{8, 8, 4, 256}, {16, 8, 2, 256}, {8, 4, 4, 128}, {16, 4, 4, 256}, {8, 8, 8, 512}};
 static const int NT3 = sizeof(TILES3) / sizeof(TILES3[0]);
 
 int fvm_k_tile_count3() { return NT3; }
@@ -419,6 +410,7 @@ static hipError_t stage3(int tile, const StageArgs& a, int ntiles, hipStream_t s
     case 1: return launch3<S, 16, 8, 2, 256, 2, PRK>(a, ntiles, st);
     case 2: return launch3<S, 8, 4, 4, 128, 2, PRK>(a, ntiles, st);
     case 3: return launch3<S, 16, 4, 4, 256, 2, PRK>(a, ntiles, st);
+    case 4: return launch3<S, 8, 8, 8, 512, 1, PRK>(a, ntiles, st);
   }
   return hipErrorInvalidValue;
 }

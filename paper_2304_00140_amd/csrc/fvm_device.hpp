@@ -123,7 +123,7 @@ struct PRab { double a, a1, a2; };
 
 __device__ inline PRab pr_a(const Comp& c, double T)
 {
-  double s = sqrt(T), is = 1.0 / s, iT = is * is;
+  double s = sqrt(T), is = frcp(s), iT = is * is;
   PRab r{0.0, 0.0, 0.0};
   for (int q = 0; q < c.npair; ++q) {
     double rs = c.prs[q], cc = c.pcc[q], wa = c.pw[q] * c.pa0[q];
@@ -137,25 +137,25 @@ __device__ inline PRab pr_a(const Comp& c, double T)
 
 __device__ inline double pr_log(double V, double b)
 {
-  return log((V + (1.0 - SQRT2) * b) / (V + (1.0 + SQRT2) * b));
+  return log((V + (1.0 - SQRT2) * b) * frcp(V + (1.0 + SQRT2) * b));
 }
 
 // molar volume at (p, T): largest root of the compressibility cubic by Newton
 // from Z = 1 + B (an upper bound of every root with V > b)
 __device__ inline double pr_volume(double p, double T, double a, double b)
 {
-  double RT = R_UNIV * T;
-  double Ad = a * p / (RT * RT), Bd = b * p / RT;
+  double RT = R_UNIV * T, iRT = frcp(RT);
+  double Bd = b * p * iRT, Ad = a * p * iRT * iRT;
   double c2 = Bd - 1.0, c1 = Ad - 3.0 * Bd * Bd - 2.0 * Bd, c0 = Bd * Bd * Bd + Bd * Bd - Ad * Bd;
   double Z = 1.0 + Bd;
   for (int it = 0; it < 60; ++it) {
     double f = ((Z + c2) * Z + c1) * Z + c0;
     double fp = (3.0 * Z + 2.0 * c2) * Z + c1;
-    double dZ = f / fp;
+    double dZ = f * frcp(fp);
     Z -= dZ;
     if (fabs(dZ) <= 1e-15 * fabs(Z)) break;
   }
-  return Z * RT / p;
+  return Z * RT * frcp(p);
 }
 
 // mass-specific volume / energy of a component at (p, T) with derivatives
@@ -165,12 +165,12 @@ __device__ inline VE comp_ve(const Comp& c, double p, double T)
 {
   VE r;
   if (c.kind == 0) {
-    double den = 1.0 / (p + c.pinf);
+    double den = frcp(p + c.pinf);
     double v = c.A * T * den;
     r.v = v;
     r.e = c.cv * T + c.pinf * v + c.qs;
     r.dvdp = -v * den;
-    r.dvdT = v / T;
+    r.dvdT = c.A * den;
     r.dedp = c.pinf * r.dvdp;
     r.dedT = c.cv + c.pinf * r.dvdT;
     return r;
@@ -179,15 +179,15 @@ __device__ inline VE comp_ve(const Comp& c, double p, double T)
   double b = c.b, M = c.M;
   double V = pr_volume(p, T, A.a, b);
   double D = V * V + 2.0 * b * V - b * b;
-  double iD = 1.0 / D, iVb = 1.0 / (V - b);
+  double iD = frcp(D), iVb = frcp(V - b);
   double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
   double dpdT = R_UNIV * iVb - A.a1 * iD;
   double L = pr_log(V, b);
-  double k = 1.0 / (2.0 * SQRT2 * b);
+  double k = frcp(2.0 * SQRT2 * b);
   double cvm = M * c.cv - T * A.a2 * k * L;
   double dedV = T * dpdT - (R_UNIV * T * iVb - A.a * iD);
-  double dVdp = 1.0 / dpdV, dVdT = -dpdT * dVdp;
-  double iM = 1.0 / M;
+  double dVdp = frcp(dpdV), dVdT = -dpdT * dVdp;
+  double iM = frcp(M);
   r.v = V * iM;
   r.e = c.cv * T + c.qs + (A.a - T * A.a1) * k * L * iM;
   r.dvdp = dVdp * iM;
@@ -203,11 +203,11 @@ __device__ inline double pr_sound_V(const Comp& c, double V, double T)
   PRab A = pr_a(c, T);
   double b = c.b, M = c.M;
   double D = V * V + 2.0 * b * V - b * b;
-  double iD = 1.0 / D, iVb = 1.0 / (V - b);
+  double iD = frcp(D), iVb = frcp(V - b);
   double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
   double dpdT = R_UNIV * iVb - A.a1 * iD;
-  double cvm = M * c.cv - T * A.a2 / (2.0 * SQRT2 * b) * pr_log(V, b);
-  return sqrt(-(V * V / M) * (dpdV - T * dpdT * dpdT / cvm));
+  double cvm = M * c.cv - T * A.a2 * frcp(2.0 * SQRT2 * b) * pr_log(V, b);
+  return sqrt(-(V * V * frcp(M)) * (dpdV - T * dpdT * dpdT * frcp(cvm)));
 }
 
 // ------------------------------------------------------------------ closure inversion
@@ -289,7 +289,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
         PRab A = pr_a(c1, Tn);
         double f = c1.cv * Tn + c1.qs + (A.a - Tn * A.a1) * k - e;
         double fp = c1.cv - Tn * A.a2 * k;
-        double dT = f / fp;
+        double dT = f * frcp(fp);
         double Tnew = Tn - dT;
         if (Tnew <= 0.0) Tnew = 0.5 * Tn;
         Tn = Tnew;
@@ -314,7 +314,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
       double F1 = Y0 * a.v + Y * b.v - v, F2 = Y0 * a.e + Y * b.e - e;
       double J11 = Y0 * a.dvdp + Y * b.dvdp, J12 = Y0 * a.dvdT + Y * b.dvdT;
       double J21 = Y0 * a.dedp + Y * b.dedp, J22 = Y0 * a.dedT + Y * b.dedT;
-      double idet = 1.0 / (J11 * J22 - J12 * J21);
+      double idet = frcp(J11 * J22 - J12 * J21);
       double dp = (F1 * J22 - F2 * J12) * idet;
       double dT = (J11 * F2 - J21 * F1) * idet;
       double Tn = T - dT;
@@ -347,13 +347,14 @@ __device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y,
     const Comp& c = C.comp[k];
     double vk, ek;
     if (!PRK || c.kind == 0) {
-      vk = c.A * T / (p + c.pinf);
+      vk = c.A * T * frcp(p + c.pinf);
       ek = c.cv * T + c.pinf * vk + c.qs;
     } else {
       PRab A = pr_a(c, T);
       double V = pr_volume(p, T, A.a, c.b);
-      vk = V / c.M;
-      ek = c.cv * T + c.qs + (A.a - T * A.a1) / (2.0 * SQRT2 * c.b * c.M) * pr_log(V, c.b);
+      double iM = frcp(c.M);
+      vk = V * iM;
+      ek = c.cv * T + c.qs + (A.a - T * A.a1) * frcp(2.0 * SQRT2 * c.b) * iM * pr_log(V, c.b);
     }
     vmix += Yk[k] * vk;
     e += Yk[k] * ek;
@@ -489,7 +490,7 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
   } else {
     double vm, em;
     closure_fwd<PRK>(C, (double)ps, (double)Tf, (double)Yf, vm, em);
-    rf = R(1.0 / vm);
+    rf = R(frcp(vm));
     ef = R(em);
   }
   R m = rf * us;

@@ -503,7 +503,8 @@ using namespace fvm;
 // tile tables: (tx, ty, threads, waves per SIMD targeted by the register budget)
 static const int TILES1[][4] = {{256, 1, 256, 4}, {128, 1, 128, 4}, {128, 1, 256, 4}};
 static const int TILES2[][4] = {{32, 8, 256, 4}, {16, 8, 256, 4}, {64, 4, 256, 4},
-                                {16, 16, 256, 4}, {32, 16, 256, 2}, {32, 4, 256, 4}};
+                                {16, 16, 256, 4}, {32, 16, 256, 2}, {32, 4, 256, 4},
+                                {32, 8, 320, 5}, {16, 16, 320, 5}, {32, 8, 384, 6}};
 static const int NT1 = sizeof(TILES1) / sizeof(TILES1[0]);
 static const int NT2 = sizeof(TILES2) / sizeof(TILES2[0]);
 
@@ -540,6 +541,10 @@ static hipError_t stage12(int dim, int tile, const StageArgs& a, int ntiles, hip
       case 3: return launch12<S, 2, 16, 16, 256, 4, PRK>(a, ntiles, st);
       case 4: return launch12<S, 2, 32, 16, 256, 2, PRK>(a, ntiles, st);
       case 5: return launch12<S, 2, 32, 4, 256, 4, PRK>(a, ntiles, st);
+      // every x and every y face of the tile in one round of threads
+      case 6: return launch12<S, 2, 32, 8, 320, 5, PRK>(a, ntiles, st);
+      case 7: return launch12<S, 2, 16, 16, 320, 5, PRK>(a, ntiles, st);
+      case 8: return launch12<S, 2, 32, 8, 384, 6, PRK>(a, ntiles, st);
     }
   }
   return hipErrorInvalidValue;

@@ -64,6 +64,10 @@ typedef struct {
   double pr_omega[2][OG_MAXSPEC], pr_M[2][OG_MAXSPEC];
   double pr_Zc[2][OG_MAXSPEC], pr_vc[2][OG_MAXSPEC];
   double pr_kij[2][OG_MAXSPEC][OG_MAXSPEC];
+  /* transport (eq. 2-2): dynamic viscosity [Pa s] and thermal conductivity
+   * [W/(m K)] per component; the cell values mix them by volume fraction
+   * (eq. 2-8 with one gas and no vapour).  All zero: inviscid, adiabatic. */
+  double mu[2], kc[2];
 } og_eos;
 
 typedef struct {
@@ -77,6 +81,7 @@ typedef struct {
   double cfl;
   double sigma;         /* surface tension [N/m]; 0 disables the CSF source */
   double eps_normal;    /* interface-normal regularisation, times 1/dx */
+  double gravity[3];    /* body-force acceleration g [m/s^2] (eq. 2-2, source Q) */
 } og_scheme;
 
 /* primitive vector of one cell */

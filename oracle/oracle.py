@@ -31,7 +31,8 @@ class Eos(C.Structure):
                 ("pr_pc", (C.c_double * MAXSPEC) * 2), ("pr_omega", (C.c_double * MAXSPEC) * 2),
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2),
-                ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2)]
+                ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
+                ("mu", C.c_double * 2), ("kc", C.c_double * 2)]
 
 
 class Scheme(C.Structure):
@@ -39,7 +40,7 @@ class Scheme(C.Structure):
                 ("beta", C.c_double), ("thinc_gamma", C.c_double), ("eps_interface", C.c_double),
                 ("theta_ducros", C.c_double), ("theta_gas", C.c_double), ("eps_ducros", C.c_double),
                 ("kappa3", C.c_double), ("rk", C.c_double * 4), ("cfl", C.c_double),
-                ("sigma", C.c_double), ("eps_normal", C.c_double)]
+                ("sigma", C.c_double), ("eps_normal", C.c_double), ("gravity", C.c_double * 3)]
 
 
 RHS_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_void_p)
@@ -125,6 +126,7 @@ def make_eos(ed):
     for k in range(2):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
+        e.mu[k], e.kc[k] = ed.get("mu", [0.0, 0.0])[k], ed.get("kc", [0.0, 0.0])[k]
         pr = ed["pr"][k]
         if pr is not None:
             sp = pr["species"]
@@ -147,6 +149,8 @@ def make_scheme(sd):
         setattr(s, name, float(sd[name]))
     for i in range(4):
         s.rk[i] = sd["rk"][i]
+    for i, gi in enumerate(sd.get("gravity", [0.0, 0.0, 0.0])):
+        s.gravity[i] = gi
     return s
 
 

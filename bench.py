@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
-                             "interface_advection_1d"])
+                             "liquid_jet_3d_viscous", "interface_advection_1d"])
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,6 +85,8 @@ def make_workload(name, steps):
         return cases, dict(workload=name, cases=256, n_min=64, n_max=256)
     if name == "liquid_jet_3d":
         return [W.liquid_jet_3d(512, 256, 256, steps)], dict(workload=name, nx=512, ny=256, nz=256)
+    if name == "liquid_jet_3d_viscous":
+        return [W.liquid_jet_3d(512, 256, 256, steps, viscous=True)], dict(workload=name, nx=512, ny=256, nz=256)
     raise ValueError(name)
 
 
@@ -140,7 +142,7 @@ def cpu_baseline(cases, seconds):
     from paper_2304_00140_amd import workloads as W
     case = cases[0]
     if case["grid"]["dim"] == 3 and np.prod(case["grid"]["n"]) > 2_000_000:
-        case = W.liquid_jet_3d(128, 64, 64, steps=1)
+        case = W.liquid_jet_3d(128, 64, 64, steps=1, viscous=case.get("viscous", False))
     o = Oracle(case)
     q = o.cons_from_prim()
     t0 = time.perf_counter()
@@ -236,7 +238,7 @@ def main():
         if mm:
             entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
         if len(cases) == 1:
-            uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0,
+            uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0, "liquid_jet_3d_viscous": 300.0,
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
         out["mixed"] = entry

@@ -93,7 +93,12 @@ typedef struct fvm_grid_desc {
  * the partial density of each stiffened gas with pinf > 0 and the energy of
  * both components are stored relative to their values at (p_ref, T_ref), which
  * keeps FP32 storage accurate in stiff liquids; T_ref = 0 disables the shifts.
- * FVM_FP64 stores the conserved variables unshifted. */
+ * FVM_FP64 stores the conserved variables unshifted.
+ * mu [Pa s], kc [W/(m K)]: dynamic viscosity and thermal conductivity of each
+ * component for the stress part of the flux of eq. (2-2); a cell mixes them by
+ * its gas volume fraction, (1 - alpha_G) value_0 + alpha_G value_1 (eq. 2-8
+ * with one gas and no vapour).  All zero: inviscid and adiabatic (the stress
+ * terms are skipped).  Negative or non-finite values are FVM_EINVAL. */
 typedef struct fvm_eos_desc {
   int kind[2];
   double gamma[2], pinf[2], cv[2], q[2];
@@ -103,6 +108,7 @@ typedef struct fvm_eos_desc {
   double pr_Zc[2][FVM_MAXSPEC], pr_vc[2][FVM_MAXSPEC];
   double pr_kij[2][FVM_MAXSPEC][FVM_MAXSPEC];
   double p_ref, T_ref;
+  double mu[2], kc[2];
 } fvm_eos_desc;
 
 /* Scheme parameters (Section 3.3, Appendix D; defaults in brackets):
@@ -114,8 +120,12 @@ typedef struct fvm_eos_desc {
  * theta_ducros [0.95], theta_gas [0.4], eps_ducros [1e-20];
  * kappa3 [1/4]: scale of the third-difference pressure term of eq. (D.5);
  * rk[4] [1/4, 1/3, 1/2, 1]: q^(k) = q^n + rk[k-1] dt R(q^(k-1));
- * cfl [0.5]: dt = cfl / max_cells sum_d (|u_d| + c) / dx_d;
- * sigma [0]: surface tension (CSF on when > 0); eps_normal [1e-12]. */
+ * cfl [0.5]: dt = cfl / max_cells [sum_d (|u_d| + c) / dx_d + 2 nu sum_d 1/dx_d^2],
+ *   nu = max(mu, kc / cv) / rho of the cell (cv mixed by mass fraction; the
+ *   second term only with viscous or conducting fluids);
+ * sigma [0]: surface tension (CSF on when > 0); eps_normal [1e-12];
+ * gravity[3] [0]: body-force acceleration g [m/s^2] of eq. (2-2): the source
+ *   rho g on the momentum and rho u.g on the energy. */
 typedef struct fvm_scheme_desc {
   int switching, lim_u, lim_s, thinc;
   double beta, thinc_gamma, eps_interface;
@@ -125,6 +135,7 @@ typedef struct fvm_scheme_desc {
   double cfl;
   double sigma;
   double eps_normal;
+  double gravity[3];
 } fvm_scheme_desc;
 
 typedef struct fvm_ctx fvm_ctx;

@@ -106,6 +106,8 @@ static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
     } else {
       return fail(b, FVM_EINVAL, "unknown closure kind");
     }
+    if (!(e->mu[k] >= 0.0 && e->mu[k] < 1e300) || !(e->kc[k] >= 0.0 && e->kc[k] < 1e300))
+      return fail(b, FVM_EINVAL, "viscosity and conductivity must be finite and >= 0");
   }
   return FVM_OK;
 }
@@ -117,6 +119,8 @@ static int check_scheme(fvm_batch* b, const fvm_scheme_desc* s)
   if (!(s->cfl > 0.0) || !(s->sigma >= 0.0) || !(s->beta > 0.0) || !(s->thinc_gamma >= 0.0) ||
       !(s->eps_normal > 0.0))
     return fail(b, FVM_EINVAL, "scheme parameters out of range");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(s->gravity[d])) return fail(b, FVM_EINVAL, "gravity must be finite");
   return FVM_OK;
 }
 
@@ -162,6 +166,8 @@ static void fill_comp(Comp& c, const fvm_eos_desc* e, int k)
   c.A = (c.gamma - 1.0) * c.cv;
   c.Cp = c.gamma * c.cv;
   c.c2T = c.gamma * (c.gamma - 1.0) * c.cv;
+  c.mu = e->mu[k];
+  c.kc = e->kc[k];
 }
 
 static int build_tiles(fvm_batch* b)
@@ -282,6 +288,9 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
     fill_comp(C.comp[0], &eos[c], 0);
     fill_comp(C.comp[1], &eos[c], 1);
+    C.diff = (eos[c].mu[0] > 0.0 || eos[c].mu[1] > 0.0 || eos[c].kc[0] > 0.0 || eos[c].kc[1] > 0.0) ? 1 : 0;
+    C.sdx2 = 0.0;
+    for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
     if (C.comp[1].kind == FVM_EOS_PR) b->prk = 1;
   }
   b->total = off;
@@ -293,6 +302,11 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   S.sigma = s->sigma; S.eps_n = s->eps_normal; S.cfl = s->cfl;
   S.tanh_b = std::tanh(s->beta); S.icosh_b = 1.0 / std::cosh(s->beta); S.itanh_b = 1.0 / std::tanh(s->beta);
   S.t_end = 0.0;
+  S.has_grav = 0;
+  for (int d = 0; d < 3; ++d) {
+    S.grav[d] = d < b->dim ? s->gravity[d] : 0.0;
+    if (S.grav[d] != 0.0) S.has_grav = 1;
+  }
   for (int i = 0; i < 4; ++i) b->rk[i] = s->rk[i];
 
   // device tables

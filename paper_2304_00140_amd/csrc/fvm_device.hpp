@@ -43,6 +43,7 @@ struct Comp {
   double pw[MAXPAIR], pa0[MAXPAIR], pcc[MAXPAIR], prs[MAXPAIR];
   double b, M;         // covolume [m^3/mol], molar mass [kg/mol]
   double gam_ig;       // 1 + R / (M cv): ideal-gas stand-in used as Newton start
+  double mu, kc;       // dynamic viscosity [Pa s], thermal conductivity [W/(m K)]
 };
 
 struct CaseC {
@@ -58,6 +59,8 @@ struct CaseC {
   double rref[2];      // partial-density shifts (FP32-exact for FP32 storage)
   double Q[2];         // energy gauge: E' = rho E - sum_k rho_k Q_k
   int tile0, tiles[3];
+  int diff;            // some component is viscous or conducting
+  double sdx2;         // sum_d 1 / dx_d^2 over the used directions
 };
 
 // per-case scalars that live on the device across steps; slot s = step & 1
@@ -80,6 +83,8 @@ struct SchemeC {
   double beta, thinc_gamma, eps_int, th_d, th_g, eps_d, k3, sigma, eps_n, cfl;
   double tanh_b, icosh_b, itanh_b;
   double t_end;
+  double grav[3];      // body-force acceleration
+  int has_grav;
 };
 
 // ------------------------------------------------------------------ math

@@ -132,6 +132,12 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
     for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
 
   const S eps = S(SC.eps_int);
+  // velocity arrays and LDS strides for the stress terms and the body force
+  const S* U[D];
+  int stv[D];
+  U[0] = s_u;
+  stv[0] = 1;
+  if constexpr (D == 2) { U[1] = s_v; stv[1] = HX; }
   // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
   auto xface = [&](int f) {
     int i = f % (TX + 1), j = f / (TX + 1);
@@ -151,6 +157,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
     S F[NQ];
     face_flux<S, D, 0, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
                             eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
+    if (C.diff) visc_flux<S, D, 0>(C, U, s_T, s_a, c, stv, F);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
   };
@@ -189,6 +196,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       S F[NQ];
       face_flux<S, D, D - 1, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
                                   eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
+      if (C.diff) visc_flux<S, D, D - 1>(C, U, s_T, s_a, c, stv, F);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     };
@@ -270,6 +278,25 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
     }
   }
 
+  // ---- body force (eq. 2-2, source Q): rho g on the momentum, rho u . g on the energy
+  if (SC.has_grav) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int c = (cc / TX + OY) * HX + cc % TX + 2;
+        S rho = s_rho[c], pw = S(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          S gd = S(SC.grav[d]);
+          R[k][2 + d] += rho * gd;
+          pw += U[d][c] * gd;
+        }
+        R[k][2 + D] += rho * pw;
+      }
+    }
+  }
+
   // ---- output
   if (!upd) {
     // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64,
@@ -317,9 +344,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
 #pragma unroll
         for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
         PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
-        double l = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+        double l = cfl_rate<D>(C, u, pt, rho, Y);
         bool finite = isfinite(l) && isfinite(pt.p);
         if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
         else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
@@ -433,8 +458,7 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
     q[1] = (double)src[total + g] + C.rref[1];
     for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
     PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
-    double l = 0.0;
-    for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+    double l = cfl_rate<D>(C, u, pt, rho, Y);
     if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.base + label_off);
     else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.base + label_off);
     else lam = l;

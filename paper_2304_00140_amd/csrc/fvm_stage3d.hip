@@ -55,9 +55,7 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
     W[7 * T + cell] = S(pt.c);
     W[8 * T + cell] = S(pt.alpha);
     if (first) {
-      double l = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+      double l = cfl_rate<3>(C, u, pt, rho, Y);
       if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, cell - C.off, step - 1);
       else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step - 1);
       else lam = fmax(lam, l);
@@ -216,6 +214,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
     for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
 
   const S eps = S(SC.eps_int);
+  const S* U[3] = {s_u, s_v, s_ww};
   // ---- faces along d: face at the lower side of tile cell (i, j, k) with index
   // i running to TX (d = 0), j to TY (d = 1) or k to TZ (d = 2)
 #pragma unroll
@@ -247,6 +246,11 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
       if (d == 0) face_flux<S, 3, 0, PRK>(SC, C, sten, disc, sl, sr, F);
       else if (d == 1) face_flux<S, 3, 1, PRK>(SC, C, sten, disc, sl, sr, F);
       else face_flux<S, 3, 2, PRK>(SC, C, sten, disc, sl, sr, F);
+      if (C.diff) {
+        if (d == 0) visc_flux<S, 3, 0>(C, U, s_T, s_a, c, st, F);
+        else if (d == 1) visc_flux<S, 3, 1>(C, U, s_T, s_a, c, st, F);
+        else visc_flux<S, 3, 2>(C, U, s_T, s_a, c, st, F);
+      }
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     }
@@ -330,6 +334,26 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
           se += uu[d][c] * Sd;
         }
         R[kk][5] += se;
+      }
+    }
+  }
+
+  // ---- body force (eq. 2-2, source Q): rho g on the momentum, rho u . g on the energy
+  if (SC.has_grav) {
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int c = (k + 2) * HXY + (j + 2) * HX + i + 2;
+        S rho = s_rho[c], pw = S(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          S gd = S(SC.grav[d]);
+          R[kk][2 + d] += rho * gd;
+          pw += U[d][c] * gd;
+        }
+        R[kk][5] += rho * pw;
       }
     }
   }

@@ -176,6 +176,72 @@ __device__ inline void step_scalars(CaseDyn& dy, long long step, double dt)
   dy.dt_last = dt;
 }
 
+// ------------------------------------------------------------------ viscous stress, heat conduction
+// transport coefficient of a cell from its gas volume fraction: eq. (2-8) with
+// one gas and no vapour, (1 - alpha_G) v0 + alpha_G v1
+template <class S>
+__device__ inline S mix_alpha(double v0, double v1, S a)
+{
+  S ac = a < S(0) ? S(0) : (a > S(1) ? S(1) : a);
+  return (S(1) - ac) * S(v0) + ac * S(v1);
+}
+
+// Stress part of the flux of eq. (2-2) through the face between the LDS cells
+// c and c + st[DIR], second-order central: normal derivatives from the two
+// cells, transverse ones as the mean of the two cells' central differences,
+// face coefficients and face velocity as the two cells' mean.
+//   tau = mu (grad u + grad u^T - 2/3 div u I);  F_rho u -= tau . n,
+//   F_rho E -= u . tau . n + kc dT/dn.
+// U[a]: LDS array of velocity component a; st: LDS strides of the directions.
+template <class S, int D, int DIR>
+__device__ inline void visc_flux(const CaseC& C, const S* const (&U)[D], const S* sT, const S* sA, int c,
+                                 const int (&st)[D], S* F)
+{
+  const int r = c + st[DIR];
+  S g[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == DIR) g[a][b] = (U[a][r] - U[a][c]) * S(C.idx[DIR]);
+      else g[a][b] = (U[a][c + st[b]] - U[a][c - st[b]] + U[a][r + st[b]] - U[a][r - st[b]]) * S(0.25 * C.idx[b]);
+    }
+  S div = S(0);
+#pragma unroll
+  for (int b = 0; b < D; ++b) div += g[b][b];
+  const S aL = sA[c], aR = sA[r];
+  const S mu = S(0.5) * (mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aL) + mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aR));
+  const S kc = S(0.5) * (mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aL) + mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aR));
+  S work = S(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S tau = mu * (g[a][DIR] + g[DIR][a]);
+    if (a == DIR) tau -= S(2.0 / 3.0) * mu * div;
+    F[2 + a] -= tau;
+    work += S(0.5) * (U[a][c] + U[a][r]) * tau;
+  }
+  F[2 + D] -= work + kc * (sT[r] - sT[c]) * S(C.idx[DIR]);
+}
+
+// CFL rate of a cell: sum_d (|u_d| + c) / dx_d, plus 2 nu sum_d 1/dx_d^2 with
+// nu = max(mu, kc / cv) / rho (cv mixed by mass fraction) for viscous or
+// conducting fluids (explicit diffusion limit)
+template <int D>
+__device__ inline double cfl_rate(const CaseC& C, const double* u, const PT& pt, double rho, double Y)
+{
+  double l = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
+  if (C.diff) {
+    double Yc = Y < 0.0 ? 0.0 : (Y > 1.0 ? 1.0 : Y);
+    double cvm = (1.0 - Yc) * C.comp[0].cv + Yc * C.comp[1].cv;
+    double mu = mix_alpha<double>(C.comp[0].mu, C.comp[1].mu, pt.alpha);
+    double kc = mix_alpha<double>(C.comp[0].kc, C.comp[1].kc, pt.alpha) / cvm;
+    l += 2.0 * (mu > kc ? mu : kc) / rho * C.sdx2;
+  }
+  return l;
+}
+
 // fold a workgroup's CFL bound into its slot; the plain read skips the atomic
 // when the slot already holds a larger value (slots only grow within a stage)
 __device__ inline void cfl_max(CaseDyn& dy, int s, double m)

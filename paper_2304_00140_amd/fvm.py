@@ -35,7 +35,7 @@ class fvm_eos_desc(C.Structure):
                 ("pr_pc", (C.c_double * MAXSPEC) * 2), ("pr_omega", (C.c_double * MAXSPEC) * 2),
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2), ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
-                ("p_ref", C.c_double), ("T_ref", C.c_double)]
+                ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 2), ("kc", C.c_double * 2)]
 
 
 class fvm_scheme_desc(C.Structure):
@@ -43,7 +43,7 @@ class fvm_scheme_desc(C.Structure):
                 ("beta", C.c_double), ("thinc_gamma", C.c_double), ("eps_interface", C.c_double),
                 ("theta_ducros", C.c_double), ("theta_gas", C.c_double), ("eps_ducros", C.c_double),
                 ("kappa3", C.c_double), ("rk", C.c_double * 4), ("cfl", C.c_double), ("sigma", C.c_double),
-                ("eps_normal", C.c_double)]
+                ("eps_normal", C.c_double), ("gravity", C.c_double * 3)]
 
 
 _P = C.c_void_p
@@ -144,6 +144,7 @@ def eos_desc(ed, storage=None):
     for k in range(2):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
+        e.mu[k], e.kc[k] = ed.get("mu", [0.0, 0.0])[k], ed.get("kc", [0.0, 0.0])[k]
         pr = ed["pr"][k]
         if pr is not None:
             e.pr_ns[k] = len(pr["species"])
@@ -167,6 +168,8 @@ def scheme_desc(sd):
         setattr(s, name, float(sd[name]))
     for i in range(4):
         s.rk[i] = sd["rk"][i]
+    for i, gi in enumerate(sd.get("gravity", [0.0, 0.0, 0.0])):
+        s.gravity[i] = gi
     return s
 
 

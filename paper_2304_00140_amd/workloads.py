@@ -217,7 +217,7 @@ def bubble_collapse_batch(ncases=256, seed=230400140, nmin=64, nmax=256, steps=5
 
 
 def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, seed=7,
-                  gas="pr", core_length=None):
+                  gas="pr", core_length=None, viscous=False):
     """n-dodecane-like jet into an 80/20 N2/CH4 ambient at 5 MPa (Section 4.7/4.8
     shape), uniform Cartesian grid, inflow at x = 0 with 5 % velocity noise.
 
@@ -226,18 +226,24 @@ def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, 
     nozzle.  A finite core (core_length in m) has a flat head that hits the gas
     at rest; the lateral relief of that impact focuses on the axis, puts the
     liquid into tension and empties cells that hold trace gas to near vacuum,
-    where the mixture has no state within a few hundred steps."""
+    where the mixture has no state within a few hundred steps.
+
+    viscous=True adds the stress and conduction terms of eq. (2-2) as in
+    Section 4.8, with n-dodecane-like liquid mu = 4.5e-4 Pa s, kc = 0.11 W/(m K)
+    and N2/CH4-like gas mu = 2.3e-5 Pa s, kc = 0.032 W/(m K) near 400 K
+    (public property tables)."""
     p0, T0, uj = 5e6, 400.0, 300.0
     rho_l, c_l, g_l = 700.0, 1100.0, 2.5
     pinf_l = rho_l * c_l * c_l / g_l - p0
-    liquid = sg(g_l, pinf_l, cv_for_density(g_l, pinf_l, rho_l, p0, T0))
+    mu_l, kc_l, mu_g, kc_g = (4.5e-4, 0.11, 2.3e-5, 0.032) if viscous else (0.0, 0.0, 0.0, 0.0)
+    liquid = sg(g_l, pinf_l, cv_for_density(g_l, pinf_l, rho_l, p0, T0), mu=mu_l, kc=kc_l)
     X = [0.8, 0.2]
     Mmix = X[0] * NITROGEN["M"] + X[1] * METHANE["M"]
     cv_g = (X[0] * 2.5 + X[1] * 3.9) * R_UNIV / Mmix
     if gas == "pr":
-        gasc = pr_mixture([NITROGEN, METHANE], X, cv_g)
+        gasc = pr_mixture([NITROGEN, METHANE], X, cv_g, mu=mu_g, kc=kc_g)
     else:   # ideal-gas stand-in of the same molar mass and cv
-        gasc = sg(1.0 + R_UNIV / (Mmix * cv_g), 0.0, cv_g)
+        gasc = sg(1.0 + R_UNIV / (Mmix * cv_g), 0.0, cv_g, mu=mu_g, kc=kc_g)
     dx = D / cells_per_D
     g = make_grid(3, [nx, ny, nz], [nx * dx, ny * dx, nz * dx],
                   [[BC_INFLOW, BC_ZEROGRAD], [BC_ZEROGRAD, BC_ZEROGRAD], [BC_ZEROGRAD, BC_ZEROGRAD]])
@@ -254,9 +260,9 @@ def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, 
     u = uj * liq
     zero = np.zeros_like(u)
     prim = pack_prim(np.full_like(u, p0), np.full_like(u, T0), alpha, [u, zero, zero])
-    return dict(name="liquid_jet_3d", grid=g, eos=make_eos(liquid, gasc),
+    return dict(name="liquid_jet_3d_viscous" if viscous else "liquid_jet_3d", grid=g, eos=make_eos(liquid, gasc),
                 scheme=default_scheme(switching=1, sigma=0.02), prim=prim, steps=steps,
-                t_end=0.0, storage=dict(p_ref=p0, T_ref=T0))
+                t_end=0.0, storage=dict(p_ref=p0, T_ref=T0), viscous=viscous)
 
 
 # ------------------------------------------------------- test-state generators

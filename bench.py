@@ -108,6 +108,12 @@ def run_path(cases, prec, args, stream, torch):
     else:
         from paper_2304_00140_amd import tune as tuner
         tile, tune = tuner.autotune(h, prec, verbose=True, retune=args.retune, save=args.retune)
+        # the tuner advances the state: start the measured run from the initial state again
+        if batch:
+            for i in range(len(cases)):
+                h.init_primitive(i)
+        else:
+            h.init_primitive()
     h.n_steps(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)

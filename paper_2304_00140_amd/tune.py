@@ -3,7 +3,7 @@
 Times every tile shape of the context's dimension on the path that production
 runs take (fvm_n_steps: HIP-graph replays of whole steps; the state advances)
 and keeps the fastest.  Choices are cached per (dimension, precision,
-switching, CSF on, closure kind, cell count): in memory for the process and in
+switching, CSF on, closure kinds, stress terms on, cell count): in memory for the process and in
 tune_cache.json beside this file, which the tuner writes when asked
 (`save=True`) and every later run reads, so that a benchmark or a profile
 uses the same launch shape as the run that chose it.
@@ -30,7 +30,9 @@ def key_of(handle, precision):
     case = handle.case if hasattr(handle, "case") else handle.cases[0]
     ncell = handle.ncell if hasattr(handle, "ncell") else handle.cells()
     s = case["scheme"]
-    return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, tuple(case["eos"]["kind"]),
+    e = case["eos"]
+    diff = any(v > 0 for v in list(e.get("mu", [])) + list(e.get("kc", [])))
+    return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, tuple(e["kind"]), diff,
             int(ncell))
 
 

@@ -27,7 +27,7 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # executed VALU lane-instructions per cell-stage (SQ_INSTS_VALU x 64 / cells)
 # and HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from
 # a 1 GiB device copy).  Keyed by (workload, precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v3"
+KERNEL_BUILD = "k_stage12-v4"
 MEASURED = {
     ("shock_bubble_2d", 0, 0, "k_stage12-v3"): dict(valu_per_cell_stage=1058.7,
                                                     traffic_bytes=(14322.3 * 2 + 10245.5) * 1024),

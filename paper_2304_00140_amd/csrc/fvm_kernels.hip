@@ -45,7 +45,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
   __shared__ S s_F[NQ][NF];
   __shared__ double s_red[NT / 64];
 
-  const int4 tl = a.tiles[blockIdx.x];
+  const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
   const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const SchemeC& SC = a.sc;

@@ -25,7 +25,10 @@ template <class S, int TX, int TY, int TZ, bool PRK>
 __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
 {
   __shared__ double s_red[4];
-  const int4 tl = a.tiles[blockIdx.x];
+  // PB workgroups of 256 threads per tile, one cell per thread
+  constexpr int PB = (TX * TY * TZ + 255) / 256;
+  const int bb = xcd_block(blockIdx.x, gridDim.x);
+  const int4 tl = a.tiles[bb / PB];
   const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const S* __restrict__ src = (const S*)a.src;
@@ -34,10 +37,10 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
   const long long step = dy.base + a.step_off;
   double lam = 0.0;
   constexpr int NC = TX * TY * TZ;
-  for (int cc = threadIdx.x; cc < NC; cc += 256) {
-    int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
-    int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
-    if (gx >= C.n[0] || gy >= C.n[1] || gz >= C.n[2]) continue;
+  const int cc = (bb % PB) * 256 + threadIdx.x;
+  const int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+  const int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
+  if (cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2]) {
     long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
     double q[6], u[3], rho, Y;
     q[0] = (double)src[cell] + C.rref[0];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   __shared__ S s_buf[NBUF];
   S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
 
-  const int4 tl = a.tiles[blockIdx.x];
+  const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
   const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const SchemeC& SC = a.sc;
@@ -398,7 +401,8 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
 {
   constexpr int Wv = PRK ? 1 : MINW;
   S* W = (S*)a.prim;
-  hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK>), dim3(ntiles), dim3(256), 0, st, a, W);
+  constexpr int PB = (TX * TY * TZ + 255) / 256;
+  hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);

@@ -176,6 +176,19 @@ __device__ inline void step_scalars(CaseDyn& dy, long long step, double dt)
   dy.dt_last = dt;
 }
 
+// ------------------------------------------------------------------ XCD-aware tile order
+// Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b % 8), and
+// each XCD has its own L2.  Remapping block b to tile
+//   (b % 8) * q + min(b % 8, r) + b / 8,   q = n / 8, r = n % 8,
+// gives each XCD one contiguous run of tiles, so neighbouring tiles, whose
+// halos overlap, are served by the same L2.  A permutation of [0, n).
+__device__ inline int xcd_block(int b, int n)
+{
+  constexpr int NX = 8;
+  int q = n / NX, r = n % NX, k = b % NX;
+  return k * q + (k < r ? k : r) + b / NX;
+}
+
 // ------------------------------------------------------------------ viscous stress, heat conduction
 // transport coefficient of a cell from its gas volume fraction: eq. (2-8) with
 // one gas and no vapour, (1 - alpha_G) v0 + alpha_G v1

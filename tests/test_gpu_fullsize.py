@@ -1,0 +1,163 @@
+"""The benchmark workloads at their full sizes, in the launch configuration
+the benchmark times (tiles from the tuner cache), against the CPU FP64 oracle:
+whole fields where the oracle finishes in seconds (shock-bubble 1024 x 256,
+drop 256^2, all 256 bubble-collapse cases), and for the 512 x 256 x 256 jet the
+right-hand side of cells sampled in windows, each of which the oracle computes
+from the window alone (every output cell at least 3 cells from the window
+edge, beyond the scheme's reach of 2)."""
+import numpy as np
+import pytest
+
+from paper_2304_00140_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_00140_amd import fvm
+    fvm.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def stream(dev):
+    return torch.cuda.Stream(device=dev)
+
+
+def field_err(a, b, uref):
+    """max |a - b| per conserved field over that field's scale: the largest rho
+    for rho and rho xi, the largest rho times the workload's reference speed
+    for every momentum component (the relative-L1 velocity scale of the
+    accuracy tables; a flow near rest, like the drop's spurious currents, is
+    not its own scale), the largest rho E for the energy"""
+    nq = b.shape[0]
+    dim = nq - 3
+    rho = np.abs(b[0]).max()
+    scale = np.array([rho] + [rho * uref] * dim + [np.abs(b[1 + dim]).max(), rho])
+    return (np.abs(a - b).max(axis=1) / np.maximum(scale, 1e-300)).max()
+
+
+def bench_context(case, prec, stream):
+    """a context with the tile the benchmark uses for this workload"""
+    from paper_2304_00140_amd import fvm, tune
+    h = fvm.Context(case, prec, stream=stream.cuda_stream)
+    h.init_primitive()
+    tile, _ = tune.autotune(h, prec)
+    h.init_primitive()
+    return h, tile
+
+
+def l1(a, b):
+    return max(np.abs(a[f] - b[f]).sum() / np.abs(b[f]).sum() for f in (0, 4))
+
+
+@pytest.mark.parametrize("name,steps,uref", [("shock_bubble_2d", 20, 113.5), ("drop_2d", 20, 0.53)])
+def test_2d_workload_full_size(dev, stream, name, steps, uref):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.shock_bubble_2d(1024, 256, steps) if name == "shock_bubble_2d" else W.drop_2d(256, steps)
+    h, tile = bench_context(case, fvm.FVM_FP64, stream)
+    t_gpu = h.n_steps(steps)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    t = o.run(q, steps)
+    err = field_err(h.get_state(), q, uref)
+    print(f"{name} full size, tile {tile}, {steps} steps: {err:.3e}", flush=True)
+    assert abs(t_gpu / t - 1) < 1e-12
+    assert err < 1e-10
+    m, mtile = bench_context(case, fvm.FVM_MIXED, stream)
+    m.n_steps(steps)
+    e1 = l1(m.get_primitive(), h.get_primitive())
+    print(f"{name} mixed (tile {mtile}) vs fp64 L1 rho/p: {e1:.2e}", flush=True)
+    assert e1 < 1e-4
+
+
+def test_bubble_collapse_batch_full_size(dev, stream):
+    """all 256 cases (7.8 M cells) advanced together in the benchmark's launch
+    shape, each against its own oracle run"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm, tune
+    cases = W.bubble_collapse_batch(256, steps=3)
+    b = fvm.Batch(cases, fvm.FVM_FP64, stream=stream.cuda_stream)
+    for i in range(len(cases)):
+        b.init_primitive(i)
+    tile, _ = tune.autotune(b, fvm.FVM_FP64)
+    for i in range(len(cases)):
+        b.init_primitive(i)
+    b.n_steps(3)
+    worst = 0.0
+    for i, c in enumerate(cases):
+        o = Oracle(c)
+        q = o.cons_from_prim()
+        o.run(q, 3)
+        pL = c["grid"]["farfield"]["p"]
+        worst = max(worst, field_err(b.get_state(i), q, (pL / 1000.0) ** 0.5))
+    print(f"batch full size, tile {tile}, 3 steps: worst case {worst:.3e}", flush=True)
+    assert worst < 1e-10
+
+
+def window_case(case, lo, size):
+    """the jet case restricted to a window of `size` cells starting at `lo`
+    (zero-gradient window sides; the sampled cells are far from them)"""
+    c = dict(case)
+    g = dict(case["grid"])
+    g["n"] = list(size)
+    g["bc"] = [[W.BC_ZEROGRAD, W.BC_ZEROGRAD]] * 3
+    g["inflow"] = dict(g["inflow"], noise=0.0)
+    c["grid"] = g
+    return c
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_liquid_jet_full_size_sampled_windows(dev, stream, viscous):
+    """512 x 256 x 256 jet (the benchmark's size and tile), 20 FP64 steps, then
+    the RHS of the state on windows at the nozzle lip, the liquid surface
+    downstream and the gas, each checked against the oracle's RHS of the
+    window; plus the mixed path within the stated L1 of FP64"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = W.liquid_jet_3d(512, 256, 256, steps=20, viscous=viscous)
+    h, tile = bench_context(case, fvm.FVM_FP64, stream)
+    h.n_steps(20)
+    qd = torch.empty((6, 512 * 256 * 256), dtype=torch.float64, device=dev)
+    h.get_state_device(qd.data_ptr())
+    rd = torch.zeros_like(qd)
+    torch.cuda.synchronize()
+    h.rhs(qd.data_ptr(), rd.data_ptr(), 20)
+    torch.cuda.synchronize()
+    N = (256, 256, 512)   # z, y, x
+    size = (22, 22, 22)
+    m = 3
+    windows = [(3, 136, 114), (200, 100, 126), (300, 30, 30), (480, 121, 140)]   # (x, y, z) corners
+    for (x0, y0, z0) in windows:
+        sl = (slice(None), slice(z0, z0 + size[2]), slice(y0, y0 + size[1]), slice(x0, x0 + size[0]))
+        qw = qd.view(6, *N)[sl].contiguous().cpu().numpy().reshape(6, -1)
+        rw = rd.view(6, *N)[sl].contiguous().cpu().numpy()
+        o = Oracle(window_case(case, (x0, y0, z0), size))
+        r_ref = o.rhs(np.ascontiguousarray(qw), 20).reshape(6, size[2], size[1], size[0])
+        inner = (slice(None), slice(m, -m), slice(m, -m), slice(m, -m))
+        a, b = rw[inner].reshape(6, -1), r_ref[inner].reshape(6, -1)
+        # a right-hand side is a difference of face fluxes: its rounding is
+        # relative to the flux scale / dx of each conserved field (mass rho U,
+        # momentum p + rho U^2, energy (rho E + p) U, U = 300 m/s)
+        w = o.prim_from_cons(np.ascontiguousarray(qw))
+        U, dx = 300.0, case["grid"]["dx"][0]
+        rmax, pmax, Emax = w[0].max(), np.abs(w[4]).max(), np.abs(qw[4]).max()
+        scale = np.array([rmax * U, pmax + rmax * U * U, pmax + rmax * U * U, pmax + rmax * U * U,
+                          (Emax + pmax) * U, rmax * U]) / dx
+        per = np.abs(a - b).max(axis=1) / scale
+        err = per.max()
+        print(f"jet (viscous={viscous}) tile {tile} window at {(x0, y0, z0)}: {err:.3e} per field "
+              f"{np.array2string(per, precision=2)}; vs RHS max {field_err(a, b, U):.2e}", flush=True)
+        assert err < 1e-10
+    del qd, rd
+    mx, mtile = bench_context(case, fvm.FVM_MIXED, stream)
+    mx.n_steps(20)
+    e1 = l1(mx.get_primitive(), h.get_primitive())
+    print(f"jet mixed (tile {mtile}) vs fp64 L1 rho/p: {e1:.2e}", flush=True)
+    assert e1 < 1e-4

@@ -51,14 +51,19 @@ typedef struct {
   double ff_p, ff_T, ff_alpha;
 } og_grid;
 
+#define OG_MAXCOMP 3
+
 typedef struct {
-  int kind[2];          /* OG_EOS_SG or OG_EOS_PR per component */
+  /* components: 0 (liquid or ambient fluid), 1 and, with ncomp = 3, 2 (gases,
+   * transported mass fractions xi_1, xi_2).  ncomp = 0 means 2. */
+  int kind[OG_MAXCOMP];   /* OG_EOS_SG or OG_EOS_PR per component */
   /* stiffened gas: p = (gamma-1) rho (e - q) - gamma p_inf, e = cv T + p_inf v + q */
-  double gamma[2], pinf[2], cv[2], q[2];
-  /* Peng-Robinson pseudo-mixture (kind == OG_EOS_PR): ns species with mole
-   * fractions X, critical data, acentric factors, molar masses [kg/mol] and
-   * binary interaction parameters; ideal-gas part with a constant specific
-   * cv (cv[k]) and reference energy q[k]. */
+  double gamma[OG_MAXCOMP], pinf[OG_MAXCOMP], cv[OG_MAXCOMP], q[OG_MAXCOMP];
+  /* Peng-Robinson pseudo-mixture (kind == OG_EOS_PR, components 0 and 1 of a
+   * two-component closure only): ns species with mole fractions X, critical
+   * data, acentric factors, molar masses [kg/mol] and binary interaction
+   * parameters; ideal-gas part with a constant specific cv (cv[k]) and
+   * reference energy q[k]. */
   int pr_ns[2];
   double pr_X[2][OG_MAXSPEC], pr_Tc[2][OG_MAXSPEC], pr_pc[2][OG_MAXSPEC];
   double pr_omega[2][OG_MAXSPEC], pr_M[2][OG_MAXSPEC];
@@ -67,7 +72,11 @@ typedef struct {
   /* transport (eq. 2-2): dynamic viscosity [Pa s] and thermal conductivity
    * [W/(m K)] per component; the cell values mix them by volume fraction
    * (eq. 2-8 with one gas and no vapour).  All zero: inviscid, adiabatic. */
-  double mu[2], kc[2];
+  double mu[OG_MAXCOMP], kc[OG_MAXCOMP];
+  /* 2 (default when 0) or 3; with 3 components every component is a
+   * stiffened gas and the gases (1, 2) are ideal (p_inf = 0), the form of
+   * Appendix A's Table A.1 and eqs. (A.1.2)-(A.1.5) */
+  int ncomp;
 } og_eos;
 
 typedef struct {
@@ -85,16 +94,28 @@ typedef struct {
 } og_scheme;
 
 /* primitive vector of one cell */
-enum { OW_RHO = 0, OW_U = 1, OW_V = 2, OW_W = 3, OW_P = 4, OW_T = 5, OW_Y = 6, OW_C = 7, OW_A = 8, OW_N = 9 };
+enum { OW_RHO = 0, OW_U = 1, OW_V = 2, OW_W = 3, OW_P = 4, OW_T = 5, OW_Y = 6, OW_C = 7, OW_A = 8,
+       OW_Y2 = 9, OW_A2 = 10, OW_N = 11 };   /* Y2, A2: second gas (0 with two components) */
 
 /* ---- thermodynamics (Appendix A) ---- */
+/* number of components (2 or 3) and of conserved fields */
+int og_ncomp(const og_eos* e);
+int og_nq(const og_grid* g, const og_eos* e);
+/* two components: Y is the mass fraction of component 1 */
 int og_eos_forward(const og_eos* e, double p, double T, double Y, double* rho, double* ein);
 int og_eos_inverse(const og_eos* e, double rho, double ein, double Y, double Tguess,
                    double* p, double* T);
+/* any number of components: Y1, Y2 the gas mass fractions (Y2 = 0 with two) */
+int og_eos_forward2(const og_eos* e, double p, double T, double Y1, double Y2, double* rho, double* ein);
+int og_eos_inverse2(const og_eos* e, double rho, double ein, double Y1, double Y2, double Tguess,
+                    double* p, double* T);
 double og_sound(const og_eos* e, int k, double p, double T);
 /* mass fraction clipped into [0, 1] for the inverse closure (NaN unchanged) */
 double og_clip_fraction(double Y);
+/* three components: the gas fractions as the closure takes them, Yk = (liquid, gas 1, gas 2) */
+void og_clip_fractions3(double Y1, double Y2, double Yk[3]);
 double og_mix_sound(const og_eos* e, double p, double T, double Y);
+double og_mix_sound2(const og_eos* e, double p, double T, double Y1, double Y2);
 double og_spec_volume(const og_eos* e, int k, double p, double T);
 double og_spec_energy(const og_eos* e, int k, double p, double T);
 int og_pr_coeffs(const og_eos* e, int k, double T, double* a, double* dadT, double* d2adT2,
@@ -111,7 +132,8 @@ double og_central4(double a, double b, double c, double d);
 
 /* one face flux from the primitives of the four cells i-1, i, i+1, i+2 along
  * direction dir.  f = 1 selects the discontinuous branch; s_left / s_right are
- * the THINC eligibilities of cells i and i+1 along dir. */
+ * the THINC eligibilities of cells i and i+1 along dir (bit 0: xi_1, bit 1:
+ * xi_2). */
 int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
                  const double W[4][OW_N], int f, int s_left, int s_right,
                  double* F, double* ustar, double* pstar);
@@ -130,7 +152,7 @@ int og_step(const og_grid* g, const og_eos* e, const og_scheme* s, double* q,
             int64_t step, double* t, double t_end, double* dt_out);
 int og_run(const og_grid* g, const og_eos* e, const og_scheme* s, double* q,
            int64_t step0, int nsteps, double* t, double t_end);
-void og_totals(const og_grid* g, const double* q, double* out);
+void og_totals(const og_grid* g, const og_eos* e, const double* q, double* out);
 
 /* low-storage RK combination with a caller-supplied right-hand side */
 typedef void (*og_rhs_fn)(const double* q, double* r, int n, void* user);

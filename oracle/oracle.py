@@ -23,16 +23,19 @@ class Grid(C.Structure):
                 ("ff_p", C.c_double), ("ff_T", C.c_double), ("ff_alpha", C.c_double)]
 
 
+MAXCOMP = 3
+
+
 class Eos(C.Structure):
-    _fields_ = [("kind", C.c_int * 2), ("gamma", C.c_double * 2), ("pinf", C.c_double * 2),
-                ("cv", C.c_double * 2), ("q", C.c_double * 2),
+    _fields_ = [("kind", C.c_int * MAXCOMP), ("gamma", C.c_double * MAXCOMP), ("pinf", C.c_double * MAXCOMP),
+                ("cv", C.c_double * MAXCOMP), ("q", C.c_double * MAXCOMP),
                 ("pr_ns", C.c_int * 2),
                 ("pr_X", (C.c_double * MAXSPEC) * 2), ("pr_Tc", (C.c_double * MAXSPEC) * 2),
                 ("pr_pc", (C.c_double * MAXSPEC) * 2), ("pr_omega", (C.c_double * MAXSPEC) * 2),
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2),
                 ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
-                ("mu", C.c_double * 2), ("kc", C.c_double * 2)]
+                ("mu", C.c_double * MAXCOMP), ("kc", C.c_double * MAXCOMP), ("ncomp", C.c_int)]
 
 
 class Scheme(C.Structure):
@@ -60,6 +63,11 @@ def lib():
         sig = {
             "og_eos_forward": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_eos_inverse": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "og_eos_forward2": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "og_eos_inverse2": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                          dp, dp]),
+            "og_mix_sound2": (C.c_double, [pe, C.c_double, C.c_double, C.c_double, C.c_double]),
+            "og_ncomp": (C.c_int, [pe]),
             "og_sound": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
             "og_mix_sound": (C.c_double, [pe, C.c_double, C.c_double, C.c_double]),
             "og_clip_fraction": (C.c_double, [C.c_double]),
@@ -83,7 +91,7 @@ def lib():
             "og_sensor_flags": (C.c_int, [pg, pe, ps, dp, C.POINTER(C.c_ubyte)]),
             "og_step": (C.c_int, [pg, pe, ps, dp, C.c_int64, dp, C.c_double, dp]),
             "og_run": (C.c_int, [pg, pe, ps, dp, C.c_int64, C.c_int, dp, C.c_double]),
-            "og_totals": (None, [pg, dp, dp]),
+            "og_totals": (None, [pg, pe, dp, dp]),
             "og_lsrk": (None, [ps, dp, C.c_int, C.c_double, RHS_FN, C.c_void_p]),
             "og_splitmix64": (C.c_uint64, [C.c_uint64]),
             "og_noise01": (C.c_double, [C.c_uint64] * 5),
@@ -123,12 +131,16 @@ def make_grid(gd):
 
 def make_eos(ed):
     e = Eos()
-    for k in range(2):
+    nc = len(ed["kind"])
+    e.ncomp = nc
+    for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
-        e.mu[k], e.kc[k] = ed.get("mu", [0.0, 0.0])[k], ed.get("kc", [0.0, 0.0])[k]
+        e.mu[k], e.kc[k] = (ed.get("mu") or [0.0] * nc)[k], (ed.get("kc") or [0.0] * nc)[k]
         pr = ed["pr"][k]
         if pr is not None:
+            if k > 1:
+                raise ValueError("a Peng-Robinson fluid is supported as component 0 or 1 of two")
             sp = pr["species"]
             e.pr_ns[k] = len(sp)
             for a, s in enumerate(sp):
@@ -164,7 +176,8 @@ class Oracle:
         self.e = make_eos(case["eos"])
         self.s = make_scheme(case["scheme"])
         self.dim = case["grid"]["dim"]
-        self.nq = self.dim + 3
+        self.ncomp = len(case["eos"]["kind"])
+        self.nq = self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
 
     def _err(self, rc, what):
@@ -179,9 +192,10 @@ class Oracle:
 
     def prim_from_cons(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
-        W = np.empty((9, self.ncell))
+        W = np.empty((11, self.ncell))
         self._err(self.L.og_prim_from_cons(C.byref(self.g), C.byref(self.e), _dp(q), _dp(W)), "prim_from_cons")
-        return W
+        # rows: rho, u, v, w, p, T, xi_1, c, alpha_1 (+ xi_2, alpha_2 with three components)
+        return W if self.ncomp == 3 else W[:9]
 
     def rhs(self, q, step=0):
         q = np.ascontiguousarray(q, dtype=np.float64)
@@ -225,5 +239,5 @@ class Oracle:
     def totals(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
         out = np.empty(self.nq)
-        self.L.og_totals(C.byref(self.g), _dp(q), _dp(out))
+        self.L.og_totals(C.byref(self.g), C.byref(self.e), _dp(q), _dp(out))
         return out

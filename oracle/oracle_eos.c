@@ -222,6 +222,21 @@ static void sg_pure(const og_eos* e, int k, double rho, double ein, double* p, d
   *T = (ein - e->q[k] - e->pinf[k] * v) / e->cv[k];
 }
 
+/* The quadratic below for groups 0 and 1 of stiffened-gas terms sharing
+ * p_inf = P0 and P1 (derivation in the next comment); its larger root. */
+static void sg_quadratic(double v, double A0, double A1, double Cv, double Cp, double eh, double P0,
+                         double P1, double* p, double* T)
+{
+  double qa = v * Cv;
+  double qb = v * (Cp * (P0 + P1) - A0 * P1 - A1 * P0) - eh * (A0 + A1);
+  double qc = v * Cp * P0 * P1 - eh * (A0 * P1 + A1 * P0);
+  double disc = qb * qb - 4.0 * qa * qc;
+  double sq = sqrt(disc);
+  double pp = (qb < 0.0) ? (-qb + sq) / (2.0 * qa) : 2.0 * qc / (-qb - sq);
+  *p = pp;
+  *T = (eh + pp * v) / Cp;
+}
+
 /* Two stiffened-gas components in p-T equilibrium.  With A_k = xi_k (g_k-1) cv_k,
  * Cv = sum xi_k cv_k, Cp = sum xi_k g_k cv_k and eh = e - sum xi_k q_k the two
  * equilibrium conditions reduce to T = (eh + p v) / Cp and the quadratic
@@ -238,14 +253,23 @@ static void sg_pair(const double gam[2], const double pinf[2], const double cv[2
   double Cv = Yk[0] * cv[0] + Yk[1] * cv[1];
   double Cp = Yk[0] * gam[0] * cv[0] + Yk[1] * gam[1] * cv[1];
   double eh = ein - Yk[0] * q[0] - Yk[1] * q[1];
-  double qa = v * Cv;
-  double qb = v * (Cp * (pinf[0] + pinf[1]) - A0 * pinf[1] - A1 * pinf[0]) - eh * (A0 + A1);
-  double qc = v * Cp * pinf[0] * pinf[1] - eh * (A0 * pinf[1] + A1 * pinf[0]);
-  double disc = qb * qb - 4.0 * qa * qc;
-  double sq = sqrt(disc);
-  double pp = (qb < 0.0) ? (-qb + sq) / (2.0 * qa) : 2.0 * qc / (-qb - sq);
-  *p = pp;
-  *T = (eh + pp * v) / Cp;
+  sg_quadratic(v, A0, A1, Cv, Cp, eh, pinf[0], pinf[1], p, T);
+}
+
+/* Three stiffened-gas components whose gases (1 and 2) are ideal: the two gas
+ * terms of sum_k xi_k (g_k-1) cv_k T / (p + P_k) = v share P = 0 and add up,
+ * so the same quadratic holds with A0 = xi_0 (g_0-1) cv_0,
+ * A1 = sum_{k=1,2} xi_k (g_k-1) cv_k and the sums Cv, Cp, eh over all three
+ * (eqs. A.1.2-A.1.3 of Table A.1 in p-T equilibrium). */
+static void sg_three(const og_eos* e, const double Yk[3], double rho, double ein, double* p, double* T)
+{
+  double v = 1.0 / rho;
+  double A0 = Yk[0] * (e->gamma[0] - 1.0) * e->cv[0];
+  double A1 = Yk[1] * (e->gamma[1] - 1.0) * e->cv[1] + Yk[2] * (e->gamma[2] - 1.0) * e->cv[2];
+  double Cv = Yk[0] * e->cv[0] + Yk[1] * e->cv[1] + Yk[2] * e->cv[2];
+  double Cp = Yk[0] * e->gamma[0] * e->cv[0] + Yk[1] * e->gamma[1] * e->cv[1] + Yk[2] * e->gamma[2] * e->cv[2];
+  double eh = ein - Yk[0] * e->q[0] - Yk[1] * e->q[1] - Yk[2] * e->q[2];
+  sg_quadratic(v, A0, A1, Cv, Cp, eh, e->pinf[0], 0.0, p, T);
 }
 
 /* Peng-Robinson component alone: T from e at fixed v by Newton (the paper's
@@ -342,4 +366,76 @@ int og_eos_inverse(const og_eos* e, double rho, double ein, double Y, double Tgu
     return 0;
   }
   return pr_mixed(e, rho, ein, Y, p, T);
+}
+
+int og_ncomp(const og_eos* e)
+{
+  return e->ncomp == 3 ? 3 : 2;
+}
+
+/* three components: every component a stiffened gas, the gases ideal */
+static int three_ok(const og_eos* e)
+{
+  for (int k = 0; k < 3; ++k)
+    if (e->kind[k] != OG_EOS_SG) return 0;
+  return e->pinf[1] == 0.0 && e->pinf[2] == 0.0;
+}
+
+int og_eos_forward2(const og_eos* e, double p, double T, double Y1, double Y2, double* rho, double* ein)
+{
+  if (og_ncomp(e) == 2) return og_eos_forward(e, p, T, Y1, rho, ein);
+  if (!three_ok(e)) return -1;
+  double Yk[3] = {1.0 - Y1 - Y2, Y1, Y2};
+  double v = 0.0, en = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    if (Yk[k] == 0.0) continue;
+    og_state_pt s;
+    if (comp_state(e, k, p, T, &s)) return -1;
+    v += Yk[k] * s.v;
+    en += Yk[k] * s.e;
+  }
+  *rho = 1.0 / v;
+  *ein = en;
+  return 0;
+}
+
+/* gas mass fractions of a cell as the closure takes them: each clipped into
+ * [0, 1] (as with two components) and, if they then sum above 1, scaled to
+ * sum to 1; the liquid gets the rest */
+void og_clip_fractions3(double Y1, double Y2, double Yk[3])
+{
+  double a = og_clip_fraction(Y1), b = og_clip_fraction(Y2);
+  double s = a + b;
+  if (s > 1.0) { a /= s; b /= s; }
+  double l = 1.0 - a - b;
+  Yk[0] = l > 0.0 ? l : 0.0;
+  Yk[1] = a;
+  Yk[2] = b;
+}
+
+int og_eos_inverse2(const og_eos* e, double rho, double ein, double Y1, double Y2, double Tguess,
+                    double* p, double* T)
+{
+  if (og_ncomp(e) == 2) return og_eos_inverse(e, rho, ein, Y1, Tguess, p, T);
+  if (!three_ok(e) || !(rho > 0.0)) return -1;
+  double Yk[3];
+  og_clip_fractions3(Y1, Y2, Yk);
+  int present = 0, only = 0;
+  for (int k = 0; k < 3; ++k)
+    if (Yk[k] > 0.0) { ++present; only = k; }
+  if (present == 1) { sg_pure(e, only, rho, ein, p, T); return 0; }
+  sg_three(e, Yk, rho, ein, p, T);
+  return 0;
+}
+
+double og_mix_sound2(const og_eos* e, double p, double T, double Y1, double Y2)
+{
+  if (og_ncomp(e) == 2) return og_mix_sound(e, p, T, Y1);
+  (void)Y2;
+  double c = 0.0;
+  for (int k = 0; k < 3; ++k) {   /* stiffened gases: c_k depends on T alone */
+    double ck = og_sound(e, k, p, T);
+    if (!(ck <= c)) c = ck;
+  }
+  return c;
 }

@@ -74,44 +74,58 @@ double og_noise01(uint64_t seed, uint64_t step, uint64_t j, uint64_t k, uint64_t
 
 /* conserved state of one cell from (p, T, alpha_G, u): the volume fraction
  * alpha_G fixes xi = alpha_G rho_G / rho at the cell's (p, T) (Table A.1). */
-static int cons_from_prim_cell(const og_eos* e, int dim, double p, double T, double al,
+static int cons_from_prim_cell(const og_eos* e, int dim, double p, double T, double al, double al2,
                                const double* u, double* qc)
 {
-  double rL, eL, rG, eG;
-  if (og_eos_forward(e, p, T, 0.0, &rL, &eL)) return -1;
-  if (og_eos_forward(e, p, T, 1.0, &rG, &eG)) return -1;
-  double rho = al * rG + (1.0 - al) * rL;
-  double Y = al * rG / rho;
-  double r2, ein;
-  if (og_eos_forward(e, p, T, Y, &r2, &ein)) return -1;
+  double rho, Y, Y2 = 0.0, r2, ein;
+  if (og_ncomp(e) == 2) {
+    double rL, eL, rG, eG;
+    if (og_eos_forward(e, p, T, 0.0, &rL, &eL)) return -1;
+    if (og_eos_forward(e, p, T, 1.0, &rG, &eG)) return -1;
+    rho = al * rG + (1.0 - al) * rL;
+    Y = al * rG / rho;
+    if (og_eos_forward(e, p, T, Y, &r2, &ein)) return -1;
+  } else {
+    /* Table A.1: rho = sum_k alpha_k rho_k, xi_k = alpha_k rho_k / rho */
+    double r[3];
+    for (int k = 0; k < 3; ++k) r[k] = 1.0 / og_spec_volume(e, k, p, T);
+    rho = (1.0 - al - al2) * r[0] + al * r[1] + al2 * r[2];
+    Y = al * r[1] / rho;
+    Y2 = al2 * r[2] / rho;
+    if (og_eos_forward2(e, p, T, Y, Y2, &r2, &ein)) return -1;
+  }
   double ke = 0.0;
   for (int d = 0; d < dim; ++d) ke += u[d] * u[d];
   qc[0] = rho;
   for (int d = 0; d < dim; ++d) qc[1 + d] = rho * u[d];
   qc[1 + dim] = rho * (ein + 0.5 * ke);
   qc[2 + dim] = rho * Y;
+  if (og_ncomp(e) == 3) qc[3 + dim] = rho * Y2;
   return 0;
 }
 
-/* prim layout: [p, T, alpha_G, u_1 .. u_D][ncell] */
+/* prim layout: [p, T, alpha_G, u_1 .. u_D][ncell], with three components
+ * followed by alpha of the second gas */
 int og_cons_from_prim(const og_grid* g, const og_eos* e, const double* prim, double* q)
 {
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
-  int dim = g->dim, nq = dim + 3, bad = 0;
+  int dim = g->dim, nq = og_nq(g, e), bad = 0;
   for (size_t c = 0; c < nc; ++c) {
-    double u[3] = {0, 0, 0}, qc[6];
+    double u[3] = {0, 0, 0}, qc[7];
     for (int d = 0; d < dim; ++d) u[d] = prim[(3 + d) * nc + c];
-    if (cons_from_prim_cell(e, dim, prim[c], prim[nc + c], prim[2 * nc + c], u, qc)) bad = 1;
+    double al2 = og_ncomp(e) == 3 ? prim[(3 + dim) * nc + c] : 0.0;
+    if (cons_from_prim_cell(e, dim, prim[c], prim[nc + c], prim[2 * nc + c], al2, u, qc)) bad = 1;
     for (int f = 0; f < nq; ++f) q[f * nc + c] = qc[f];
   }
   return bad ? -1 : 0;
 }
 
 /* primitives of one cell (Algorithm 1, "update primitive variables"):
- * u = rho u / rho, e = E - |u|^2/2, xi = rho xi / rho, (p, T) from the closure,
- * alpha_G = xi rho v_G(p, T), c from og_mix_sound. */
+ * u = rho u / rho, e = E - |u|^2/2, xi_k = rho xi_k / rho, (p, T) from the
+ * closure, alpha_k = xi_k rho v_k(p, T) of each gas (with the fractions as the
+ * closure takes them), c from og_mix_sound2. */
 static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
 {
   double rho = qc[0];
@@ -119,14 +133,24 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   for (int d = 0; d < dim; ++d) { u[d] = qc[1 + d] / rho; ke += u[d] * u[d]; }
   double ein = qc[1 + dim] / rho - 0.5 * ke;
   double Y = qc[2 + dim] / rho;
+  int three = og_ncomp(e) == 3;
+  double Y2 = three ? qc[3 + dim] / rho : 0.0;
   double p, T;
-  int rc = og_eos_inverse(e, rho, ein, Y, 0.0, &p, &T);
+  int rc = og_eos_inverse2(e, rho, ein, Y, Y2, 0.0, &p, &T);
   W[OW_RHO] = rho;
   W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
-  W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y;
-  W[OW_C] = og_mix_sound(e, p, T, Y);
-  double Yc = og_clip_fraction(Y);
-  W[OW_A] = (Yc == 0.0) ? 0.0 : Yc * rho * og_spec_volume(e, 1, p, T);
+  W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y; W[OW_Y2] = Y2;
+  W[OW_C] = og_mix_sound2(e, p, T, Y, Y2);
+  if (!three) {
+    double Yc = og_clip_fraction(Y);
+    W[OW_A] = (Yc == 0.0) ? 0.0 : Yc * rho * og_spec_volume(e, 1, p, T);
+    W[OW_A2] = 0.0;
+  } else {
+    double Yk[3];
+    og_clip_fractions3(Y, Y2, Yk);
+    W[OW_A] = (Yk[1] == 0.0) ? 0.0 : Yk[1] * rho * og_spec_volume(e, 1, p, T);
+    W[OW_A2] = (Yk[2] == 0.0) ? 0.0 : Yk[2] * rho * og_spec_volume(e, 2, p, T);
+  }
   if (rc || !(rho > 0.0) || !(T > 0.0) || !isfinite(p) || !isfinite(W[OW_C])) return -1;
   return 0;
 }
@@ -136,9 +160,9 @@ int og_prim_from_cons(const og_grid* g, const og_eos* e, const double* q, double
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
-  int dim = g->dim, nq = dim + 3, bad = 0;
+  int dim = g->dim, nq = og_nq(g, e), bad = 0;
   for (size_t c = 0; c < nc; ++c) {
-    double qc[6], w[OW_N];
+    double qc[7], w[OW_N];
     for (int f = 0; f < nq; ++f) qc[f] = q[f * nc + c];
     if (prim_cell(e, dim, qc, w)) bad = 1;
     for (int f = 0; f < OW_N; ++f) W[f * nc + c] = w[f];
@@ -153,7 +177,7 @@ int og_prim_from_cons(const og_grid* g, const og_eos* e, const double* q, double
  * edge and corner ghosts combine the two boundary kinds. */
 static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, double* qp, int64_t step)
 {
-  int dim = g->dim, nq = dim + 3;
+  int dim = g->dim, nq = og_nq(g, e);
   for (int d = 0; d < dim; ++d) {
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
@@ -181,12 +205,12 @@ static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, doub
                 if (dim > 2) z = (k + 0.5) * g->dx[2] - g->in_center[1];
                 r = sqrt(y * y + z * z);
                 if (dim == 1 || r < g->in_radius) {
-                  double u[3] = {g->in_u, 0.0, 0.0}, qc[6];
+                  double u[3] = {g->in_u, 0.0, 0.0}, qc[7];
                   uint64_t jj = (uint64_t)(int64_t)j, kk = (uint64_t)(int64_t)k;
                   for (int c = 0; c < dim; ++c)
                     u[c] += g->in_noise * g->in_u *
                             (2.0 * og_noise01(g->in_seed, (uint64_t)step, jj, kk, (uint64_t)c) - 1.0);
-                  if (cons_from_prim_cell(e, dim, g->in_p, g->in_T, g->in_alpha, u, qc)) return -1;
+                  if (cons_from_prim_cell(e, dim, g->in_p, g->in_T, g->in_alpha, 0.0, u, qc)) return -1;
                   for (int f = 0; f < nq; ++f) qp[f * pd->npad + gi] = qc[f];
                   continue;
                 }
@@ -195,8 +219,8 @@ static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, doub
               if (bc == OG_BC_FARFIELD) {
                 /* a far-field reservoir at rest (stands in for the paper's
                  * non-reflective boundaries around a collapsing bubble) */
-                double u[3] = {0.0, 0.0, 0.0}, qc[6];
-                if (cons_from_prim_cell(e, dim, g->ff_p, g->ff_T, g->ff_alpha, u, qc)) return -1;
+                double u[3] = {0.0, 0.0, 0.0}, qc[7];
+                if (cons_from_prim_cell(e, dim, g->ff_p, g->ff_T, g->ff_alpha, 0.0, u, qc)) return -1;
                 for (int f = 0; f < nq; ++f) qp[f * pd->npad + gi] = qc[f];
                 continue;
               }
@@ -238,12 +262,16 @@ static void sensors(const og_grid* g, const og_scheme* s, const og_pad* pd, cons
         size_t c = og_pidx(pd, i, j, k);
         size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
         unsigned char fl = 0;
-        /* THINC eligibility: eps < xi_i < 1 - eps and xi monotone through i along d */
-        double Y = W[OW_Y * np + c];
-        for (int d = 0; d < dim; ++d) {
-          double Ym = W[OW_Y * np + c - st[d]], Yp = W[OW_Y * np + c + st[d]];
-          if (Y > s->eps_interface && Y < 1.0 - s->eps_interface && (Y - Ym) * (Yp - Y) > 0.0)
-            fl |= (unsigned char)(2u << d);
+        /* THINC eligibility: eps < xi_i < 1 - eps and xi monotone through i along d;
+         * bits 1+d for xi_1, 4+d for xi_2 */
+        for (int g2 = 0; g2 < 2; ++g2) {
+          int f = g2 ? OW_Y2 : OW_Y;
+          double Y = W[f * np + c];
+          for (int d = 0; d < dim; ++d) {
+            double Ym = W[f * np + c - st[d]], Yp = W[f * np + c + st[d]];
+            if (Y > s->eps_interface && Y < 1.0 - s->eps_interface && (Y - Ym) * (Yp - Y) > 0.0)
+              fl |= (unsigned char)((g2 ? 16u : 2u) << d);
+          }
         }
         if (!s->switching) {
           fl |= 1u;
@@ -261,11 +289,14 @@ static void sensors(const og_grid* g, const og_scheme* s, const og_pad* pd, cons
           double w2 = grad[1][0] - grad[0][1];
           double curl2 = w0 * w0 + w1 * w1 + w2 * w2;
           double thD = div * div / (div * div + curl2 + s->eps_ducros);
-          /* gas-volume-fraction variation over all directions */
+          /* gas-volume-fraction variation over all directions (both gases together) */
           double thG = 0.0;
-          double a0 = W[OW_A * np + c];
-          for (int d = 0; d < dim; ++d)
-            thG += fabs(a0 - W[OW_A * np + c - st[d]]) + fabs(W[OW_A * np + c + st[d]] - a0);
+          double a0 = W[OW_A * np + c] + W[OW_A2 * np + c];
+          for (int d = 0; d < dim; ++d) {
+            double am = W[OW_A * np + c - st[d]] + W[OW_A2 * np + c - st[d]];
+            double ap = W[OW_A * np + c + st[d]] + W[OW_A2 * np + c + st[d]];
+            thG += fabs(a0 - am) + fabs(ap - a0);
+          }
           if (thD > s->theta_ducros || thG > s->theta_gas) fl |= 1u;   /* eq. (D.4) */
         }
         flag[c] = fl;
@@ -304,7 +335,8 @@ static void curvature_field(const og_grid* g, const og_scheme* s, const og_pad* 
             for (int di = -r1; di <= r1; ++di) {
               double w = (di == 0 ? 2.0 : 1.0) * (dim > 1 ? (dj == 0 ? 2.0 : 1.0) : 1.0) *
                          (dim > 2 ? (dk == 0 ? 2.0 : 1.0) : 1.0);
-              acc += w * W[OW_Y * np + c + di * st[0] + dj * st[1] + dk * st[2]];
+              size_t cc = c + di * st[0] + dj * st[1] + dk * st[2];
+              acc += w * (W[OW_Y * np + cc] + W[OW_Y2 * np + cc]);
               wsum += w;
             }
         Hs[c] = acc / wsum;
@@ -368,19 +400,31 @@ static void curvature_field(const og_grid* g, const og_scheme* s, const og_pad* 
   free(nv);
 }
 
+int og_nq(const og_grid* g, const og_eos* e)
+{
+  return g->dim + og_ncomp(e) + 1;
+}
+
 /* ---------------- viscous stress and heat conduction (eq. 2-2) ---------------- */
 
 static int has_diffusion(const og_eos* e)
 {
-  return e->mu[0] > 0.0 || e->mu[1] > 0.0 || e->kc[0] > 0.0 || e->kc[1] > 0.0;
+  for (int k = 0; k < og_ncomp(e); ++k)
+    if (e->mu[k] > 0.0 || e->kc[k] > 0.0) return 1;
+  return 0;
 }
 
-/* a transport coefficient of a cell from its gas volume fraction: eq. (2-8)
- * with one gas and no vapour, (1 - alpha_G) value_L + alpha_G value_G */
-static double mix_alpha(const double v[2], double a)
+/* a transport coefficient of a cell from its gas volume fractions: eq. (2-8)
+ * without vapour, (1 - alpha_1 - alpha_2) value_L + alpha_1 value_1 +
+ * alpha_2 value_2 (alpha_2 = 0 with two components) */
+static double mix_alpha(const double* v, int ncomp, double a, double a2)
 {
   double ac = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
-  return (1.0 - ac) * v[0] + ac * v[1];
+  if (ncomp == 2) return (1.0 - ac) * v[0] + ac * v[1];
+  double bc = a2 < 0.0 ? 0.0 : (a2 > 1.0 ? 1.0 : a2);
+  double sum = ac + bc;
+  if (sum > 1.0) { ac /= sum; bc /= sum; }
+  return (1.0 - ac - bc) * v[0] + ac * v[1] + bc * v[2];
 }
 
 /* Stress part S(q) of the flux of eq. (2-2) through the face between the
@@ -406,9 +450,11 @@ static void viscous_flux(const og_grid* g, const og_eos* e, const og_pad* pd, co
   }
   double div = 0.0;
   for (int b = 0; b < dim; ++b) div += grad[b][b];
+  int nc = og_ncomp(e);
   double aL = W[OW_A * np + c], aR = W[OW_A * np + R];
-  double mu = 0.5 * (mix_alpha(e->mu, aL) + mix_alpha(e->mu, aR));
-  double kc = 0.5 * (mix_alpha(e->kc, aL) + mix_alpha(e->kc, aR));
+  double bL = W[OW_A2 * np + c], bR = W[OW_A2 * np + R];
+  double mu = 0.5 * (mix_alpha(e->mu, nc, aL, bL) + mix_alpha(e->mu, nc, aR, bR));
+  double kc = 0.5 * (mix_alpha(e->kc, nc, aL, bL) + mix_alpha(e->kc, nc, aR, bR));
   double work = 0.0;
   Fv[0] = 0.0;
   for (int a = 0; a < dim; ++a) {
@@ -419,6 +465,7 @@ static void viscous_flux(const og_grid* g, const og_eos* e, const og_pad* pd, co
   }
   Fv[1 + dim] = -work - kc * (W[OW_T * np + R] - W[OW_T * np + c]) / g->dx[d];
   Fv[2 + dim] = 0.0;
+  Fv[3 + dim] = 0.0;
 }
 
 /* ---------------- right-hand side ---------------- */
@@ -433,7 +480,7 @@ typedef struct {
 static int work_setup(og_work* w, const og_grid* g, const og_eos* e, const double* q, int64_t step)
 {
   og_pad_init(&w->pd, g);
-  int dim = g->dim, nq = dim + 3;
+  int dim = g->dim, nq = og_nq(g, e);
   size_t np = w->pd.npad, nc = w->pd.ncell;
   w->qp = (double*)calloc((size_t)nq * np, sizeof(double));
   w->W = (double*)calloc((size_t)OW_N * np, sizeof(double));
@@ -449,7 +496,7 @@ static int work_setup(og_work* w, const og_grid* g, const og_eos* e, const doubl
   int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (long long c = 0; c < (long long)np; ++c) {
-    double qc[6], wc[OW_N];
+    double qc[7], wc[OW_N];
     int anyq = 0;
     for (int f = 0; f < nq; ++f) { qc[f] = w->qp[f * np + c]; anyq |= (qc[f] != 0.0); }
     if (!anyq) { for (int f = 0; f < OW_N; ++f) w->W[f * np + c] = 0.0; continue; } /* unused corner */
@@ -471,7 +518,7 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
   og_work w;
   int rc = work_setup(&w, g, e, q, step);
   if (rc) { work_free(&w); return rc; }
-  int dim = g->dim, nq = dim + 3;
+  int dim = g->dim, nq = og_nq(g, e);
   og_pad* pd = &w.pd;
   size_t np = pd->npad, nc = pd->ncell;
   size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
@@ -495,11 +542,14 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
           for (int m = 0; m < 4; ++m)
             for (int f = 0; f < OW_N; ++f) Wl[m][f] = w.W[f * np + c + (m - 1) * st[d]];
           int f = (w.flag[c] | w.flag[c + st[d]]) & 1;
-          int sl = (w.flag[c] >> (1 + d)) & 1, sr = (w.flag[c + st[d]] >> (1 + d)) & 1;
-          double F[6];
+          /* THINC eligibility of cells i and i+1 along d: bit 0 xi_1, bit 1 xi_2 */
+          int fl = w.flag[c], fr = w.flag[c + st[d]];
+          int sl = ((fl >> (1 + d)) & 1) | (((fl >> (4 + d)) & 1) << 1);
+          int sr = ((fr >> (1 + d)) & 1) | (((fr >> (4 + d)) & 1) << 1);
+          double F[7];
           if (og_face_flux(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL)) bad = 1;
           if (diffusive) {
-            double Fv[6];
+            double Fv[7];
             viscous_flux(g, e, pd, w.W, c, d, Fv);
             for (int v = 0; v < nq; ++v) F[v] += Fv[v];
           }
@@ -530,7 +580,9 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
           size_t c = og_pidx(pd, i, j, k), ci = og_cidx(pd, i, j, k);
           double se = 0.0;
           for (int d = 0; d < dim; ++d) {
-            double gH = (w.W[OW_A * np + c + st[d]] - w.W[OW_A * np + c - st[d]]) / (2.0 * g->dx[d]);
+            size_t cp = c + st[d], cm = c - st[d];
+            double gH = (w.W[OW_A * np + cp] + w.W[OW_A2 * np + cp] - (w.W[OW_A * np + cm] + w.W[OW_A2 * np + cm])) /
+                        (2.0 * g->dx[d]);
             double S = s->sigma * kap[ci] * gH;
             r[(1 + d) * nc + ci] += S;
             se += w.W[(OW_U + d) * np + c] * S;
@@ -597,21 +649,30 @@ double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
-  int dim = g->dim, nq = dim + 3;
+  int dim = g->dim, nq = og_nq(g, e);
   int diffusive = has_diffusion(e);
   double sdx2 = 0.0;
   for (int d = 0; d < dim; ++d) sdx2 += 1.0 / (g->dx[d] * g->dx[d]);
   double lam = 0.0;
   for (size_t c = 0; c < nc; ++c) {
-    double qc[6], w[OW_N];
+    double qc[7], w[OW_N];
     for (int f = 0; f < nq; ++f) qc[f] = q[f * nc + c];
     if (prim_cell(e, dim, qc, w)) return NAN;
     double l = 0.0;
     for (int d = 0; d < dim; ++d) l += (fabs(w[OW_U + d]) + w[OW_C]) / g->dx[d];
     if (diffusive) {
-      double Yc = og_clip_fraction(w[OW_Y]);
-      double cvm = (1.0 - Yc) * e->cv[0] + Yc * e->cv[1];
-      double mu = mix_alpha(e->mu, w[OW_A]), kc = mix_alpha(e->kc, w[OW_A]) / cvm;
+      int ncomp = og_ncomp(e);
+      double cvm;
+      if (ncomp == 2) {
+        double Yc = og_clip_fraction(w[OW_Y]);
+        cvm = (1.0 - Yc) * e->cv[0] + Yc * e->cv[1];
+      } else {
+        double Yk[3];
+        og_clip_fractions3(w[OW_Y], w[OW_Y2], Yk);
+        cvm = Yk[0] * e->cv[0] + Yk[1] * e->cv[1] + Yk[2] * e->cv[2];
+      }
+      double mu = mix_alpha(e->mu, ncomp, w[OW_A], w[OW_A2]);
+      double kc = mix_alpha(e->kc, ncomp, w[OW_A], w[OW_A2]) / cvm;
       l += 2.0 * (mu > kc ? mu : kc) / w[OW_RHO] * sdx2;
     }
     if (l > lam) lam = l;
@@ -648,7 +709,7 @@ int og_step(const og_grid* g, const og_eos* e, const og_scheme* s, double* q,
 {
   og_pad pd;
   og_pad_init(&pd, g);
-  int n = (int)((size_t)(g->dim + 3) * pd.ncell);
+  int n = (int)((size_t)og_nq(g, e) * pd.ncell);
   double dt = og_dt(g, e, s, q);
   if (!isfinite(dt)) { og_set_error("non-physical state at the start of a step"); return -2; }
   if (t_end > 0.0 && *t + dt > t_end) dt = t_end - *t;
@@ -672,12 +733,12 @@ int og_run(const og_grid* g, const og_eos* e, const og_scheme* s, double* q,
 }
 
 /* conserved totals: sum over cells of q times the cell volume, fixed order */
-void og_totals(const og_grid* g, const double* q, double* out)
+void og_totals(const og_grid* g, const og_eos* e, const double* q, double* out)
 {
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
-  int nq = g->dim + 3;
+  int nq = og_nq(g, e);
   double vol = 1.0;
   for (int d = 0; d < g->dim; ++d) vol *= g->dx[d];
   for (int f = 0; f < nq; ++f) {

@@ -95,6 +95,9 @@ static void upwind_pair(int lim, double a, double b, double c, double d, double*
  *  - TDU (eq. 3-5, Appendix B): the face temperature is reconstructed and
  *    rho_f, e_f follow from the closure at (p*, T_f, xi_f);
  *  - flux of eq. (2-2): m = rho_f u*; (m, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*, m xi_f).
+ * With three components the second gas fraction xi_2 is reconstructed like
+ * xi_1 (limited, THINC where eligible, central) and TDU takes both
+ * (Section 3.4: the TDU of rho_f with the gas fractions of Remark 2).
  */
 int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
                  const double W[4][OW_N], int f, int s_left, int s_right,
@@ -104,29 +107,39 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
   double IL = (3.0 * W[1][OW_RHO] + W[2][OW_RHO]) * cm / 4.0;
   double IR = (W[1][OW_RHO] + 3.0 * W[2][OW_RHO]) * cm / 4.0;
   double uf[3] = {0.0, 0.0, 0.0};
-  double us, ps, Tf, Yf;
+  double us, ps, Tf, Yf, Y2f = 0.0;
+  const int three = og_ncomp(e) == 3;
 
   if (f) {
-    double uL[3] = {0, 0, 0}, uR[3] = {0, 0, 0}, pL, pR, TL, TR, YL, YR;
+    double uL[3] = {0, 0, 0}, uR[3] = {0, 0, 0}, pL, pR, TL, TR, YL, YR, Y2L = 0.0, Y2R = 0.0;
     for (int d = 0; d < dim; ++d)
       upwind_pair(s->lim_u, W[0][OW_U + d], W[1][OW_U + d], W[2][OW_U + d], W[3][OW_U + d], &uL[d], &uR[d]);
     upwind_pair(s->lim_s, W[0][OW_P], W[1][OW_P], W[2][OW_P], W[3][OW_P], &pL, &pR);
     upwind_pair(s->lim_s, W[0][OW_T], W[1][OW_T], W[2][OW_T], W[3][OW_T], &TL, &TR);
     upwind_pair(s->lim_s, W[0][OW_Y], W[1][OW_Y], W[2][OW_Y], W[3][OW_Y], &YL, &YR);
+    if (three) upwind_pair(s->lim_s, W[0][OW_Y2], W[1][OW_Y2], W[2][OW_Y2], W[3][OW_Y2], &Y2L, &Y2R);
     ps = 0.5 * (pL + pR);
     us = (IL * uL[dir] + IR * uR[dir] + pL - pR) / (IL + IR);
     if (us >= 0.0) {
       for (int d = 0; d < dim; ++d) uf[d] = uL[d];
       Tf = TL;
-      Yf = (s->thinc && s_left)
+      Yf = (s->thinc && (s_left & 1))
                ? og_thinc_left(W[0][OW_Y], W[1][OW_Y], W[2][OW_Y], s->beta, s->thinc_gamma)
                : YL;
+      if (three)
+        Y2f = (s->thinc && (s_left & 2))
+                  ? og_thinc_left(W[0][OW_Y2], W[1][OW_Y2], W[2][OW_Y2], s->beta, s->thinc_gamma)
+                  : Y2L;
     } else {
       for (int d = 0; d < dim; ++d) uf[d] = uR[d];
       Tf = TR;
-      Yf = (s->thinc && s_right)
+      Yf = (s->thinc && (s_right & 1))
                ? og_thinc_right(W[1][OW_Y], W[2][OW_Y], W[3][OW_Y], s->beta, s->thinc_gamma)
                : YR;
+      if (three)
+        Y2f = (s->thinc && (s_right & 2))
+                  ? og_thinc_right(W[1][OW_Y2], W[2][OW_Y2], W[3][OW_Y2], s->beta, s->thinc_gamma)
+                  : Y2R;
     }
   } else {
     for (int d = 0; d < dim; ++d)
@@ -136,10 +149,19 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
     us = uf[dir] + s->kappa3 * d3p / (IL + IR);
     Tf = 0.5 * (W[1][OW_T] + W[2][OW_T]);
     Yf = 0.5 * (W[1][OW_Y] + W[2][OW_Y]);
+    if (three) Y2f = 0.5 * (W[1][OW_Y2] + W[2][OW_Y2]);
   }
 
+  /* the two gas fractions are reconstructed independently; a face state
+   * whose gas fractions sum above one (a negative liquid fraction, which
+   * would move liquid mass into pure-gas cells) is rescaled to sum to one */
+  if (three && Yf + Y2f > 1.0) {
+    double sum = Yf + Y2f;
+    Yf /= sum;
+    Y2f /= sum;
+  }
   double rf, ef;
-  if (og_eos_forward(e, ps, Tf, Yf, &rf, &ef)) return -1;
+  if (og_eos_forward2(e, ps, Tf, Yf, Y2f, &rf, &ef)) return -1;
   double m = rf * us;
   double ke = 0.0;
   for (int d = 0; d < dim; ++d) ke += uf[d] * uf[d];
@@ -147,6 +169,7 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
   for (int d = 0; d < dim; ++d) F[1 + d] = m * uf[d] + (d == dir ? ps : 0.0);
   F[1 + dim] = m * (ef + 0.5 * ke) + ps * us;
   F[2 + dim] = m * Yf;
+  if (three) F[3 + dim] = m * Y2f;
   if (ustar) *ustar = us;
   if (pstar) *pstar = ps;
   return 0;

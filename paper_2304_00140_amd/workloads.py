@@ -54,8 +54,10 @@ def pr_mixture(species, X, cv, q=0.0, mu=0.0, kc=0.0):
                 kij=[[0.0] * len(sp) for _ in sp], mu=mu, kc=kc)
 
 
-def make_eos(c0, c1):
-    comps = [c0, c1]
+def make_eos(c0, c1, c2=None):
+    """closure of two components, or of three (liquid c0 and two ideal gases
+    c1, c2 whose mass fractions are both transported)"""
+    comps = [c0, c1] if c2 is None else [c0, c1, c2]
     return dict(kind=[c["kind"] for c in comps], gamma=[c["gamma"] for c in comps],
                 pinf=[c["pinf"] for c in comps], cv=[c["cv"] for c in comps],
                 q=[c["q"] for c in comps], pr=[c if c["kind"] == EOS_PR else None for c in comps],
@@ -268,9 +270,11 @@ def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, 
 # ------------------------------------------------------- test-state generators
 
 def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.0,
-                 bc=None, sigma=0.0, switching=0, gas="sg"):
+                 bc=None, sigma=0.0, switching=0, gas="sg", second_gas=False):
     """Seeded smooth random fields with a wavy interface: used for one-RHS and
-    few-step comparisons.  Periodic by default."""
+    few-step comparisons.  Periodic by default.  second_gas=True makes a
+    three-component case: the gas side is shared between an air-like and a
+    helium-like ideal gas by a smooth random split."""
     rng = np.random.default_rng(seed)
     n3 = list(n) + [1] * (3 - len(n))
     if bc is None:
@@ -312,7 +316,13 @@ def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.
         alpha = np.clip(alpha + rng.uniform(-1, 1, size=alpha.shape) * 1e-3 * alpha * (1 - alpha), 0, 1)
     else:
         alpha = 0.5 + smooth(0.3)
-    prim = pack_prim(p, T, alpha, u)
-    return dict(name=f"random_{dim}d_{seed}", grid=g, eos=make_eos(c0, c1),
+    if second_gas:
+        share = 0.5 + 0.45 * np.tanh(3.0 * smooth(1.0))
+        prim = pack_prim(p, T, alpha * share, list(u) + [alpha * (1.0 - share)])
+        eos = make_eos(c0, c1, sg(1.67, 0.0, 3110.0))
+    else:
+        prim = pack_prim(p, T, alpha, u)
+        eos = make_eos(c0, c1)
+    return dict(name=f"random_{dim}d_{seed}", grid=g, eos=eos,
                 scheme=default_scheme(sigma=sigma, switching=switching), prim=prim, steps=None,
                 t_end=0.0, storage=dict(p_ref=p0, T_ref=T0))

@@ -131,7 +131,7 @@ def face(W4, f=1, sl=0, sr=0, dim=2, d=0, scheme=None):
     e = make_eos(EOSD)
     s = make_scheme(scheme or W.default_scheme())
     arr = np.ascontiguousarray(W4, dtype=np.float64)
-    F = np.zeros(6)
+    F = np.zeros(7)
     us, ps = C.c_double(), C.c_double()
     rc = L().og_face_flux(C.byref(e), C.byref(s), dim, d, arr.ctypes.data_as(C.POINTER(C.c_double)),
                           f, sl, sr, F.ctypes.data_as(C.POINTER(C.c_double)), C.byref(us), C.byref(ps))
@@ -144,7 +144,7 @@ def prim_row(e, p, T, Y, u):
     L().og_eos_forward(C.byref(e), p, T, Y, C.byref(r), C.byref(en))
     c = L().og_mix_sound(C.byref(e), p, T, Y)
     v_g = L().og_spec_volume(C.byref(e), 1, p, T)
-    return [r.value, u[0], u[1], u[2], p, T, Y, c, Y * r.value * v_g], en.value
+    return [r.value, u[0], u[1], u[2], p, T, Y, c, Y * r.value * v_g, 0.0, 0.0], en.value
 
 
 @pytest.mark.parametrize("f", [1, 0])

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FVM_VERSION 1
+#define FVM_VERSION 2
 
 enum {
   FVM_OK = 0,
@@ -98,17 +98,26 @@ typedef struct fvm_grid_desc {
  * component for the stress part of the flux of eq. (2-2); a cell mixes them by
  * its gas volume fraction, (1 - alpha_G) value_0 + alpha_G value_1 (eq. 2-8
  * with one gas and no vapour).  All zero: inviscid and adiabatic (the stress
- * terms are skipped).  Negative or non-finite values are FVM_EINVAL. */
+ * terms are skipped).  Negative or non-finite values are FVM_EINVAL.
+ * ncomp: 2 (0 means 2) or 3.  With three components (Table A.1, eqs.
+ * A.1.2-A.1.5: a liquid and two gases, the second gas species of eq. 2-1)
+ * every component is a stiffened gas and components 1 and 2 are ideal gases
+ * (pinf = 0); the state gains rho xi_2 (N_q = D + 4: rho, rho u, rho E,
+ * rho xi_1, rho xi_2), the primitive input gains alpha_2 after u, the
+ * primitive output gains xi_2 and alpha_2 (11 rows), and the mixing above is
+ * (1 - alpha_1 - alpha_2) value_0 + alpha_1 value_1 + alpha_2 value_2.  Three
+ * components are supported in 1D and 2D (FVM_EINVAL in 3D). */
 typedef struct fvm_eos_desc {
-  int kind[2];
-  double gamma[2], pinf[2], cv[2], q[2];
+  int kind[3];
+  double gamma[3], pinf[3], cv[3], q[3];
   int pr_ns[2];
   double pr_X[2][FVM_MAXSPEC], pr_Tc[2][FVM_MAXSPEC], pr_pc[2][FVM_MAXSPEC];
   double pr_omega[2][FVM_MAXSPEC], pr_M[2][FVM_MAXSPEC];
   double pr_Zc[2][FVM_MAXSPEC], pr_vc[2][FVM_MAXSPEC];
   double pr_kij[2][FVM_MAXSPEC][FVM_MAXSPEC];
   double p_ref, T_ref;
-  double mu[2], kc[2];
+  double mu[3], kc[3];
+  int ncomp;
 } fvm_eos_desc;
 
 /* Scheme parameters (Section 3.3, Appendix D; defaults in brackets):
@@ -148,7 +157,8 @@ int fvm_create(fvm_ctx** out, const fvm_grid_desc* g, const fvm_eos_desc* e,
 void fvm_destroy(fvm_ctx* ctx);
 
 /* Set the state from primitives on the host: prim[(3 + D) x ncell] =
- * (p, T, alpha_G, u_1..u_D); xi follows from alpha_G at the cell's (p, T).
+ * (p, T, alpha_G, u_1..u_D) (three components: [(4 + D) x ncell], alpha_2
+ * last); xi follows from alpha_G at the cell's (p, T).
  * Resets t and the step counter to 0.  FVM_ENONPHYS if a cell has no state. */
 int fvm_init_primitive(fvm_ctx* ctx, const double* prim_host);
 /* Set / read the conserved state (host or device arrays, [N_q x ncell] FP64).
@@ -158,7 +168,8 @@ int fvm_set_state_device(fvm_ctx* ctx, const double* q_dev);
 int fvm_get_state(fvm_ctx* ctx, double* q_host);
 int fvm_get_state_device(fvm_ctx* ctx, double* q_dev);
 /* Primitives of the current state [9 x ncell] FP64 on the host:
- * rho, u_1, u_2, u_3, p, T, xi, c, alpha_G (unused velocity rows are 0). */
+ * rho, u_1, u_2, u_3, p, T, xi, c, alpha_G (unused velocity rows are 0);
+ * three components: [11 x ncell], with xi_2 and alpha_2 appended. */
 int fvm_get_primitive(fvm_ctx* ctx, double* w_host);
 
 /* One right-hand side R(q) of Algorithm 1 without time update:

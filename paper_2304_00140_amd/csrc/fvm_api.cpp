@@ -18,7 +18,7 @@ using fvm::Comp;
 using fvm::SchemeC;
 
 struct fvm_batch {
-  int ncases = 0, dim = 0, mixed = 0, prk = 0, nq = 0;
+  int ncases = 0, dim = 0, mixed = 0, kind = FVM_KIND_SG, nq = 0, ncomp = 2;
   hipStream_t st = nullptr;
   std::vector<CaseC> hc;
   std::vector<double> vol;
@@ -88,10 +88,20 @@ static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
   return FVM_OK;
 }
 
+static int eos_ncomp(const fvm_eos_desc* e) { return e->ncomp == 3 ? 3 : 2; }
+
 static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
 {
   if (!e) return fail(b, FVM_EINVAL, "eos descriptor is NULL");
-  for (int k = 0; k < 2; ++k) {
+  if (e->ncomp != 0 && e->ncomp != 2 && e->ncomp != 3) return fail(b, FVM_EINVAL, "ncomp must be 2 or 3");
+  const int nc = eos_ncomp(e);
+  if (nc == 3) {
+    for (int k = 0; k < 3; ++k)
+      if (e->kind[k] != FVM_EOS_SG) return fail(b, FVM_EINVAL, "three components are all stiffened gases");
+    if (e->pinf[1] != 0.0 || e->pinf[2] != 0.0)
+      return fail(b, FVM_EINVAL, "the gases of a three-component closure are ideal (pinf = 0)");
+  }
+  for (int k = 0; k < nc; ++k) {
     if (e->kind[k] == FVM_EOS_SG) {
       if (!(e->gamma[k] > 1.0) || !(e->cv[k] > 0.0) || !(e->pinf[k] >= 0.0))
         return fail(b, FVM_EINVAL, "stiffened gas needs gamma > 1, cv > 0, pinf >= 0");
@@ -249,7 +259,6 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   b->ncases = ncases;
   b->dim = grids[0].dim;
   b->mixed = precision == FVM_MIXED;
-  b->nq = b->dim + 3;
   b->esz = b->mixed ? sizeof(float) : sizeof(double);
   b->st = (hipStream_t)stream;
   b->hc.resize(ncases);
@@ -261,6 +270,10 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     if ((rc = check_grid(b, g))) return bail(rc);
     if (g->dim != b->dim) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the dimension"));
     if ((rc = check_eos(b, &eos[c]))) return bail(rc);
+    const int nc = eos_ncomp(&eos[c]);
+    if (c == 0) b->ncomp = nc;
+    if (nc != b->ncomp) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the number of components"));
+    if (nc == 3 && g->dim == 3) return bail(fail(b, FVM_EINVAL, "three components are supported in 1D and 2D"));
     CaseC& C = b->hc[c];
     std::memset(&C, 0, sizeof C);
     C.dim = g->dim;
@@ -286,13 +299,17 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     C.any_ff = 0;
     for (int d = 0; d < g->dim; ++d)
       for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
-    fill_comp(C.comp[0], &eos[c], 0);
-    fill_comp(C.comp[1], &eos[c], 1);
-    C.diff = (eos[c].mu[0] > 0.0 || eos[c].mu[1] > 0.0 || eos[c].kc[0] > 0.0 || eos[c].kc[1] > 0.0) ? 1 : 0;
+    C.ncomp = nc;
+    for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], &eos[c], k);
+    C.diff = 0;
+    for (int k = 0; k < nc; ++k)
+      if (eos[c].mu[k] > 0.0 || eos[c].kc[k] > 0.0) C.diff = 1;
     C.sdx2 = 0.0;
     for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
-    if (C.comp[1].kind == FVM_EOS_PR) b->prk = 1;
+    if (C.comp[1].kind == FVM_EOS_PR) b->kind = FVM_KIND_PR;
   }
+  if (b->ncomp == 3) b->kind = FVM_KIND_THREE;
+  b->nq = b->dim + b->ncomp + 1;
   b->total = off;
   // scheme constants
   SchemeC& S = b->sc;
@@ -317,7 +334,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
 
   // storage shifts: rho_k(p_ref, T_ref) and e_k(p_ref, T_ref), evaluated by the device closure
   {
-    std::vector<double> pT(2 * ncases), sh(4 * ncases);
+    std::vector<double> pT(2 * ncases), sh(6 * ncases);
     bool any = false;
     for (int c = 0; c < ncases; ++c) {
       pT[2 * c] = eos[c].p_ref;
@@ -325,12 +342,12 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       any = any || (eos[c].T_ref > 0.0);
     }
     if (any && b->mixed) {
-      if ((rc = ensure_scratch(b, sizeof(double) * 6 * ncases))) return bail(rc);
+      if ((rc = ensure_scratch(b, sizeof(double) * 8 * ncases))) return bail(rc);
       double* dpT = (double*)b->scratch;
       double* dsh = dpT + 2 * ncases;
       HIPCHECK(b, hipMemcpy(dpT, pT.data(), sizeof(double) * 2 * ncases, hipMemcpyHostToDevice));
       HIPCHECK(b, fvm_k_ref_shift(b->dc, ncases, dsh, dpT, nullptr));
-      HIPCHECK(b, hipMemcpy(sh.data(), dsh, sizeof(double) * 4 * ncases, hipMemcpyDeviceToHost));
+      HIPCHECK(b, hipMemcpy(sh.data(), dsh, sizeof(double) * 6 * ncases, hipMemcpyDeviceToHost));
     }
     for (int c = 0; c < ncases; ++c) {
       CaseC& C = b->hc[c];
@@ -339,12 +356,13 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       // pressure) and the energy of both components.  Gases keep their
       // partial density unshifted so that trace amounts keep full relative
       // precision.
-      bool on = b->mixed && eos[c].T_ref > 0.0 && std::isfinite(sh[4 * c]) && std::isfinite(sh[4 * c + 1]) &&
-                std::isfinite(sh[4 * c + 2]) && std::isfinite(sh[4 * c + 3]);
-      for (int k = 0; k < 2; ++k) {
+      const int nc = b->ncomp;
+      bool on = b->mixed && eos[c].T_ref > 0.0;
+      for (int k = 0; k < nc; ++k) on = on && std::isfinite(sh[6 * c + k]) && std::isfinite(sh[6 * c + 3 + k]);
+      for (int k = 0; k < nc; ++k) {
         bool stiff = eos[c].kind[k] == FVM_EOS_SG && eos[c].pinf[k] > 0.0;
-        double rref = (on && stiff) ? sh[4 * c + k] : 0.0;
-        double qs = on ? eos[c].q[k] - sh[4 * c + 2 + k] : eos[c].q[k];
+        double rref = (on && stiff) ? sh[6 * c + k] : 0.0;
+        double qs = on ? eos[c].q[k] - sh[6 * c + 3 + k] : eos[c].q[k];
         if (b->mixed) { rref = (double)(float)rref; qs = (double)(float)qs; }
         C.rref[k] = rref;
         C.comp[k].qs = qs;
@@ -401,7 +419,7 @@ static hipError_t launch_stages(fvm_batch* b, int off, double t_end, hipEvent_t*
     a.ak = b->rk[k];
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[2 * k], b->st)) != hipSuccess) return e;
-    e = fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st);
+    e = fvm_k_stage(b->dim, b->mixed, b->kind, b->tile, a, b->ntiles, b->st);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2 * k + 1], b->st)) != hipSuccess) return e;
   }
@@ -446,7 +464,7 @@ static hipError_t end_check(fvm_batch* b)
 {
   if (b->dim != 3) return hipSuccess;
   for (int c = 0; c < b->ncases; ++c) {
-    hipError_t e = fvm_k_dt_init(b->dim, b->mixed, b->prk, b->dc, b->dd, c, b->hc[c].ncell, b->q[0], b->total, -1,
+    hipError_t e = fvm_k_dt_init(b->dim, b->mixed, b->kind, b->dc, b->dd, c, b->hc[c].ncell, b->q[0], b->total, -1,
                                  b->st);
     if (e != hipSuccess) return e;
   }
@@ -485,7 +503,7 @@ static int run_steps(fvm_batch* b, int n, double t_end)
 static int set_from_device_cons(fvm_batch* b, int c, const double* qdev)
 {
   const CaseC& C = b->hc[c];
-  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->dc, c, C.ncell, qdev, b->q[0], b->total, b->st));
+  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->kind, b->dc, c, C.ncell, qdev, b->q[0], b->total, b->st));
   return FVM_OK;
 }
 
@@ -495,7 +513,7 @@ static int finish_set(fvm_batch* b, int c)
   CaseDyn z;
   std::memset(&z, 0, sizeof z);
   HIPCHECK(b, hipMemcpyAsync(b->dd + c, &z, sizeof z, hipMemcpyHostToDevice, b->st));
-  HIPCHECK(b, fvm_k_dt_init(b->dim, b->mixed, b->prk, b->dc, b->dd, c, C.ncell, b->q[0], b->total, 0, b->st));
+  HIPCHECK(b, fvm_k_dt_init(b->dim, b->mixed, b->kind, b->dc, b->dd, c, C.ncell, b->q[0], b->total, 0, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
   b->has_state[c] = 1;
   int rc = check_errors(b);
@@ -507,11 +525,11 @@ static int batch_init_primitive(fvm_batch* b, int c, const double* prim)
 {
   if (c < 0 || c >= b->ncases || !prim) return fail(b, FVM_EINVAL, "bad case or NULL array");
   const CaseC& C = b->hc[c];
-  size_t bytes = sizeof(double) * (3 + b->dim) * (size_t)C.ncell;
+  size_t bytes = sizeof(double) * (3 + b->dim + (b->ncomp == 3 ? 1 : 0)) * (size_t)C.ncell;
   int rc = ensure_scratch(b, bytes);
   if (rc) return rc;
   HIPCHECK(b, hipMemcpyAsync(b->scratch, prim, bytes, hipMemcpyHostToDevice, b->st));
-  HIPCHECK(b, fvm_k_prim_to_state(b->dim, b->mixed, b->prk, b->dc, c, C.ncell, (const double*)b->scratch,
+  HIPCHECK(b, fvm_k_prim_to_state(b->dim, b->mixed, b->kind, b->dc, c, C.ncell, (const double*)b->scratch,
                                   b->q[0], b->total, b->st));
   return finish_set(b, c);
 }
@@ -545,7 +563,7 @@ static int batch_get_state(fvm_batch* b, int c, double* q, bool device)
     if (rc) return rc;
     qd = (double*)b->scratch;
   }
-  HIPCHECK(b, fvm_k_state_to_cons(b->dim, b->mixed, b->dc, c, C.ncell, b->q[0], qd, b->total, b->st));
+  HIPCHECK(b, fvm_k_state_to_cons(b->dim, b->mixed, b->kind, b->dc, c, C.ncell, b->q[0], qd, b->total, b->st));
   if (!device) HIPCHECK(b, hipMemcpyAsync(q, qd, bytes, hipMemcpyDeviceToHost, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
   return FVM_OK;
@@ -557,7 +575,7 @@ static int batch_totals(fvm_batch* b, int c, double* out)
   if (!b->has_state[c]) return fail(b, FVM_ESTATE, "no state set");
   const CaseC& C = b->hc[c];
   int nblk = (int)std::min<long long>(1024, (C.ncell + 255) / 256);
-  HIPCHECK(b, fvm_k_totals(b->dim, b->mixed, b->dc, c, C.ncell, b->q[0], b->total, b->dpart, nblk, b->vol[c],
+  HIPCHECK(b, fvm_k_totals(b->dim, b->mixed, b->kind, b->dc, c, C.ncell, b->q[0], b->total, b->dpart, nblk, b->vol[c],
                            b->dout, b->st));
   HIPCHECK(b, hipMemcpyAsync(out, b->dout, sizeof(double) * b->nq, hipMemcpyDeviceToHost, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
@@ -661,10 +679,11 @@ int fvm_get_primitive(fvm_ctx* ctx, double* w_host)
   if (!w_host) return fail(b, FVM_EINVAL, "NULL array");
   if (!b->has_state[0]) return fail(b, FVM_ESTATE, "no state set");
   const CaseC& C = b->hc[0];
-  size_t bytes = sizeof(double) * 9 * (size_t)C.ncell;
+  size_t rows = b->ncomp == 3 ? 11 : 9;
+  size_t bytes = sizeof(double) * rows * (size_t)C.ncell;
   int rc = ensure_scratch(b, bytes);
   if (rc) return rc;
-  HIPCHECK(b, fvm_k_state_to_prim(b->dim, b->mixed, b->prk, b->dc, 0, C.ncell, b->q[0], (double*)b->scratch,
+  HIPCHECK(b, fvm_k_state_to_prim(b->dim, b->mixed, b->kind, b->dc, 0, C.ncell, b->q[0], (double*)b->scratch,
                                   b->total, b->st));
   HIPCHECK(b, hipMemcpyAsync(w_host, b->scratch, bytes, hipMemcpyDeviceToHost, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
@@ -678,7 +697,7 @@ int fvm_rhs(fvm_ctx* ctx, const double* q_dev_in, double* r_dev_out, int64_t ste
   if (!q_dev_in || !r_dev_out) return fail(b, FVM_EINVAL, "NULL device array");
   const CaseC& C = b->hc[0];
   // the input goes to the first stage buffer; the case's own state q^n is untouched
-  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->dc, 0, C.ncell, q_dev_in, b->q[1], b->total, b->st));
+  HIPCHECK(b, fvm_k_cons_to_state(b->dim, b->mixed, b->kind, b->dc, 0, C.ncell, q_dev_in, b->q[1], b->total, b->st));
   StageArgs a = stage_args(b);
   a.src = b->q[1];
   a.qn = b->q[1];
@@ -686,7 +705,7 @@ int fvm_rhs(fvm_ctx* ctx, const double* q_dev_in, double* r_dev_out, int64_t ste
   a.stage = -1;
   a.rhs_out = r_dev_out;
   a.rhs_step = step;
-  HIPCHECK(b, fvm_k_stage(b->dim, b->mixed, b->prk, b->tile, a, b->ntiles, b->st));
+  HIPCHECK(b, fvm_k_stage(b->dim, b->mixed, b->kind, b->tile, a, b->ntiles, b->st));
   HIPCHECK(b, hipStreamSynchronize(b->st));
   return FVM_OK;
 }

@@ -55,9 +55,10 @@ struct CaseC {
   unsigned long long in_seed;
   double ff_p, ff_T, ff_alpha;   // far-field reservoir state (at rest)
   int any_ff;                    // some side is a far-field reservoir
-  Comp comp[2];
-  double rref[2];      // partial-density shifts (FP32-exact for FP32 storage)
-  double Q[2];         // energy gauge: E' = rho E - sum_k rho_k Q_k
+  Comp comp[3];        // component 2: second gas (three-component closure only)
+  int ncomp;           // 2 or 3
+  double rref[3];      // partial-density shifts (FP32-exact for FP32 storage)
+  double Q[3];         // energy gauge: E' = rho E - sum_k rho_k Q_k
   int tile0, tiles[3];
   int diff;            // some component is viscous or conducting
   double sdx2;         // sum_d 1 / dx_d^2 over the used directions
@@ -216,7 +217,20 @@ __device__ inline double pr_sound_V(const Comp& c, double V, double T)
 }
 
 // ------------------------------------------------------------------ closure inversion
-struct PT { double p, T, c, alpha; int ok; };
+struct PT { double p, T, c, alpha, alpha2; int ok; };   // alpha2: second gas (0 with two components)
+
+// the larger root of the quadratic below for groups 0 and 1 of stiffened-gas
+// terms (A_k = sum of xi (g-1) cv over the group, sharing p_inf = P_k)
+__device__ inline void sg_quad(double v, double A0, double A1, double Cv, double Cp, double eh, double P0,
+                               double P1, double& p, double& T)
+{
+  double qa = v * Cv;
+  double qb = v * (Cp * (P0 + P1) - A0 * P1 - A1 * P0) - eh * (A0 + A1);
+  double qc = v * Cp * P0 * P1 - eh * (A0 * P1 + A1 * P0);
+  double sq = sqrt(qb * qb - 4.0 * qa * qc);
+  p = (qb < 0.0) ? (-qb + sq) * frcp(2.0 * qa) : 2.0 * qc * frcp(-qb - sq);
+  T = (eh + p * v) * frcp(Cp);
+}
 
 // stiffened-gas pair in p-T equilibrium: T = (eh + p v) / Cp and the larger
 // root of  (v Cv) p^2 + [v (Cp (P0+P1) - A0 P1 - A1 P0) - eh (A0+A1)] p
@@ -230,12 +244,56 @@ __device__ inline void sg_pair(double g0, double P0, double cv0, double q0,
   double Cv = Y0 * cv0 + Y * cv1;
   double Cp = Y0 * g0 * cv0 + Y * g1 * cv1;
   double eh = e - Y0 * q0 - Y * q1;
-  double qa = v * Cv;
-  double qb = v * (Cp * (P0 + P1) - A0 * P1 - A1 * P0) - eh * (A0 + A1);
-  double qc = v * Cp * P0 * P1 - eh * (A0 * P1 + A1 * P0);
-  double sq = sqrt(qb * qb - 4.0 * qa * qc);
-  p = (qb < 0.0) ? (-qb + sq) * frcp(2.0 * qa) : 2.0 * qc * frcp(-qb - sq);
-  T = (eh + p * v) * frcp(Cp);
+  sg_quad(v, A0, A1, Cv, Cp, eh, P0, P1, p, T);
+}
+
+// gas fractions of a three-component cell as the closure takes them: each
+// clipped into [0, 1], rescaled if they sum above one; the liquid the rest
+__device__ inline void clip_fractions3(double Y1, double Y2, double& y0, double& y1, double& y2)
+{
+  double a = (Y1 < 0.0) ? 0.0 : ((Y1 > 1.0) ? 1.0 : Y1);
+  double b = (Y2 < 0.0) ? 0.0 : ((Y2 > 1.0) ? 1.0 : Y2);
+  double s = a + b;
+  if (s > 1.0) { double is = 1.0 / s; a *= is; b *= is; }
+  double l = 1.0 - a - b;
+  y0 = l > 0.0 ? l : 0.0;
+  y1 = a;
+  y2 = b;
+}
+
+// Three stiffened-gas components whose gases (1, 2) are ideal (Table A.1,
+// eqs. A.1.2-A.1.5): the gas terms share p_inf = 0 and add up, so the
+// two-group quadratic holds; c is the largest of the three sound speeds.
+__device__ inline PT closure3(const CaseC& C, double rho, double Y1, double Y2, double e)
+{
+  const Comp& c0 = C.comp[0];
+  const Comp& c1 = C.comp[1];
+  const Comp& c2 = C.comp[2];
+  PT r;
+  r.ok = 1;
+  double y0, y1, y2;
+  clip_fractions3(Y1, Y2, y0, y1, y2);
+  double v = frcp(rho);
+  double p, T;
+  int present = (y0 > 0.0) + (y1 > 0.0) + (y2 > 0.0);
+  if (present == 1) {
+    const Comp& c = (y0 > 0.0) ? c0 : ((y1 > 0.0) ? c1 : c2);
+    p = (c.gamma - 1.0) * rho * (e - c.qs) - c.gamma * c.pinf;
+    T = (e - c.qs - c.pinf * v) / c.cv;
+  } else {
+    double A0 = y0 * (c0.gamma - 1.0) * c0.cv;
+    double A1 = y1 * (c1.gamma - 1.0) * c1.cv + y2 * (c2.gamma - 1.0) * c2.cv;
+    double Cv = y0 * c0.cv + y1 * c1.cv + y2 * c2.cv;
+    double Cp = y0 * c0.gamma * c0.cv + y1 * c1.gamma * c1.cv + y2 * c2.gamma * c2.cv;
+    double eh = e - y0 * c0.qs - y1 * c1.qs - y2 * c2.qs;
+    sg_quad(v, A0, A1, Cv, Cp, eh, c0.pinf, 0.0, p, T);
+  }
+  r.p = p;
+  r.T = T;
+  r.c = sqrt(fmax(fmax(c0.c2T * T, c1.c2T * T), c2.c2T * T));
+  r.alpha = (y1 == 0.0) ? 0.0 : y1 * rho * c1.A * T * frcp(p);
+  r.alpha2 = (y2 == 0.0) ? 0.0 : y2 * rho * c2.A * T * frcp(p);
+  return r;
 }
 
 // (rho, xi, e) -> (p, T), c = max of the components' sound speeds, alpha_G.
@@ -248,6 +306,7 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
   const Comp& c1 = C.comp[1];
   PT r;
   r.ok = 1;
+  r.alpha2 = 0.0;
   // a mass fraction a little outside [0, 1] (the central reconstruction is not
   // bounded) is closed as the nearer pure component; NaN passes through
   Y = (Y < 0.0) ? 0.0 : ((Y > 1.0) ? 1.0 : Y);
@@ -339,6 +398,25 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
   return r;
 }
 
+// forward closure of three stiffened-gas components at (p, T, xi_1, xi_2) in
+// precision R: 1 / rho and e (storage gauge); zero fractions are skipped
+template <class R>
+__device__ inline void tdu3(const CaseC& C, R ps, R Tf, R Y1, R Y2, R& rf, R& ef)
+{
+  R Yk[3] = {R(1) - Y1 - Y2, Y1, Y2};
+  R vs = R(0), es = R(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (Yk[k] == R(0)) continue;
+    const Comp& c = C.comp[k];
+    R vk = R(c.A) * Tf * frcp(ps + R(c.pinf));
+    vs += Yk[k] * vk;
+    es += Yk[k] * (R(c.cv) * Tf + R(c.pinf) * vk + R(c.qs));
+  }
+  rf = frcp(vs);
+  ef = es;
+}
+
 // forward closure at (p, T, xi) in FP64: 1 / rho and e (storage gauge)
 template <bool PRK>
 __device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y, double& vmix, double& e)
@@ -410,8 +488,24 @@ template <class R, int D>
 struct Stencil {
   R u[D][4];
   R p[4], T[4], Y[4];
+  R Y2[4];             // second gas fraction (three components only)
   R rho1, rho2, c1, c2;
 };
+
+// THINC face value of the upwind cell b between neighbours a, c
+// (eqs. 3-3/3-4 with the range denominator): left = value at the cell's
+// right face, else at its left face
+template <class R>
+__device__ inline R thinc_value(const SchemeC& S, bool left, R a, R b, R c)
+{
+  R mn = fmin(a, c), mx = fmax(a, c);
+  R th = (c >= a) ? R(1) : R(-1);
+  R Fv = fdiv(b - mn + R(S.thinc_gamma), mx - mn + R(S.thinc_gamma));
+  R tb = R(S.tanh_b);
+  R E = (fexp(th * R(S.beta) * (R(2) * Fv - R(1))) * R(S.icosh_b) - R(1)) * R(S.itanh_b);
+  R prof = left ? fdiv(tb + E, R(1) + E * tb) : E;
+  return mn + R(0.5) * (mx - mn) * (R(1) + th * prof);
+}
 
 // Thermodynamic dependent update at (p*, T_f, xi_f) in precision R for a
 // stiffened-gas pair: 1 / rho_f and e_f (storage gauge)
@@ -440,9 +534,9 @@ __device__ inline void tdu_sg(const CaseC& C, R ps, R Tf, R Yf, R& rf, R& ef)
 //   u* = u_C + k3 (p_{i+2} - 3 p_{i+1} + 3 p_i - p_{i-1}) / (I_L + I_R);
 //  TDU: rho_f, e_f from the closure at (p*, T_f, xi_f);
 //  flux (storage variables): (m xi_L, m xi_G, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*).
-template <class R, int D, int DIR, bool PRK>
+template <class R, int D, int DIR, bool PRK, bool G2 = false>
 __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil<R, D>& s,
-                                 bool disc, bool sl, bool sr, R* F)
+                                 bool disc, bool sl, bool sr, R* F, bool sl2 = false, bool sr2 = false)
 {
   R cm = fmax(s.c1, s.c2);
   R rsum = s.rho1 + s.rho2;
@@ -450,7 +544,7 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
   R IR = (s.rho1 + R(3) * s.rho2) * cm * R(0.25);
   R iI = frcp(rsum * cm);
   R uf[D];
-  R us, ps, Tf, Yf;
+  R us, ps, Tf, Yf, Y2f = R(0);
   if (disc) {
     R uL[D], uR[D];
 #pragma unroll
@@ -466,17 +560,15 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
     for (int d = 0; d < D; ++d) uf[d] = left ? uL[d] : uR[d];
     Tf = left ? TL : TR;
     Yf = left ? YL : YR;
-    if (S.thinc && (left ? sl : sr)) {
-      R a = left ? s.Y[0] : s.Y[1];
-      R b = left ? s.Y[1] : s.Y[2];
-      R c = left ? s.Y[2] : s.Y[3];
-      R mn = fmin(a, c), mx = fmax(a, c);
-      R th = (c >= a) ? R(1) : R(-1);
-      R Fv = fdiv(b - mn + R(S.thinc_gamma), mx - mn + R(S.thinc_gamma));
-      R tb = R(S.tanh_b);
-      R E = (fexp(th * R(S.beta) * (R(2) * Fv - R(1))) * R(S.icosh_b) - R(1)) * R(S.itanh_b);
-      R prof = left ? fdiv(tb + E, R(1) + E * tb) : E;
-      Yf = mn + R(0.5) * (mx - mn) * (R(1) + th * prof);
+    if (S.thinc && (left ? sl : sr))
+      Yf = thinc_value<R>(S, left, left ? s.Y[0] : s.Y[1], left ? s.Y[1] : s.Y[2], left ? s.Y[2] : s.Y[3]);
+    if constexpr (G2) {
+      R Y2L, Y2R;
+      recon<R>(S.lim_s, s.Y2[0], s.Y2[1], s.Y2[2], s.Y2[3], Y2L, Y2R);
+      Y2f = left ? Y2L : Y2R;
+      if (S.thinc && (left ? sl2 : sr2))
+        Y2f = thinc_value<R>(S, left, left ? s.Y2[0] : s.Y2[1], left ? s.Y2[1] : s.Y2[2],
+                             left ? s.Y2[2] : s.Y2[3]);
     }
   } else {
     const R c12 = R(1.0 / 12.0);
@@ -488,9 +580,20 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
     us = uf[DIR] + R(S.k3) * d3p * iI;
     Tf = R(0.5) * (s.T[1] + s.T[2]);
     Yf = R(0.5) * (s.Y[1] + s.Y[2]);
+    if constexpr (G2) Y2f = R(0.5) * (s.Y2[1] + s.Y2[2]);
   }
   R rf, ef;
-  if (!PRK || C.comp[1].kind == 0 || Yf == R(0)) {
+  if constexpr (G2) {
+    // independently reconstructed gas fractions summing above one are
+    // rescaled (no liquid mass may leave through a pure-gas face)
+    R sum = Yf + Y2f;
+    if (sum > R(1)) {
+      R is = frcp(sum);
+      Yf *= is;
+      Y2f *= is;
+    }
+    tdu3<R>(C, ps, Tf, Yf, Y2f, rf, ef);
+  } else if (!PRK || C.comp[1].kind == 0 || Yf == R(0)) {
     tdu_sg<R>(C, ps, Tf, Yf, rf, ef);
   } else {
     double vm, em;
@@ -502,11 +605,12 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
   R ke = R(0);
 #pragma unroll
   for (int d = 0; d < D; ++d) ke += uf[d] * uf[d];
-  F[0] = m * (R(1) - Yf);
+  F[0] = m * (R(1) - Yf - Y2f);
   F[1] = m * Yf;
 #pragma unroll
   for (int d = 0; d < D; ++d) F[2 + d] = m * uf[d] + (d == DIR ? ps : R(0));
   F[2 + D] = m * (ef + R(0.5) * ke) + ps * us;
+  if constexpr (G2) F[3 + D] = m * Y2f;
 }
 
 }  // namespace fvm

@@ -23,13 +23,13 @@ namespace fvm {
 // Tile TX x TY cells, NT threads (NT may exceed TX*TY: then several threads
 // share the halo and face work of fewer cells).  MINW: waves per SIMD the
 // register budget is held to.
-template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK>
+template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK, bool G2>
 __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
 {
   static_assert(D == 1 || D == 2, "1D/2D kernel");
   static_assert(D == 2 || TY == 1, "1D tiles are one row");
   constexpr int HX = TX + 4, HY = (D == 2) ? TY + 4 : 1, NH = HX * HY;
-  constexpr int NQ = D + 3;
+  constexpr int NQ = D + 3 + (G2 ? 1 : 0);   // G2: second gas, its partial density last
   constexpr int NC = TX * TY;
   constexpr int CPT = (NC + NT - 1) / NT;
   constexpr int NIT = (NH + NT - 1) / NT;
@@ -41,6 +41,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
   static_assert(FX * FY + D * VX * VY <= NQ * NF, "CSF scratch fits in the flux buffer");
 
   __shared__ S s_rho[NH], s_u[NH], s_v[D == 2 ? NH : 1], s_p[NH], s_T[NH], s_Y[NH], s_c[NH], s_a[NH];
+  __shared__ S s_Y2[G2 ? NH : 1], s_a2[G2 ? NH : 1];
   __shared__ unsigned char s_fl[NH];
   __shared__ S s_F[NQ][NF];
   __shared__ double s_red[NT / 64];
@@ -78,15 +79,15 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       int h = tid + it * NT;
       if (h < NH) {
         int hx = h % HX, hy = h / HX;
-        load_cell<S, D, PRK>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
+        load_cell<S, D, PRK, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
       }
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       int h = tid + it * NT;
       if (h < NH) {
-        double u[D], rho, Y;
-        PT pt = cell_prim<D, PRK>(C, qv[it], u, rho, Y);
+        double u[D], rho, Y, Y2;
+        PT pt = cell_prim_any<D, PRK, G2>(C, qv[it], u, rho, Y, Y2);
         s_rho[h] = S(rho);
         s_u[h] = S(u[0]);
         if (D == 2) s_v[h] = S(u[D - 1]);
@@ -95,10 +96,23 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         s_Y[h] = S(Y);
         s_c[h] = S(pt.c);
         s_a[h] = S(pt.alpha);
+        if constexpr (G2) {
+          s_Y2[h] = S(Y2);
+          s_a2[h] = S(pt.alpha2);
+        }
       }
     }
   }
   __syncthreads();
+  // total gas volume fraction and mass fraction of a staged cell
+  auto aG = [&](int c) -> S {
+    if constexpr (G2) return s_a[c] + s_a2[c];
+    else return s_a[c];
+  };
+  auto YG = [&](int c) -> S {
+    if constexpr (G2) return s_Y[c] + s_Y2[c];
+    else return s_Y[c];
+  };
 
   // ---- switching sensors (Appendix D) on tile + one halo layer
   if (SC.switching) {
@@ -108,7 +122,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       S idx2 = S(0.5 * C.idx[0]);
       S dudx = (s_u[c + 1] - s_u[c - 1]) * idx2;
       S div = dudx, curl2 = S(0);
-      S thg = fabs(s_a[c] - s_a[c - 1]) + fabs(s_a[c + 1] - s_a[c]);
+      S thg = fabs(aG(c) - aG(c - 1)) + fabs(aG(c + 1) - aG(c));
       if (D == 2) {
         S idy2 = S(0.5 * C.idx[1]);
         S dvdy = (s_v[c + HX] - s_v[c - HX]) * idy2;
@@ -117,7 +131,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         div += dvdy;
         S w = dvdx - dudy;
         curl2 = w * w;
-        thg += fabs(s_a[c] - s_a[c - HX]) + fabs(s_a[c + HX] - s_a[c]);
+        thg += fabs(aG(c) - aG(c - HX)) + fabs(aG(c + HX) - aG(c));
       }
       S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
       s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
@@ -150,14 +164,20 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       st.p[m] = s_p[c - 1 + m];
       st.T[m] = s_T[c - 1 + m];
       st.Y[m] = s_Y[c - 1 + m];
+      if constexpr (G2) st.Y2[m] = s_Y2[c - 1 + m];
     }
     st.rho1 = s_rho[c]; st.rho2 = s_rho[c + 1];
     st.c1 = s_c[c]; st.c2 = s_c[c + 1];
     bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
     S F[NQ];
-    face_flux<S, D, 0, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
-                            eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
-    if (C.diff) visc_flux<S, D, 0>(C, U, s_T, s_a, c, stv, F);
+    bool sl2 = false, sr2 = false;
+    if constexpr (G2) {
+      sl2 = eligible(st.Y2[0], st.Y2[1], st.Y2[2], eps);
+      sr2 = eligible(st.Y2[1], st.Y2[2], st.Y2[3], eps);
+    }
+    face_flux<S, D, 0, PRK, G2>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                                eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
+    if (C.diff) visc_flux<S, D, 0, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
   };
@@ -189,14 +209,20 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         st.p[m] = s_p[cm];
         st.T[m] = s_T[cm];
         st.Y[m] = s_Y[cm];
+        if constexpr (G2) st.Y2[m] = s_Y2[cm];
       }
       st.rho1 = s_rho[c]; st.rho2 = s_rho[c + HX];
       st.c1 = s_c[c]; st.c2 = s_c[c + HX];
       bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
       S F[NQ];
-      face_flux<S, D, D - 1, PRK>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
-                                  eligible(st.Y[1], st.Y[2], st.Y[3], eps), F);
-      if (C.diff) visc_flux<S, D, D - 1>(C, U, s_T, s_a, c, stv, F);
+      bool sl2 = false, sr2 = false;
+      if constexpr (G2) {
+        sl2 = eligible(st.Y2[0], st.Y2[1], st.Y2[2], eps);
+        sr2 = eligible(st.Y2[1], st.Y2[2], st.Y2[3], eps);
+      }
+      face_flux<S, D, D - 1, PRK, G2>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                                      eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
+      if (C.diff) visc_flux<S, D, D - 1, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     };
@@ -225,11 +251,11 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
       S acc;
       if (D == 1) {
-        acc = (s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1]) * S(0.25);
+        acc = (YG(c - 1) + S(2) * YG(c) + YG(c + 1)) * S(0.25);
       } else {
-        S r0 = s_Y[c - HX - 1] + S(2) * s_Y[c - HX] + s_Y[c - HX + 1];
-        S r1 = s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1];
-        S r2 = s_Y[c + HX - 1] + S(2) * s_Y[c + HX] + s_Y[c + HX + 1];
+        S r0 = YG(c - HX - 1) + S(2) * YG(c - HX) + YG(c - HX + 1);
+        S r1 = YG(c - 1) + S(2) * YG(c) + YG(c + 1);
+        S r2 = YG(c + HX - 1) + S(2) * YG(c + HX) + YG(c + HX + 1);
         acc = (r0 + S(2) * r1 + r2) * S(1.0 / 16.0);
       }
       s_H[h] = acc;
@@ -261,14 +287,14 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         S kap, Sx, Sy = S(0);
         if (D == 1) {
           kap = -(s_nx[i + 1] - s_nx[i]) * S(C.idx[0]);
-          Sx = sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
+          Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
         } else {
           int v = (j + 1) * VX + (i + 1);   // vertex (i, j) = upper corner of cell (i, j)
           S dnx = s_nx[v] + s_nx[v - VX] - s_nx[v - 1] - s_nx[v - VX - 1];
           S dny = s_ny[v] + s_ny[v - 1] - s_ny[v - VX] - s_ny[v - VX - 1];
           kap = -(dnx * S(0.5 * C.idx[0]) + dny * S(0.5 * C.idx[1]));
-          Sx = sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
-          Sy = sig * kap * (s_a[c + HX] - s_a[c - HX]) * S(0.5 * C.idx[1]);
+          Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
+          Sy = sig * kap * (aG(c + HX) - aG(c - HX)) * S(0.5 * C.idx[1]);
         }
         R[k][2] += Sx;
         S se = s_u[c] * Sx;
@@ -310,11 +336,14 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         const long long RS = C.ncell;
         long long cell = gx + (long long)C.n[0] * gy;
         double r0 = (double)R[k][0], r1 = (double)R[k][1];
-        a.rhs_out[cell] = r0 + r1;
+        double r2 = G2 ? (double)R[k][NQ - 1] : 0.0;
+        a.rhs_out[cell] = G2 ? r0 + r1 + r2 : r0 + r1;
 #pragma unroll
         for (int d = 0; d < D; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
-        a.rhs_out[(1 + D) * RS + cell] = (double)R[k][2 + D] + C.Q[0] * r0 + C.Q[1] * r1;
+        double rE = (double)R[k][2 + D] + C.Q[0] * r0 + C.Q[1] * r1;
+        a.rhs_out[(1 + D) * RS + cell] = G2 ? rE + C.Q[2] * r2 : rE;
         a.rhs_out[(2 + D) * RS + cell] = r1;
+        if constexpr (G2) a.rhs_out[(3 + D) * RS + cell] = r2;
       }
     }
     return;
@@ -338,13 +367,14 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         dst[v * T + cell] = nv[v];
       }
       if (a.stage == 3) {
-        double q[NQ], u[D], rho, Y;
+        double q[NQ], u[D], rho, Y, Y2;
         q[0] = (double)nv[0] + C.rref[0];
         q[1] = (double)nv[1] + C.rref[1];
 #pragma unroll
         for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
-        PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
-        double l = cfl_rate<D>(C, u, pt, rho, Y);
+        if constexpr (G2) q[NQ - 1] += C.rref[2];
+        PT pt = cell_prim_any<D, PRK, G2>(C, q, u, rho, Y, Y2);
+        double l = cfl_rate<D, G2>(C, u, pt, rho, Y, Y2);
         bool finite = isfinite(l) && isfinite(pt.p);
         if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
         else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
@@ -372,23 +402,29 @@ __global__ void k_advance(CaseDyn* dyn, int ncases, int nsteps)
 }
 
 // ------------------------------------------------------------------ per-cell kernels of one case
-template <class S, int D, bool PRK>
+// G2: three components; the second gas's partial density is the last storage
+// field, the last conserved field is rho xi_2 and alpha_2 follows u in the
+// primitive input
+template <class S, int D, bool PRK, bool G2>
 __global__ void k_prim_to_state(const CaseC* cases, int icase, const double* __restrict__ prim,
                                 S* __restrict__ dst, long long total)
 {
+  constexpr int NQ = D + 3 + (G2 ? 1 : 0);
   const CaseC& C = cases[icase];
   long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (c >= C.ncell) return;
-  double u[3] = {0, 0, 0}, q[D + 3];
+  double u[3] = {0, 0, 0}, q[NQ];
   for (int d = 0; d < D; ++d) u[d] = prim[(3 + d) * C.ncell + c];
-  state_from_prim<PRK>(C, prim[c], prim[C.ncell + c], prim[2 * C.ncell + c], u, D, q);
+  double al2 = G2 ? prim[(3 + D) * C.ncell + c] : 0.0;
+  state_from_prim<PRK, G2>(C, prim[c], prim[C.ncell + c], prim[2 * C.ncell + c], u, D, q, al2);
   long long g = C.off + c;
   dst[g] = S(q[0] - C.rref[0]);
   dst[total + g] = S(q[1] - C.rref[1]);
   for (int v = 2; v < D + 3; ++v) dst[v * total + g] = S(q[v]);
+  if constexpr (G2) dst[(NQ - 1) * total + g] = S(q[NQ - 1] - C.rref[2]);
 }
 
-template <class S, int D>
+template <class S, int D, bool G2>
 __global__ void k_cons_to_state(const CaseC* cases, int icase, const double* __restrict__ qin,
                                 S* __restrict__ dst, long long total)
 {
@@ -397,14 +433,21 @@ __global__ void k_cons_to_state(const CaseC* cases, int icase, const double* __r
   if (c >= C.ncell) return;
   long long n = C.ncell, g = C.off + c;
   double rho = qin[c], rY = qin[(2 + D) * n + c];
-  double rL = rho - rY, rG = rY;
+  double rY2 = G2 ? qin[(3 + D) * n + c] : 0.0;
+  double rL = G2 ? rho - rY - rY2 : rho - rY, rG = rY;
   dst[g] = S(rL - C.rref[0]);
   dst[total + g] = S(rG - C.rref[1]);
   for (int d = 0; d < D; ++d) dst[(2 + d) * total + g] = S(qin[(1 + d) * n + c]);
-  dst[(2 + D) * total + g] = S(qin[(1 + D) * n + c] - C.Q[0] * rL - C.Q[1] * rG);
+  double E = qin[(1 + D) * n + c] - C.Q[0] * rL - C.Q[1] * rG;
+  if constexpr (G2) {
+    dst[(2 + D) * total + g] = S(E - C.Q[2] * rY2);
+    dst[(3 + D) * total + g] = S(rY2 - C.rref[2]);
+  } else {
+    dst[(2 + D) * total + g] = S(E);
+  }
 }
 
-template <class S, int D>
+template <class S, int D, bool G2>
 __global__ void k_state_to_cons(const CaseC* cases, int icase, const S* __restrict__ src,
                                 double* __restrict__ qout, long long total)
 {
@@ -413,25 +456,39 @@ __global__ void k_state_to_cons(const CaseC* cases, int icase, const S* __restri
   if (c >= C.ncell) return;
   long long n = C.ncell, g = C.off + c;
   double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g] + C.rref[1];
-  qout[c] = rL + rG;
+  double r2 = G2 ? (double)src[(3 + D) * total + g] + C.rref[2] : 0.0;
+  qout[c] = G2 ? rL + rG + r2 : rL + rG;
   for (int d = 0; d < D; ++d) qout[(1 + d) * n + c] = (double)src[(2 + d) * total + g];
-  qout[(1 + D) * n + c] = (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+  double E = (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+  qout[(1 + D) * n + c] = G2 ? E + C.Q[2] * r2 : E;
   qout[(2 + D) * n + c] = rG;
+  if constexpr (G2) qout[(3 + D) * n + c] = r2;
 }
 
-template <class S, int D, bool PRK>
+// load the storage of one interior cell (physical partial densities)
+template <class S, int D, bool G2>
+__device__ inline void load_own(const CaseC& C, const S* __restrict__ src, long long total, long long g,
+                                double* q)
+{
+  q[0] = (double)src[g] + C.rref[0];
+  q[1] = (double)src[total + g] + C.rref[1];
+  for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
+  if constexpr (G2) q[D + 3] = (double)src[(D + 3) * total + g] + C.rref[2];
+}
+
+// primitives rows: rho, u, v, w, p, T, xi_1, c, alpha_1 (+ xi_2, alpha_2 with G2)
+template <class S, int D, bool PRK, bool G2>
 __global__ void k_state_to_prim(const CaseC* cases, int icase, const S* __restrict__ src,
                                 double* __restrict__ w, long long total)
 {
+  constexpr int NQ = D + 3 + (G2 ? 1 : 0);
   const CaseC& C = cases[icase];
   long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (c >= C.ncell) return;
   long long n = C.ncell, g = C.off + c;
-  double q[D + 3], u[D], rho, Y;
-  q[0] = (double)src[g] + C.rref[0];
-  q[1] = (double)src[total + g] + C.rref[1];
-  for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
-  PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
+  double q[NQ], u[D], rho, Y, Y2;
+  load_own<S, D, G2>(C, src, total, g, q);
+  PT pt = cell_prim_any<D, PRK, G2>(C, q, u, rho, Y, Y2);
   w[c] = rho;
   for (int d = 0; d < 3; ++d) w[(1 + d) * n + c] = d < D ? u[d] : 0.0;
   w[4 * n + c] = pt.p;
@@ -439,13 +496,18 @@ __global__ void k_state_to_prim(const CaseC* cases, int icase, const S* __restri
   w[6 * n + c] = Y;
   w[7 * n + c] = pt.c;
   w[8 * n + c] = pt.alpha;
+  if constexpr (G2) {
+    w[9 * n + c] = Y2;
+    w[10 * n + c] = pt.alpha2;
+  }
 }
 
 // CFL bound of the current state of one case into dtmax[step & 1]
-template <class S, int D, bool PRK>
+template <class S, int D, bool PRK, bool G2>
 __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dyn, int icase,
                                                  const S* __restrict__ src, long long total, long long label_off)
 {
+  constexpr int NQ = D + 3 + (G2 ? 1 : 0);
   __shared__ double s_red[4];
   const CaseC& C = cases[icase];
   CaseDyn& dy = dyn[icase];
@@ -453,12 +515,10 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
   double lam = 0.0;
   if (c < C.ncell) {
     long long g = C.off + c;
-    double q[D + 3], u[D], rho, Y;
-    q[0] = (double)src[g] + C.rref[0];
-    q[1] = (double)src[total + g] + C.rref[1];
-    for (int v = 2; v < D + 3; ++v) q[v] = (double)src[v * total + g];
-    PT pt = cell_prim<D, PRK>(C, q, u, rho, Y);
-    double l = cfl_rate<D>(C, u, pt, rho, Y);
+    double q[NQ], u[D], rho, Y, Y2;
+    load_own<S, D, G2>(C, src, total, g, q);
+    PT pt = cell_prim_any<D, PRK, G2>(C, q, u, rho, Y, Y2);
+    double l = cfl_rate<D, G2>(C, u, pt, rho, Y, Y2);
     if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, c, dy.base + label_off);
     else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, c, dy.base + label_off);
     else lam = l;
@@ -473,11 +533,11 @@ __global__ __launch_bounds__(256) void k_dt_init(const CaseC* cases, CaseDyn* dy
 }
 
 // deterministic conserved totals of one case: fixed-shape tree per block, then one block
-template <class S, int D>
+template <class S, int D, bool G2>
 __global__ __launch_bounds__(256) void k_totals_part(const CaseC* cases, int icase, const S* __restrict__ src,
                                                      long long total, double* __restrict__ part)
 {
-  constexpr int NQ = D + 3;
+  constexpr int NQ = D + 3 + (G2 ? 1 : 0);
   __shared__ double s[NQ][256];
   const CaseC& C = cases[icase];
   double acc[NQ];
@@ -485,10 +545,13 @@ __global__ __launch_bounds__(256) void k_totals_part(const CaseC* cases, int ica
   for (long long c = blockIdx.x * 256ll + threadIdx.x; c < C.ncell; c += 256ll * gridDim.x) {
     long long g = C.off + c;
     double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g] + C.rref[1];
-    acc[0] += rL + rG;
+    double r2 = G2 ? (double)src[(3 + D) * total + g] + C.rref[2] : 0.0;
+    acc[0] += G2 ? rL + rG + r2 : rL + rG;
     for (int d = 0; d < D; ++d) acc[1 + d] += (double)src[(2 + d) * total + g];
-    acc[1 + D] += (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+    double E = (double)src[(2 + D) * total + g] + C.Q[0] * rL + C.Q[1] * rG;
+    acc[1 + D] += G2 ? E + C.Q[2] * r2 : E;
     acc[2 + D] += rG;
+    if constexpr (G2) acc[3 + D] += r2;
   }
   for (int v = 0; v < NQ; ++v) s[v][threadIdx.x] = acc[v];
   __syncthreads();
@@ -511,12 +574,12 @@ __global__ void k_totals_final(const double* __restrict__ part, int nblk, int nq
 }
 
 // ------------------------------------------------------------------ host-side launchers
-template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK>
+template <class S, int D, int TX, int TY, int NT, int MINW, bool PRK, bool G2>
 static hipError_t launch12(const StageArgs& a, int ntiles, hipStream_t st)
 {
   // the Peng-Robinson closure needs more registers than the stiffened-gas one
   constexpr int W = PRK ? 1 : MINW;
-  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, W, PRK>), dim3(ntiles), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, W, PRK, G2>), dim3(ntiles), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -548,37 +611,48 @@ int fvm_k_tile_shape(int dim, int t, int* tx, int* ty, int* nt)
   return -1;
 }
 
-template <class S, bool PRK>
+template <class S, bool PRK, bool G2>
 static hipError_t stage12(int dim, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
   if (dim == 1) {
     switch (tile) {
-      case 0: return launch12<S, 1, 256, 1, 256, 4, PRK>(a, ntiles, st);
-      case 1: return launch12<S, 1, 128, 1, 128, 4, PRK>(a, ntiles, st);
-      case 2: return launch12<S, 1, 128, 1, 256, 4, PRK>(a, ntiles, st);
+      case 0: return launch12<S, 1, 256, 1, 256, 4, PRK, G2>(a, ntiles, st);
+      case 1: return launch12<S, 1, 128, 1, 128, 4, PRK, G2>(a, ntiles, st);
+      case 2: return launch12<S, 1, 128, 1, 256, 4, PRK, G2>(a, ntiles, st);
     }
   } else {
     switch (tile) {
-      case 0: return launch12<S, 2, 32, 8, 256, 4, PRK>(a, ntiles, st);
-      case 1: return launch12<S, 2, 16, 8, 256, 4, PRK>(a, ntiles, st);
-      case 2: return launch12<S, 2, 64, 4, 256, 4, PRK>(a, ntiles, st);
-      case 3: return launch12<S, 2, 16, 16, 256, 4, PRK>(a, ntiles, st);
-      case 4: return launch12<S, 2, 32, 16, 256, 2, PRK>(a, ntiles, st);
-      case 5: return launch12<S, 2, 32, 4, 256, 4, PRK>(a, ntiles, st);
+      case 0: return launch12<S, 2, 32, 8, 256, 4, PRK, G2>(a, ntiles, st);
+      case 1: return launch12<S, 2, 16, 8, 256, 4, PRK, G2>(a, ntiles, st);
+      case 2: return launch12<S, 2, 64, 4, 256, 4, PRK, G2>(a, ntiles, st);
+      case 3: return launch12<S, 2, 16, 16, 256, 4, PRK, G2>(a, ntiles, st);
+      case 4: return launch12<S, 2, 32, 16, 256, 2, PRK, G2>(a, ntiles, st);
+      case 5: return launch12<S, 2, 32, 4, 256, 4, PRK, G2>(a, ntiles, st);
       // every x and every y face of the tile in one round of threads
-      case 6: return launch12<S, 2, 32, 8, 320, 5, PRK>(a, ntiles, st);
-      case 7: return launch12<S, 2, 16, 16, 320, 5, PRK>(a, ntiles, st);
-      case 8: return launch12<S, 2, 32, 8, 384, 6, PRK>(a, ntiles, st);
+      case 6: return launch12<S, 2, 32, 8, 320, 5, PRK, G2>(a, ntiles, st);
+      case 7: return launch12<S, 2, 16, 16, 320, 5, PRK, G2>(a, ntiles, st);
+      case 8: return launch12<S, 2, 32, 8, 384, 6, PRK, G2>(a, ntiles, st);
     }
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+// kind: closure of the batch, FVM_KIND_SG (stiffened-gas pair), FVM_KIND_PR
+// (Peng-Robinson component 1) or FVM_KIND_THREE (liquid and two ideal gases)
+hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  if (dim == 3) return fvm_k_stage3(mixed, prk, tile, a, ntiles, st);
-  if (mixed) return prk ? stage12<float, true>(dim, tile, a, ntiles, st) : stage12<float, false>(dim, tile, a, ntiles, st);
-  return prk ? stage12<double, true>(dim, tile, a, ntiles, st) : stage12<double, false>(dim, tile, a, ntiles, st);
+  if (dim == 3) {
+    if (kind == FVM_KIND_THREE) return hipErrorInvalidValue;
+    return fvm_k_stage3(mixed, kind == FVM_KIND_PR, tile, a, ntiles, st);
+  }
+  if (mixed) {
+    if (kind == FVM_KIND_THREE) return stage12<float, false, true>(dim, tile, a, ntiles, st);
+    return kind == FVM_KIND_PR ? stage12<float, true, false>(dim, tile, a, ntiles, st)
+                               : stage12<float, false, false>(dim, tile, a, ntiles, st);
+  }
+  if (kind == FVM_KIND_THREE) return stage12<double, false, true>(dim, tile, a, ntiles, st);
+  return kind == FVM_KIND_PR ? stage12<double, true, false>(dim, tile, a, ntiles, st)
+                             : stage12<double, false, false>(dim, tile, a, ntiles, st);
 }
 
 hipError_t fvm_k_advance(CaseDyn* dyn, int ncases, int nsteps, hipStream_t st)
@@ -587,77 +661,89 @@ hipError_t fvm_k_advance(CaseDyn* dyn, int ncases, int nsteps, hipStream_t st)
   return hipGetLastError();
 }
 
-#define FVM_DISPATCH(MIXED, DIM, PRK, CALL)                                            \
-  do {                                                                                 \
-    if (MIXED) {                                                                       \
-      if (DIM == 1) { if (PRK) { CALL(float, 1, true); } else { CALL(float, 1, false); } }   \
-      else if (DIM == 2) { if (PRK) { CALL(float, 2, true); } else { CALL(float, 2, false); } } \
-      else { if (PRK) { CALL(float, 3, true); } else { CALL(float, 3, false); } }     \
-    } else {                                                                           \
-      if (DIM == 1) { if (PRK) { CALL(double, 1, true); } else { CALL(double, 1, false); } } \
-      else if (DIM == 2) { if (PRK) { CALL(double, 2, true); } else { CALL(double, 2, false); } } \
-      else { if (PRK) { CALL(double, 3, true); } else { CALL(double, 3, false); } }   \
-    }                                                                                  \
+#define FVM_DISPATCH_D(S, DIM, KIND, CALL)                                            \
+  do {                                                                                \
+    if (DIM == 1) {                                                                   \
+      if (KIND == FVM_KIND_THREE) { CALL(S, 1, false, true); }                        \
+      else if (KIND == FVM_KIND_PR) { CALL(S, 1, true, false); }                      \
+      else { CALL(S, 1, false, false); }                                              \
+    } else if (DIM == 2) {                                                            \
+      if (KIND == FVM_KIND_THREE) { CALL(S, 2, false, true); }                        \
+      else if (KIND == FVM_KIND_PR) { CALL(S, 2, true, false); }                      \
+      else { CALL(S, 2, false, false); }                                              \
+    } else {                                                                          \
+      if (KIND == FVM_KIND_THREE) { CALL(S, 3, false, true); }                        \
+      else if (KIND == FVM_KIND_PR) { CALL(S, 3, true, false); }                      \
+      else { CALL(S, 3, false, false); }                                              \
+    }                                                                                 \
+  } while (0)
+#define FVM_DISPATCH(MIXED, DIM, KIND, CALL)                                          \
+  do {                                                                                \
+    if (MIXED) FVM_DISPATCH_D(float, DIM, KIND, CALL);                                \
+    else FVM_DISPATCH_D(double, DIM, KIND, CALL);                                     \
   } while (0)
 
 static unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t fvm_k_prim_to_state(int dim, int mixed, int prk, const CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const double* prim, void* dst, long long total, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_prim_to_state<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
-  FVM_DISPATCH(mixed, dim, prk, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_prim_to_state<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
-hipError_t fvm_k_cons_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_cons_to_state(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const double* q, void* dst, long long total, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_cons_to_state<S, D>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
-  FVM_DISPATCH(mixed, dim, false, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_cons_to_state<S, D, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
-hipError_t fvm_k_state_to_cons(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_state_to_cons(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const void* src, double* q, long long total, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_state_to_cons<S, D>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
-  FVM_DISPATCH(mixed, dim, false, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_state_to_cons<S, D, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
-hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_state_to_prim(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const void* src, double* w, long long total, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_state_to_prim<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
-  FVM_DISPATCH(mixed, dim, prk, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_state_to_prim<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
-hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
+hipError_t fvm_k_dt_init(int dim, int mixed, int kind, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
                          const void* src, long long total, long long label_off, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_dt_init<S, D, P>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
-  FVM_DISPATCH(mixed, dim, prk, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_dt_init<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
-hipError_t fvm_k_totals(int dim, int mixed, const CaseC* cases, int icase, long long ncell, const void* src,
+hipError_t fvm_k_totals(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell, const void* src,
                         long long total, double* part, int nblk, double vol, double* out, hipStream_t st)
 {
-#define CALL(S, D, P) hipLaunchKernelGGL((k_totals_part<S, D>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
-  FVM_DISPATCH(mixed, dim, false, CALL);
+#define CALL(S, D, P, G) hipLaunchKernelGGL((k_totals_part<S, D, G>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
+  FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
-  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, part, nblk, dim + 3, vol, out);
+  int nq = dim + (kind == FVM_KIND_THREE ? 4 : 3);
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, part, nblk, nq, vol, out);
   return hipGetLastError();
 }
 
-// storage shifts: partial densities and energies of both pure components at (p_ref, T_ref)
+// storage shifts: partial densities and energies of the pure components at
+// (p_ref, T_ref): out[6c + k] = rho_k, out[6c + 3 + k] = e_k (k = 2 only with
+// three components)
 template <bool PRK>
 __global__ void k_ref_shift(const CaseC* cases, int ncases, double* out, const double* pT)
 {
@@ -668,10 +754,19 @@ __global__ void k_ref_shift(const CaseC* cases, int ncases, double* out, const d
   double v0, e0, v1, e1;
   closure_fwd<PRK>(C, p, T, 0.0, v0, e0);
   closure_fwd<PRK>(C, p, T, 1.0, v1, e1);
-  out[4 * c] = 1.0 / v0;
-  out[4 * c + 1] = 1.0 / v1;
-  out[4 * c + 2] = e0;
-  out[4 * c + 3] = e1;
+  double r2 = 0.0, e2 = 0.0;
+  if (C.ncomp == 3) {
+    const Comp& k = C.comp[2];
+    double v2 = k.A * T / (p + k.pinf);
+    r2 = 1.0 / v2;
+    e2 = k.cv * T + k.pinf * v2 + k.qs;
+  }
+  out[6 * c] = 1.0 / v0;
+  out[6 * c + 1] = 1.0 / v1;
+  out[6 * c + 2] = r2;
+  out[6 * c + 3] = e0;
+  out[6 * c + 4] = e1;
+  out[6 * c + 5] = e2;
 }
 
 hipError_t fvm_k_ref_shift(const CaseC* cases, int ncases, double* out, const double* pT, hipStream_t st)

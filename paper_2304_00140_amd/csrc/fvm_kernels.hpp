@@ -20,6 +20,10 @@ struct StageArgs {
   fvm::SchemeC sc;
 };
 
+// closure of a batch: stiffened-gas pair, Peng-Robinson component 1, or a
+// liquid with two ideal gases (three components, one more storage field)
+enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2 };
+
 int fvm_k_tile_count(int dim);
 int fvm_k_tile_shape(int dim, int tile, int* tx, int* ty, int* nt);
 int fvm_k_tile_count3();
@@ -27,22 +31,22 @@ int fvm_k_tile_shape3(int tile, int* tx, int* ty, int* nt);
 // 3D tiles march along z over this many planes per workgroup
 int fvm_k_tile_zchunk3(int tile);
 
-hipError_t fvm_k_stage(int dim, int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
-hipError_t fvm_k_prim_to_state(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,
                                const double* prim, void* dst, long long total, hipStream_t st);
-hipError_t fvm_k_cons_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_cons_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,
                                const double* q, void* dst, long long total, hipStream_t st);
-hipError_t fvm_k_state_to_cons(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_state_to_cons(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,
                                const void* src, double* q, long long total, hipStream_t st);
-hipError_t fvm_k_state_to_prim(int dim, int mixed, int prk, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_k_state_to_prim(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,
                                const void* src, double* w, long long total, hipStream_t st);
 // CFL bound of the current state into the slot of the next step, and its
 // checks; an error is reported as one of step (base + label_off)
-hipError_t fvm_k_dt_init(int dim, int mixed, int prk, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
+hipError_t fvm_k_dt_init(int dim, int mixed, int kind, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
                          long long ncell, const void* src, long long total, long long label_off, hipStream_t st);
-hipError_t fvm_k_totals(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell, const void* src,
+hipError_t fvm_k_totals(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell, const void* src,
                         long long total, double* part, int nblk, double vol, double* out, hipStream_t st);
-hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /* [ncases][4] */,
+hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /* [ncases][6] */,
                            const double* pT /* [ncases][2] */, hipStream_t st);

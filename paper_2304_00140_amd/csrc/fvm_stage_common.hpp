@@ -23,11 +23,31 @@ __device__ inline void map_index(int& i, int n, int bclo, int bchi, bool& flip)
 }
 
 // physical partial densities, momentum and gauge energy of a cell from its
-// primitives (p, T, alpha_G, u); xi = alpha_G rho_G / rho at (p, T)
-template <bool PRK>
+// primitives (p, T, alpha_G, u); xi = alpha_G rho_G / rho at (p, T).  G2:
+// three components, al2 = alpha of the second gas, whose partial density
+// follows the energy (index 3 + D).
+template <bool PRK, bool G2 = false>
 __device__ inline void state_from_prim(const CaseC& C, double p, double T, double al, const double* u,
-                                       int D, double* q)
+                                       int D, double* q, double al2 = 0.0)
 {
+  if constexpr (G2) {
+    double r[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = (p + C.comp[k].pinf) / (C.comp[k].A * T);
+    double rho = (1.0 - al - al2) * r[0] + al * r[1] + al2 * r[2];
+    double ir = 1.0 / rho;
+    double Y1 = al * r[1] * ir, Y2 = al2 * r[2] * ir;
+    double vm, em;
+    tdu3<double>(C, p, T, Y1, Y2, vm, em);
+    double ke = 0.0;
+    for (int d = 0; d < D; ++d) ke += u[d] * u[d];
+    q[0] = rho - rho * Y1 - rho * Y2;
+    q[1] = rho * Y1;
+    for (int d = 0; d < D; ++d) q[2 + d] = rho * u[d];
+    q[2 + D] = rho * (em + 0.5 * ke);
+    q[3 + D] = rho * Y2;
+    return;
+  }
   double vL, eL, vG, eG;
   closure_fwd<PRK>(C, p, T, 0.0, vL, eL);
   closure_fwd<PRK>(C, p, T, 1.0, vG, eG);
@@ -55,14 +75,15 @@ __device__ inline bool beyond_farfield(const CaseC& C, int gx, int gy, int gz)
   return f;
 }
 
-// load one (possibly ghost) cell: physical partial densities, momentum, gauge energy
-template <class S, int D, bool PRK>
+// load one (possibly ghost) cell: physical partial densities, momentum, gauge
+// energy (and the second gas's partial density with G2)
+template <class S, int D, bool PRK, bool G2 = false>
 __device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long long total,
                                  int gx, int gy, int gz, long long step, double* q)
 {
   if (beyond_farfield<D>(C, gx, gy, gz)) {
     const double u0[3] = {0.0, 0.0, 0.0};
-    state_from_prim<PRK>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, D, q);
+    state_from_prim<PRK, G2>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, D, q);
     return;
   }
   bool fx = false, fy = false, fz = false;
@@ -78,7 +99,7 @@ __device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long
         u[c] += C.in_noise * C.in_u *
                 (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
                                (unsigned long long)iz, (unsigned long long)c) - 1.0);
-      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, D, q);
+      state_from_prim<PRK, G2>(C, C.in_p, C.in_T, C.in_alpha, u, D, q);
       if (D >= 2 && fy) q[3] = -q[3];
       if (D >= 3 && fz) q[4] = -q[4];
       return;
@@ -94,6 +115,7 @@ __device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long
 #pragma unroll
   for (int d = 0; d < D; ++d) q[2 + d] = (double)src[(2 + d) * total + cell];
   q[2 + D] = (double)src[(2 + D) * total + cell];
+  if constexpr (G2) q[3 + D] = (double)src[(3 + D) * total + cell] + C.rref[2];
   if (fx) q[2] = -q[2];
   if (D >= 2 && fy) q[3] = -q[3];
   if (D >= 3 && fz) q[4] = -q[4];
@@ -111,6 +133,32 @@ __device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, doubl
   for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
   double e = q[2 + D] * ir - 0.5 * ke;
   return closure<PRK>(C, rho, Y, e);
+}
+
+// primitives of a loaded three-component cell (second gas at index 3 + D)
+template <int D>
+__device__ inline PT cell_prim3(const CaseC& C, const double* q, double* u, double& rho, double& Y,
+                                double& Y2)
+{
+  rho = q[0] + q[1] + q[3 + D];
+  double ir = frcp(rho);
+  Y = q[1] * ir;
+  Y2 = q[3 + D] * ir;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
+  double e = q[2 + D] * ir - 0.5 * ke;
+  return closure3(C, rho, Y, Y2, e);
+}
+
+// either closure: G2 selects the three-component one
+template <int D, bool PRK, bool G2>
+__device__ inline PT cell_prim_any(const CaseC& C, const double* q, double* u, double& rho, double& Y,
+                                   double& Y2)
+{
+  if constexpr (G2) return cell_prim3<D>(C, q, u, rho, Y, Y2);
+  Y2 = 0.0;
+  return cell_prim<D, PRK>(C, q, u, rho, Y);
 }
 
 __device__ inline void record_error(CaseDyn& dy, int code, long long cell, long long step)
@@ -199,6 +247,18 @@ __device__ inline S mix_alpha(double v0, double v1, S a)
   return (S(1) - ac) * S(v0) + ac * S(v1);
 }
 
+// three components: (1 - alpha_1 - alpha_2) v0 + alpha_1 v1 + alpha_2 v2, the
+// fractions clipped into [0, 1] and rescaled when they sum above one
+template <class S>
+__device__ inline S mix_alpha3(double v0, double v1, double v2, S a, S b)
+{
+  S ac = a < S(0) ? S(0) : (a > S(1) ? S(1) : a);
+  S bc = b < S(0) ? S(0) : (b > S(1) ? S(1) : b);
+  S sum = ac + bc;
+  if (sum > S(1)) { ac = ac / sum; bc = bc / sum; }
+  return (S(1) - ac - bc) * S(v0) + ac * S(v1) + bc * S(v2);
+}
+
 // Stress part of the flux of eq. (2-2) through the face between the LDS cells
 // c and c + st[DIR], second-order central: normal derivatives from the two
 // cells, transverse ones as the mean of the two cells' central differences,
@@ -206,9 +266,9 @@ __device__ inline S mix_alpha(double v0, double v1, S a)
 //   tau = mu (grad u + grad u^T - 2/3 div u I);  F_rho u -= tau . n,
 //   F_rho E -= u . tau . n + kc dT/dn.
 // U[a]: LDS array of velocity component a; st: LDS strides of the directions.
-template <class S, int D, int DIR>
+template <class S, int D, int DIR, bool G2 = false>
 __device__ inline void visc_flux(const CaseC& C, const S* const (&U)[D], const S* sT, const S* sA, int c,
-                                 const int (&st)[D], S* F)
+                                 const int (&st)[D], S* F, const S* sA2 = nullptr)
 {
   const int r = c + st[DIR];
   S g[D][D];
@@ -223,8 +283,16 @@ __device__ inline void visc_flux(const CaseC& C, const S* const (&U)[D], const S
 #pragma unroll
   for (int b = 0; b < D; ++b) div += g[b][b];
   const S aL = sA[c], aR = sA[r];
-  const S mu = S(0.5) * (mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aL) + mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aR));
-  const S kc = S(0.5) * (mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aL) + mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aR));
+  S mu, kc;
+  if constexpr (G2) {
+    const S bL = sA2[c], bR = sA2[r];
+    const Comp* k = C.comp;
+    mu = S(0.5) * (mix_alpha3<S>(k[0].mu, k[1].mu, k[2].mu, aL, bL) + mix_alpha3<S>(k[0].mu, k[1].mu, k[2].mu, aR, bR));
+    kc = S(0.5) * (mix_alpha3<S>(k[0].kc, k[1].kc, k[2].kc, aL, bL) + mix_alpha3<S>(k[0].kc, k[1].kc, k[2].kc, aR, bR));
+  } else {
+    mu = S(0.5) * (mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aL) + mix_alpha<S>(C.comp[0].mu, C.comp[1].mu, aR));
+    kc = S(0.5) * (mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aL) + mix_alpha<S>(C.comp[0].kc, C.comp[1].kc, aR));
+  }
   S work = S(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -239,17 +307,28 @@ __device__ inline void visc_flux(const CaseC& C, const S* const (&U)[D], const S
 // CFL rate of a cell: sum_d (|u_d| + c) / dx_d, plus 2 nu sum_d 1/dx_d^2 with
 // nu = max(mu, kc / cv) / rho (cv mixed by mass fraction) for viscous or
 // conducting fluids (explicit diffusion limit)
-template <int D>
-__device__ inline double cfl_rate(const CaseC& C, const double* u, const PT& pt, double rho, double Y)
+template <int D, bool G2 = false>
+__device__ inline double cfl_rate(const CaseC& C, const double* u, const PT& pt, double rho, double Y,
+                                  double Y2 = 0.0)
 {
   double l = 0.0;
 #pragma unroll
   for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pt.c) * C.idx[d];
   if (C.diff) {
-    double Yc = Y < 0.0 ? 0.0 : (Y > 1.0 ? 1.0 : Y);
-    double cvm = (1.0 - Yc) * C.comp[0].cv + Yc * C.comp[1].cv;
-    double mu = mix_alpha<double>(C.comp[0].mu, C.comp[1].mu, pt.alpha);
-    double kc = mix_alpha<double>(C.comp[0].kc, C.comp[1].kc, pt.alpha) / cvm;
+    double cvm, mu, kc;
+    const Comp* k = C.comp;
+    if constexpr (G2) {
+      double y0, y1, y2;
+      clip_fractions3(Y, Y2, y0, y1, y2);
+      cvm = y0 * k[0].cv + y1 * k[1].cv + y2 * k[2].cv;
+      mu = mix_alpha3<double>(k[0].mu, k[1].mu, k[2].mu, pt.alpha, pt.alpha2);
+      kc = mix_alpha3<double>(k[0].kc, k[1].kc, k[2].kc, pt.alpha, pt.alpha2) / cvm;
+    } else {
+      double Yc = Y < 0.0 ? 0.0 : (Y > 1.0 ? 1.0 : Y);
+      cvm = (1.0 - Yc) * k[0].cv + Yc * k[1].cv;
+      mu = mix_alpha<double>(k[0].mu, k[1].mu, pt.alpha);
+      kc = mix_alpha<double>(k[0].kc, k[1].kc, pt.alpha) / cvm;
+    }
     l += 2.0 * (mu > kc ? mu : kc) / rho * C.sdx2;
   }
   return l;

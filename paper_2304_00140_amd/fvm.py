@@ -29,13 +29,14 @@ class fvm_grid_desc(C.Structure):
 
 
 class fvm_eos_desc(C.Structure):
-    _fields_ = [("kind", C.c_int * 2), ("gamma", C.c_double * 2), ("pinf", C.c_double * 2),
-                ("cv", C.c_double * 2), ("q", C.c_double * 2), ("pr_ns", C.c_int * 2),
+    _fields_ = [("kind", C.c_int * 3), ("gamma", C.c_double * 3), ("pinf", C.c_double * 3),
+                ("cv", C.c_double * 3), ("q", C.c_double * 3), ("pr_ns", C.c_int * 2),
                 ("pr_X", (C.c_double * MAXSPEC) * 2), ("pr_Tc", (C.c_double * MAXSPEC) * 2),
                 ("pr_pc", (C.c_double * MAXSPEC) * 2), ("pr_omega", (C.c_double * MAXSPEC) * 2),
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2), ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
-                ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 2), ("kc", C.c_double * 2)]
+                ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 3), ("kc", C.c_double * 3),
+                ("ncomp", C.c_int)]
 
 
 class fvm_scheme_desc(C.Structure):
@@ -141,12 +142,16 @@ def grid_desc(gd):
 
 def eos_desc(ed, storage=None):
     e = fvm_eos_desc()
-    for k in range(2):
+    nc = len(ed["kind"])
+    e.ncomp = nc
+    for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
-        e.mu[k], e.kc[k] = ed.get("mu", [0.0, 0.0])[k], ed.get("kc", [0.0, 0.0])[k]
+        e.mu[k], e.kc[k] = (ed.get("mu") or [0.0] * nc)[k], (ed.get("kc") or [0.0] * nc)[k]
         pr = ed["pr"][k]
         if pr is not None:
+            if k > 1:
+                raise ValueError("a Peng-Robinson fluid is supported as component 0 or 1 of two")
             e.pr_ns[k] = len(pr["species"])
             for a, s in enumerate(pr["species"]):
                 e.pr_X[k][a] = pr["X"][a]
@@ -193,7 +198,8 @@ class Context:
         self.L = lib()
         self.case = case
         self.dim = case["grid"]["dim"]
-        self.nq = self.dim + 3
+        self.ncomp = len(case["eos"]["kind"])
+        self.nq = self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
         self._g = grid_desc(case["grid"])
         self._e = eos_desc(case["eos"], case.get("storage") if shifts else None)
@@ -240,7 +246,7 @@ class Context:
         self._chk(self.L.fvm_get_state_device(self._h, C.c_void_p(q_ptr)))
 
     def get_primitive(self):
-        w = np.empty((9, self.ncell))
+        w = np.empty((11 if self.ncomp == 3 else 9, self.ncell))
         self._chk(self.L.fvm_get_primitive(self._h, _dp(w)))
         return w
 
@@ -290,7 +296,7 @@ class Batch:
         self.cases = cases
         n = len(cases)
         self.dim = cases[0]["grid"]["dim"]
-        self.nq = self.dim + 3
+        self.nq = self.dim + len(cases[0]["eos"]["kind"]) + 1
         self._g = (fvm_grid_desc * n)(*[grid_desc(c["grid"]) for c in cases])
         self._e = (fvm_eos_desc * n)(*[eos_desc(c["eos"], c.get("storage") if shifts else None) for c in cases])
         self._s = scheme_desc(cases[0]["scheme"])

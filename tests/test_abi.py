@@ -40,7 +40,7 @@ def test_binding_covers_the_header(fvm_mod):
 
 
 def test_version(fvm_mod):
-    assert fvm_mod.lib().fvm_version() == 1
+    assert fvm_mod.lib().fvm_version() == 2
 
 
 def test_descriptor_layout_matches_c(fvm_mod, tmp_path):

@@ -24,23 +24,28 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Per-unit figures of the dominant kernel measured with rocprofv3 on these
 # workloads and launch shapes (profiles/k_stage12_shock_bubble_2d_counters.md,
+# profiles/k_stage12_dual_gas_layer_2d_counters.md,
 # profiles/k_face3_liquid_jet_3d_counters.md): executed VALU lane-instructions
 # per cell-stage (SQ_INSTS_VALU x 64 / cells; in 3D the closure and face kernels
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v4"
+KERNEL_BUILD = "k_stage12-v5"
 MEASURED = {
-    ("shock_bubble_2d", 0, 0, "k_stage12-v4"): dict(valu_per_cell_stage=4463395.3 * 64 / 262144,
-                                                    traffic_bytes=(9911.0 * 2 + 10244.2) * 1024),
-    ("shock_bubble_2d", 1, 8, "k_stage12-v4"): dict(valu_per_cell_stage=4286123.0 * 64 / 262144,
-                                                    traffic_bytes=(5003.8 * 2 + 5124.5) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v4"): dict(valu_per_cell_stage=(460998317.2 + 1418865154.9) * 64 / 33554432,
-                                                  traffic_bytes=((794457.8 + 3520179.8) * 2 +
-                                                                 (2663806.3 + 1656191.5)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v4"): dict(valu_per_cell_stage=(434323127.2 + 1517992336.7) * 64 / 33554432,
-                                                  traffic_bytes=((395429.4 + 1689192.4) * 2 +
-                                                                 (1212739.4 + 814292.6)) * 1024),
+    ("shock_bubble_2d", 0, 0, "k_stage12-v5"): dict(valu_per_cell_stage=4463388.4 * 64 / 262144,
+                                                    traffic_bytes=(9921.1 * 2 + 10244.2) * 1024),
+    ("shock_bubble_2d", 1, 8, "k_stage12-v5"): dict(valu_per_cell_stage=4286166.0 * 64 / 262144,
+                                                    traffic_bytes=(5007.1 * 2 + 5124.8) * 1024),
+    ("dual_gas_layer_2d", 0, 1, "k_stage12-v5"): dict(valu_per_cell_stage=13198302.5 * 64 / 524288,
+                                                      traffic_bytes=(22485.0 * 2 + 24583.1) * 1024),
+    ("dual_gas_layer_2d", 1, 1, "k_stage12-v5"): dict(valu_per_cell_stage=11555077.5 * 64 / 524288,
+                                                      traffic_bytes=(11337.9 * 2 + 12297.4) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v5"): dict(valu_per_cell_stage=(460998389.7 + 1418865154.9) * 64 / 33554432,
+                                                  traffic_bytes=((794332.9 + 3520314.4) * 2 +
+                                                                 (2660488.5 + 1657931.5)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v5"): dict(valu_per_cell_stage=(434323125.0 + 1517992336.7) * 64 / 33554432,
+                                                  traffic_bytes=((395413.2 + 1689465.0) * 2 +
+                                                                 (1211757.2 + 814460.2)) * 1024),
 }
 
 
@@ -51,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
-                             "liquid_jet_3d_viscous", "interface_advection_1d"])
+                             "liquid_jet_3d_viscous", "dual_gas_layer_2d", "interface_advection_1d"])
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +98,9 @@ def make_workload(name, steps):
         return cases, dict(workload=name, cases=256, n_min=64, n_max=256)
     if name == "liquid_jet_3d":
         return [W.liquid_jet_3d(512, 256, 256, steps)], dict(workload=name, nx=512, ny=256, nz=256)
+    if name == "dual_gas_layer_2d":
+        return [W.dual_gas_layer_2d(1024, 512, steps)], dict(workload=name, nx=1024, ny=512, components=3,
+                                                             sigma=0.028)
     if name == "liquid_jet_3d_viscous":
         return [W.liquid_jet_3d(512, 256, 256, steps, viscous=True)], dict(workload=name, nx=512, ny=256, nz=256)
     raise ValueError(name)
@@ -132,7 +140,7 @@ def run_path(cases, prec, args, stream, torch):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     stage_ms = h.time_stages(args.timing_steps)
-    nq = cases[0]["grid"]["dim"] + 3
+    nq = h.nq
     return dict(handle=h, ncell=ncell, ms=ms, stage_ms=stage_ms, nq=nq, tile=tile,
                 tune={str(k): round(v, 5) for k, v in (tune or {}).items()})
 
@@ -140,12 +148,15 @@ def run_path(cases, prec, args, stream, torch):
 def l1_errors(a, b, uref):
     """relative L1 of the mixed-path primitives a against FP64-path b"""
     n = a.shape[1]
-    return {
+    out = {
         "rho": float(np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum()),
         "u": float(np.abs(a[1:4] - b[1:4]).sum() / (n * uref)),
         "p": float(np.abs(a[4] - b[4]).sum() / np.abs(b[4]).sum()),
         "Y": float(np.abs(a[6] - b[6]).sum() / n),
     }
+    if a.shape[0] > 9:
+        out["Y2"] = float(np.abs(a[9] - b[9]).sum() / n)
+    return out
 
 
 def cpu_baseline(cases, seconds):
@@ -257,7 +268,7 @@ def main():
             entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0, "liquid_jet_3d_viscous": 300.0,
-                    "interface_advection_1d": 100.0}.get(args.workload, 1.0)
+                    "dual_gas_layer_2d": 25.0, "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
         out["mixed"] = entry
     if not args.no_cpu_baseline:

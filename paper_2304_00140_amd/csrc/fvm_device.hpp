@@ -6,11 +6,13 @@
 // (Section 3.2, eq. D.5/D.6), thermodynamic dependent update (eq. 3-5,
 // Appendix B) and the face flux of eq. (2-2).
 //
-// Storage ("internal") variables of a cell, N_q = D + 3:
+// Storage ("internal") variables of a cell, N_q = D + 3 (D + 4 with a second
+// gas species):
 //   0: rho_L - rref_L   partial density of component 0 minus a reference
 //   1: rho_G - rref_G   partial density of component 1 minus a reference
 //   2..1+D: rho u
-//   2+D: E' = rho E - rho_L Q_L - rho_G Q_G   (energy in a shifted gauge)
+//   2+D: E' = rho E - sum_k rho_k Q_k   (energy in a shifted gauge)
+//   3+D: rho_G2 - rref_G2 (second gas species only)
 // The shifts are linear in the conserved variables, so fluxes telescope and
 // conservation is unchanged; they keep FP32 storage accurate in stiff liquids
 // (near the reference state the stored numbers are small).

@@ -267,6 +267,44 @@ def liquid_jet_3d(nx=512, ny=256, nz=256, steps=200, D=89.4e-6, cells_per_D=32, 
                 t_end=0.0, storage=dict(p_ref=p0, T_ref=T0), viscous=viscous)
 
 
+def dual_gas_layer_2d(nx=1024, ny=512, steps=1000, seed=2304, L=1e-3):
+    """Temporal liquid layer between two different gases (the second gas
+    species: three components), shaped like Section 4.6's dual-fuel shear layer:
+    an n-dodecane-like stiffened-gas layer at +25 m/s between nitrogen-like
+    (above) and methane-like (below) ideal gases at -25 m/s, 6 MPa, 400 K;
+    periodic in x, slip walls in y; both interfaces carry seeded sinusoidal
+    perturbations; sigma = 0.028 N/m (Section 4.8), sensor switching on."""
+    rng = np.random.default_rng(seed)
+    p0, T0, du = 6e6, 400.0, 25.0
+    rho_l, c_l, g_l = 700.0, 1100.0, 2.5
+    pinf_l = rho_l * c_l * c_l / g_l - p0
+    liquid = sg(g_l, pinf_l, cv_for_density(g_l, pinf_l, rho_l, p0, T0))
+    n2 = sg(1.4, 0.0, 2.5 * R_UNIV / NITROGEN["M"])
+    ch4 = sg(1.0 + 1.0 / 3.3, 0.0, 3.3 * R_UNIV / METHANE["M"])
+    g = make_grid(2, [nx, ny], [L, L * ny / nx], [[BC_PERIODIC, BC_PERIODIC], [BC_WALL, BC_WALL]])
+    dx = g["dx"][0]
+    x, y = cell_centres(g)
+    Ly = ny * dx
+    h = 0.0625 * Ly * 2.0                       # layer half-thickness
+    def wave():
+        f = np.zeros_like(x)
+        for _ in range(4):
+            k = int(rng.integers(1, 9))
+            f += rng.uniform(-1, 1) * np.sin(2 * np.pi * k * x / L + rng.uniform(0, 2 * np.pi))
+        return 2.0 * dx * f
+    top = 0.5 * Ly + h + wave()
+    bot = 0.5 * Ly - h + wave()
+    liq = (1.0 - smeared(y - top, dx)) * smeared(y - bot, dx)
+    a_n2 = (1.0 - liq) * smeared(y - 0.5 * Ly, 4 * dx)
+    a_ch4 = np.clip(1.0 - liq - a_n2, 0.0, 1.0)
+    u = du * (2.0 * liq - 1.0)
+    v = np.zeros_like(u)
+    prim = pack_prim(np.full_like(x, p0), np.full_like(x, T0), a_n2, [u, v, a_ch4])
+    return dict(name="dual_gas_layer_2d", grid=g, eos=make_eos(liquid, n2, ch4),
+                scheme=default_scheme(switching=1, sigma=0.028), prim=prim, steps=steps, t_end=0.0,
+                storage=dict(p_ref=p0, T_ref=T0))
+
+
 # ------------------------------------------------------- test-state generators
 
 def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.0,

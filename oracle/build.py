@@ -8,7 +8,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle_eos.c", "oracle_scheme.c", "oracle_field.c"]
+SOURCES = ["oracle_eos.c", "oracle_scheme.c", "oracle_field.c", "oracle_baro.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

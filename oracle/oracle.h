@@ -15,7 +15,9 @@
  *
  * State layout: SoA, q[f * ncell + cell], cell = i + n0 * (j + n1 * k), interior
  * cells only, x fastest.  Fields f: rho, rho*u_1 .. rho*u_D, rho*E, rho*xi
- * (N_q = D + 3), xi = mass fraction of component 2 ("G").
+ * (N_q = D + 3), xi = mass fraction of component 2 ("G"); with a second gas
+ * rho*xi_2 follows (N_q = D + 4).  The barotropic model (Section 2.2) has no
+ * energy equation: rho, rho*u_1 .. rho*u_D, rho*xi (N_q = D + 2).
  */
 #ifndef ORACLE_H
 #define ORACLE_H
@@ -28,6 +30,7 @@ extern "C" {
 
 enum { OG_BC_PERIODIC = 0, OG_BC_WALL = 1, OG_BC_ZEROGRAD = 2, OG_BC_INFLOW = 3, OG_BC_FARFIELD = 4 };
 enum { OG_EOS_SG = 0, OG_EOS_PR = 1 };
+enum { OG_MODEL_FOUR_EQ = 0, OG_MODEL_BAROTROPIC = 1 };
 enum {
   OG_LIM_MINMOD = 0, OG_LIM_KOREN = 1, OG_LIM_VANALBADA = 2, OG_LIM_VANLEER = 3,
   OG_LIM_CHAKRAVARTHY = 4, OG_LIM_MC = 5, OG_LIM_SUPERBEE = 6, OG_LIM_NONE = 7
@@ -77,6 +80,14 @@ typedef struct {
    * stiffened gas and the gases (1, 2) are ideal (p_inf = 0), the form of
    * Appendix A's Table A.1 and eqs. (A.1.2)-(A.1.5) */
   int ncomp;
+  /* model = OG_MODEL_BAROTROPIC: the barotropic equilibrium model of
+   * Section 2.2 (eqs. 2-3 .. 2-7) replaces the components above: a liquid
+   * (saturated density bt_rho_sat at bt_p_sat, speed of sound bt_c_liq)
+   * that becomes a liquid-vapour mixture below bt_p_sat (c_M^2 = p_sat /
+   * rho_sat; saturated vapour density bt_rho_vap for the vapour fraction),
+   * and one isothermal ideal gas with rho_G = p / bt_RT (bt_RT = R_Gas T_ref). */
+  int model;
+  double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
 } og_eos;
 
 typedef struct {
@@ -93,9 +104,11 @@ typedef struct {
   double gravity[3];    /* body-force acceleration g [m/s^2] (eq. 2-2, source Q) */
 } og_scheme;
 
-/* primitive vector of one cell */
+/* primitive vector of one cell.  Y2, A2: second gas (0 with two components);
+ * AV: vapour volume fraction (barotropic model; 0 otherwise); T is 0 in the
+ * barotropic model */
 enum { OW_RHO = 0, OW_U = 1, OW_V = 2, OW_W = 3, OW_P = 4, OW_T = 5, OW_Y = 6, OW_C = 7, OW_A = 8,
-       OW_Y2 = 9, OW_A2 = 10, OW_N = 11 };   /* Y2, A2: second gas (0 with two components) */
+       OW_Y2 = 9, OW_A2 = 10, OW_AV = 11, OW_N = 12 };
 
 /* ---- thermodynamics (Appendix A) ---- */
 /* number of components (2 or 3) and of conserved fields */
@@ -123,6 +136,14 @@ int og_pr_coeffs(const og_eos* e, int k, double T, double* a, double* dadT, doub
 double og_pr_pressure(const og_eos* e, int k, double T, double vmass);
 double og_pr_energy_tv(const og_eos* e, int k, double T, double vmass);
 
+/* ---- barotropic model (Section 2.2) ---- */
+int og_is_barotropic(const og_eos* e);
+double og_baro_liquid_density(const og_eos* e, double p);
+double og_baro_density(const og_eos* e, double p, double Y);
+int og_baro_pressure(const og_eos* e, double rho, double Y, double* p);
+double og_baro_sound(const og_eos* e, double p);
+void og_baro_fractions(const og_eos* e, double rho, double Y, double p, double* alpha_G, double* alpha_V);
+
 /* ---- reconstruction (Section 3.3, Table 4.2, Appendix D) ---- */
 double og_limiter_table(int kind, double r);
 double og_slope(int kind, double dfar, double dnear);
@@ -137,6 +158,10 @@ double og_central4(double a, double b, double c, double d);
 int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
                  const double W[4][OW_N], int f, int s_left, int s_right,
                  double* F, double* ustar, double* pstar);
+/* the same for the barotropic model (bit 0: xi, bit 1: the vapour fraction) */
+int og_face_flux_baro(const og_eos* e, const og_scheme* s, int dim, int dir,
+                      const double W[4][OW_N], int f, int s_left, int s_right,
+                      double* F, double* ustar, double* pstar);
 
 /* ---- whole-field operations ---- */
 int og_cons_from_prim(const og_grid* g, const og_eos* e, const double* prim, double* q);

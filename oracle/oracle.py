@@ -35,7 +35,9 @@ class Eos(C.Structure):
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2),
                 ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
-                ("mu", C.c_double * MAXCOMP), ("kc", C.c_double * MAXCOMP), ("ncomp", C.c_int)]
+                ("mu", C.c_double * MAXCOMP), ("kc", C.c_double * MAXCOMP), ("ncomp", C.c_int),
+                ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
+                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double)]
 
 
 class Scheme(C.Structure):
@@ -68,6 +70,14 @@ def lib():
                                           dp, dp]),
             "og_mix_sound2": (C.c_double, [pe, C.c_double, C.c_double, C.c_double, C.c_double]),
             "og_ncomp": (C.c_int, [pe]),
+            "og_is_barotropic": (C.c_int, [pe]),
+            "og_baro_liquid_density": (C.c_double, [pe, C.c_double]),
+            "og_baro_density": (C.c_double, [pe, C.c_double, C.c_double]),
+            "og_baro_pressure": (C.c_int, [pe, C.c_double, C.c_double, dp]),
+            "og_baro_sound": (C.c_double, [pe, C.c_double]),
+            "og_baro_fractions": (None, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "og_face_flux_baro": (C.c_int, [pe, ps, C.c_int, C.c_int, dp, C.c_int, C.c_int, C.c_int,
+                                            dp, dp, dp]),
             "og_sound": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
             "og_mix_sound": (C.c_double, [pe, C.c_double, C.c_double, C.c_double]),
             "og_clip_fraction": (C.c_double, [C.c_double]),
@@ -133,6 +143,11 @@ def make_eos(ed):
     e = Eos()
     nc = len(ed["kind"])
     e.ncomp = nc
+    e.model = int(ed.get("model", 0))
+    if e.model == 1:
+        b = ed["baro"]
+        e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
+        e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
@@ -177,7 +192,8 @@ class Oracle:
         self.s = make_scheme(case["scheme"])
         self.dim = case["grid"]["dim"]
         self.ncomp = len(case["eos"]["kind"])
-        self.nq = self.dim + self.ncomp + 1
+        self.barotropic = int(case["eos"].get("model", 0)) == 1
+        self.nq = self.dim + 2 if self.barotropic else self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
 
     def _err(self, rc, what):
@@ -192,10 +208,13 @@ class Oracle:
 
     def prim_from_cons(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
-        W = np.empty((11, self.ncell))
+        W = np.empty((12, self.ncell))
         self._err(self.L.og_prim_from_cons(C.byref(self.g), C.byref(self.e), _dp(q), _dp(W)), "prim_from_cons")
-        # rows: rho, u, v, w, p, T, xi_1, c, alpha_1 (+ xi_2, alpha_2 with three components)
-        return W if self.ncomp == 3 else W[:9]
+        # rows: rho, u, v, w, p, T, xi_1, c, alpha_1 (+ xi_2, alpha_2 with three components;
+        # + xi_2 = 0, alpha_2 = 0, alpha_V in the barotropic model)
+        if self.barotropic:
+            return W
+        return W[:11] if self.ncomp == 3 else W[:9]
 
     def rhs(self, q, step=0):
         q = np.ascontiguousarray(q, dtype=np.float64)

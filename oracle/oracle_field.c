@@ -78,6 +78,17 @@ static int cons_from_prim_cell(const og_eos* e, int dim, double p, double T, dou
                                const double* u, double* qc)
 {
   double rho, Y, Y2 = 0.0, r2, ein;
+  if (og_is_barotropic(e)) {
+    /* Section 2.2: rho = alpha_G rho_G(p) + (1 - alpha_G) rho_L/M(p) with
+     * rho_G = p / (R T) (eq. 2-5), rho xi = alpha_G rho_G; T is not used */
+    if (!(p > 0.0)) return -1;
+    double rG = p / e->bt_RT, rL = og_baro_liquid_density(e, p);
+    rho = al * rG + (1.0 - al) * rL;
+    qc[0] = rho;
+    for (int d = 0; d < dim; ++d) qc[1 + d] = rho * u[d];
+    qc[1 + dim] = al * rG;
+    return rho > 0.0 ? 0 : -1;
+  }
   if (og_ncomp(e) == 2) {
     double rL, eL, rG, eG;
     if (og_eos_forward(e, p, T, 0.0, &rL, &eL)) return -1;
@@ -131,6 +142,18 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   double rho = qc[0];
   double u[3] = {0, 0, 0}, ke = 0.0;
   for (int d = 0; d < dim; ++d) { u[d] = qc[1 + d] / rho; ke += u[d] * u[d]; }
+  if (og_is_barotropic(e)) {
+    /* p = f(rho, xi) (Section 2.2), alpha_G (eq. 2-6), alpha_V (eq. 2-7) */
+    double Y = qc[1 + dim] / rho, p;
+    int rc = og_baro_pressure(e, rho, Y, &p);
+    W[OW_RHO] = rho;
+    W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
+    W[OW_P] = p; W[OW_T] = 0.0; W[OW_Y] = Y; W[OW_Y2] = 0.0; W[OW_A2] = 0.0;
+    W[OW_C] = og_baro_sound(e, p);
+    og_baro_fractions(e, rho, Y, p, &W[OW_A], &W[OW_AV]);
+    if (rc || !(rho > 0.0) || !(p > 0.0) || !isfinite(p)) return -1;
+    return 0;
+  }
   double ein = qc[1 + dim] / rho - 0.5 * ke;
   double Y = qc[2 + dim] / rho;
   int three = og_ncomp(e) == 3;
@@ -141,6 +164,7 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
   W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y; W[OW_Y2] = Y2;
   W[OW_C] = og_mix_sound2(e, p, T, Y, Y2);
+  W[OW_AV] = 0.0;
   if (!three) {
     double Yc = og_clip_fraction(Y);
     W[OW_A] = (Yc == 0.0) ? 0.0 : Yc * rho * og_spec_volume(e, 1, p, T);
@@ -248,8 +272,8 @@ static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, doub
 
 /* per padded cell with one neighbour on each side: bit 0 = f (discontinuous
  * branch), bit 1+d = THINC eligibility along d */
-static void sensors(const og_grid* g, const og_scheme* s, const og_pad* pd, const double* W,
-                    unsigned char* flag)
+static void sensors(const og_grid* g, const og_eos* e, const og_scheme* s, const og_pad* pd,
+                    const double* W, unsigned char* flag)
 {
   int dim = g->dim;
   size_t np = pd->npad;
@@ -263,14 +287,22 @@ static void sensors(const og_grid* g, const og_scheme* s, const og_pad* pd, cons
         size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
         unsigned char fl = 0;
         /* THINC eligibility: eps < xi_i < 1 - eps and xi monotone through i along d;
-         * bits 1+d for xi_1, 4+d for xi_2 */
+         * bits 1+d for xi_1, 4+d for xi_2 or, in the barotropic model, for the
+         * vapour fraction alpha_V (liquid-vapour interface, Remark 1) */
         for (int g2 = 0; g2 < 2; ++g2) {
-          int f = g2 ? OW_Y2 : OW_Y;
+          int f = g2 ? (og_is_barotropic(e) ? OW_AV : OW_Y2) : OW_Y;
           double Y = W[f * np + c];
           for (int d = 0; d < dim; ++d) {
             double Ym = W[f * np + c - st[d]], Yp = W[f * np + c + st[d]];
-            if (Y > s->eps_interface && Y < 1.0 - s->eps_interface && (Y - Ym) * (Yp - Y) > 0.0)
-              fl |= (unsigned char)((g2 ? 16u : 2u) << d);
+            int ok = Y > s->eps_interface && Y < 1.0 - s->eps_interface && (Y - Ym) * (Yp - Y) > 0.0;
+            if (f == OW_AV) {
+              /* the density that THINC then sharpens must be monotone too (with
+               * gas present alpha_V alone does not make it so, and THINC of a
+               * value outside its neighbours' range is unbounded) */
+              double r0 = W[OW_RHO * np + c];
+              ok = ok && (r0 - W[OW_RHO * np + c - st[d]]) * (W[OW_RHO * np + c + st[d]] - r0) > 0.0;
+            }
+            if (ok) fl |= (unsigned char)((g2 ? 16u : 2u) << d);
           }
         }
         if (!s->switching) {
@@ -297,7 +329,13 @@ static void sensors(const og_grid* g, const og_scheme* s, const og_pad* pd, cons
             double ap = W[OW_A * np + c + st[d]] + W[OW_A2 * np + c + st[d]];
             thG += fabs(a0 - am) + fabs(ap - a0);
           }
-          if (thD > s->theta_ducros || thG > s->theta_gas) fl |= 1u;   /* eq. (D.4) */
+          /* the vapour-fraction detector theta^alpha, same expression and
+           * (not given separately) the same threshold as theta^Gas */
+          double thV = 0.0;
+          for (int d = 0; d < dim; ++d)
+            thV += fabs(W[OW_AV * np + c] - W[OW_AV * np + c - st[d]]) +
+                   fabs(W[OW_AV * np + c + st[d]] - W[OW_AV * np + c]);
+          if (thD > s->theta_ducros || thV > s->theta_gas || thG > s->theta_gas) fl |= 1u;   /* eq. (D.4) */
         }
         flag[c] = fl;
       }
@@ -402,6 +440,7 @@ static void curvature_field(const og_grid* g, const og_scheme* s, const og_pad* 
 
 int og_nq(const og_grid* g, const og_eos* e)
 {
+  if (og_is_barotropic(e)) return g->dim + 2;
   return g->dim + og_ncomp(e) + 1;
 }
 
@@ -522,10 +561,16 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
   og_pad* pd = &w.pd;
   size_t np = pd->npad, nc = pd->ncell;
   size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
-  sensors(g, s, pd, w.W, w.flag);
+  sensors(g, e, s, pd, w.W, w.flag);
   memset(r, 0, sizeof(double) * (size_t)nq * nc);
   int bad = 0;
   const int diffusive = has_diffusion(e);
+  const int baro = og_is_barotropic(e);
+  if (baro && diffusive) {
+    work_free(&w);
+    og_set_error("stress terms are not part of the barotropic model here");
+    return -4;
+  }
   for (int d = 0; d < dim; ++d) {
     /* faces i-1/2 for i = 0 .. n_d along d; transverse interior */
     int hi[3] = {pd->n[0], pd->n[1], pd->n[2]};
@@ -547,7 +592,9 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
           int sl = ((fl >> (1 + d)) & 1) | (((fl >> (4 + d)) & 1) << 1);
           int sr = ((fr >> (1 + d)) & 1) | (((fr >> (4 + d)) & 1) << 1);
           double F[7];
-          if (og_face_flux(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL)) bad = 1;
+          if (baro ? og_face_flux_baro(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL)
+                   : og_face_flux(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL))
+            bad = 1;
           if (diffusive) {
             double Fv[7];
             viscous_flux(g, e, pd, w.W, c, d, Fv);
@@ -587,7 +634,7 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
             r[(1 + d) * nc + ci] += S;
             se += w.W[(OW_U + d) * np + c] * S;
           }
-          r[(1 + dim) * nc + ci] += se;
+          if (!baro) r[(1 + dim) * nc + ci] += se;
         }
     free(kap);
   }
@@ -602,7 +649,7 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
             r[(1 + d) * nc + ci] += rho * s->gravity[d];
             pw += w.W[(OW_U + d) * np + c] * s->gravity[d];
           }
-          r[(1 + dim) * nc + ci] += rho * pw;
+          if (!baro) r[(1 + dim) * nc + ci] += rho * pw;
         }
   }
   work_free(&w);
@@ -618,7 +665,7 @@ int og_sensor_flags(const og_grid* g, const og_eos* e, const og_scheme* s, const
   og_work w;
   int rc = work_setup(&w, g, e, q, 0);
   if (!rc) {
-    sensors(g, s, &w.pd, w.W, w.flag);
+    sensors(g, e, s, &w.pd, w.W, w.flag);
     for (int k = 0; k < w.pd.n[2]; ++k)
       for (int j = 0; j < w.pd.n[1]; ++j)
         for (int i = 0; i < w.pd.n[0]; ++i)
@@ -650,7 +697,7 @@ double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
   int dim = g->dim, nq = og_nq(g, e);
-  int diffusive = has_diffusion(e);
+  int diffusive = has_diffusion(e) && !og_is_barotropic(e);
   double sdx2 = 0.0;
   for (int d = 0; d < dim; ++d) sdx2 += 1.0 / (g->dx[d] * g->dx[d]);
   double lam = 0.0;

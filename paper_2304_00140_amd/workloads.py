@@ -12,6 +12,8 @@ Every case dict has:
   name, grid{dim, n[3], dx[3], bc[3][2], inflow{...}}, eos{kind[2], gamma[2],
   pinf[2], cv[2], q[2], pr[2]}, scheme{...}, prim[(3+D), ncell] (p, T, alpha_G,
   u_1..u_D; x fastest), steps, t_end, storage{p_ref, T_ref}.
+A barotropic-model case (eos["model"] = MODEL_BAROTROPIC) carries the
+parameters of Section 2.2 in eos["baro"]; its T row is not used.
 """
 import math
 
@@ -19,6 +21,7 @@ import numpy as np
 
 BC_PERIODIC, BC_WALL, BC_ZEROGRAD, BC_INFLOW, BC_FARFIELD = 0, 1, 2, 3, 4
 EOS_SG, EOS_PR = 0, 1
+MODEL_FOUR_EQ, MODEL_BAROTROPIC = 0, 1
 LIM = {"minmod": 0, "koren": 1, "vanalbada": 2, "vanleer": 3, "chakravarthy": 4,
        "mc": 5, "superbee": 6, "none": 7}
 R_UNIV = 8.314462618
@@ -62,6 +65,16 @@ def make_eos(c0, c1, c2=None):
                 pinf=[c["pinf"] for c in comps], cv=[c["cv"] for c in comps],
                 q=[c["q"] for c in comps], pr=[c if c["kind"] == EOS_PR else None for c in comps],
                 mu=[c.get("mu", 0.0) for c in comps], kc=[c.get("kc", 0.0) for c in comps])
+
+
+def baro_eos(rho_sat=1000.0, p_sat=2340.0, c_liq=1500.0, rho_vap=0.0173, R_gas=296.8, T_gas=336.9):
+    """barotropic equilibrium model (Section 2.2): a liquid that becomes a
+    liquid-vapour mixture below p_sat, and one isothermal ideal gas.  Defaults:
+    Section 4.5's liquid and gas values; the saturated vapour density is that
+    of water vapour at 2340 Pa, 293 K (p / (R_v T), R_v = 461.5 J/(kg K))."""
+    return dict(model=MODEL_BAROTROPIC, kind=[EOS_SG, EOS_SG], gamma=[0.0, 0.0], pinf=[0.0, 0.0],
+                cv=[0.0, 0.0], q=[0.0, 0.0], pr=[None, None], mu=[0.0, 0.0], kc=[0.0, 0.0],
+                baro=dict(rho_sat=rho_sat, p_sat=p_sat, c_liq=c_liq, rho_vap=rho_vap, RT=R_gas * T_gas))
 
 
 def cv_for_density(gamma, pinf, rho, p, T):
@@ -305,14 +318,66 @@ def dual_gas_layer_2d(nx=1024, ny=512, steps=1000, seed=2304, L=1e-3):
                 storage=dict(p_ref=p0, T_ref=T0))
 
 
+def square_to_circle_2d(n=150, steps=2000, L=0.75, side=0.2, sigma=800.0):
+    """Section 4.5's 2D shape recovery: a square liquid body (rho 1000) of side
+    0.2 m centred in a 0.75 m box of gas (rho 1 at 1 bar), sigma = 800 N/m,
+    barotropic model with the section's values; zero-gradient sides stand in
+    for its non-reflective boundaries; uniform 1 bar, at rest."""
+    g = make_grid(2, [n, n], [L, L], [[BC_ZEROGRAD, BC_ZEROGRAD], [BC_ZEROGRAD, BC_ZEROGRAD]])
+    x, y = cell_centres(g)
+    dist = np.maximum(np.abs(x - 0.5 * L), np.abs(y - 0.5 * L)) - 0.5 * side
+    alpha = smeared(dist, g["dx"][0])
+    z = np.zeros_like(x)
+    prim = pack_prim(np.full_like(x, 1e5), z, alpha, [z, z])
+    return dict(name="square_to_circle_2d", grid=g, eos=baro_eos(),
+                scheme=default_scheme(sigma=sigma, switching=1), prim=prim, steps=steps, t_end=0.0,
+                storage=dict(p_ref=1e5, T_ref=0.0))
+
+
+def vapour_bubble_wall_2d(nx=1024, ny=512, steps=2000, dx=4e-6, R=400e-6, H=440e-6, p_b=1342.0,
+                          p_inf=1e6):
+    """Section 4.9's vapour bubble near a wall on a uniform 4 um grid: radius
+    400 um, centre 440 um above a slip wall (y = 0), interior a liquid-vapour
+    mixture at 1342 Pa (barotropic model, water-like liquid with p_sat = 2340
+    Pa), liquid at p_inf = 1 MPa far away with the Rayleigh-collapse profile
+    p = p_inf + (p_b - p_inf) R / r in between; the other sides are a far-field
+    reservoir at p_inf."""
+    g = make_grid(2, [nx, ny], [nx * dx, ny * dx], [[BC_FARFIELD, BC_FARFIELD], [BC_WALL, BC_FARFIELD]])
+    g["farfield"] = dict(p=p_inf, T=0.0, alpha=0.0)
+    x, y = cell_centres(g)
+    r = np.hypot(x - 0.5 * nx * dx, y - H)
+    inside = 1.0 - smeared(r - R, dx)
+    p_liq = p_inf + (p_b - p_inf) * np.minimum(1.0, R / np.maximum(r, 1e-300))
+    p = p_b * inside + p_liq * (1.0 - inside)
+    z = np.zeros_like(x)
+    prim = pack_prim(p, z, z, [z, z])
+    return dict(name="vapour_bubble_wall_2d", grid=g, eos=baro_eos(), scheme=default_scheme(switching=1),
+                prim=prim, steps=steps, t_end=0.0, storage=dict(p_ref=p_inf, T_ref=0.0))
+
+
+def cavitation_tube_1d(n=400, u0=10.0, p0=1e5, L=1.0):
+    """1D expansion: water at p0 with u = -u0 left of the middle and +u0 right of
+    it between two slip walls; the rarefaction drops the pressure below p_sat
+    and a liquid-vapour mixture forms in the middle (barotropic model)."""
+    g = make_grid(1, [n], [L], [[BC_WALL, BC_WALL]])
+    x = cell_centres(g)[0]
+    u = np.where(x < 0.5 * L, -u0, u0)
+    z = np.zeros_like(x)
+    prim = pack_prim(np.full_like(x, p0), z, z, [u])
+    return dict(name="cavitation_tube_1d", grid=g, eos=baro_eos(), scheme=default_scheme(),
+                prim=prim, steps=None, t_end=0.0, storage=dict(p_ref=p0, T_ref=0.0))
+
+
 # ------------------------------------------------------- test-state generators
 
 def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.0,
-                 bc=None, sigma=0.0, switching=0, gas="sg", second_gas=False):
+                 bc=None, sigma=0.0, switching=0, gas="sg", second_gas=False, barotropic=False):
     """Seeded smooth random fields with a wavy interface: used for one-RHS and
     few-step comparisons.  Periodic by default.  second_gas=True makes a
     three-component case: the gas side is shared between an air-like and a
-    helium-like ideal gas by a smooth random split."""
+    helium-like ideal gas by a smooth random split.  barotropic=True makes a
+    barotropic-model case whose pressure spans about 0.2 .. 2 p_sat, so
+    that liquid, liquid-vapour mixture and gas all occur."""
     rng = np.random.default_rng(seed)
     n3 = list(n) + [1] * (3 - len(n))
     if bc is None:
@@ -354,6 +419,16 @@ def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.
         alpha = np.clip(alpha + rng.uniform(-1, 1, size=alpha.shape) * 1e-3 * alpha * (1 - alpha), 0, 1)
     else:
         alpha = 0.5 + smooth(0.3)
+    if barotropic:
+        eos = baro_eos()
+        pb = eos["baro"]["p_sat"] * np.maximum(0.2, 1.0 + 1.6 * smooth(1.0))
+        # a tenth of the velocity: near p_sat the mixture is soft (c_M ~ 1.5 m/s)
+        # and a stronger random compression drives cells across the kink of the
+        # law at p_sat within a few steps
+        prim = pack_prim(pb, np.zeros_like(pb), alpha, [0.1 * ud for ud in u])
+        return dict(name=f"random_baro_{dim}d_{seed}", grid=g, eos=eos,
+                    scheme=default_scheme(sigma=sigma, switching=switching), prim=prim, steps=None,
+                    t_end=0.0, storage=dict(p_ref=eos["baro"]["p_sat"], T_ref=0.0))
     if second_gas:
         share = 0.5 + 0.45 * np.tanh(3.0 * smooth(1.0))
         prim = pack_prim(p, T, alpha * share, list(u) + [alpha * (1.0 - share)])

@@ -1,0 +1,229 @@
+"""Pins of the oracle's barotropic model (Section 2.2, eqs. 2-3 .. 2-7; the
+liquid-vapour density THINC of Section 3.4) against what the equations and
+the mathematics fix: each branch of the one-fluid equation reduces to its
+component law, round trips through the closure, continuity at p_sat, the
+volume-fraction identities of eq. 2-6 and 2-7, stationarity, pressure /
+velocity equilibrium of a moving gas-liquid interface, conservation, the
+acoustic speed of the liquid, mirror symmetry of a cavitating expansion and
+the face density of an eligible liquid-vapour cell."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, lib, make_eos, make_scheme
+from paper_2304_00140_amd import workloads as W
+
+EOS = W.baro_eos()
+B = EOS["baro"]
+RS, PS, CL, RV, RT = B["rho_sat"], B["p_sat"], B["c_liq"], B["rho_vap"], B["RT"]
+
+
+def pressure(e, rho, Y):
+    p = C.c_double()
+    assert lib().og_baro_pressure(C.byref(e), rho, Y, C.byref(p)) == 0
+    return p.value
+
+
+def fractions(e, rho, Y, p):
+    a, v = C.c_double(), C.c_double()
+    lib().og_baro_fractions(C.byref(e), rho, Y, p, C.byref(a), C.byref(v))
+    return a.value, v.value
+
+
+def test_pure_liquid_and_mixture_laws():
+    """xi = 0: p = p_sat + c_L^2 (rho - rho_sat) above rho_sat (eq. 2-3) and
+    p = p_sat + c_M^2 (rho - rho_sat), c_M^2 = p_sat / rho_sat below (eq. 2-4)"""
+    e = make_eos(EOS)
+    for rho in (1000.5, 1002.0, 1044.0):
+        assert pressure(e, rho, 0.0) == pytest.approx(PS + CL * CL * (rho - RS), rel=1e-12)
+    for rho in (999.0, 600.0, 20.0, 0.5):
+        assert pressure(e, rho, 0.0) == pytest.approx(PS + PS / RS * (rho - RS), rel=1e-10, abs=1e-9)
+
+
+def test_pure_gas_is_isothermal_ideal():
+    e = make_eos(EOS)
+    for rho in (0.01, 1.0, 30.0):
+        assert pressure(e, rho, 1.0) == pytest.approx(rho * RT, rel=1e-13)
+
+
+def test_round_trip_over_both_branches():
+    """(p, xi) -> rho by the volume fractions, back to p by the one-fluid
+    equation; the recovered state satisfies the equation itself and eq. 2-6"""
+    e = make_eos(EOS)
+    L = lib()
+    rng = np.random.default_rng(4)
+    for _ in range(400):
+        p = 10 ** rng.uniform(1.0, 7.5)
+        Y = rng.choice([0.0, 1.0, rng.uniform(0, 1), 10 ** rng.uniform(-9, -1)])
+        rho = L.og_baro_density(C.byref(e), p, Y)
+        rl = L.og_baro_liquid_density(C.byref(e), p)
+        # volume fractions from the densities of the components at p
+        aG = Y * rho / (p / RT)
+        assert rho == pytest.approx(aG * p / RT + (1.0 - aG) * rl, rel=1e-12)
+        pp = pressure(e, rho, Y)
+        assert pp == pytest.approx(p, rel=1e-9)
+        # the one-fluid equation of Section 2.2 at the recovered pressure
+        lhs = (1.0 - rho * Y * RT / pp) * L.og_baro_liquid_density(C.byref(e), pp)
+        assert lhs == pytest.approx((1.0 - Y) * rho, rel=1e-8, abs=1e-9 * rho)
+        a, _ = fractions(e, rho, Y, pp)
+        assert a == pytest.approx(aG, rel=1e-8, abs=1e-12)
+
+
+def test_continuous_across_the_saturation_pressure():
+    e = make_eos(EOS)
+    L = lib()
+    for Y in (0.0, 1e-4, 0.3):
+        r0 = L.og_baro_density(C.byref(e), PS, Y)
+        lo, hi = pressure(e, r0 * (1 - 1e-12), Y), pressure(e, r0 * (1 + 1e-12), Y)
+        assert lo <= PS * (1 + 1e-9) and hi >= PS * (1 - 1e-9)
+        assert abs(hi - lo) < 1e-6 * PS * (1 + CL * CL * r0 / PS * 1e-12 * 10)
+
+
+def test_vapour_fraction():
+    """eq. 2-7: (1 - alpha_G)(rho_sat - rho_M)/(rho_sat - rho_vap) in the
+    mixture, 0 in compressed liquid, at most 0.995"""
+    e = make_eos(EOS)
+    L = lib()
+    p = 0.5 * PS
+    rM = RS * p / PS
+    _, v = fractions(e, rM, 0.0, p)
+    assert v == pytest.approx((RS - rM) / (RS - RV), rel=1e-12)
+    rho = L.og_baro_density(C.byref(e), p, 0.2)
+    a, v = fractions(e, rho, 0.2, p)
+    assert v == pytest.approx((1 - a) * (RS - rM) / (RS - RV), rel=1e-12)
+    _, v = fractions(e, 1001.0, 0.0, pressure(e, 1001.0, 0.0))
+    assert v == 0.0
+    _, v = fractions(e, 1.0, 0.0, pressure(e, 1.0, 0.0))
+    assert v == 0.995
+
+
+def test_sound_speed_is_the_largest_component_speed():
+    e = make_eos(EOS)
+    L = lib()
+    assert L.og_baro_sound(C.byref(e), 1e5) == CL
+    assert L.og_baro_sound(C.byref(e), 0.5 * PS) == pytest.approx(max(np.sqrt(PS / RS), np.sqrt(RT)))
+
+
+def random_baro(dim, n, seed, **kw):
+    return W.random_state(dim, n, seed, barotropic=True, **kw)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_uniform_state_is_stationary(dim):
+    n = {1: [20], 2: [12, 9], 3: [7, 6, 5]}[dim]
+    c = random_baro(dim, n, 3)
+    xs = W.cell_centres(c["grid"])
+    for p in (1e5, 0.4 * PS):
+        u = [np.full_like(xs[0], 3.0 - d) for d in range(dim)]
+        c["prim"] = W.pack_prim(np.full_like(xs[0], p), np.zeros_like(xs[0]), np.full_like(xs[0], 0.3), u)
+        o = Oracle(c)
+        q = o.cons_from_prim()
+        assert q.shape[0] == dim + 2
+        r = o.rhs(q)
+        scale = np.abs(q).max(axis=1, keepdims=True) / c["grid"]["dx"][0] * 1e-13 * 100
+        assert np.all(np.abs(r) <= scale)
+
+
+def test_gas_liquid_interface_advection_keeps_pressure_and_velocity():
+    """a liquid slab in gas moving at 20 m/s through a periodic box at uniform
+    p: the TDU face density (eq. 3-5) keeps p and u uniform to round-off"""
+    n = 100
+    g = W.make_grid(1, [n], [1.0], [[W.BC_PERIODIC, W.BC_PERIODIC]])
+    x = W.cell_centres(g)[0]
+    alpha = 1.0 - (1.0 - W.smeared(x - 0.7, 0.01)) * W.smeared(x - 0.3, 0.01)
+    prim = W.pack_prim(np.full(n, 1e5), np.zeros(n), alpha, [np.full(n, 20.0)])
+    case = dict(name="adv_baro", grid=g, eos=W.baro_eos(), scheme=W.default_scheme(), prim=prim,
+                steps=None, t_end=0.0, storage=dict(p_ref=1e5, T_ref=0.0))
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    tot0 = o.totals(q)
+    o.run(q, 200)
+    w = o.prim_from_cons(q)
+    assert np.abs(w[4] - 1e5).max() < 1e-12 * CL * CL * RS * 1e-3
+    assert np.abs(w[1] - 20.0).max() < 1e-11 * 20.0
+    np.testing.assert_allclose(o.totals(q), tot0, rtol=1e-13, atol=1e-13 * np.abs(tot0).max())
+
+
+@pytest.mark.parametrize("dim,switching,sigma", [(1, 0, 0.0), (2, 1, 0.0), (2, 1, 0.05), (3, 1, 0.0)])
+def test_conservation_on_periodic_domains(dim, switching, sigma):
+    n = {1: [64], 2: [20, 16], 3: [10, 9, 8]}[dim]
+    c = random_baro(dim, n, 11 + dim, switching=switching, sigma=sigma)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    tot0 = o.totals(q)
+    o.run(q, 5)
+    tot = o.totals(q)
+    scale = np.abs(tot0).max()
+    assert abs(tot[0] - tot0[0]) < 1e-13 * abs(tot0[0])
+    assert abs(tot[-1] - tot0[-1]) < 1e-13 * abs(tot0[0])
+    if sigma == 0.0:
+        np.testing.assert_allclose(tot[1:1 + dim], tot0[1:1 + dim], atol=1e-12 * scale)
+
+
+def test_liquid_acoustic_pulse_moves_at_the_liquid_sound_speed():
+    """a small right-running simple wave in the liquid (u' = p' / (rho c_L)):
+    its pressure centroid moves at c_L"""
+    n = 800
+    Lx = 8.0
+    g = W.make_grid(1, [n], [Lx], [[W.BC_PERIODIC, W.BC_PERIODIC]])
+    x = W.cell_centres(g)[0]
+    p0 = 1e5
+    dp = 50.0 * np.exp(-((x - 2.0) / 0.15) ** 2)
+    rho0 = RS + (p0 - PS) / CL ** 2
+    prim = W.pack_prim(p0 + dp, np.zeros(n), np.zeros(n), [dp / (rho0 * CL)])
+    case = dict(name="pulse", grid=g, eos=W.baro_eos(), scheme=W.default_scheme(), prim=prim,
+                steps=None, t_end=0.0, storage=dict(p_ref=p0, T_ref=0.0))
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    t = o.run(q, 400)
+    w = o.prim_from_cons(q)
+    d = w[4] - p0
+    shift = (x * d).sum() / d.sum() - 2.0
+    assert shift == pytest.approx(CL * t, rel=2e-3)
+
+
+def test_cavitating_expansion_is_mirror_symmetric_and_vaporises():
+    """two liquid columns moving apart at 1 m/s: the pressure in the middle
+    falls below p_sat and a liquid-vapour mixture forms; x -> -x, u -> -u
+    symmetry holds to round-off and the walls keep the mass"""
+    c = W.cavitation_tube_1d(200, 1.0)
+    o = Oracle(c)
+    q = o.cons_from_prim()
+    m0 = q[0].sum()
+    o.run(q, 40)
+    w = o.prim_from_cons(q)
+    assert w[4].min() < PS and w[11].max() > 0.0
+    np.testing.assert_allclose(w[0], w[0][::-1], rtol=1e-12)
+    np.testing.assert_allclose(w[1], -w[1][::-1], atol=1e-12)
+    assert abs(q[0].sum() - m0) < 1e-12 * m0
+
+
+def test_liquid_vapour_face_density_is_the_thinc_value():
+    """Remark 1: across an eligible liquid-vapour cell (eps < alpha_V < 1 - eps,
+    monotone) the face density is the THINC value of rho (eq. 3-7), otherwise
+    the TDU value rho(p*, xi_f) (eq. 3-5)"""
+    L = lib()
+    e = make_eos(EOS)
+    s = make_scheme(W.default_scheme())
+    Wst = np.zeros((4, 12))
+    ps = [0.3 * PS, 0.5 * PS, 0.7 * PS, 0.9 * PS]
+    for m in range(4):
+        rho = RS * ps[m] / PS
+        Wst[m, 0], Wst[m, 1], Wst[m, 4] = rho, 2.0, ps[m]
+        Wst[m, 7] = L.og_baro_sound(C.byref(e), ps[m])
+        Wst[m, 11] = (RS - rho) / (RS - RV)
+    F = np.zeros(7)
+    us, pst = C.c_double(), C.c_double()
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    for bits in (0, 2):
+        assert L.og_face_flux_baro(C.byref(e), C.byref(s), 1, 0, dp(np.ascontiguousarray(Wst)), 1, bits, 0,
+                                   dp(F), C.byref(us), C.byref(pst)) == 0
+        assert us.value > 0
+        rf = F[0] / us.value
+        if bits:
+            th = L.og_thinc_left(Wst[0, 0], Wst[1, 0], Wst[2, 0], s.beta, s.thinc_gamma)
+            assert rf == pytest.approx(th, rel=1e-14)
+        else:
+            assert rf == pytest.approx(L.og_baro_density(C.byref(e), pst.value, 0.0), rel=1e-14)
+        assert F[1] == pytest.approx(F[0] * 2.0 + pst.value, rel=1e-12)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FVM_VERSION 2
+#define FVM_VERSION 3
 
 enum {
   FVM_OK = 0,
@@ -55,6 +55,7 @@ enum { FVM_FP64 = 0,      /* FP64 storage and arithmetic */
 
 enum { FVM_BC_PERIODIC = 0, FVM_BC_WALL = 1, FVM_BC_ZEROGRAD = 2, FVM_BC_INFLOW = 3, FVM_BC_FARFIELD = 4 };
 enum { FVM_EOS_SG = 0, FVM_EOS_PR = 1 };
+enum { FVM_MODEL_FOUR_EQ = 0, FVM_MODEL_BAROTROPIC = 1 };
 enum { FVM_LIM_MINMOD = 0, FVM_LIM_KOREN = 1, FVM_LIM_VANALBADA = 2, FVM_LIM_VANLEER = 3,
        FVM_LIM_CHAKRAVARTHY = 4, FVM_LIM_MC = 5, FVM_LIM_SUPERBEE = 6, FVM_LIM_NONE = 7 };
 
@@ -106,7 +107,24 @@ typedef struct fvm_grid_desc {
  * rho xi_1, rho xi_2), the primitive input gains alpha_2 after u, the
  * primitive output gains xi_2 and alpha_2 (11 rows), and the mixing above is
  * (1 - alpha_1 - alpha_2) value_0 + alpha_1 value_1 + alpha_2 value_2.  Three
- * components are supported in 1D and 2D (FVM_EINVAL in 3D). */
+ * components are supported in 1D and 2D (FVM_EINVAL in 3D).
+ * model: FVM_MODEL_FOUR_EQ (0, everything above) or FVM_MODEL_BAROTROPIC, the
+ * barotropic equilibrium model of Section 2.2 (eqs. 2-3 .. 2-7), which
+ * replaces the components above (kind, gamma, pinf, cv, q, PR data and T_ref
+ * are ignored; mu and kc must be 0; ncomp must be 0 or 2): a liquid with
+ * rho = bt_rho_sat + (p - bt_p_sat) / bt_c_liq^2 at p >= bt_p_sat that is a
+ * liquid-vapour mixture below it (the same law with c_M^2 = p_sat / rho_sat),
+ * and one isothermal ideal gas rho_G = p / bt_RT (bt_RT = R_Gas T_ref).
+ * There is no energy equation: N_q = D + 2 (rho, rho u, rho xi); p follows
+ * from (rho, xi); the T row of the primitive input is ignored; the primitive
+ * output has 12 rows (the 11 above with T = xi_2 = alpha_2 = 0, then the
+ * vapour volume fraction of eq. 2-7, at most 0.995).  Where the upwind cell
+ * of a face is a liquid-vapour interface cell (eps < alpha_V < 1 - eps, and
+ * alpha_V and rho monotone through it) the face density is the THINC value
+ * of rho (eqs. 3-7, 3-8, Remarks 1-2), elsewhere rho(p*, xi_face).  FP32
+ * storage (FVM_MIXED) keeps the liquid's partial density relative to its
+ * density at p_ref.  Requires bt_rho_sat > 0, bt_p_sat > 0, bt_c_liq > 0,
+ * 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0; 1D and 2D only (FVM_EINVAL in 3D). */
 typedef struct fvm_eos_desc {
   int kind[3];
   double gamma[3], pinf[3], cv[3], q[3];
@@ -118,11 +136,14 @@ typedef struct fvm_eos_desc {
   double p_ref, T_ref;
   double mu[3], kc[3];
   int ncomp;
+  int model;
+  double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
 } fvm_eos_desc;
 
 /* Scheme parameters (Section 3.3, Appendix D; defaults in brackets):
  * switching: 0 = discontinuous branch at every face (Section 3), 1 = sensor
- * switching of eq. (D.3)/(D.4) with the Ducros and gas-volume-fraction sensors;
+ * switching of eq. (D.3)/(D.4) with the Ducros and gas-volume-fraction sensors
+ * (barotropic model: also the vapour-volume-fraction sensor, threshold theta_gas);
  * lim_u / lim_s: limiter for velocities [Koren] / for p, T, xi [Minmod];
  * thinc: THINC for xi at interface cells [1]; beta [1.6], thinc_gamma [1e-20],
  * eps_interface [1e-4] (eligibility eps < xi < 1 - eps and monotone);
@@ -158,7 +179,7 @@ void fvm_destroy(fvm_ctx* ctx);
 
 /* Set the state from primitives on the host: prim[(3 + D) x ncell] =
  * (p, T, alpha_G, u_1..u_D) (three components: [(4 + D) x ncell], alpha_2
- * last); xi follows from alpha_G at the cell's (p, T).
+ * last); xi follows from alpha_G at the cell's (p, T) (barotropic model: at p).
  * Resets t and the step counter to 0.  FVM_ENONPHYS if a cell has no state. */
 int fvm_init_primitive(fvm_ctx* ctx, const double* prim_host);
 /* Set / read the conserved state (host or device arrays, [N_q x ncell] FP64).
@@ -169,7 +190,8 @@ int fvm_get_state(fvm_ctx* ctx, double* q_host);
 int fvm_get_state_device(fvm_ctx* ctx, double* q_dev);
 /* Primitives of the current state [9 x ncell] FP64 on the host:
  * rho, u_1, u_2, u_3, p, T, xi, c, alpha_G (unused velocity rows are 0);
- * three components: [11 x ncell], with xi_2 and alpha_2 appended. */
+ * three components: [11 x ncell], with xi_2 and alpha_2 appended;
+ * barotropic model: [12 x ncell], T = xi_2 = alpha_2 = 0, alpha_V last. */
 int fvm_get_primitive(fvm_ctx* ctx, double* w_host);
 
 /* One right-hand side R(q) of Algorithm 1 without time update:

@@ -93,6 +93,19 @@ static int eos_ncomp(const fvm_eos_desc* e) { return e->ncomp == 3 ? 3 : 2; }
 static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
 {
   if (!e) return fail(b, FVM_EINVAL, "eos descriptor is NULL");
+  if (e->model != FVM_MODEL_FOUR_EQ && e->model != FVM_MODEL_BAROTROPIC)
+    return fail(b, FVM_EINVAL, "unknown model");
+  if (e->model == FVM_MODEL_BAROTROPIC) {
+    if (e->ncomp != 0 && e->ncomp != 2) return fail(b, FVM_EINVAL, "the barotropic model has one gas (ncomp 2)");
+    if (!(e->bt_rho_sat > 0.0) || !(e->bt_p_sat > 0.0) || !(e->bt_c_liq > 0.0) || !(e->bt_RT > 0.0) ||
+        !(e->bt_rho_vap >= 0.0) || !(e->bt_rho_vap < e->bt_rho_sat) || !std::isfinite(e->bt_rho_sat) ||
+        !std::isfinite(e->bt_p_sat) || !std::isfinite(e->bt_c_liq) || !std::isfinite(e->bt_RT))
+      return fail(b, FVM_EINVAL, "barotropic model needs rho_sat, p_sat, c_liq, RT > 0 and 0 <= rho_vap < rho_sat");
+    for (int k = 0; k < 3; ++k)
+      if (e->mu[k] != 0.0 || e->kc[k] != 0.0)
+        return fail(b, FVM_EINVAL, "the barotropic model is inviscid and adiabatic (mu = kc = 0)");
+    return FVM_OK;
+  }
   if (e->ncomp != 0 && e->ncomp != 2 && e->ncomp != 3) return fail(b, FVM_EINVAL, "ncomp must be 2 or 3");
   const int nc = eos_ncomp(e);
   if (nc == 3) {
@@ -274,6 +287,10 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     if (c == 0) b->ncomp = nc;
     if (nc != b->ncomp) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the number of components"));
     if (nc == 3 && g->dim == 3) return bail(fail(b, FVM_EINVAL, "three components are supported in 1D and 2D"));
+    const int baro = eos[c].model == FVM_MODEL_BAROTROPIC;
+    if (c == 0) b->kind = baro ? FVM_KIND_BARO : FVM_KIND_SG;
+    if (baro != (b->kind == FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
+    if (baro && g->dim == 3) return bail(fail(b, FVM_EINVAL, "the barotropic model is supported in 1D and 2D"));
     CaseC& C = b->hc[c];
     std::memset(&C, 0, sizeof C);
     C.dim = g->dim;
@@ -300,16 +317,30 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     for (int d = 0; d < g->dim; ++d)
       for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
     C.ncomp = nc;
+    C.sdx2 = 0.0;
+    for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
+    if (baro) {
+      const fvm_eos_desc& e = eos[c];
+      C.model = 1;
+      C.bt_rs = e.bt_rho_sat;
+      C.bt_ps = e.bt_p_sat;
+      C.bt_cl2 = e.bt_c_liq * e.bt_c_liq;
+      C.bt_cm2 = e.bt_p_sat / e.bt_rho_sat;
+      C.bt_rv = e.bt_rho_vap;
+      C.bt_RT = e.bt_RT;
+      double cg = std::sqrt(e.bt_RT), cm = std::sqrt(C.bt_cm2);
+      C.bt_c_hi = e.bt_c_liq > cg ? e.bt_c_liq : cg;
+      C.bt_c_lo = cm > cg ? cm : cg;
+      continue;
+    }
     for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], &eos[c], k);
     C.diff = 0;
     for (int k = 0; k < nc; ++k)
       if (eos[c].mu[k] > 0.0 || eos[c].kc[k] > 0.0) C.diff = 1;
-    C.sdx2 = 0.0;
-    for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
     if (C.comp[1].kind == FVM_EOS_PR) b->kind = FVM_KIND_PR;
   }
   if (b->ncomp == 3) b->kind = FVM_KIND_THREE;
-  b->nq = b->dim + b->ncomp + 1;
+  b->nq = (b->kind == FVM_KIND_BARO) ? b->dim + 2 : b->dim + b->ncomp + 1;
   b->total = off;
   // scheme constants
   SchemeC& S = b->sc;
@@ -341,6 +372,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       pT[2 * c + 1] = eos[c].T_ref;
       any = any || (eos[c].T_ref > 0.0);
     }
+    if (b->kind == FVM_KIND_BARO) any = false;
     if (any && b->mixed) {
       if ((rc = ensure_scratch(b, sizeof(double) * 8 * ncases))) return bail(rc);
       double* dpT = (double*)b->scratch;
@@ -351,6 +383,17 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     }
     for (int c = 0; c < ncases; ++c) {
       CaseC& C = b->hc[c];
+      if (b->kind == FVM_KIND_BARO) {
+        // FP32 storage keeps the liquid's partial density relative to the
+        // liquid density at p_ref (eq. 2-3 / 2-4); the gas is unshifted
+        double pr = eos[c].p_ref, rl = 0.0;
+        if (b->mixed && pr > 0.0 && std::isfinite(pr)) {
+          double c2 = pr >= C.bt_ps ? C.bt_cl2 : C.bt_cm2;
+          rl = (double)(float)(C.bt_rs + (pr - C.bt_ps) / c2);
+        }
+        C.rref[0] = rl;
+        continue;
+      }
       // FP64 storage needs no shift; FP32 storage shifts the partial density of
       // stiff components (pinf > 0, where one FP32 ulp of density is a large
       // pressure) and the energy of both components.  Gases keep their
@@ -679,7 +722,7 @@ int fvm_get_primitive(fvm_ctx* ctx, double* w_host)
   if (!w_host) return fail(b, FVM_EINVAL, "NULL array");
   if (!b->has_state[0]) return fail(b, FVM_ESTATE, "no state set");
   const CaseC& C = b->hc[0];
-  size_t rows = b->ncomp == 3 ? 11 : 9;
+  size_t rows = b->kind == FVM_KIND_BARO ? 12 : (b->ncomp == 3 ? 11 : 9);
   size_t bytes = sizeof(double) * rows * (size_t)C.ncell;
   int rc = ensure_scratch(b, bytes);
   if (rc) return rc;

@@ -1,0 +1,772 @@
+// fvm_baro.hip -- gfx950 kernels of the barotropic cavitation model
+// (Section 2.2, eqs. 2-3 .. 2-7): a liquid that becomes a liquid-vapour
+// mixture below its saturation pressure and one isothermal ideal gas, with no
+// energy equation; face density by TDU (eq. 3-5) or, across liquid-vapour
+// interface cells, by THINC of the density (eqs. 3-7, 3-8, Remarks 1-2).
+//
+// Storage of a cell, N_q = D + 2:
+//   0: rho (1 - xi) - rref_L   liquid / mixture partial density minus a reference
+//   1: rho xi                  gas partial density
+//   2..1+D: rho u
+// One fused kernel per Runge-Kutta stage on 1D/2D tiles, shaped like the
+// four-equation kernel: tile + two-cell halo staged in LDS after the FP64
+// closure p = f(rho, xi), sensors, x and y face sweeps, CSF, body force,
+// update, and in the last stage the CFL bound of the new state.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "fvm_device.hpp"
+#include "fvm_kernels.hpp"
+#include "fvm_stage_common.hpp"
+
+namespace fvm {
+
+// ------------------------------------------------------------------ closure
+// liquid (p >= p_sat, eq. 2-3) or liquid-vapour mixture (eq. 2-4) density
+template <class R>
+__device__ inline R baro_liq(const CaseC& C, R p)
+{
+  R c2 = p >= R(C.bt_ps) ? R(C.bt_cl2) : R(C.bt_cm2);
+  return R(C.bt_rs) + fdiv(p - R(C.bt_ps), c2);
+}
+
+// density at (p, xi): 1/rho = xi R T / p + (1 - xi) / rho_L/M(p)
+template <class R>
+__device__ inline R baro_rho(const CaseC& C, R p, R Y)
+{
+  R v = R(0);
+  if (Y != R(0)) v += Y * fdiv(R(C.bt_RT), p);
+  if (Y != R(1)) v += fdiv(R(1) - Y, baro_liq<R>(C, p));
+  return frcp(v);
+}
+
+struct PB { double p, c, aG, aV; };
+
+// p = f(rho, xi): (p - a) rho_L/M(p) - b p = 0 with a = rho xi R T,
+// b = (1 - xi) rho; the sign at p = p_sat selects the branch of rho_L/M, on
+// which the equation is the quadratic p^2 + B p + C = 0 (K = rho_sat c^2 - p_sat,
+// B = K - a - b c^2, C = -a K); its positive root without cancellation.
+// Also the sound speed of impedances and CFL and the volume fractions
+// alpha_G (eq. 2-6) and alpha_V (eq. 2-7, at most 0.995).
+__device__ inline PB baro_closure(const CaseC& C, double rho, double Y)
+{
+  double Yc = Y < 0.0 ? 0.0 : (Y > 1.0 ? 1.0 : Y);
+  double a = rho * Yc * C.bt_RT, b = (1.0 - Yc) * rho;
+  double ps = C.bt_ps, rs = C.bt_rs;
+  bool liq = (ps - a) * rs - b * ps <= 0.0;
+  double c2 = liq ? C.bt_cl2 : C.bt_cm2;
+  double K = rs * c2 - ps;
+  double B = K - a - b * c2, Cc = -a * K;
+  double s = sqrt(B * B - 4.0 * Cc);
+  PB r;
+  r.p = (B <= 0.0) ? 0.5 * (-B + s) : (-2.0 * Cc) / (B + s);
+  r.c = (r.p >= ps) ? C.bt_c_hi : C.bt_c_lo;
+  r.aG = (Yc == 0.0) ? 0.0 : a / r.p;
+  double rM = baro_liq<double>(C, r.p);
+  double aV = (rM < rs) ? (1.0 - r.aG) * (rs - rM) / (rs - C.bt_rv) : 0.0;
+  r.aV = aV > 0.995 ? 0.995 : (aV < 0.0 ? 0.0 : aV);
+  return r;
+}
+
+// partial densities and momentum of a cell from (p, alpha_G, u)
+template <int D>
+__device__ inline void baro_from_prim(const CaseC& C, double p, double al, const double* u, double* q)
+{
+  double rG = p / C.bt_RT, rL = baro_liq<double>(C, p);
+  q[0] = (1.0 - al) * rL;
+  q[1] = al * rG;
+  double rho = q[0] + q[1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) q[2 + d] = rho * u[d];
+}
+
+// load one (possibly ghost) cell: physical partial densities and momentum
+template <class S, int D>
+__device__ inline void baro_load(const CaseC& C, const S* __restrict__ src, long long total, int gx, int gy,
+                                 long long step, double* q)
+{
+  if (beyond_farfield<D>(C, gx, gy, 0)) {
+    const double u0[3] = {0.0, 0.0, 0.0};
+    baro_from_prim<D>(C, C.ff_p, C.ff_alpha, u0, q);
+    return;
+  }
+  bool fx = false, fy = false;
+  int ix = gx, iy = gy;
+  if (D >= 2) map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
+  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
+    double yy = (D >= 2) ? (iy + 0.5) * C.dx[1] - C.in_c0 : 0.0;
+    if (D == 1 || fabs(yy) < C.in_radius) {
+      double u[3] = {C.in_u, 0.0, 0.0};
+      for (int c = 0; c < D; ++c)
+        u[c] += C.in_noise * C.in_u *
+                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy, 0ull,
+                               (unsigned long long)c) - 1.0);
+      baro_from_prim<D>(C, C.in_p, C.in_alpha, u, q);
+      if (D >= 2 && fy) q[3] = -q[3];
+      return;
+    }
+    ix = -1 - ix;
+    fx = true;
+  } else {
+    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
+  }
+  long long cell = C.off + ix + (long long)C.n[0] * iy;
+  q[0] = (double)src[cell] + C.rref[0];
+  q[1] = (double)src[total + cell];
+#pragma unroll
+  for (int d = 0; d < D; ++d) q[2 + d] = (double)src[(2 + d) * total + cell];
+  if (fx) q[2] = -q[2];
+  if (D >= 2 && fy) q[3] = -q[3];
+}
+
+// primitives of a loaded cell
+template <int D>
+__device__ inline PB baro_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
+{
+  rho = q[0] + q[1];
+  double ir = 1.0 / rho;
+  Y = q[1] * ir;
+#pragma unroll
+  for (int d = 0; d < D; ++d) u[d] = q[2 + d] * ir;
+  return baro_closure(C, rho, Y);
+}
+
+// ------------------------------------------------------------------ face flux
+template <class R, int D>
+struct BStencil {
+  R u[D][4];
+  R p[4], Y[4], r[4];
+  R c1, c2;
+};
+
+// One face between stencil cells 1 and 2 (Section 3.2/3.3, Appendix D, Section
+// 3.4): impedances and p*, u* as in the four-equation model; xi limited, by
+// THINC where the upwind cell is a gas interface cell (bit 0 of its
+// eligibility), second-order central in the smooth branch; the face gas
+// fraction taken in [0, 1]; face density rho(p*, xi_f) (TDU, eq. 3-5), or the
+// THINC value of rho where the upwind cell is a liquid-vapour interface cell
+// (bit 1); storage flux (m (1 - xi_f), m xi_f, m u_f + p* n), m = rho_f u*.
+// A face with p* <= 0 has no density: its flux is NaN, which the closure of
+// the updated cells reports.
+template <class R, int D, int DIR>
+__device__ inline void baro_face(const SchemeC& S, const CaseC& C, const BStencil<R, D>& s, bool disc, int el,
+                                 int er, R* F)
+{
+  R cm = fmax(s.c1, s.c2);
+  R IL = (R(3) * s.r[1] + s.r[2]) * cm * R(0.25);
+  R IR = (s.r[1] + R(3) * s.r[2]) * cm * R(0.25);
+  R iI = frcp((s.r[1] + s.r[2]) * cm);
+  R uf[D];
+  R us, ps, Yf;
+  bool left = true, lv = false;
+  if (disc) {
+    R uL[D], uR[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) recon<R>(S.lim_u, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
+    R pL, pR, YL, YR;
+    recon<R>(S.lim_s, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
+    recon<R>(S.lim_s, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
+    ps = R(0.5) * (pL + pR);
+    us = (IL * uL[DIR] + IR * uR[DIR] + pL - pR) * iI;
+    left = us >= R(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) uf[d] = left ? uL[d] : uR[d];
+    Yf = left ? YL : YR;
+    int eb = left ? el : er;
+    if (S.thinc && (eb & 1))
+      Yf = thinc_value<R>(S, left, left ? s.Y[0] : s.Y[1], left ? s.Y[1] : s.Y[2], left ? s.Y[2] : s.Y[3]);
+    lv = S.thinc && (eb & 2);
+  } else {
+    const R c12 = R(1.0 / 12.0);
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      uf[d] = (R(7) * (s.u[d][1] + s.u[d][2]) - s.u[d][0] - s.u[d][3]) * c12;
+    ps = (R(7) * (s.p[1] + s.p[2]) - s.p[0] - s.p[3]) * c12;
+    R d3p = s.p[3] - R(3) * s.p[2] + R(3) * s.p[1] - s.p[0];
+    us = uf[DIR] + R(S.k3) * d3p * iI;
+    Yf = R(0.5) * (s.Y[1] + s.Y[2]);
+  }
+  Yf = fmin(fmax(Yf, R(0)), R(1));
+  R rf;
+  if (lv) rf = thinc_value<R>(S, left, left ? s.r[0] : s.r[1], left ? s.r[1] : s.r[2], left ? s.r[2] : s.r[3]);
+  else rf = baro_rho<R>(C, ps, Yf);
+  if (!(ps > R(0))) rf = R(__builtin_nan(""));
+  R m = rf * us;
+  F[0] = m * (R(1) - Yf);
+  F[1] = m * Yf;
+#pragma unroll
+  for (int d = 0; d < D; ++d) F[2 + d] = m * uf[d] + (d == DIR ? ps : R(0));
+}
+
+// THINC eligibility bits of the middle cell of (a, b, c): bit 0 gas fraction,
+// bit 1 liquid-vapour interface (vapour fraction and density both monotone)
+template <class R>
+__device__ inline int baro_elig(R Ya, R Yb, R Yc, R va, R vb, R vc, R ra, R rb, R rc, R eps)
+{
+  int e = eligible<R>(Ya, Yb, Yc, eps) ? 1 : 0;
+  if (eligible<R>(va, vb, vc, eps) && (rb - ra) * (rc - rb) > R(0)) e |= 2;
+  return e;
+}
+
+// ------------------------------------------------------------------ fused 1D/2D stage
+template <class S, int D, int TX, int TY, int NT, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
+{
+  static_assert(D == 1 || D == 2, "1D/2D kernel");
+  static_assert(D == 2 || TY == 1, "1D tiles are one row");
+  constexpr int HX = TX + 4, HY = (D == 2) ? TY + 4 : 1, NH = HX * HY;
+  constexpr int NQ = D + 2;
+  constexpr int NC = TX * TY;
+  constexpr int CPT = (NC + NT - 1) / NT;
+  constexpr int NIT = (NH + NT - 1) / NT;
+  constexpr int NFX = (TX + 1) * TY, NFY = (D == 2) ? TX * (TY + 1) : 0;
+  constexpr int NF = NFX > NFY ? NFX : NFY;
+  constexpr int OY = (D == 2) ? 2 : 0;
+  constexpr int FX = TX + 2, FY = (D == 2) ? TY + 2 : 1;
+  constexpr int VX = TX + 1, VY = (D == 2) ? TY + 1 : 1;
+  static_assert(FX * FY + D * VX * VY <= NQ * NF, "CSF scratch fits in the flux buffer");
+
+  __shared__ S s_rho[NH], s_u[NH], s_v[D == 2 ? NH : 1], s_p[NH], s_Y[NH], s_c[NH], s_a[NH], s_av[NH];
+  __shared__ unsigned char s_fl[NH];
+  __shared__ S s_F[NQ][NF];
+  __shared__ double s_red[NT / 64];
+
+  const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const SchemeC& SC = a.sc;
+  const int x0 = tl.y * TX, y0 = tl.z * TY;
+  const int tid = threadIdx.x;
+  const bool upd = a.stage >= 0;
+  const long long step = upd ? dy.base + a.step_off : a.rhs_step;
+  const S* __restrict__ src = (const S*)a.src;
+  const long long T = a.total;
+
+  S qn_reg[CPT][NQ];
+  if (upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      int gx = x0 + cc % TX, gy = y0 + cc / TX;
+      bool own = cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1]);
+      long long cell = C.off + (own ? gx + (long long)C.n[0] * gy : 0);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+    }
+  }
+
+  // ---- tile + halo: loads, FP64 closure, primitives to LDS
+  {
+    double qv[NIT][NQ];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        int hx = h % HX, hy = h / HX;
+        baro_load<S, D>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, step, qv[it]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        double u[D], rho, Y;
+        PB pb = baro_prim<D>(C, qv[it], u, rho, Y);
+        s_rho[h] = S(rho);
+        s_u[h] = S(u[0]);
+        if (D == 2) s_v[h] = S(u[D - 1]);
+        s_p[h] = S(pb.p);
+        s_Y[h] = S(Y);
+        s_c[h] = S(pb.c);
+        s_a[h] = S(pb.aG);
+        s_av[h] = S(pb.aV);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- switching sensors (Appendix D: Ducros, gas and vapour volume fractions)
+  if (SC.switching) {
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+      S idx2 = S(0.5 * C.idx[0]);
+      S div = (s_u[c + 1] - s_u[c - 1]) * idx2, curl2 = S(0);
+      S thg = fabs(s_a[c] - s_a[c - 1]) + fabs(s_a[c + 1] - s_a[c]);
+      S thv = fabs(s_av[c] - s_av[c - 1]) + fabs(s_av[c + 1] - s_av[c]);
+      if (D == 2) {
+        S idy2 = S(0.5 * C.idx[1]);
+        S dvdy = (s_v[c + HX] - s_v[c - HX]) * idy2;
+        S dvdx = (s_v[c + 1] - s_v[c - 1]) * idx2;
+        S dudy = (s_u[c + HX] - s_u[c - HX]) * idy2;
+        div += dvdy;
+        S w = dvdx - dudy;
+        curl2 = w * w;
+        thg += fabs(s_a[c] - s_a[c - HX]) + fabs(s_a[c + HX] - s_a[c]);
+        thv += fabs(s_av[c] - s_av[c - HX]) + fabs(s_av[c + HX] - s_av[c]);
+      }
+      S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
+      s_fl[c] = (thd > S(SC.th_d) || thv > S(SC.th_g) || thg > S(SC.th_g)) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+
+  S R[CPT][NQ];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
+
+  const S eps = S(SC.eps_int);
+  // stencil of the face between LDS cells c and c + st (cells c - st .. c + 2 st)
+  auto stencil = [&](int c, int st, BStencil<S, D>& bs, int& el, int& er) {
+    S av[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      int cm = c + (m - 1) * st;
+      bs.u[0][m] = s_u[cm];
+      if (D == 2) bs.u[D - 1][m] = s_v[cm];
+      bs.p[m] = s_p[cm];
+      bs.Y[m] = s_Y[cm];
+      bs.r[m] = s_rho[cm];
+      av[m] = s_av[cm];
+    }
+    bs.c1 = s_c[c];
+    bs.c2 = s_c[c + st];
+    el = baro_elig<S>(bs.Y[0], bs.Y[1], bs.Y[2], av[0], av[1], av[2], bs.r[0], bs.r[1], bs.r[2], eps);
+    er = baro_elig<S>(bs.Y[1], bs.Y[2], bs.Y[3], av[1], av[2], av[3], bs.r[1], bs.r[2], bs.r[3], eps);
+  };
+  auto xface = [&](int f) {
+    int i = f % (TX + 1), j = f / (TX + 1);
+    int c = (j + OY) * HX + i + 1;
+    BStencil<S, D> bs;
+    int el, er;
+    stencil(c, 1, bs, el, er);
+    bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
+    S F[NQ];
+    baro_face<S, D, 0>(SC, C, bs, disc, el, er, F);
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+  };
+  for_faces<NFX, NT>(tid, xface);
+  __syncthreads();
+  {
+    S ix = S(C.idx[0]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int f = (cc / TX) * (TX + 1) + cc % TX;
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + 1]) * ix;
+      }
+    }
+  }
+  if (D == 2) {
+    __syncthreads();
+    auto yface = [&](int f) {
+      int i = f % TX, j = f / TX;
+      int c = (j + 1) * HX + i + 2;
+      BStencil<S, D> bs;
+      int el, er;
+      stencil(c, HX, bs, el, er);
+      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
+      S F[NQ];
+      baro_face<S, D, D - 1>(SC, C, bs, disc, el, er, F);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+    };
+    for_faces<NFY, NT>(tid, yface);
+    __syncthreads();
+    S iy = S(C.idx[D - 1]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int f = cc;
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + TX]) * iy;
+      }
+    }
+  }
+
+  // ---- CSF (Section 3.5): kappa from the Gaussian-smoothed xi, force sigma kappa grad(alpha_G)
+  if (SC.sigma > 0.0) {
+    __syncthreads();
+    S* s_H = &s_F[0][0];
+    S* s_nx = s_H + FX * FY;
+    S* s_ny = s_nx + VX * VY;
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+      S acc;
+      if (D == 1) {
+        acc = (s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1]) * S(0.25);
+      } else {
+        S r0 = s_Y[c - HX - 1] + S(2) * s_Y[c - HX] + s_Y[c - HX + 1];
+        S r1 = s_Y[c - 1] + S(2) * s_Y[c] + s_Y[c + 1];
+        S r2 = s_Y[c + HX - 1] + S(2) * s_Y[c + HX] + s_Y[c + HX + 1];
+        acc = (r0 + S(2) * r1 + r2) * S(1.0 / 16.0);
+      }
+      s_H[h] = acc;
+    }
+    __syncthreads();
+    S en = S(SC.eps_n * C.idx[0]);
+    for (int h = tid; h < VX * VY; h += NT) {
+      int vx = h % VX, vy = h / VX;
+      int c = vy * FX + vx;
+      S gx, gy = S(0);
+      if (D == 1) {
+        gx = (s_H[c + 1] - s_H[c]) * S(C.idx[0]);
+      } else {
+        gx = (s_H[c + 1] + s_H[c + FX + 1] - s_H[c] - s_H[c + FX]) * S(0.5 * C.idx[0]);
+        gy = (s_H[c + FX] + s_H[c + FX + 1] - s_H[c] - s_H[c + 1]) * S(0.5 * C.idx[1]);
+      }
+      S inv = frcp(sqrt(gx * gx + gy * gy) + en);
+      s_nx[h] = gx * inv;
+      if (D == 2) s_ny[h] = gy * inv;
+    }
+    __syncthreads();
+    S sig = S(SC.sigma);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = cc / TX;
+        int c = (j + OY) * HX + i + 2;
+        if (D == 1) {
+          S kap = -(s_nx[i + 1] - s_nx[i]) * S(C.idx[0]);
+          R[k][2] += sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
+        } else {
+          int v = (j + 1) * VX + (i + 1);
+          S dnx = s_nx[v] + s_nx[v - VX] - s_nx[v - 1] - s_nx[v - VX - 1];
+          S dny = s_ny[v] + s_ny[v - 1] - s_ny[v - VX] - s_ny[v - VX - 1];
+          S kap = -(dnx * S(0.5 * C.idx[0]) + dny * S(0.5 * C.idx[1]));
+          R[k][2] += sig * kap * (s_a[c + 1] - s_a[c - 1]) * S(0.5 * C.idx[0]);
+          R[k][3] += sig * kap * (s_a[c + HX] - s_a[c - HX]) * S(0.5 * C.idx[1]);
+        }
+      }
+    }
+  }
+
+  // ---- body force (eq. 2-2, source Q): rho g on the momentum
+  if (SC.has_grav) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int c = (cc / TX + OY) * HX + cc % TX + 2;
+#pragma unroll
+        for (int d = 0; d < D; ++d) R[k][2 + d] += s_rho[c] * S(SC.grav[d]);
+      }
+    }
+  }
+
+  // ---- output
+  if (!upd) {
+    // right-hand side in the conserved variables (rho, rho u, rho xi), FP64
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      int i = cc % TX, j = cc / TX;
+      int gx = x0 + i, gy = y0 + j;
+      if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
+        const long long RS = C.ncell;
+        long long cell = gx + (long long)C.n[0] * gy;
+        double r0 = (double)R[k][0], r1 = (double)R[k][1];
+        a.rhs_out[cell] = r0 + r1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
+        a.rhs_out[(1 + D) * RS + cell] = r1;
+      }
+    }
+    return;
+  }
+  const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
+  if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
+  S* dst = (S*)a.dst;
+  const S adt = S(a.ak * dt);
+  double lam = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int cc = tid + k * NT;
+    int i = cc % TX, j = cc / TX;
+    int gx = x0 + i, gy = y0 + j;
+    if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
+      long long cell = C.off + gx + (long long)C.n[0] * gy;
+      S nv[NQ];
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        nv[v] = qn_reg[k][v] + adt * R[k][v];
+        dst[v * T + cell] = nv[v];
+      }
+      if (a.stage == 3) {
+        double q[NQ], u[D], rho, Y;
+        q[0] = (double)nv[0] + C.rref[0];
+#pragma unroll
+        for (int v = 1; v < NQ; ++v) q[v] = (double)nv[v];
+        PB pb = baro_prim<D>(C, q, u, rho, Y);
+        double l = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+        if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, cell - C.off, step);
+        else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, cell - C.off, step);
+        else lam = fmax(lam, l);
+      }
+    }
+  }
+  if (a.stage == 3) {
+    lam = wave_max(lam);
+    if ((tid & 63) == 0) s_red[tid >> 6] = lam;
+    __syncthreads();
+    if (tid == 0) {
+      double m = s_red[0];
+      for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
+      cfl_max(dy, (int)((step + 1) & 1), m);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ per-cell kernels of one case
+template <class S, int D>
+__global__ void k_baro_prim_to_state(const CaseC* cases, int icase, const double* __restrict__ prim,
+                                     S* __restrict__ dst, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  double u[3] = {0, 0, 0}, q[D + 2];
+  for (int d = 0; d < D; ++d) u[d] = prim[(3 + d) * C.ncell + c];
+  baro_from_prim<D>(C, prim[c], prim[2 * C.ncell + c], u, q);
+  long long g = C.off + c;
+  dst[g] = S(q[0] - C.rref[0]);
+  for (int v = 1; v < D + 2; ++v) dst[v * total + g] = S(q[v]);
+}
+
+template <class S, int D>
+__global__ void k_baro_cons_to_state(const CaseC* cases, int icase, const double* __restrict__ qin,
+                                     S* __restrict__ dst, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double rY = qin[(1 + D) * n + c];
+  dst[g] = S(qin[c] - rY - C.rref[0]);
+  dst[total + g] = S(rY);
+  for (int d = 0; d < D; ++d) dst[(2 + d) * total + g] = S(qin[(1 + d) * n + c]);
+}
+
+template <class S, int D>
+__global__ void k_baro_state_to_cons(const CaseC* cases, int icase, const S* __restrict__ src,
+                                     double* __restrict__ qout, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g];
+  qout[c] = rL + rG;
+  for (int d = 0; d < D; ++d) qout[(1 + d) * n + c] = (double)src[(2 + d) * total + g];
+  qout[(1 + D) * n + c] = rG;
+}
+
+template <class S, int D>
+__device__ inline void baro_own(const CaseC& C, const S* __restrict__ src, long long total, long long g, double* q)
+{
+  q[0] = (double)src[g] + C.rref[0];
+  for (int v = 1; v < D + 2; ++v) q[v] = (double)src[v * total + g];
+}
+
+// primitive rows: rho, u, v, w, p, T (0), xi, c, alpha_G, xi_2 (0), alpha_2 (0), alpha_V
+template <class S, int D>
+__global__ void k_baro_state_to_prim(const CaseC* cases, int icase, const S* __restrict__ src,
+                                     double* __restrict__ w, long long total)
+{
+  const CaseC& C = cases[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= C.ncell) return;
+  long long n = C.ncell, g = C.off + c;
+  double q[D + 2], u[D], rho, Y;
+  baro_own<S, D>(C, src, total, g, q);
+  PB pb = baro_prim<D>(C, q, u, rho, Y);
+  w[c] = rho;
+  for (int d = 0; d < 3; ++d) w[(1 + d) * n + c] = d < D ? u[d] : 0.0;
+  w[4 * n + c] = pb.p;
+  w[5 * n + c] = 0.0;
+  w[6 * n + c] = Y;
+  w[7 * n + c] = pb.c;
+  w[8 * n + c] = pb.aG;
+  w[9 * n + c] = 0.0;
+  w[10 * n + c] = 0.0;
+  w[11 * n + c] = pb.aV;
+}
+
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_baro_dt_init(const CaseC* cases, CaseDyn* dyn, int icase,
+                                                      const S* __restrict__ src, long long total,
+                                                      long long label_off)
+{
+  __shared__ double s_red[4];
+  const CaseC& C = cases[icase];
+  CaseDyn& dy = dyn[icase];
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double lam = 0.0;
+  if (c < C.ncell) {
+    double q[D + 2], u[D], rho, Y;
+    baro_own<S, D>(C, src, total, C.off + c, q);
+    PB pb = baro_prim<D>(C, q, u, rho, Y);
+    double l = 0.0;
+    for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+    if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, c, dy.base + label_off);
+    else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, c, dy.base + label_off);
+    else lam = l;
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+    cfl_max(dy, (int)(dy.base & 1), m);
+  }
+}
+
+// deterministic conserved totals (rho, rho u, rho xi) of one case, partial sums per block
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_baro_totals_part(const CaseC* cases, int icase, const S* __restrict__ src,
+                                                          long long total, double* __restrict__ part)
+{
+  constexpr int NQ = D + 2;
+  __shared__ double s[NQ][256];
+  const CaseC& C = cases[icase];
+  double acc[NQ];
+  for (int v = 0; v < NQ; ++v) acc[v] = 0.0;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < C.ncell; c += 256ll * gridDim.x) {
+    long long g = C.off + c;
+    double rL = (double)src[g] + C.rref[0], rG = (double)src[total + g];
+    acc[0] += rL + rG;
+    for (int d = 0; d < D; ++d) acc[1 + d] += (double)src[(2 + d) * total + g];
+    acc[1 + D] += rG;
+  }
+  for (int v = 0; v < NQ; ++v) s[v][threadIdx.x] = acc[v];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int v = 0; v < NQ; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int v = 0; v < NQ; ++v) part[blockIdx.x * NQ + v] = s[v][0];
+}
+
+template <class S, int D, int TX, int TY, int NT, int MINW>
+static hipError_t launch_b(const StageArgs& a, int ntiles, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_baro12<S, D, TX, TY, NT, MINW>), dim3(ntiles), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+// the same tile shapes (and indices) as the four-equation kernel
+template <class S>
+static hipError_t stage_b(int dim, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (dim == 1) {
+    switch (tile) {
+      case 0: return launch_b<S, 1, 256, 1, 256, 4>(a, ntiles, st);
+      case 1: return launch_b<S, 1, 128, 1, 128, 4>(a, ntiles, st);
+      case 2: return launch_b<S, 1, 128, 1, 256, 4>(a, ntiles, st);
+    }
+  } else if (dim == 2) {
+    switch (tile) {
+      case 0: return launch_b<S, 2, 32, 8, 256, 4>(a, ntiles, st);
+      case 1: return launch_b<S, 2, 16, 8, 256, 4>(a, ntiles, st);
+      case 2: return launch_b<S, 2, 64, 4, 256, 4>(a, ntiles, st);
+      case 3: return launch_b<S, 2, 16, 16, 256, 4>(a, ntiles, st);
+      case 4: return launch_b<S, 2, 32, 16, 256, 2>(a, ntiles, st);
+      case 5: return launch_b<S, 2, 32, 4, 256, 4>(a, ntiles, st);
+      case 6: return launch_b<S, 2, 32, 8, 320, 5>(a, ntiles, st);
+      case 7: return launch_b<S, 2, 16, 16, 320, 5>(a, ntiles, st);
+      case 8: return launch_b<S, 2, 32, 8, 384, 6>(a, ntiles, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fvm
+
+using namespace fvm;
+
+static unsigned blocks_b(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t fvm_kb_stage(int dim, int mixed, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  return mixed ? stage_b<float>(dim, tile, a, ntiles, st) : stage_b<double>(dim, tile, a, ntiles, st);
+}
+
+#define FVM_BDISPATCH(MIXED, DIM, CALL)                      \
+  do {                                                       \
+    if (MIXED) {                                             \
+      if (DIM == 1) { CALL(float, 1); } else { CALL(float, 2); } \
+    } else {                                                 \
+      if (DIM == 1) { CALL(double, 1); } else { CALL(double, 2); } \
+    }                                                        \
+  } while (0)
+
+hipError_t fvm_kb_prim_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                                const double* prim, void* dst, long long total, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_prim_to_state<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_kb_cons_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                                const double* q, void* dst, long long total, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_cons_to_state<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_kb_state_to_cons(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                                const void* src, double* q, long long total, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_state_to_cons<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_kb_state_to_prim(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
+                                const void* src, double* w, long long total, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_state_to_prim<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_kb_dt_init(int dim, int mixed, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
+                          const void* src, long long total, long long label_off, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_dt_init<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t fvm_kb_totals_part(int dim, int mixed, const CaseC* cases, int icase, const void* src, long long total,
+                              double* part, int nblk, hipStream_t st)
+{
+  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+#define CALL(S, D) hipLaunchKernelGGL((k_baro_totals_part<S, D>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
+  FVM_BDISPATCH(mixed, dim, CALL);
+#undef CALL
+  return hipGetLastError();
+}

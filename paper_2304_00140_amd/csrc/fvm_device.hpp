@@ -64,6 +64,11 @@ struct CaseC {
   int tile0, tiles[3];
   int diff;            // some component is viscous or conducting
   double sdx2;         // sum_d 1 / dx_d^2 over the used directions
+  // barotropic model (Section 2.2; model = 1): saturated liquid density and
+  // pressure, c_L^2, c_M^2 = p_sat / rho_sat, saturated vapour density, R T of
+  // the gas, and the sound speed of impedances and CFL at p >= p_sat / below
+  int model;
+  double bt_rs, bt_ps, bt_cl2, bt_cm2, bt_rv, bt_RT, bt_c_hi, bt_c_lo;
 };
 
 // per-case scalars that live on the device across steps; slot s = step & 1

@@ -20,9 +20,10 @@ struct StageArgs {
   fvm::SchemeC sc;
 };
 
-// closure of a batch: stiffened-gas pair, Peng-Robinson component 1, or a
-// liquid with two ideal gases (three components, one more storage field)
-enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2 };
+// closure of a batch: stiffened-gas pair, Peng-Robinson component 1, a
+// liquid with two ideal gases (three components, one more storage field), or
+// the barotropic model (no energy field; its own kernels, 1D/2D)
+enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2, FVM_KIND_BARO = 3 };
 
 int fvm_k_tile_count(int dim);
 int fvm_k_tile_shape(int dim, int tile, int* tx, int* ty, int* nt);
@@ -50,3 +51,18 @@ hipError_t fvm_k_totals(int dim, int mixed, int kind, const fvm::CaseC* cases, i
                         long long total, double* part, int nblk, double vol, double* out, hipStream_t st);
 hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /* [ncases][6] */,
                            const double* pT /* [ncases][2] */, hipStream_t st);
+
+// barotropic model (fvm_baro.hip), 1D and 2D
+hipError_t fvm_kb_stage(int dim, int mixed, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+hipError_t fvm_kb_prim_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                                const double* prim, void* dst, long long total, hipStream_t st);
+hipError_t fvm_kb_cons_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                                const double* q, void* dst, long long total, hipStream_t st);
+hipError_t fvm_kb_state_to_cons(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                                const void* src, double* q, long long total, hipStream_t st);
+hipError_t fvm_kb_state_to_prim(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+                                const void* src, double* w, long long total, hipStream_t st);
+hipError_t fvm_kb_dt_init(int dim, int mixed, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
+                          long long ncell, const void* src, long long total, long long label_off, hipStream_t st);
+hipError_t fvm_kb_totals_part(int dim, int mixed, const fvm::CaseC* cases, int icase, const void* src,
+                              long long total, double* part, int nblk, hipStream_t st);

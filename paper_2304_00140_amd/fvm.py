@@ -36,7 +36,8 @@ class fvm_eos_desc(C.Structure):
                 ("pr_M", (C.c_double * MAXSPEC) * 2), ("pr_Zc", (C.c_double * MAXSPEC) * 2),
                 ("pr_vc", (C.c_double * MAXSPEC) * 2), ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
                 ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 3), ("kc", C.c_double * 3),
-                ("ncomp", C.c_int)]
+                ("ncomp", C.c_int), ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
+                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double)]
 
 
 class fvm_scheme_desc(C.Structure):
@@ -144,6 +145,11 @@ def eos_desc(ed, storage=None):
     e = fvm_eos_desc()
     nc = len(ed["kind"])
     e.ncomp = nc
+    e.model = int(ed.get("model", 0))
+    if e.model == 1:
+        b = ed["baro"]
+        e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
+        e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
@@ -199,7 +205,8 @@ class Context:
         self.case = case
         self.dim = case["grid"]["dim"]
         self.ncomp = len(case["eos"]["kind"])
-        self.nq = self.dim + self.ncomp + 1
+        self.barotropic = int(case["eos"].get("model", 0)) == 1
+        self.nq = self.dim + 2 if self.barotropic else self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
         self._g = grid_desc(case["grid"])
         self._e = eos_desc(case["eos"], case.get("storage") if shifts else None)
@@ -246,7 +253,7 @@ class Context:
         self._chk(self.L.fvm_get_state_device(self._h, C.c_void_p(q_ptr)))
 
     def get_primitive(self):
-        w = np.empty((11 if self.ncomp == 3 else 9, self.ncell))
+        w = np.empty((12 if self.barotropic else (11 if self.ncomp == 3 else 9), self.ncell))
         self._chk(self.L.fvm_get_primitive(self._h, _dp(w)))
         return w
 
@@ -296,7 +303,10 @@ class Batch:
         self.cases = cases
         n = len(cases)
         self.dim = cases[0]["grid"]["dim"]
-        self.nq = self.dim + len(cases[0]["eos"]["kind"]) + 1
+        if int(cases[0]["eos"].get("model", 0)) == 1:
+            self.nq = self.dim + 2
+        else:
+            self.nq = self.dim + len(cases[0]["eos"]["kind"]) + 1
         self._g = (fvm_grid_desc * n)(*[grid_desc(c["grid"]) for c in cases])
         self._e = (fvm_eos_desc * n)(*[eos_desc(c["eos"], c.get("storage") if shifts else None) for c in cases])
         self._s = scheme_desc(cases[0]["scheme"])

@@ -3,7 +3,7 @@
 Times every tile shape of the context's dimension on the path that production
 runs take (fvm_n_steps: HIP-graph replays of whole steps; the state advances)
 and keeps the fastest.  Choices are cached per (dimension, precision,
-switching, CSF on, closure kinds, stress terms on, cell count): in memory for the process and in
+switching, CSF on, closure kinds or the barotropic model, stress terms on, cell count): in memory for the process and in
 tune_cache.json beside this file, which the tuner writes when asked
 (`save=True`) and every later run reads, so that a benchmark or a profile
 uses the same launch shape as the run that chose it.
@@ -32,8 +32,8 @@ def key_of(handle, precision):
     s = case["scheme"]
     e = case["eos"]
     diff = any(v > 0 for v in list(e.get("mu", [])) + list(e.get("kc", [])))
-    return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, tuple(e["kind"]), diff,
-            int(ncell))
+    kinds = ("barotropic",) if int(e.get("model", 0)) == 1 else tuple(e["kind"])
+    return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, kinds, diff, int(ncell))
 
 
 def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, save=False):

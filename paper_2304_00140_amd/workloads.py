@@ -343,7 +343,7 @@ def vapour_bubble_wall_2d(nx=1024, ny=512, steps=2000, dx=4e-6, R=400e-6, H=440e
     p = p_inf + (p_b - p_inf) R / r in between; the other sides are a far-field
     reservoir at p_inf."""
     g = make_grid(2, [nx, ny], [nx * dx, ny * dx], [[BC_FARFIELD, BC_FARFIELD], [BC_WALL, BC_FARFIELD]])
-    g["farfield"] = dict(p=p_inf, T=0.0, alpha=0.0)
+    g["farfield"] = dict(p=p_inf, T=293.15, alpha=0.0)   # T is not used by the barotropic model
     x, y = cell_centres(g)
     r = np.hypot(x - 0.5 * nx * dx, y - H)
     inside = 1.0 - smeared(r - R, dx)
@@ -351,7 +351,7 @@ def vapour_bubble_wall_2d(nx=1024, ny=512, steps=2000, dx=4e-6, R=400e-6, H=440e
     p = p_b * inside + p_liq * (1.0 - inside)
     z = np.zeros_like(x)
     prim = pack_prim(p, z, z, [z, z])
-    return dict(name="vapour_bubble_wall_2d", grid=g, eos=baro_eos(), scheme=default_scheme(switching=1),
+    return dict(name="vapour_bubble_wall_2d", grid=g, eos=baro_eos(), scheme=default_scheme(),
                 prim=prim, steps=steps, t_end=0.0, storage=dict(p_ref=p_inf, T_ref=0.0))
 
 

@@ -25,6 +25,7 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # Per-unit figures of the dominant kernel measured with rocprofv3 on these
 # workloads and launch shapes (profiles/k_stage12_shock_bubble_2d_counters.md,
 # profiles/k_stage12_dual_gas_layer_2d_counters.md,
+# profiles/k_baro12_vapour_bubble_wall_2d_counters.md,
 # profiles/k_face3_liquid_jet_3d_counters.md): executed VALU lane-instructions
 # per cell-stage (SQ_INSTS_VALU x 64 / cells; in 3D the closure and face kernels
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
@@ -40,6 +41,10 @@ MEASURED = {
                                                       traffic_bytes=(22485.0 * 2 + 24583.1) * 1024),
     ("dual_gas_layer_2d", 1, 1, "k_stage12-v5"): dict(valu_per_cell_stage=11555077.5 * 64 / 524288,
                                                       traffic_bytes=(11337.9 * 2 + 12297.4) * 1024),
+    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v5"): dict(valu_per_cell_stage=9047274.7 * 64 / 524288,
+                                                          traffic_bytes=(15165.1 * 2 + 16389.8) * 1024),
+    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v5"): dict(valu_per_cell_stage=8384947.0 * 64 / 524288,
+                                                          traffic_bytes=(7699.1 * 2 + 8199.0) * 1024),
     ("liquid_jet_3d", 0, 4, "k_stage12-v5"): dict(valu_per_cell_stage=(460998389.7 + 1418865154.9) * 64 / 33554432,
                                                   traffic_bytes=((794332.9 + 3520314.4) * 2 +
                                                                  (2660488.5 + 1657931.5)) * 1024),
@@ -56,7 +61,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
-                             "liquid_jet_3d_viscous", "dual_gas_layer_2d", "interface_advection_1d"])
+                             "liquid_jet_3d_viscous", "dual_gas_layer_2d", "vapour_bubble_wall_2d",
+                             "interface_advection_1d"])
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,6 +107,9 @@ def make_workload(name, steps):
     if name == "dual_gas_layer_2d":
         return [W.dual_gas_layer_2d(1024, 512, steps)], dict(workload=name, nx=1024, ny=512, components=3,
                                                              sigma=0.028)
+    if name == "vapour_bubble_wall_2d":
+        return [W.vapour_bubble_wall_2d(1024, 512, steps)], dict(workload=name, nx=1024, ny=512, dx=4e-6,
+                                                                 model="barotropic")
     if name == "liquid_jet_3d_viscous":
         return [W.liquid_jet_3d(512, 256, 256, steps, viscous=True)], dict(workload=name, nx=512, ny=256, nz=256)
     raise ValueError(name)
@@ -243,7 +252,8 @@ def main():
             "unit": "T VALU lane-instr/s",
             "frac": None if achieved is None else achieved / VALU_PEAK_TINSTR,
             "traffic": traffic,
-            "kernel": "k_stage12" if cases[0]["grid"]["dim"] < 3 else "k_prim3+k_face3",
+            "kernel": ("k_prim3+k_face3" if cases[0]["grid"]["dim"] == 3 else
+                       "k_baro12" if int(cases[0]["eos"].get("model", 0)) == 1 else "k_stage12"),
             "kernel_build": KERNEL_BUILD,
             "valu_per_cell_stage": None if meas is None else meas["valu_per_cell_stage"],
             "stage_launch_ms": stage_avg_ms,
@@ -268,7 +278,8 @@ def main():
             entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0, "liquid_jet_3d_viscous": 300.0,
-                    "dual_gas_layer_2d": 25.0, "interface_advection_1d": 100.0}.get(args.workload, 1.0)
+                    "dual_gas_layer_2d": 25.0, "vapour_bubble_wall_2d": 31.6,
+                    "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
         out["mixed"] = entry
     if not args.no_cpu_baseline:

@@ -9,8 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfvm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fvm_kernels.hip", "fvm_stage3d.hip", "fvm_baro.hip", "fvm_api.cpp"]
-HEADERS = ["fvm_device.hpp", "fvm_kernels.hpp", "fvm_stage_common.hpp"]
+SOURCES = ["fvm_kernels.hip", "fvm_stage12_deflim.hip", "fvm_stage3d.hip", "fvm_baro.hip", "fvm_api.cpp"]
+HEADERS = ["fvm_device.hpp", "fvm_kernels.hpp", "fvm_stage_common.hpp", "fvm_stage12.hpp"]
 ARCH = os.environ.get("FVM_OFFLOAD_ARCH", "gfx950")
 
 # packed FP32 instructions are disabled: the compiler would otherwise form them

@@ -147,10 +147,12 @@ struct BStencil {
 // (bit 1); storage flux (m (1 - xi_f), m xi_f, m u_f + p* n), m = rho_f u*.
 // A face with p* <= 0 has no density: its flux is NaN, which the closure of
 // the updated cells reports.
-template <class R, int D, int DIR>
+template <class R, int D, int DIR, int LIM>
 __device__ inline void baro_face(const SchemeC& S, const CaseC& C, const BStencil<R, D>& s, bool disc, int el,
                                  int er, R* F)
 {
+  const int lu = LIM ? int(LIM_KOREN) : S.lim_u;   // LIM = 1: the default limiters fixed
+  const int ls = LIM ? int(LIM_MINMOD) : S.lim_s;
   R cm = fmax(s.c1, s.c2);
   R IL = (R(3) * s.r[1] + s.r[2]) * cm * R(0.25);
   R IR = (s.r[1] + R(3) * s.r[2]) * cm * R(0.25);
@@ -161,10 +163,10 @@ __device__ inline void baro_face(const SchemeC& S, const CaseC& C, const BStenci
   if (disc) {
     R uL[D], uR[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) recon<R>(S.lim_u, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
+    for (int d = 0; d < D; ++d) recon<R>(lu, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
     R pL, pR, YL, YR;
-    recon<R>(S.lim_s, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
-    recon<R>(S.lim_s, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
+    recon<R>(ls, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
+    recon<R>(ls, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
     ps = R(0.5) * (pL + pR);
     us = (IL * uL[DIR] + IR * uR[DIR] + pL - pR) * iI;
     left = us >= R(0);
@@ -208,7 +210,7 @@ __device__ inline int baro_elig(R Ya, R Yb, R Yc, R va, R vb, R vc, R ra, R rb, 
 }
 
 // ------------------------------------------------------------------ fused 1D/2D stage
-template <class S, int D, int TX, int TY, int NT, int MINW>
+template <class S, int D, int TX, int TY, int NT, int MINW, int LIM>
 __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
 {
   static_assert(D == 1 || D == 2, "1D/2D kernel");
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
     stencil(c, 1, bs, el, er);
     bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
     S F[NQ];
-    baro_face<S, D, 0>(SC, C, bs, disc, el, er, F);
+    baro_face<S, D, 0, LIM>(SC, C, bs, disc, el, er, F);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
   };
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
       stencil(c, HX, bs, el, er);
       bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
       S F[NQ];
-      baro_face<S, D, D - 1>(SC, C, bs, disc, el, er, F);
+      baro_face<S, D, D - 1, LIM>(SC, C, bs, disc, el, er, F);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     };
@@ -661,7 +663,10 @@ __global__ __launch_bounds__(256) void k_baro_totals_part(const CaseC* cases, in
 template <class S, int D, int TX, int TY, int NT, int MINW>
 static hipError_t launch_b(const StageArgs& a, int ntiles, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_baro12<S, D, TX, TY, NT, MINW>), dim3(ntiles), dim3(NT), 0, st, a);
+  if (fvm_default_limiters(a.sc))
+    hipLaunchKernelGGL((k_baro12<S, D, TX, TY, NT, MINW, 1>), dim3(ntiles), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_baro12<S, D, TX, TY, NT, MINW, 0>), dim3(ntiles), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -541,10 +541,14 @@ __device__ inline void tdu_sg(const CaseC& C, R ps, R Tf, R Yf, R& rf, R& ef)
 //   u* = u_C + k3 (p_{i+2} - 3 p_{i+1} + 3 p_i - p_{i-1}) / (I_L + I_R);
 //  TDU: rho_f, e_f from the closure at (p*, T_f, xi_f);
 //  flux (storage variables): (m xi_L, m xi_G, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*).
-template <class R, int D, int DIR, bool PRK, bool G2 = false>
+// LIM = 1 fixes the default limiters (Koren for velocities, Minmod for p, T,
+// xi) at compile time; LIM = 0 takes the scheme's limiters at run time.
+template <class R, int D, int DIR, bool PRK, bool G2 = false, int LIM = 0>
 __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil<R, D>& s,
                                  bool disc, bool sl, bool sr, R* F, bool sl2 = false, bool sr2 = false)
 {
+  const int lu = LIM ? int(LIM_KOREN) : S.lim_u;
+  const int ls = LIM ? int(LIM_MINMOD) : S.lim_s;
   R cm = fmax(s.c1, s.c2);
   R rsum = s.rho1 + s.rho2;
   R IL = (R(3) * s.rho1 + s.rho2) * cm * R(0.25);
@@ -555,11 +559,11 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
   if (disc) {
     R uL[D], uR[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) recon<R>(S.lim_u, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
+    for (int d = 0; d < D; ++d) recon<R>(lu, s.u[d][0], s.u[d][1], s.u[d][2], s.u[d][3], uL[d], uR[d]);
     R pL, pR, TL, TR, YL, YR;
-    recon<R>(S.lim_s, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
-    recon<R>(S.lim_s, s.T[0], s.T[1], s.T[2], s.T[3], TL, TR);
-    recon<R>(S.lim_s, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
+    recon<R>(ls, s.p[0], s.p[1], s.p[2], s.p[3], pL, pR);
+    recon<R>(ls, s.T[0], s.T[1], s.T[2], s.T[3], TL, TR);
+    recon<R>(ls, s.Y[0], s.Y[1], s.Y[2], s.Y[3], YL, YR);
     ps = R(0.5) * (pL + pR);
     us = (IL * uL[DIR] + IR * uR[DIR] + pL - pR) * iI;
     bool left = us >= R(0);
@@ -571,7 +575,7 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
       Yf = thinc_value<R>(S, left, left ? s.Y[0] : s.Y[1], left ? s.Y[1] : s.Y[2], left ? s.Y[2] : s.Y[3]);
     if constexpr (G2) {
       R Y2L, Y2R;
-      recon<R>(S.lim_s, s.Y2[0], s.Y2[1], s.Y2[2], s.Y2[3], Y2L, Y2R);
+      recon<R>(ls, s.Y2[0], s.Y2[1], s.Y2[2], s.Y2[3], Y2L, Y2R);
       Y2f = left ? Y2L : Y2R;
       if (S.thinc && (left ? sl2 : sr2))
         Y2f = thinc_value<R>(S, left, left ? s.Y2[0] : s.Y2[1], left ? s.Y2[1] : s.Y2[2],

@@ -25,6 +25,14 @@ struct StageArgs {
 // the barotropic model (no energy field; its own kernels, 1D/2D)
 enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2, FVM_KIND_BARO = 3 };
 
+// the scheme uses the default limiters (Koren for velocities, Minmod for the
+// thermodynamic variables): the stage kernels then take them as compile-time
+// constants instead of branching on the limiter kind at every slope
+inline bool fvm_default_limiters(const fvm::SchemeC& s)
+{
+  return s.lim_u == fvm::LIM_KOREN && s.lim_s == fvm::LIM_MINMOD;
+}
+
 int fvm_k_tile_count(int dim);
 int fvm_k_tile_shape(int dim, int tile, int* tx, int* ty, int* nt);
 int fvm_k_tile_count3();
@@ -33,6 +41,9 @@ int fvm_k_tile_shape3(int tile, int* tx, int* ty, int* nt);
 int fvm_k_tile_zchunk3(int tile);
 
 hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+// 1D/2D stage kernels with the default limiters fixed (fvm_stage12_deflim.hip)
+hipError_t fvm_k_stage12_deflim(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles,
+                                hipStream_t st);
 hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,

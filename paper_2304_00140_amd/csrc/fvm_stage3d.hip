@@ -120,7 +120,7 @@ __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long 
   if (fz) w[3] = -w[3];
 }
 
-template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK>
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, int LIM>
 __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __restrict__ W)
 {
   constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HXY = HX * HY, NH = HXY * HZ;
@@ -246,9 +246,9 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
       bool sl = eligible(sten.Y[0], sten.Y[1], sten.Y[2], eps);
       bool sr = eligible(sten.Y[1], sten.Y[2], sten.Y[3], eps);
       S F[NQ];
-      if (d == 0) face_flux<S, 3, 0, PRK>(SC, C, sten, disc, sl, sr, F);
-      else if (d == 1) face_flux<S, 3, 1, PRK>(SC, C, sten, disc, sl, sr, F);
-      else face_flux<S, 3, 2, PRK>(SC, C, sten, disc, sl, sr, F);
+      if (d == 0) face_flux<S, 3, 0, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
+      else if (d == 1) face_flux<S, 3, 1, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
+      else face_flux<S, 3, 2, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
       if (C.diff) {
         if (d == 0) visc_flux<S, 3, 0>(C, U, s_T, s_a, c, st, F);
         else if (d == 1) visc_flux<S, 3, 1>(C, U, s_T, s_a, c, st, F);
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   }
 }
 
-template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK>
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, int LIM>
 static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
 {
   constexpr int Wv = PRK ? 1 : MINW;
@@ -405,7 +405,7 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
   hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
+  hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK, LIM>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
   return hipGetLastError();
 }
 
@@ -430,21 +430,29 @@ int fvm_k_tile_shape3(int t, int* tx, int* ty, int* nt)
 
 int fvm_k_tile_zchunk3(int t) { return (t >= 0 && t < NT3) ? TILES3[t][2] : 1; }
 
-template <class S, bool PRK>
+template <class S, bool PRK, int LIM>
 static hipError_t stage3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
   switch (tile) {
-    case 0: return launch3<S, 8, 8, 4, 256, 2, PRK>(a, ntiles, st);
-    case 1: return launch3<S, 16, 8, 2, 256, 2, PRK>(a, ntiles, st);
-    case 2: return launch3<S, 8, 4, 4, 128, 2, PRK>(a, ntiles, st);
-    case 3: return launch3<S, 16, 4, 4, 256, 2, PRK>(a, ntiles, st);
-    case 4: return launch3<S, 8, 8, 8, 512, 1, PRK>(a, ntiles, st);
+    case 0: return launch3<S, 8, 8, 4, 256, 2, PRK, LIM>(a, ntiles, st);
+    case 1: return launch3<S, 16, 8, 2, 256, 2, PRK, LIM>(a, ntiles, st);
+    case 2: return launch3<S, 8, 4, 4, 128, 2, PRK, LIM>(a, ntiles, st);
+    case 3: return launch3<S, 16, 4, 4, 256, 2, PRK, LIM>(a, ntiles, st);
+    case 4: return launch3<S, 8, 8, 8, 512, 1, PRK, LIM>(a, ntiles, st);
   }
   return hipErrorInvalidValue;
 }
 
+template <int LIM>
+static hipError_t stage3_any(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (mixed) return prk ? stage3<float, true, LIM>(tile, a, ntiles, st) : stage3<float, false, LIM>(tile, a, ntiles, st);
+  return prk ? stage3<double, true, LIM>(tile, a, ntiles, st) : stage3<double, false, LIM>(tile, a, ntiles, st);
+}
+
+// the default limiters (Koren, Minmod) as compile-time constants, any others at run time
 hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  if (mixed) return prk ? stage3<float, true>(tile, a, ntiles, st) : stage3<float, false>(tile, a, ntiles, st);
-  return prk ? stage3<double, true>(tile, a, ntiles, st) : stage3<double, false>(tile, a, ntiles, st);
+  if (fvm_default_limiters(a.sc)) return stage3_any<1>(mixed, prk, tile, a, ntiles, st);
+  return stage3_any<0>(mixed, prk, tile, a, ntiles, st);
 }

@@ -33,24 +33,24 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # precision, tile, kernel build).
 KERNEL_BUILD = "k_stage12-v6"
 MEASURED = {
-    ("shock_bubble_2d", 0, 0, "k_stage12-v5"): dict(valu_per_cell_stage=4463388.4 * 64 / 262144,
-                                                    traffic_bytes=(9921.1 * 2 + 10244.2) * 1024),
-    ("shock_bubble_2d", 1, 8, "k_stage12-v5"): dict(valu_per_cell_stage=4286166.0 * 64 / 262144,
-                                                    traffic_bytes=(5007.1 * 2 + 5124.8) * 1024),
-    ("dual_gas_layer_2d", 0, 1, "k_stage12-v5"): dict(valu_per_cell_stage=13198302.5 * 64 / 524288,
-                                                      traffic_bytes=(22485.0 * 2 + 24583.1) * 1024),
-    ("dual_gas_layer_2d", 1, 1, "k_stage12-v5"): dict(valu_per_cell_stage=11555077.5 * 64 / 524288,
-                                                      traffic_bytes=(11337.9 * 2 + 12297.4) * 1024),
-    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v5"): dict(valu_per_cell_stage=9047274.7 * 64 / 524288,
-                                                          traffic_bytes=(15165.1 * 2 + 16389.8) * 1024),
-    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v5"): dict(valu_per_cell_stage=8384947.0 * 64 / 524288,
-                                                          traffic_bytes=(7699.1 * 2 + 8199.0) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v5"): dict(valu_per_cell_stage=(460998389.7 + 1418865154.9) * 64 / 33554432,
-                                                  traffic_bytes=((794332.9 + 3520314.4) * 2 +
-                                                                 (2660488.5 + 1657931.5)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v5"): dict(valu_per_cell_stage=(434323125.0 + 1517992336.7) * 64 / 33554432,
-                                                  traffic_bytes=((395413.2 + 1689465.0) * 2 +
-                                                                 (1211757.2 + 814460.2)) * 1024),
+    ("shock_bubble_2d", 0, 3, "k_stage12-v6"): dict(valu_per_cell_stage=4218140.4 * 64 / 262144,
+                                               traffic_bytes=(9777.8 * 2 + 10244.1) * 1024),
+    ("shock_bubble_2d", 1, 8, "k_stage12-v6"): dict(valu_per_cell_stage=4060792.1 * 64 / 262144,
+                                               traffic_bytes=(4945.3 * 2 + 5124.4) * 1024),
+    ("dual_gas_layer_2d", 0, 0, "k_stage12-v6"): dict(valu_per_cell_stage=10562551.4 * 64 / 524288,
+                                                 traffic_bytes=(22480.4 * 2 + 24581.2) * 1024),
+    ("dual_gas_layer_2d", 1, 1, "k_stage12-v6"): dict(valu_per_cell_stage=11505893.2 * 64 / 524288,
+                                                 traffic_bytes=(11309.2 * 2 + 12300.3) * 1024),
+    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v6"): dict(valu_per_cell_stage=8821924.3 * 64 / 524288,
+                                                     traffic_bytes=(15049.6 * 2 + 16389.2) * 1024),
+    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v6"): dict(valu_per_cell_stage=8159430.9 * 64 / 524288,
+                                                     traffic_bytes=(7601.3 * 2 + 8197.1) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v6"): dict(valu_per_cell_stage=(460998295.7 + 1322165409.0) * 64 / 33554432,
+                                                  traffic_bytes=((803568.6 + 3477200.9) * 2 +
+                                                                 (2659306.4 + 1669630.8)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v6"): dict(valu_per_cell_stage=(434323140.2 + 1424810008.0) * 64 / 33554432,
+                                                  traffic_bytes=((395372.7 + 1799769.9) * 2 +
+                                                                 (1212148.4 + 808751.9)) * 1024),
 }
 
 

@@ -124,7 +124,7 @@ typedef struct fvm_grid_desc {
  * of rho (eqs. 3-7, 3-8, Remarks 1-2), elsewhere rho(p*, xi_face).  FP32
  * storage (FVM_MIXED) keeps the liquid's partial density relative to its
  * density at p_ref.  Requires bt_rho_sat > 0, bt_p_sat > 0, bt_c_liq > 0,
- * 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0; 1D and 2D only (FVM_EINVAL in 3D). */
+ * 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0; 1D, 2D and 3D. */
 typedef struct fvm_eos_desc {
   int kind[3];
   double gamma[3], pinf[3], cv[3], q[3];

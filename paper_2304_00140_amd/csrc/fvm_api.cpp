@@ -290,7 +290,6 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     const int baro = eos[c].model == FVM_MODEL_BAROTROPIC;
     if (c == 0) b->kind = baro ? FVM_KIND_BARO : FVM_KIND_SG;
     if (baro != (b->kind == FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
-    if (baro && g->dim == 3) return bail(fail(b, FVM_EINVAL, "the barotropic model is supported in 1D and 2D"));
     CaseC& C = b->hc[c];
     std::memset(&C, 0, sizeof C);
     C.dim = g->dim;

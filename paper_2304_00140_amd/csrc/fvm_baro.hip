@@ -11,7 +11,8 @@
 // One fused kernel per Runge-Kutta stage on 1D/2D tiles, shaped like the
 // four-equation kernel: tile + two-cell halo staged in LDS after the FP64
 // closure p = f(rho, xi), sensors, x and y face sweeps, CSF, body force,
-// update, and in the last stage the CFL bound of the new state.
+// update, and in the last stage the CFL bound of the new state.  In 3D a
+// closure kernel and a face kernel, as for the four-equation model.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "fvm_device.hpp"
@@ -660,6 +661,405 @@ __global__ __launch_bounds__(256) void k_baro_totals_part(const CaseC* cases, in
     for (int v = 0; v < NQ; ++v) part[blockIdx.x * NQ + v] = s[v][0];
 }
 
+// ------------------------------------------------------------------ 3D: closure kernel + face kernel
+// As for the four-equation model in 3D: the FP64 closure runs once per cell in
+// its own kernel and writes the primitives in the storage precision; the face
+// kernel stages tile + two-cell halo primitives in LDS.
+constexpr int NWB3 = 9;   // rho, u, v, w, p, xi, c, alpha_G, alpha_V
+
+// primitives of every owned cell; in the first stage of a step also the CFL
+// bound of q^n and its checks (an error of the step before)
+template <class S, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
+{
+  __shared__ double s_red[4];
+  constexpr int NB = (TX * TY * TZ + 255) / 256;   // workgroups per tile
+  const int bb = xcd_block(blockIdx.x, gridDim.x);
+  const int4 tl = a.tiles[bb / NB];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const S* __restrict__ src = (const S*)a.src;
+  const long long T = a.total;
+  const bool first = a.stage == 0;
+  const long long step = dy.base + a.step_off;
+  double lam = 0.0;
+  constexpr int NC = TX * TY * TZ;
+  const int cc = (bb % NB) * 256 + threadIdx.x;
+  const int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+  const int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
+  if (cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2]) {
+    long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+    double q[5], u[3], rho, Y;
+    q[0] = (double)src[cell] + C.rref[0];
+#pragma unroll
+    for (int v = 1; v < 5; ++v) q[v] = (double)src[v * T + cell];
+    PB pb = baro_prim<3>(C, q, u, rho, Y);
+    W[cell] = S(rho);
+    W[T + cell] = S(u[0]);
+    W[2 * T + cell] = S(u[1]);
+    W[3 * T + cell] = S(u[2]);
+    W[4 * T + cell] = S(pb.p);
+    W[5 * T + cell] = S(Y);
+    W[6 * T + cell] = S(pb.c);
+    W[7 * T + cell] = S(pb.aG);
+    W[8 * T + cell] = S(pb.aV);
+    if (first) {
+      double l = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+      if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, cell - C.off, step - 1);
+      else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, cell - C.off, step - 1);
+      else lam = fmax(lam, l);
+    }
+  }
+  if (first) {
+    lam = wave_max(lam);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lam;
+    __syncthreads();
+    if (threadIdx.x == 0) cfl_max(dy, (int)(step & 1), fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3])));
+  }
+}
+
+template <class S>
+__device__ inline void bprim_of(const CaseC& C, const double* q, S* w)
+{
+  double u[3], rho, Y;
+  PB pb = baro_prim<3>(C, q, u, rho, Y);
+  w[0] = S(rho); w[1] = S(u[0]); w[2] = S(u[1]); w[3] = S(u[2]);
+  w[4] = S(pb.p); w[5] = S(Y); w[6] = S(pb.c); w[7] = S(pb.aG); w[8] = S(pb.aV);
+}
+
+// primitives of one (possibly ghost) cell
+template <class S>
+__device__ inline void load_bprim3(const CaseC& C, const S* __restrict__ W, long long T, int gx, int gy, int gz,
+                                   long long step, S* w)
+{
+  if (beyond_farfield<3>(C, gx, gy, gz)) {
+    const double u0[3] = {0.0, 0.0, 0.0};
+    double q[5];
+    baro_from_prim<3>(C, C.ff_p, C.ff_alpha, u0, q);
+    bprim_of<S>(C, q, w);
+    return;
+  }
+  bool fx = false, fy = false, fz = false;
+  int ix = gx, iy = gy, iz = gz;
+  map_index(iy, C.n[1], C.bc[1][0], C.bc[1][1], fy);
+  map_index(iz, C.n[2], C.bc[2][0], C.bc[2][1], fz);
+  if (ix < 0 && C.bc[0][0] == BC_INFLOW) {
+    double yy = (iy + 0.5) * C.dx[1] - C.in_c0;
+    double zz = (iz + 0.5) * C.dx[2] - C.in_c1;
+    if (sqrt(yy * yy + zz * zz) < C.in_radius) {
+      double u[3] = {C.in_u, 0.0, 0.0}, q[5];
+      for (int c = 0; c < 3; ++c)
+        u[c] += C.in_noise * C.in_u *
+                (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
+                               (unsigned long long)iz, (unsigned long long)c) - 1.0);
+      baro_from_prim<3>(C, C.in_p, C.in_alpha, u, q);
+      if (fy) q[3] = -q[3];
+      if (fz) q[4] = -q[4];
+      bprim_of<S>(C, q, w);
+      return;
+    }
+    ix = -1 - ix;
+    fx = true;
+  } else {
+    map_index(ix, C.n[0], C.bc[0][0], C.bc[0][1], fx);
+  }
+  long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
+#pragma unroll
+  for (int v = 0; v < NWB3; ++v) w[v] = W[v * T + cell];
+  if (fx) w[1] = -w[1];
+  if (fy) w[2] = -w[2];
+  if (fz) w[3] = -w[3];
+}
+
+template <class S, int TX, int TY, int TZ, int NT, int MINW, int LIM>
+__global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __restrict__ W)
+{
+  constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HXY = HX * HY, NH = HXY * HZ;
+  constexpr int NQ = 5;
+  constexpr int NC = TX * TY * TZ;
+  constexpr int CPT = (NC + NT - 1) / NT;
+  constexpr int NFX = (TX + 1) * TY * TZ, NFY = TX * (TY + 1) * TZ, NFZ = TX * TY * (TZ + 1);
+  constexpr int NF = NFX > NFY ? (NFX > NFZ ? NFX : NFZ) : (NFY > NFZ ? NFY : NFZ);
+  constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2, NFH = FX * FY * FZ;
+  constexpr int VX = TX + 1, VY = TY + 1, VZ = TZ + 1, NV = VX * VY * VZ;
+  constexpr int NBUF = (NQ * NF > NFH + 3 * NV) ? NQ * NF : NFH + 3 * NV;
+
+  __shared__ S s_w[NWB3][NH];
+  __shared__ unsigned char s_fl[NH];
+  __shared__ S s_buf[NBUF];
+  S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
+
+  const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const SchemeC& SC = a.sc;
+  const int x0 = tl.y * TX, y0 = tl.z * TY, z0 = tl.w * TZ;
+  const int tid = threadIdx.x;
+  const bool upd = a.stage >= 0;
+  const long long step = upd ? dy.base + a.step_off : a.rhs_step;
+  const long long T = a.total;
+  S* s_rho = s_w[0];
+  S* s_u = s_w[1];
+  S* s_v = s_w[2];
+  S* s_ww = s_w[3];
+  S* s_p = s_w[4];
+  S* s_Y = s_w[5];
+  S* s_c = s_w[6];
+  S* s_a = s_w[7];
+  S* s_av = s_w[8];
+
+  auto owned = [&](int cc, int& gx, int& gy, int& gz) {
+    int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+    gx = x0 + i; gy = y0 + j; gz = z0 + k;
+    return cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2];
+  };
+
+  S qn_reg[CPT][NQ];
+  if (upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int gx, gy, gz;
+      bool own = owned(tid + k * NT, gx, gy, gz);
+      long long cell = C.off + (own ? gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz) : 0);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+    }
+  }
+
+  for (int h = tid; h < NH; h += NT) {
+    int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+    S w[NWB3];
+    load_bprim3<S>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+#pragma unroll
+    for (int v = 0; v < NWB3; ++v) s_w[v][h] = w[v];
+  }
+  __syncthreads();
+
+  const int st[3] = {1, HX, HXY};
+  // ---- switching sensors (Ducros, gas and vapour volume fractions) on tile + one halo layer
+  if (SC.switching) {
+    for (int h = tid; h < NFH; h += NT) {
+      int lx = h % FX, ly = (h / FX) % FY, lz = h / (FX * FY);
+      int c = (lz + 1) * HXY + (ly + 1) * HX + lx + 1;
+      S g[3][3];
+      const S* uu[3] = {s_u, s_v, s_ww};
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          g[comp][d] = (uu[comp][c + st[d]] - uu[comp][c - st[d]]) * S(0.5 * C.idx[d]);
+      S div = g[0][0] + g[1][1] + g[2][2];
+      S w0 = g[2][1] - g[1][2], w1 = g[0][2] - g[2][0], w2 = g[1][0] - g[0][1];
+      S curl2 = w0 * w0 + w1 * w1 + w2 * w2;
+      S thg = S(0), thv = S(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        thg += fabs(s_a[c] - s_a[c - st[d]]) + fabs(s_a[c + st[d]] - s_a[c]);
+        thv += fabs(s_av[c] - s_av[c - st[d]]) + fabs(s_av[c + st[d]] - s_av[c]);
+      }
+      S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
+      s_fl[c] = (thd > S(SC.th_d) || thv > S(SC.th_g) || thg > S(SC.th_g)) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+
+  S R[CPT][NQ];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
+
+  const S eps = S(SC.eps_int);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int EX = TX + (d == 0), EY = TY + (d == 1);
+    const int NFD = d == 0 ? NFX : (d == 1 ? NFY : NFZ);
+    const int sd = st[d];
+    if (d > 0) __syncthreads();
+    for (int f = tid; f < NFD; f += NT) {
+      int i = f % EX, j = (f / EX) % EY, k = f / (EX * EY);
+      int c = (k + 2) * HXY + (j + 2) * HX + (i + 2) - sd;   // lower cell of the face
+      BStencil<S, 3> bs;
+      S av[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int cm = c + (m - 1) * sd;
+        bs.u[0][m] = s_u[cm];
+        bs.u[1][m] = s_v[cm];
+        bs.u[2][m] = s_ww[cm];
+        bs.p[m] = s_p[cm];
+        bs.Y[m] = s_Y[cm];
+        bs.r[m] = s_rho[cm];
+        av[m] = s_av[cm];
+      }
+      bs.c1 = s_c[c];
+      bs.c2 = s_c[c + sd];
+      int el = baro_elig<S>(bs.Y[0], bs.Y[1], bs.Y[2], av[0], av[1], av[2], bs.r[0], bs.r[1], bs.r[2], eps);
+      int er = baro_elig<S>(bs.Y[1], bs.Y[2], bs.Y[3], av[1], av[2], av[3], bs.r[1], bs.r[2], bs.r[3], eps);
+      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + sd]) != 0);
+      S F[NQ];
+      if (d == 0) baro_face<S, 3, 0, LIM>(SC, C, bs, disc, el, er, F);
+      else if (d == 1) baro_face<S, 3, 1, LIM>(SC, C, bs, disc, el, er, F);
+      else baro_face<S, 3, 2, LIM>(SC, C, bs, disc, el, er, F);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+    }
+    __syncthreads();
+    const S id = S(C.idx[d]);
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int f = (k * EY + j) * EX + i;
+        int fn = f + (d == 0 ? 1 : (d == 1 ? EX : EX * EY));
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[kk][v] += (s_F[v][f] - s_F[v][fn]) * id;
+      }
+    }
+  }
+
+  // ---- CSF (Section 3.5): 3D binomial kernel /64 of xi, vertex normals, kappa = -div n,
+  // force sigma kappa grad(alpha_G) on the momentum
+  if (SC.sigma > 0.0) {
+    __syncthreads();
+    S* s_H = s_buf;
+    S* s_n = s_H + NFH;
+    for (int h = tid; h < NFH; h += NT) {
+      int lx = h % FX, ly = (h / FX) % FY, lz = h / (FX * FY);
+      int c = (lz + 1) * HXY + (ly + 1) * HX + lx + 1;
+      S acc = S(0);
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dyy = -1; dyy <= 1; ++dyy) {
+          S row = s_Y[c + dz * HXY + dyy * HX - 1] + S(2) * s_Y[c + dz * HXY + dyy * HX] +
+                  s_Y[c + dz * HXY + dyy * HX + 1];
+          acc += row * S((dz == 0 ? 2 : 1) * (dyy == 0 ? 2 : 1));
+        }
+      s_H[h] = acc * S(1.0 / 64.0);
+    }
+    __syncthreads();
+    S en = S(SC.eps_n * C.idx[0]);
+    for (int h = tid; h < NV; h += NT) {
+      int vx = h % VX, vy = (h / VX) % VY, vz = h / (VX * VY);
+      int c = (vz * FY + vy) * FX + vx;
+      const int sx = 1, sy = FX, sz = FX * FY;
+      S gx = (s_H[c + sx] + s_H[c + sx + sy] + s_H[c + sx + sz] + s_H[c + sx + sy + sz] -
+              s_H[c] - s_H[c + sy] - s_H[c + sz] - s_H[c + sy + sz]) * S(0.25 * C.idx[0]);
+      S gy = (s_H[c + sy] + s_H[c + sy + sx] + s_H[c + sy + sz] + s_H[c + sy + sx + sz] -
+              s_H[c] - s_H[c + sx] - s_H[c + sz] - s_H[c + sx + sz]) * S(0.25 * C.idx[1]);
+      S gz = (s_H[c + sz] + s_H[c + sz + sx] + s_H[c + sz + sy] + s_H[c + sz + sx + sy] -
+              s_H[c] - s_H[c + sx] - s_H[c + sy] - s_H[c + sx + sy]) * S(0.25 * C.idx[2]);
+      S inv = frcp(sqrt(gx * gx + gy * gy + gz * gz) + en);
+      s_n[h] = gx * inv;
+      s_n[NV + h] = gy * inv;
+      s_n[2 * NV + h] = gz * inv;
+    }
+    __syncthreads();
+    S sig = S(SC.sigma);
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int c = (k + 2) * HXY + (j + 2) * HX + i + 2;
+        int v = ((k + 1) * VY + (j + 1)) * VX + (i + 1);
+        const int vs[3] = {1, VX, VX * VY};
+        S kap = S(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int t1 = vs[(d + 1) % 3], t2 = vs[(d + 2) % 3];
+          const S* nd = s_n + d * NV;
+          S plus = nd[v] + nd[v - t1] + nd[v - t2] + nd[v - t1 - t2];
+          S minus = nd[v - vs[d]] + nd[v - vs[d] - t1] + nd[v - vs[d] - t2] + nd[v - vs[d] - t1 - t2];
+          kap += (plus - minus) * S(0.25 * C.idx[d]);
+        }
+        kap = -kap;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) R[kk][2 + d] += sig * kap * (s_a[c + st[d]] - s_a[c - st[d]]) * S(0.5 * C.idx[d]);
+      }
+    }
+  }
+
+  // ---- body force (eq. 2-2, source Q): rho g on the momentum
+  if (SC.has_grav) {
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      int cc = tid + kk * NT;
+      if (cc < NC) {
+        int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
+        int c = (k + 2) * HXY + (j + 2) * HX + i + 2;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) R[kk][2 + d] += s_rho[c] * S(SC.grav[d]);
+      }
+    }
+  }
+
+  if (!upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int gx, gy, gz;
+      if (owned(tid + k * NT, gx, gy, gz)) {
+        const long long RS = C.ncell;
+        long long cell = gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+        double r0 = (double)R[k][0], r1 = (double)R[k][1];
+        a.rhs_out[cell] = r0 + r1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
+        a.rhs_out[4 * RS + cell] = r1;
+      }
+    }
+    return;
+  }
+  const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
+  if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
+  // the last stage writes q^(n+1); its CFL bound and checks come from the
+  // closure kernel of the next step's first stage (or the end-of-run check)
+  S* dst = (S*)a.dst;
+  const S adt = S(a.ak * dt);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int gx, gy, gz;
+    if (owned(tid + k * NT, gx, gy, gz)) {
+      long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) dst[v * T + cell] = qn_reg[k][v] + adt * R[k][v];
+    }
+  }
+}
+
+template <class S, int TX, int TY, int TZ, int NT, int MINW>
+static hipError_t launch_b3(const StageArgs& a, int ntiles, hipStream_t st)
+{
+  S* W = (S*)a.prim;
+  constexpr int NB = (TX * TY * TZ + 255) / 256;
+  hipLaunchKernelGGL((k_bprim3<S, TX, TY, TZ>), dim3(ntiles * NB), dim3(256), 0, st, a, W);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (fvm_default_limiters(a.sc))
+    hipLaunchKernelGGL((k_bface3<S, TX, TY, TZ, NT, MINW, 1>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
+  else
+    hipLaunchKernelGGL((k_bface3<S, TX, TY, TZ, NT, MINW, 0>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
+  return hipGetLastError();
+}
+
+// the tile shapes (and indices) of the four-equation 3D kernels
+template <class S>
+static hipError_t stage_b3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  switch (tile) {
+    case 0: return launch_b3<S, 8, 8, 4, 256, 2>(a, ntiles, st);
+    case 1: return launch_b3<S, 16, 8, 2, 256, 2>(a, ntiles, st);
+    case 2: return launch_b3<S, 8, 4, 4, 128, 2>(a, ntiles, st);
+    case 3: return launch_b3<S, 16, 4, 4, 256, 2>(a, ntiles, st);
+    case 4: return launch_b3<S, 8, 8, 8, 512, 1>(a, ntiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <class S, int D, int TX, int TY, int NT, int MINW>
 static hipError_t launch_b(const StageArgs& a, int ntiles, hipStream_t st)
 {
@@ -704,22 +1104,23 @@ static unsigned blocks_b(long long n, int bs) { return (unsigned)((n + bs - 1) /
 
 hipError_t fvm_kb_stage(int dim, int mixed, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
+  if (dim == 3) return mixed ? stage_b3<float>(tile, a, ntiles, st) : stage_b3<double>(tile, a, ntiles, st);
   return mixed ? stage_b<float>(dim, tile, a, ntiles, st) : stage_b<double>(dim, tile, a, ntiles, st);
 }
 
-#define FVM_BDISPATCH(MIXED, DIM, CALL)                      \
-  do {                                                       \
-    if (MIXED) {                                             \
-      if (DIM == 1) { CALL(float, 1); } else { CALL(float, 2); } \
-    } else {                                                 \
-      if (DIM == 1) { CALL(double, 1); } else { CALL(double, 2); } \
-    }                                                        \
+#define FVM_BDISPATCH(MIXED, DIM, CALL)                                                 \
+  do {                                                                                  \
+    if (MIXED) {                                                                        \
+      if (DIM == 1) { CALL(float, 1); } else if (DIM == 2) { CALL(float, 2); } else { CALL(float, 3); } \
+    } else {                                                                            \
+      if (DIM == 1) { CALL(double, 1); } else if (DIM == 2) { CALL(double, 2); } else { CALL(double, 3); } \
+    }                                                                                   \
   } while (0)
 
 hipError_t fvm_kb_prim_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
                                 const double* prim, void* dst, long long total, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_prim_to_state<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL
@@ -729,7 +1130,7 @@ hipError_t fvm_kb_prim_to_state(int dim, int mixed, const CaseC* cases, int icas
 hipError_t fvm_kb_cons_to_state(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
                                 const double* q, void* dst, long long total, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_cons_to_state<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL
@@ -739,7 +1140,7 @@ hipError_t fvm_kb_cons_to_state(int dim, int mixed, const CaseC* cases, int icas
 hipError_t fvm_kb_state_to_cons(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
                                 const void* src, double* q, long long total, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_state_to_cons<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL
@@ -749,7 +1150,7 @@ hipError_t fvm_kb_state_to_cons(int dim, int mixed, const CaseC* cases, int icas
 hipError_t fvm_kb_state_to_prim(int dim, int mixed, const CaseC* cases, int icase, long long ncell,
                                 const void* src, double* w, long long total, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_state_to_prim<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL
@@ -759,7 +1160,7 @@ hipError_t fvm_kb_state_to_prim(int dim, int mixed, const CaseC* cases, int icas
 hipError_t fvm_kb_dt_init(int dim, int mixed, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
                           const void* src, long long total, long long label_off, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_dt_init<S, D>), dim3(blocks_b(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL
@@ -769,7 +1170,7 @@ hipError_t fvm_kb_dt_init(int dim, int mixed, const CaseC* cases, CaseDyn* dyn, 
 hipError_t fvm_kb_totals_part(int dim, int mixed, const CaseC* cases, int icase, const void* src, long long total,
                               double* part, int nblk, hipStream_t st)
 {
-  if (dim < 1 || dim > 2) return hipErrorInvalidValue;
+  if (dim < 1 || dim > 3) return hipErrorInvalidValue;
 #define CALL(S, D) hipLaunchKernelGGL((k_baro_totals_part<S, D>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
   FVM_BDISPATCH(mixed, dim, CALL);
 #undef CALL

@@ -334,6 +334,21 @@ def square_to_circle_2d(n=150, steps=2000, L=0.75, side=0.2, sigma=800.0):
                 storage=dict(p_ref=1e5, T_ref=0.0))
 
 
+def cube_to_sphere_3d(n=64, steps=2000, L=0.75, side=0.2, sigma=800.0):
+    """Section 4.5's 3D shape recovery: a cubic liquid body (rho 1000) of side
+    0.2 m centred in a 0.75 m box of gas (rho 1 at 1 bar), sigma = 800 N/m,
+    barotropic model with the section's values, zero-gradient sides, at rest."""
+    g = make_grid(3, [n, n, n], [L, L, L], [[BC_ZEROGRAD, BC_ZEROGRAD]] * 3)
+    x, y, z = cell_centres(g)
+    dist = np.maximum(np.maximum(np.abs(x - 0.5 * L), np.abs(y - 0.5 * L)), np.abs(z - 0.5 * L)) - 0.5 * side
+    alpha = smeared(dist, g["dx"][0])
+    zero = np.zeros_like(x)
+    prim = pack_prim(np.full_like(x, 1e5), zero, alpha, [zero, zero, zero])
+    return dict(name="cube_to_sphere_3d", grid=g, eos=baro_eos(),
+                scheme=default_scheme(sigma=sigma, switching=1), prim=prim, steps=steps, t_end=0.0,
+                storage=dict(p_ref=1e5, T_ref=0.0))
+
+
 def vapour_bubble_wall_2d(nx=1024, ny=512, steps=2000, dx=4e-6, R=400e-6, H=440e-6, p_b=1342.0,
                           p_inf=1e6):
     """Section 4.9's vapour bubble near a wall on a uniform 4 um grid: radius

@@ -1,6 +1,6 @@
 """GPU (gfx950) barotropic cavitation model (Section 2.2; liquid-vapour density
 THINC of Section 3.4) against the CPU FP64 oracle through the C ABI: one RHS
-on every tile in 1D and 2D (walls, far field, switching, CSF, gravity),
+on every tile in 1D, 2D and 3D (walls, far field, switching, CSF, gravity),
 primitives, steps, totals, the mixed path against FP64, a moving gas-liquid
 interface in equilibrium, a cavitating expansion, the vapour bubble near a
 wall and the square-to-circle case, and the rejected configurations."""
@@ -204,15 +204,82 @@ def test_barotropic_workloads_steps(dev, stream, name):
     assert l1 < 1e-4
 
 
+SPECS3 = [dict(n=[19, 13, 11], seed=81), dict(n=[17, 14, 12], seed=82, switching=1, sigma=0.05),
+          dict(n=[13, 12, 18], seed=83, switching=1, bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC],
+                                                        [W.BC_ZEROGRAD, W.BC_WALL]], gravity=[0.0, 0.0, -9.81])]
+
+
+@pytest.mark.parametrize("spec", SPECS3, ids=lambda s: f"3d-{s['seed']}")
+def test_barotropic_rhs_3d_every_tile(dev, stream, spec):
+    """the 3D closure + face kernels of the barotropic model, one RHS on every
+    3D tile (periodic, walls, zero gradient, switching, CSF, gravity)"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    spec = dict(spec)
+    n, seed = spec.pop("n"), spec.pop("seed")
+    grav = spec.pop("gravity", None)
+    case = W.random_state(3, n, seed, barotropic=True, **spec)
+    if grav is not None:
+        case["scheme"] = dict(case["scheme"], gravity=grav)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    assert q.shape[0] == 5
+    r_ref = o.rhs(q)
+    fl = o.sensor_flags(q)
+    for tile in range(fvm.lib().fvm_tile_count(3)):
+        ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+        ctx.set_tile(tile)
+        ok, rel = rhs_ok(gpu_rhs(ctx, q, dev), r_ref, case)
+        print(f"barotropic 3D {n} seed {seed} tile {tile}: {np.array2string(rel, precision=2)} "
+              f"(liquid-vapour THINC cells {int(((fl >> 4) & 7).astype(bool).sum())})", flush=True)
+        assert ok
+        ctx.close()
+
+
+def test_barotropic_3d_steps_mixed_and_cube_to_sphere(dev, stream):
+    """a 3D random barotropic state over 4 steps (FP64 against the oracle,
+    mixed within L1 1e-4), and Section 4.5's cube (40^3, sigma = 800) over
+    10 steps against the oracle"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    for case, steps in ((W.random_state(3, [18, 15, 13], 84, barotropic=True, sigma=0.05), 4),
+                        (W.cube_to_sphere_3d(40, 10), 10)):
+        ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+        ctx.init_primitive()
+        t_gpu = ctx.n_steps(steps)
+        o = Oracle(case)
+        q0 = o.cons_from_prim()
+        q = q0.copy()
+        t = o.run(q, steps)
+        qs = q0.copy()
+        qs[0] *= 1.0 + EPS
+        o.run(qs, steps)
+        scale = np.maximum(np.abs(q).max(axis=1), 1e-300)
+        sens = np.abs(qs - q).max(axis=1) / scale
+        rel = np.abs(ctx.get_state() - q).max(axis=1) / scale
+        print(f"{case['name']} 3D {steps} steps: {np.array2string(rel, precision=2)} "
+              f"(oracle one-ulp sensitivity {np.array2string(sens, precision=2)})", flush=True)
+        assert abs(t_gpu / t - 1) < 1e-12
+        assert np.all(rel <= np.maximum(1e-10, 4.0 * sens))
+        m = fvm.Context(case, fvm.FVM_MIXED, stream=stream.cuda_stream)
+        m.init_primitive()
+        m.n_steps(steps)
+        a, b = m.get_primitive(), ctx.get_primitive()
+        l1 = max(np.abs(a[f] - b[f]).sum() / np.abs(b[f]).sum() for f in (0, 4))
+        print(f"{case['name']} 3D mixed vs fp64 L1 rho/p: {l1:.2e}", flush=True)
+        assert l1 < 1e-4
+
+
 def test_barotropic_rejections(dev, stream):
     from paper_2304_00140_amd import fvm
-    c3 = W.random_state(3, [8, 8, 8], 67, barotropic=True)
-    with pytest.raises(fvm.FvmError):
-        fvm.Context(c3, fvm.FVM_FP64, stream=stream.cuda_stream)
     c2 = W.random_state(2, [16, 16], 68, barotropic=True)
     c2["eos"] = dict(c2["eos"], mu=[1e-3, 0.0])
     with pytest.raises(fvm.FvmError):
         fvm.Context(c2, fvm.FVM_FP64, stream=stream.cuda_stream)
+    c3 = W.random_state(2, [16, 16], 69, barotropic=True)
+    c3["eos"] = dict(c3["eos"], baro=dict(c3["eos"]["baro"], rho_vap=2000.0))
+    with pytest.raises(fvm.FvmError):
+        fvm.Context(c3, fvm.FVM_FP64, stream=stream.cuda_stream)
 
 
 def test_vapour_bubble_full_size_in_the_benchmark_launch(dev, stream):

@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
                              "liquid_jet_3d_viscous", "dual_gas_layer_2d", "vapour_bubble_wall_2d",
-                             "interface_advection_1d"])
+                             "cube_to_sphere_3d", "interface_advection_1d"])
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--tile", type=int, default=-1, help="stage-kernel tile index (-1: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -110,6 +110,9 @@ def make_workload(name, steps):
     if name == "vapour_bubble_wall_2d":
         return [W.vapour_bubble_wall_2d(1024, 512, steps)], dict(workload=name, nx=1024, ny=512, dx=4e-6,
                                                                  model="barotropic")
+    if name == "cube_to_sphere_3d":
+        return [W.cube_to_sphere_3d(256, steps)], dict(workload=name, nx=256, ny=256, nz=256, sigma=800.0,
+                                                       model="barotropic")
     if name == "liquid_jet_3d_viscous":
         return [W.liquid_jet_3d(512, 256, 256, steps, viscous=True)], dict(workload=name, nx=512, ny=256, nz=256)
     raise ValueError(name)
@@ -154,6 +157,13 @@ def run_path(cases, prec, args, stream, torch):
                 tune={str(k): round(v, 5) for k, v in (tune or {}).items()})
 
 
+def kernel_name(case):
+    baro = int(case["eos"].get("model", 0)) == 1
+    if case["grid"]["dim"] == 3:
+        return "k_bprim3+k_bface3" if baro else "k_prim3+k_face3"
+    return "k_baro12" if baro else "k_stage12"
+
+
 def l1_errors(a, b, uref):
     """relative L1 of the mixed-path primitives a against FP64-path b"""
     n = a.shape[1]
@@ -170,13 +180,16 @@ def l1_errors(a, b, uref):
 
 def cpu_baseline(cases, seconds):
     """the oracle on the host cores, on a bounded sample of the workload: whole
-    steps of the first case (for the 3D jet a reduced grid of the same case)
+    steps of the first case (for the large 3D cases a reduced grid of the same case)
     until about `seconds` of CPU work"""
     from oracle.oracle import Oracle
     from paper_2304_00140_amd import workloads as W
     case = cases[0]
     if case["grid"]["dim"] == 3 and np.prod(case["grid"]["n"]) > 2_000_000:
-        case = W.liquid_jet_3d(128, 64, 64, steps=1, viscous=case.get("viscous", False))
+        if case["name"] == "cube_to_sphere_3d":
+            case = W.cube_to_sphere_3d(64, 1)
+        else:
+            case = W.liquid_jet_3d(128, 64, 64, steps=1, viscous=case.get("viscous", False))
     o = Oracle(case)
     q = o.cons_from_prim()
     t0 = time.perf_counter()
@@ -252,8 +265,7 @@ def main():
             "unit": "T VALU lane-instr/s",
             "frac": None if achieved is None else achieved / VALU_PEAK_TINSTR,
             "traffic": traffic,
-            "kernel": ("k_prim3+k_face3" if cases[0]["grid"]["dim"] == 3 else
-                       "k_baro12" if int(cases[0]["eos"].get("model", 0)) == 1 else "k_stage12"),
+            "kernel": kernel_name(cases[0]),
             "kernel_build": KERNEL_BUILD,
             "valu_per_cell_stage": None if meas is None else meas["valu_per_cell_stage"],
             "stage_launch_ms": stage_avg_ms,
@@ -278,7 +290,7 @@ def main():
             entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0, "liquid_jet_3d_viscous": 300.0,
-                    "dual_gas_layer_2d": 25.0, "vapour_bubble_wall_2d": 31.6,
+                    "dual_gas_layer_2d": 25.0, "vapour_bubble_wall_2d": 31.6, "cube_to_sphere_3d": 3.0,
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
         out["mixed"] = entry

@@ -421,6 +421,8 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   if (b->dim == 3) {
     if (hipMalloc(&b->prim, (size_t)9 * (size_t)b->total * b->esz) != hipSuccess)
       return bail(fail(b, FVM_ENOMEM, "primitive buffer allocation failed"));
+    // zero T: the first closure of a Peng-Robinson cell takes the ideal-gas start
+    HIPCHECK(b, hipMemset(b->prim, 0, (size_t)9 * (size_t)b->total * b->esz));
   }
   HIPCHECK(b, hipMalloc(&b->dpart, sizeof(double) * 1024 * 8));
   HIPCHECK(b, hipMalloc(&b->dout, sizeof(double) * 16));

@@ -305,9 +305,11 @@ __device__ inline PT closure3(const CaseC& C, double rho, double Y1, double Y2, 
 
 // (rho, xi, e) -> (p, T), c = max of the components' sound speeds, alpha_G.
 // e is the specific internal energy in the storage gauge.  PRK: component 1
-// may be a Peng-Robinson fluid.
+// may be a Peng-Robinson fluid; its Newton iterations start from (pw, Tw)
+// when given (Tw > 0: the cell's state of the previous stage, Appendix B) and
+// from the ideal-gas stand-in otherwise or if that start does not converge.
 template <bool PRK>
-__device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
+__device__ inline PT closure(const CaseC& C, double rho, double Y, double e, double Tw = 0.0, double pw = 0.0)
 {
   const Comp& c0 = C.comp[0];
   const Comp& c1 = C.comp[1];
@@ -353,18 +355,25 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
       double V = c1.M * v;
       double L = pr_log(V, c1.b);
       double k = L / (2.0 * SQRT2 * c1.b * c1.M);
-      double Tn = (e - c1.qs) / c1.cv;
-      if (!(Tn > 0.0)) Tn = 100.0;
+      double Tn = 0.0;
       int conv = 0;
-      for (int it = 0; it < 60; ++it) {
-        PRab A = pr_a(c1, Tn);
-        double f = c1.cv * Tn + c1.qs + (A.a - Tn * A.a1) * k - e;
-        double fp = c1.cv - Tn * A.a2 * k;
-        double dT = f * frcp(fp);
-        double Tnew = Tn - dT;
-        if (Tnew <= 0.0) Tnew = 0.5 * Tn;
-        Tn = Tnew;
-        if (fabs(dT) <= 1e-13 * Tn) { conv = 1; break; }
+      for (int start = (Tw > 0.0 && Tw < 1e300) ? 0 : 1; start < 2 && !conv; ++start) {
+        if (start == 0) {
+          Tn = Tw;
+        } else {
+          Tn = (e - c1.qs) / c1.cv;
+          if (!(Tn > 0.0)) Tn = 100.0;
+        }
+        for (int it = 0; it < 60; ++it) {
+          PRab A = pr_a(c1, Tn);
+          double f = c1.cv * Tn + c1.qs + (A.a - Tn * A.a1) * k - e;
+          double fp = c1.cv - Tn * A.a2 * k;
+          double dT = f * frcp(fp);
+          double Tnew = Tn - dT;
+          if (Tnew <= 0.0) Tnew = 0.5 * Tn;
+          Tn = Tnew;
+          if (fabs(dT) <= 1e-13 * Tn) { conv = 1; break; }
+        }
       }
       PRab A = pr_a(c1, Tn);
       r.T = Tn;
@@ -374,25 +383,34 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e)
       r.ok = conv;
       return r;
     }
-    // mixed cell: Newton on sum xi_k v_k = v, sum xi_k e_k = e from the ideal-gas stand-in
-    sg_pair(c0.gamma, c0.pinf, c0.cv, c0.qs, c1.gam_ig, 0.0, c1.cv, c1.qs, v, e, Y, p, T);
+    // mixed cell: Newton on sum xi_k v_k = v, sum xi_k e_k = e from the
+    // previous stage's (p, T) or the ideal-gas stand-in
     double Y0 = 1.0 - Y;
     // pressure is resolved to rounding relative to p + p_inf of the stiff component
     const double pscale = fmax(c0.pinf, 1.0);
     int conv = 0;
-    for (int it = 0; it < 60; ++it) {
-      VE a = comp_ve(c0, p, T), b = comp_ve(c1, p, T);
-      double F1 = Y0 * a.v + Y * b.v - v, F2 = Y0 * a.e + Y * b.e - e;
-      double J11 = Y0 * a.dvdp + Y * b.dvdp, J12 = Y0 * a.dvdT + Y * b.dvdT;
-      double J21 = Y0 * a.dedp + Y * b.dedp, J22 = Y0 * a.dedT + Y * b.dedT;
-      double idet = frcp(J11 * J22 - J12 * J21);
-      double dp = (F1 * J22 - F2 * J12) * idet;
-      double dT = (J11 * F2 - J21 * F1) * idet;
-      double Tn = T - dT;
-      if (Tn <= 0.0) Tn = 0.5 * T;
-      p -= dp;
-      T = Tn;
-      if (fabs(dT) <= 1e-12 * T && fabs(dp) <= 1e-12 * (fabs(p) + pscale)) { conv = 1; break; }
+    const bool warm = Tw > 0.0 && Tw < 1e300 && fabs(pw) < 1e300;
+    for (int start = warm ? 0 : 1; start < 2 && !conv; ++start) {
+      if (start == 0) {
+        p = pw;
+        T = Tw;
+      } else {
+        sg_pair(c0.gamma, c0.pinf, c0.cv, c0.qs, c1.gam_ig, 0.0, c1.cv, c1.qs, v, e, Y, p, T);
+      }
+      for (int it = 0; it < 60; ++it) {
+        VE a = comp_ve(c0, p, T), b = comp_ve(c1, p, T);
+        double F1 = Y0 * a.v + Y * b.v - v, F2 = Y0 * a.e + Y * b.e - e;
+        double J11 = Y0 * a.dvdp + Y * b.dvdp, J12 = Y0 * a.dvdT + Y * b.dvdT;
+        double J21 = Y0 * a.dedp + Y * b.dedp, J22 = Y0 * a.dedT + Y * b.dedT;
+        double idet = frcp(J11 * J22 - J12 * J21);
+        double dp = (F1 * J22 - F2 * J12) * idet;
+        double dT = (J11 * F2 - J21 * F1) * idet;
+        double Tn = T - dT;
+        if (Tn <= 0.0) Tn = 0.5 * T;
+        p -= dp;
+        T = Tn;
+        if (fabs(dT) <= 1e-12 * T && fabs(dp) <= 1e-12 * (fabs(p) + pscale)) { conv = 1; break; }
+      }
     }
     r.p = p;
     r.T = T;

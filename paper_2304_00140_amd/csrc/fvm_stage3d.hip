@@ -17,7 +17,9 @@ namespace fvm {
 
 constexpr int NW3 = 9;   // rho, u, v, w, p, T, xi, c, alpha_G
 
-// primitives of every owned cell of the tile.  In the first stage of a step
+// primitives of every owned cell of the tile (a Peng-Robinson closure starts
+// its Newton iterations from the cell's previous primitives, which the paper
+// suggests for convergence speed).  In the first stage of a step
 // the cells hold q^n, so this kernel also folds the CFL bound of q^n into the
 // case's slot for this step (read by the face kernel of the same stage) and
 // reports a non-finite or non-physical q^n as an error of the step before.
@@ -47,7 +49,14 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
     q[1] = (double)src[T + cell] + C.rref[1];
 #pragma unroll
     for (int v = 2; v < 6; ++v) q[v] = (double)src[v * T + cell];
-    PT pt = cell_prim<3, PRK>(C, q, u, rho, Y);
+    // the Peng-Robinson Newton starts from this cell's (p, T) of the previous
+    // stage, still in the primitive buffer (zero before the first stage)
+    double Tw = 0.0, pw = 0.0;
+    if constexpr (PRK) {
+      Tw = (double)W[5 * T + cell];
+      pw = (double)W[4 * T + cell];
+    }
+    PT pt = cell_prim<3, PRK>(C, q, u, rho, Y, Tw, pw);
     W[cell] = S(rho);
     W[T + cell] = S(u[0]);
     W[2 * T + cell] = S(u[1]);

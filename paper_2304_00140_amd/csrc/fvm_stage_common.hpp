@@ -123,7 +123,8 @@ __device__ inline void load_cell(const CaseC& C, const S* __restrict__ src, long
 
 // primitives of a loaded cell
 template <int D, bool PRK>
-__device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y)
+__device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, double& rho, double& Y,
+                               double Tw = 0.0, double pw = 0.0)
 {
   rho = q[0] + q[1];
   double ir = frcp(rho);
@@ -132,7 +133,7 @@ __device__ inline PT cell_prim(const CaseC& C, const double* q, double* u, doubl
 #pragma unroll
   for (int d = 0; d < D; ++d) { u[d] = q[2 + d] * ir; ke += u[d] * u[d]; }
   double e = q[2 + D] * ir - 0.5 * ke;
-  return closure<PRK>(C, rho, Y, e);
+  return closure<PRK>(C, rho, Y, e, Tw, pw);
 }
 
 // primitives of a loaded three-component cell (second gas at index 3 + D)

@@ -116,7 +116,8 @@ typedef struct fvm_grid_desc {
  * liquid-vapour mixture below it (the same law with c_M^2 = p_sat / rho_sat),
  * and one isothermal ideal gas rho_G = p / bt_RT (bt_RT = R_Gas T_ref).
  * There is no energy equation: N_q = D + 2 (rho, rho u, rho xi); p follows
- * from (rho, xi); the T row of the primitive input is ignored; the primitive
+ * from (rho, xi); the T row of the primitive input and in_T, ff_T of the grid
+ * are ignored (a far-field or inflow state needs p > 0 instead); the primitive
  * output has 12 rows (the 11 above with T = xi_2 = alpha_2 = 0, then the
  * vapour volume fraction of eq. 2-7, at most 0.995).  Where the upwind cell
  * of a face is a liquid-vapour interface cell (eps < alpha_V < 1 - eps, and

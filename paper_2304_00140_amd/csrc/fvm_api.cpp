@@ -62,7 +62,9 @@ static int fail(fvm_batch* b, int code, const std::string& msg)
   } while (0)
 
 // ------------------------------------------------------------------ descriptors -> tables
-static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
+// baro: the barotropic model, whose far-field and inflow states need no
+// temperature but a positive pressure
+static int check_grid(fvm_batch* b, const fvm_grid_desc* g, bool baro)
 {
   if (!g) return fail(b, FVM_EINVAL, "grid descriptor is NULL");
   if (g->dim < 1 || g->dim > 3) return fail(b, FVM_EINVAL, "dim must be 1, 2 or 3");
@@ -73,8 +75,10 @@ static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
       for (int s = 0; s < 2; ++s) {
         int k = g->bc[d][s];
         if (k < 0 || k > 4) return fail(b, FVM_EINVAL, "unknown boundary kind");
-        if (k == FVM_BC_FARFIELD && !(g->ff_T > 0.0 && g->ff_alpha >= 0.0 && g->ff_alpha <= 1.0))
-          return fail(b, FVM_EINVAL, "far-field state needs ff_T > 0 and 0 <= ff_alpha <= 1");
+        if (k == FVM_BC_FARFIELD && !((baro ? g->ff_p > 0.0 : g->ff_T > 0.0) && g->ff_alpha >= 0.0 &&
+                                      g->ff_alpha <= 1.0))
+          return fail(b, FVM_EINVAL, baro ? "far-field state needs ff_p > 0 and 0 <= ff_alpha <= 1"
+                                          : "far-field state needs ff_T > 0 and 0 <= ff_alpha <= 1");
         if (k == FVM_BC_INFLOW && !(d == 0 && s == 0)) return fail(b, FVM_EINVAL, "inflow only at the x-min side");
       }
       if ((g->bc[d][0] == FVM_BC_PERIODIC) != (g->bc[d][1] == FVM_BC_PERIODIC))
@@ -83,8 +87,8 @@ static int check_grid(fvm_batch* b, const fvm_grid_desc* g)
       return fail(b, FVM_EINVAL, "n[d] must be 1 in unused directions");
     }
   }
-  if (g->bc[0][0] == FVM_BC_INFLOW && !(g->in_p > -1e300 && g->in_T > 0.0))
-    return fail(b, FVM_EINVAL, "inflow state needs in_T > 0");
+  if (g->bc[0][0] == FVM_BC_INFLOW && !(baro ? g->in_p > 0.0 : (g->in_p > -1e300 && g->in_T > 0.0)))
+    return fail(b, FVM_EINVAL, baro ? "inflow state needs in_p > 0" : "inflow state needs in_T > 0");
   return FVM_OK;
 }
 
@@ -280,7 +284,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   long long off = 0;
   for (int c = 0; c < ncases; ++c) {
     const fvm_grid_desc* g = &grids[c];
-    if ((rc = check_grid(b, g))) return bail(rc);
+    if ((rc = check_grid(b, g, eos[c].model == FVM_MODEL_BAROTROPIC))) return bail(rc);
     if (g->dim != b->dim) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the dimension"));
     if ((rc = check_eos(b, &eos[c]))) return bail(rc);
     const int nc = eos_ncomp(&eos[c]);

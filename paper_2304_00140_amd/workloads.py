@@ -358,7 +358,7 @@ def vapour_bubble_wall_2d(nx=1024, ny=512, steps=2000, dx=4e-6, R=400e-6, H=440e
     p = p_inf + (p_b - p_inf) R / r in between; the other sides are a far-field
     reservoir at p_inf."""
     g = make_grid(2, [nx, ny], [nx * dx, ny * dx], [[BC_FARFIELD, BC_FARFIELD], [BC_WALL, BC_FARFIELD]])
-    g["farfield"] = dict(p=p_inf, T=293.15, alpha=0.0)   # T is not used by the barotropic model
+    g["farfield"] = dict(p=p_inf, T=0.0, alpha=0.0)   # the barotropic model has no temperature
     x, y = cell_centres(g)
     r = np.hypot(x - 0.5 * nx * dx, y - H)
     inside = 1.0 - smeared(r - R, dx)

@@ -280,6 +280,11 @@ def test_barotropic_rejections(dev, stream):
     c3["eos"] = dict(c3["eos"], baro=dict(c3["eos"]["baro"], rho_vap=2000.0))
     with pytest.raises(fvm.FvmError):
         fvm.Context(c3, fvm.FVM_FP64, stream=stream.cuda_stream)
+    # a far-field reservoir needs a positive pressure (no temperature in the model)
+    c4 = W.vapour_bubble_wall_2d(32, 24, 1, dx=40e-6)
+    c4["grid"] = dict(c4["grid"], farfield=dict(p=0.0, T=300.0, alpha=0.0))
+    with pytest.raises(fvm.FvmError):
+        fvm.Context(c4, fvm.FVM_FP64, stream=stream.cuda_stream)
 
 
 def test_vapour_bubble_full_size_in_the_benchmark_launch(dev, stream):

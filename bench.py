@@ -26,31 +26,38 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # workloads and launch shapes (profiles/k_stage12_shock_bubble_2d_counters.md,
 # profiles/k_stage12_dual_gas_layer_2d_counters.md,
 # profiles/k_baro12_vapour_bubble_wall_2d_counters.md,
+# profiles/k_bface3_cube_to_sphere_3d_counters.md,
 # profiles/k_face3_liquid_jet_3d_counters.md): executed VALU lane-instructions
 # per cell-stage (SQ_INSTS_VALU x 64 / cells; in 3D the closure and face kernels
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v6"
+KERNEL_BUILD = "k_stage12-v7"
 MEASURED = {
-    ("shock_bubble_2d", 0, 3, "k_stage12-v6"): dict(valu_per_cell_stage=4218140.4 * 64 / 262144,
-                                               traffic_bytes=(9777.8 * 2 + 10244.1) * 1024),
-    ("shock_bubble_2d", 1, 8, "k_stage12-v6"): dict(valu_per_cell_stage=4060792.1 * 64 / 262144,
-                                               traffic_bytes=(4945.3 * 2 + 5124.4) * 1024),
-    ("dual_gas_layer_2d", 0, 0, "k_stage12-v6"): dict(valu_per_cell_stage=10562551.4 * 64 / 524288,
-                                                 traffic_bytes=(22480.4 * 2 + 24581.2) * 1024),
-    ("dual_gas_layer_2d", 1, 1, "k_stage12-v6"): dict(valu_per_cell_stage=11505893.2 * 64 / 524288,
-                                                 traffic_bytes=(11309.2 * 2 + 12300.3) * 1024),
-    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v6"): dict(valu_per_cell_stage=8821924.3 * 64 / 524288,
-                                                     traffic_bytes=(15049.6 * 2 + 16389.2) * 1024),
-    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v6"): dict(valu_per_cell_stage=8159430.9 * 64 / 524288,
-                                                     traffic_bytes=(7601.3 * 2 + 8197.1) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v6"): dict(valu_per_cell_stage=(460998295.7 + 1322165409.0) * 64 / 33554432,
-                                                  traffic_bytes=((803568.6 + 3477200.9) * 2 +
-                                                                 (2659306.4 + 1669630.8)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v6"): dict(valu_per_cell_stage=(434323140.2 + 1424810008.0) * 64 / 33554432,
-                                                  traffic_bytes=((395372.7 + 1799769.9) * 2 +
-                                                                 (1212148.4 + 808751.9)) * 1024),
+    ("shock_bubble_2d", 0, 3, "k_stage12-v7"): dict(valu_per_cell_stage=4218134.0 * 64 / 262144,
+                                             traffic_bytes=(9777.9 * 2 + 10244.1) * 1024),
+    ("shock_bubble_2d", 1, 6, "k_stage12-v7"): dict(valu_per_cell_stage=3899133.9 * 64 / 262144,
+                                             traffic_bytes=(4944.7 * 2 + 5125.3) * 1024),
+    ("dual_gas_layer_2d", 0, 0, "k_stage12-v7"): dict(valu_per_cell_stage=10562538.6 * 64 / 524288,
+                                               traffic_bytes=(22480.6 * 2 + 24581.1) * 1024),
+    ("dual_gas_layer_2d", 1, 1, "k_stage12-v7"): dict(valu_per_cell_stage=11505871.5 * 64 / 524288,
+                                               traffic_bytes=(11309.8 * 2 + 12298.0) * 1024),
+    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v7"): dict(valu_per_cell_stage=8821944.9 * 64 / 524288,
+                                                   traffic_bytes=(15049.5 * 2 + 16389.4) * 1024),
+    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v7"): dict(valu_per_cell_stage=8159441.5 * 64 / 524288,
+                                                   traffic_bytes=(7601.4 * 2 + 8197.1) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(333927615.7 + 1321888126.9) * 64 / 33554432,
+                                           traffic_bytes=((929056.2 + 3487349.9) * 2 +
+                                                          (2542475.8 + 1661430.1)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v7"): dict(valu_per_cell_stage=(376284417.5 + 1424810008.0) * 64 / 33554432,
+                                           traffic_bytes=((462774.8 + 1730970.9) * 2 +
+                                                          (1185751.8 + 790480.3)) * 1024),
+    ("cube_to_sphere_3d", 0, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(50992877.8 + 402984771.5) * 64 / 16777216,
+                                               traffic_bytes=((360270.7 + 1574571.9) * 2 +
+                                                              (1374991.2 + 686094.7)) * 1024),
+    ("cube_to_sphere_3d", 1, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(54662919.5 + 359542514.4) * 64 / 16777216,
+                                               traffic_bytes=((164571.1 + 623408.4) * 2 +
+                                                              (640975.8 + 355229.7)) * 1024),
 }
 
 

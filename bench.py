@@ -32,39 +32,40 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v7"
+KERNEL_BUILD = "k_stage12-v8"
 MEASURED = {
-    ("shock_bubble_2d", 0, 3, "k_stage12-v7"): dict(valu_per_cell_stage=4218134.0 * 64 / 262144,
-                                             traffic_bytes=(9777.9 * 2 + 10244.1) * 1024),
-    ("shock_bubble_2d", 1, 6, "k_stage12-v7"): dict(valu_per_cell_stage=3899133.9 * 64 / 262144,
-                                             traffic_bytes=(4944.7 * 2 + 5125.3) * 1024),
-    ("dual_gas_layer_2d", 0, 0, "k_stage12-v7"): dict(valu_per_cell_stage=10562538.6 * 64 / 524288,
-                                               traffic_bytes=(22480.6 * 2 + 24581.1) * 1024),
-    ("dual_gas_layer_2d", 1, 1, "k_stage12-v7"): dict(valu_per_cell_stage=11505871.5 * 64 / 524288,
-                                               traffic_bytes=(11309.8 * 2 + 12298.0) * 1024),
-    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v7"): dict(valu_per_cell_stage=8821944.9 * 64 / 524288,
-                                                   traffic_bytes=(15049.5 * 2 + 16389.4) * 1024),
-    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v7"): dict(valu_per_cell_stage=8159441.5 * 64 / 524288,
-                                                   traffic_bytes=(7601.4 * 2 + 8197.1) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(333927615.7 + 1321888126.9) * 64 / 33554432,
-                                           traffic_bytes=((929056.2 + 3487349.9) * 2 +
-                                                          (2542475.8 + 1661430.1)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v7"): dict(valu_per_cell_stage=(376284417.5 + 1424810008.0) * 64 / 33554432,
-                                           traffic_bytes=((462774.8 + 1730970.9) * 2 +
-                                                          (1185751.8 + 790480.3)) * 1024),
-    ("cube_to_sphere_3d", 0, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(50992877.8 + 402984771.5) * 64 / 16777216,
-                                               traffic_bytes=((360270.7 + 1574571.9) * 2 +
-                                                              (1374991.2 + 686094.7)) * 1024),
-    ("cube_to_sphere_3d", 1, 4, "k_stage12-v7"): dict(valu_per_cell_stage=(54662919.5 + 359542514.4) * 64 / 16777216,
-                                               traffic_bytes=((164571.1 + 623408.4) * 2 +
-                                                              (640975.8 + 355229.7)) * 1024),
+    ("shock_bubble_2d", 0, 3, "k_stage12-v8"): dict(valu_per_cell_stage=4218125.3 * 64 / 262144,
+                                             traffic_bytes=(9767.0 * 2 + 10248.1) * 1024),
+    ("shock_bubble_2d", 1, 7, "k_stage12-v8"): dict(valu_per_cell_stage=3877406.2 * 64 / 262144,
+                                             traffic_bytes=(4945.9 * 2 + 5128.1) * 1024),
+    ("dual_gas_layer_2d", 0, 0, "k_stage12-v8"): dict(valu_per_cell_stage=10562916.3 * 64 / 524288,
+                                               traffic_bytes=(22495.1 * 2 + 24592.1) * 1024),
+    ("dual_gas_layer_2d", 1, 0, "k_stage12-v8"): dict(valu_per_cell_stage=9379870.9 * 64 / 524288,
+                                               traffic_bytes=(11368.0 * 2 + 12304.1) * 1024),
+    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v8"): dict(valu_per_cell_stage=8822294.0 * 64 / 524288,
+                                                   traffic_bytes=(15054.7 * 2 + 16400.1) * 1024),
+    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v8"): dict(valu_per_cell_stage=8159818.5 * 64 / 524288,
+                                                   traffic_bytes=(7609.7 * 2 + 8208.1) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
+                                           traffic_bytes=((928092.7 + 3519918.0) * 2 +
+                                                          (2547638.9 + 1670954.9)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v8"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
+                                           traffic_bytes=((462806.3 + 1687543.7) * 2 +
+                                                          (1216205.0 + 814994.2)) * 1024),
+    ("cube_to_sphere_3d", 0, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(51025400.0 + 402984771.5) * 64 / 16777216,
+                                               traffic_bytes=((342717.2 + 1523396.9) * 2 +
+                                                              (1378574.6 + 683563.0)) * 1024),
+    ("cube_to_sphere_3d", 1, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(54695416.0 + 359542514.4) * 64 / 16777216,
+                                               traffic_bytes=((164771.2 + 629509.0) * 2 +
+                                                              (672127.7 + 359111.2)) * 1024),
 }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's own step count, 2000 for the 2D cases)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
@@ -78,7 +79,16 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=20, help="steps of per-stage event timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates the HBM byte counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS.get(args.workload, 2000)
+    return args
+
+
+# step counts the workloads are specified with (the 3D cases 200 steps, the
+# batch of bubble collapses 500 steps each, the drop 10^4 steps)
+DEFAULT_STEPS = {"bubble_collapse_batch": 500, "liquid_jet_3d": 200, "liquid_jet_3d_viscous": 200,
+                 "cube_to_sphere_3d": 200, "drop_2d": 10000}
 
 
 def copy_probe(mib):

@@ -107,7 +107,8 @@ typedef struct fvm_grid_desc {
  * rho xi_1, rho xi_2), the primitive input gains alpha_2 after u, the
  * primitive output gains xi_2 and alpha_2 (11 rows), and the mixing above is
  * (1 - alpha_1 - alpha_2) value_0 + alpha_1 value_1 + alpha_2 value_2.  Three
- * components are supported in 1D and 2D (FVM_EINVAL in 3D).
+ * components run in 1D, 2D and 3D; in 3D in FP64 the 8x8x8 tile does not fit
+ * the LDS of a workgroup (fvm_set_tile returns FVM_EINVAL for it).
  * model: FVM_MODEL_FOUR_EQ (0, everything above) or FVM_MODEL_BAROTROPIC, the
  * barotropic equilibrium model of Section 2.2 (eqs. 2-3 .. 2-7), which
  * replaces the components above (kind, gamma, pinf, cv, q, PR data and T_ref
@@ -217,7 +218,10 @@ int fvm_totals(fvm_ctx* ctx, double* out);
 int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step);
 
 /* Launch configuration: tile shape index of the fused stage kernel for this
- * context's dimension (0 .. fvm_tile_count(dim) - 1) and its extent. */
+ * context's dimension (0 .. fvm_tile_count(dim) - 1) and its extent.
+ * fvm_set_tile / fvm_batch_set_tile return FVM_EINVAL (state unchanged) for an
+ * index out of range or a tile whose kernels do not fit this closure and
+ * precision (3D, three components, FP64: the 8x8x8 tile). */
 int fvm_tile_count(int dim);
 int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads);
 int fvm_set_tile(fvm_ctx* ctx, int tile);

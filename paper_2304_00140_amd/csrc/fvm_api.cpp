@@ -290,7 +290,6 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     const int nc = eos_ncomp(&eos[c]);
     if (c == 0) b->ncomp = nc;
     if (nc != b->ncomp) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the number of components"));
-    if (nc == 3 && g->dim == 3) return bail(fail(b, FVM_EINVAL, "three components are supported in 1D and 2D"));
     const int baro = eos[c].model == FVM_MODEL_BAROTROPIC;
     if (c == 0) b->kind = baro ? FVM_KIND_BARO : FVM_KIND_SG;
     if (baro != (b->kind == FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
@@ -423,10 +422,12 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     HIPCHECK(b, hipMemset(b->q[i], 0, bytes));
   }
   if (b->dim == 3) {
-    if (hipMalloc(&b->prim, (size_t)9 * (size_t)b->total * b->esz) != hipSuccess)
+    // rho, u, v, w, p, T, xi, c, alpha (+ xi_2, alpha_2 with three components)
+    const size_t rows = (b->kind == FVM_KIND_THREE) ? 11 : 9;
+    if (hipMalloc(&b->prim, rows * (size_t)b->total * b->esz) != hipSuccess)
       return bail(fail(b, FVM_ENOMEM, "primitive buffer allocation failed"));
     // zero T: the first closure of a Peng-Robinson cell takes the ideal-gas start
-    HIPCHECK(b, hipMemset(b->prim, 0, (size_t)9 * (size_t)b->total * b->esz));
+    HIPCHECK(b, hipMemset(b->prim, 0, rows * (size_t)b->total * b->esz));
   }
   HIPCHECK(b, hipMalloc(&b->dpart, sizeof(double) * 1024 * 8));
   HIPCHECK(b, hipMalloc(&b->dout, sizeof(double) * 16));
@@ -824,11 +825,21 @@ int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads)
   return FVM_OK;
 }
 
+// a tile index that exists and whose kernels fit this batch's closure and precision
+static int check_tile(fvm_batch* b, int tile)
+{
+  if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  if (b->dim == 3 && b->kind == FVM_KIND_THREE && !fvm_k_tile_ok3(b->mixed, b->kind, tile))
+    return fail(b, FVM_EINVAL, "this 3D tile does not fit the LDS of a workgroup with three components in FP64");
+  return FVM_OK;
+}
+
 int fvm_set_tile(fvm_ctx* ctx, int tile)
 {
   CTX_CHECK(ctx);
   fvm_batch* b = ctx->b;
-  if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  int rc = check_tile(b, tile);
+  if (rc) return rc;
   drop_graph(b);
   b->tile = tile;
   return build_tiles(b);
@@ -918,7 +929,8 @@ int fvm_batch_time_stages(fvm_batch* b, int steps, double* ms_per_stage)
 int fvm_batch_set_tile(fvm_batch* b, int tile)
 {
   if (!b) return FVM_EINVAL;
-  if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  int rc = check_tile(b, tile);
+  if (rc) return rc;
   drop_graph(b);
   b->tile = tile;
   return build_tiles(b);

@@ -228,10 +228,7 @@ int fvm_k_tile_shape(int dim, int t, int* tx, int* ty, int* nt)
 hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
   if (kind == FVM_KIND_BARO) return fvm_kb_stage(dim, mixed, tile, a, ntiles, st);
-  if (dim == 3) {
-    if (kind == FVM_KIND_THREE) return hipErrorInvalidValue;
-    return fvm_k_stage3(mixed, kind == FVM_KIND_PR, tile, a, ntiles, st);
-  }
+  if (dim == 3) return fvm_k_stage3(mixed, kind, tile, a, ntiles, st);
   if (fvm_default_limiters(a.sc)) return fvm_k_stage12_deflim(dim, mixed, kind, tile, a, ntiles, st);
   return stage12_any<0>(dim, mixed, kind, tile, a, ntiles, st);
 }

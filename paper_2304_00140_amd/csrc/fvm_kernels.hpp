@@ -10,7 +10,7 @@ struct StageArgs {
   const void* src;            // q^(k-1), storage variables [N_q][total]
   const void* qn;             // q^n
   void* dst;                  // q^(k)
-  void* prim;                 // 3D: primitives of q^(k-1) [9][total] in the storage precision
+  void* prim;                 // 3D: primitives of q^(k-1) [9][total] (three components: [11][total]), storage precision
   long long total;            // field stride (cells of all cases)
   double* rhs_out;            // stage < 0: R in conserved variables [N_q][total]
   long long rhs_step;         // stage < 0: step number for the inflow noise
@@ -44,7 +44,8 @@ hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& 
 // 1D/2D stage kernels with the default limiters fixed (fvm_stage12_deflim.hip)
 hipError_t fvm_k_stage12_deflim(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles,
                                 hipStream_t st);
-hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+hipError_t fvm_k_stage3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+int fvm_k_tile_ok3(int mixed, int kind, int tile);
 hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,
                                const double* prim, void* dst, long long total, hipStream_t st);

@@ -7,7 +7,9 @@
 // the face kernel stages tile + halo primitives in LDS (ghosts generated from
 // the boundary kinds), evaluates the sensors, every face flux once (x, y, z
 // sweeps), the CSF source with the 3D Gaussian kernel (/64) and vertex normals
-// of the 2x2x2 cell blocks, and the stage update.
+// of the 2x2x2 cell blocks, and the stage update.  G2: three components (a
+// liquid and two gases); the second gas adds its partial density as the last
+// storage field and (xi_2, alpha_2) as primitive rows 9 and 10.
 #include <hip/hip_runtime.h>
 #include "fvm_device.hpp"
 #include "fvm_kernels.hpp"
@@ -15,7 +17,9 @@
 
 namespace fvm {
 
-constexpr int NW3 = 9;   // rho, u, v, w, p, T, xi, c, alpha_G
+// primitive rows: rho, u, v, w, p, T, xi, c, alpha_G (+ xi_2, alpha_2 with G2)
+template <bool G2>
+constexpr int nw3() { return G2 ? 11 : 9; }
 
 // primitives of every owned cell of the tile (a Peng-Robinson closure starts
 // its Newton iterations from the cell's previous primitives, which the paper
@@ -23,7 +27,7 @@ constexpr int NW3 = 9;   // rho, u, v, w, p, T, xi, c, alpha_G
 // the cells hold q^n, so this kernel also folds the CFL bound of q^n into the
 // case's slot for this step (read by the face kernel of the same stage) and
 // reports a non-finite or non-physical q^n as an error of the step before.
-template <class S, int TX, int TY, int TZ, bool PRK>
+template <class S, int TX, int TY, int TZ, bool PRK, bool G2>
 __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
 {
   __shared__ double s_red[4];
@@ -44,19 +48,25 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
   const int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
   if (cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2]) {
     long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
-    double q[6], u[3], rho, Y;
+    double q[G2 ? 7 : 6], u[3], rho, Y, Y2 = 0.0;
     q[0] = (double)src[cell] + C.rref[0];
     q[1] = (double)src[T + cell] + C.rref[1];
 #pragma unroll
     for (int v = 2; v < 6; ++v) q[v] = (double)src[v * T + cell];
-    // the Peng-Robinson Newton starts from this cell's (p, T) of the previous
-    // stage, still in the primitive buffer (zero before the first stage)
-    double Tw = 0.0, pw = 0.0;
-    if constexpr (PRK) {
-      Tw = (double)W[5 * T + cell];
-      pw = (double)W[4 * T + cell];
+    PT pt;
+    if constexpr (G2) {
+      q[6] = (double)src[6 * T + cell] + C.rref[2];
+      pt = cell_prim3<3>(C, q, u, rho, Y, Y2);
+    } else {
+      // the Peng-Robinson Newton starts from this cell's (p, T) of the previous
+      // stage, still in the primitive buffer (zero before the first stage)
+      double Tw = 0.0, pw = 0.0;
+      if constexpr (PRK) {
+        Tw = (double)W[5 * T + cell];
+        pw = (double)W[4 * T + cell];
+      }
+      pt = cell_prim<3, PRK>(C, q, u, rho, Y, Tw, pw);
     }
-    PT pt = cell_prim<3, PRK>(C, q, u, rho, Y, Tw, pw);
     W[cell] = S(rho);
     W[T + cell] = S(u[0]);
     W[2 * T + cell] = S(u[1]);
@@ -66,8 +76,12 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
     W[6 * T + cell] = S(Y);
     W[7 * T + cell] = S(pt.c);
     W[8 * T + cell] = S(pt.alpha);
+    if constexpr (G2) {
+      W[9 * T + cell] = S(Y2);
+      W[10 * T + cell] = S(pt.alpha2);
+    }
     if (first) {
-      double l = cfl_rate<3>(C, u, pt, rho, Y);
+      double l = cfl_rate<3, G2>(C, u, pt, rho, Y, Y2);
       if (!isfinite(l) || !isfinite(pt.p)) record_error(dy, ERR_NAN, cell - C.off, step - 1);
       else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step - 1);
       else lam = fmax(lam, l);
@@ -82,16 +96,18 @@ __global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
 }
 
 // primitives of one (possibly ghost) cell
-template <class S, bool PRK>
+template <class S, bool PRK, bool G2>
 __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long long T, int gx, int gy, int gz,
                                   long long step, S* w)
 {
+  // far-field and inflow states hold no second gas
   if (beyond_farfield<3>(C, gx, gy, gz)) {
-    double u0[3] = {0.0, 0.0, 0.0}, q[6], uu[3], rho, Y;
-    state_from_prim<PRK>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, 3, q);
-    PT pt = cell_prim<3, PRK>(C, q, uu, rho, Y);
+    double u0[3] = {0.0, 0.0, 0.0}, q[G2 ? 7 : 6], uu[3], rho, Y, Y2;
+    state_from_prim<PRK, G2>(C, C.ff_p, C.ff_T, C.ff_alpha, u0, 3, q);
+    PT pt = cell_prim_any<3, PRK, G2>(C, q, uu, rho, Y, Y2);
     w[0] = S(rho); w[1] = S(uu[0]); w[2] = S(uu[1]); w[3] = S(uu[2]);
     w[4] = S(pt.p); w[5] = S(pt.T); w[6] = S(Y); w[7] = S(pt.c); w[8] = S(pt.alpha);
+    if constexpr (G2) { w[9] = S(Y2); w[10] = S(pt.alpha2); }
     return;
   }
   bool fx = false, fy = false, fz = false;
@@ -102,18 +118,19 @@ __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long 
     double yy = (iy + 0.5) * C.dx[1] - C.in_c0;
     double zz = (iz + 0.5) * C.dx[2] - C.in_c1;
     if (sqrt(yy * yy + zz * zz) < C.in_radius) {
-      double u[3] = {C.in_u, 0.0, 0.0}, q[6], uu[3], rho, Y;
+      double u[3] = {C.in_u, 0.0, 0.0}, q[G2 ? 7 : 6], uu[3], rho, Y, Y2;
       for (int c = 0; c < 3; ++c)
         u[c] += C.in_noise * C.in_u *
                 (2.0 * noise01(C.in_seed, (unsigned long long)step, (unsigned long long)iy,
                                (unsigned long long)iz, (unsigned long long)c) - 1.0);
-      state_from_prim<PRK>(C, C.in_p, C.in_T, C.in_alpha, u, 3, q);
-      PT pt = cell_prim<3, PRK>(C, q, uu, rho, Y);
+      state_from_prim<PRK, G2>(C, C.in_p, C.in_T, C.in_alpha, u, 3, q);
+      PT pt = cell_prim_any<3, PRK, G2>(C, q, uu, rho, Y, Y2);
       w[0] = S(rho);
       w[1] = S(uu[0]);
       w[2] = S(fy ? -uu[1] : uu[1]);
       w[3] = S(fz ? -uu[2] : uu[2]);
       w[4] = S(pt.p); w[5] = S(pt.T); w[6] = S(Y); w[7] = S(pt.c); w[8] = S(pt.alpha);
+      if constexpr (G2) { w[9] = S(Y2); w[10] = S(pt.alpha2); }
       return;
     }
     ix = -1 - ix;
@@ -123,17 +140,18 @@ __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long 
   }
   long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
 #pragma unroll
-  for (int v = 0; v < NW3; ++v) w[v] = W[v * T + cell];
+  for (int v = 0; v < nw3<G2>(); ++v) w[v] = W[v * T + cell];
   if (fx) w[1] = -w[1];
   if (fy) w[2] = -w[2];
   if (fz) w[3] = -w[3];
 }
 
-template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, int LIM>
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, bool G2, int LIM>
 __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __restrict__ W)
 {
   constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HXY = HX * HY, NH = HXY * HZ;
-  constexpr int NQ = 6;
+  constexpr int NQ = G2 ? 7 : 6;   // G2: the second gas's partial density last
+  constexpr int NW3 = nw3<G2>();
   constexpr int NC = TX * TY * TZ;
   constexpr int CPT = (NC + NT - 1) / NT;
   constexpr int NFX = (TX + 1) * TY * TZ, NFY = TX * (TY + 1) * TZ, NFZ = TX * TY * (TZ + 1);
@@ -165,6 +183,17 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   S* s_Y = s_w[6];
   S* s_c = s_w[7];
   S* s_a = s_w[8];
+  S* s_Y2 = G2 ? s_w[NW3 - 2] : nullptr;
+  S* s_a2 = G2 ? s_w[NW3 - 1] : nullptr;
+  // total gas volume fraction and mass fraction of a staged cell
+  auto aG = [&](int c) -> S {
+    if constexpr (G2) return s_a[c] + s_a2[c];
+    else return s_a[c];
+  };
+  auto YG = [&](int c) -> S {
+    if constexpr (G2) return s_Y[c] + s_Y2[c];
+    else return s_Y[c];
+  };
 
   auto owned = [&](int cc, int& gx, int& gy, int& gz) {
     int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
@@ -188,7 +217,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   for (int h = tid; h < NH; h += NT) {
     int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
     S w[NW3];
-    load_prim3<S, PRK>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+    load_prim3<S, PRK, G2>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
 #pragma unroll
     for (int v = 0; v < NW3; ++v) s_w[v][h] = w[v];
   }
@@ -212,7 +241,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
       S curl2 = w0 * w0 + w1 * w1 + w2 * w2;
       S thg = S(0);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) thg += fabs(s_a[c] - s_a[c - st[d]]) + fabs(s_a[c + st[d]] - s_a[c]);
+      for (int d = 0; d < 3; ++d) thg += fabs(aG(c) - aG(c - st[d])) + fabs(aG(c + st[d]) - aG(c));
       S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
       s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
     }
@@ -248,20 +277,26 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
         sten.p[m] = s_p[cm];
         sten.T[m] = s_T[cm];
         sten.Y[m] = s_Y[cm];
+        if constexpr (G2) sten.Y2[m] = s_Y2[cm];
       }
       sten.rho1 = s_rho[c]; sten.rho2 = s_rho[c + sd];
       sten.c1 = s_c[c]; sten.c2 = s_c[c + sd];
       bool disc = !SC.switching || ((s_fl[c] | s_fl[c + sd]) != 0);
       bool sl = eligible(sten.Y[0], sten.Y[1], sten.Y[2], eps);
       bool sr = eligible(sten.Y[1], sten.Y[2], sten.Y[3], eps);
+      bool sl2 = false, sr2 = false;
+      if constexpr (G2) {
+        sl2 = eligible(sten.Y2[0], sten.Y2[1], sten.Y2[2], eps);
+        sr2 = eligible(sten.Y2[1], sten.Y2[2], sten.Y2[3], eps);
+      }
       S F[NQ];
-      if (d == 0) face_flux<S, 3, 0, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
-      else if (d == 1) face_flux<S, 3, 1, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
-      else face_flux<S, 3, 2, PRK, false, LIM>(SC, C, sten, disc, sl, sr, F);
+      if (d == 0) face_flux<S, 3, 0, PRK, G2, LIM>(SC, C, sten, disc, sl, sr, F, sl2, sr2);
+      else if (d == 1) face_flux<S, 3, 1, PRK, G2, LIM>(SC, C, sten, disc, sl, sr, F, sl2, sr2);
+      else face_flux<S, 3, 2, PRK, G2, LIM>(SC, C, sten, disc, sl, sr, F, sl2, sr2);
       if (C.diff) {
-        if (d == 0) visc_flux<S, 3, 0>(C, U, s_T, s_a, c, st, F);
-        else if (d == 1) visc_flux<S, 3, 1>(C, U, s_T, s_a, c, st, F);
-        else visc_flux<S, 3, 2>(C, U, s_T, s_a, c, st, F);
+        if (d == 0) visc_flux<S, 3, 0, G2>(C, U, s_T, s_a, c, st, F, s_a2);
+        else if (d == 1) visc_flux<S, 3, 1, G2>(C, U, s_T, s_a, c, st, F, s_a2);
+        else visc_flux<S, 3, 2, G2>(C, U, s_T, s_a, c, st, F, s_a2);
       }
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
@@ -294,8 +329,8 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
       for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
         for (int dyy = -1; dyy <= 1; ++dyy) {
-          S row = s_Y[c + dz * HXY + dyy * HX - 1] + S(2) * s_Y[c + dz * HXY + dyy * HX] +
-                  s_Y[c + dz * HXY + dyy * HX + 1];
+          S row = YG(c + dz * HXY + dyy * HX - 1) + S(2) * YG(c + dz * HXY + dyy * HX) +
+                  YG(c + dz * HXY + dyy * HX + 1);
           acc += row * S((dz == 0 ? 2 : 1) * (dyy == 0 ? 2 : 1));
         }
       s_H[h] = acc * S(1.0 / 64.0);
@@ -341,7 +376,7 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
         const S* uu[3] = {s_u, s_v, s_ww};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          S Sd = sig * kap * (s_a[c + st[d]] - s_a[c - st[d]]) * S(0.5 * C.idx[d]);
+          S Sd = sig * kap * (aG(c + st[d]) - aG(c - st[d])) * S(0.5 * C.idx[d]);
           R[kk][2 + d] += Sd;
           se += uu[d][c] * Sd;
         }
@@ -379,11 +414,14 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
         const long long RS = C.ncell;
         long long cell = gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
         double r0 = (double)R[k][0], r1 = (double)R[k][1];
-        a.rhs_out[cell] = r0 + r1;
+        double r2 = G2 ? (double)R[k][NQ - 1] : 0.0;
+        a.rhs_out[cell] = G2 ? r0 + r1 + r2 : r0 + r1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
-        a.rhs_out[4 * RS + cell] = (double)R[k][5] + C.Q[0] * r0 + C.Q[1] * r1;
+        double rE = (double)R[k][5] + C.Q[0] * r0 + C.Q[1] * r1;
+        a.rhs_out[4 * RS + cell] = G2 ? rE + C.Q[2] * r2 : rE;
         a.rhs_out[5 * RS + cell] = r1;
+        if constexpr (G2) a.rhs_out[6 * RS + cell] = r2;
       }
     }
     return;
@@ -405,17 +443,39 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   }
 }
 
-template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, int LIM>
+// LDS of a face-kernel tile: primitives of tile + halo, flags, flux / CSF buffer
+template <class S, int TX, int TY, int TZ, bool G2>
+constexpr long long lds3()
+{
+  constexpr long long NH = (TX + 4LL) * (TY + 4) * (TZ + 4);
+  constexpr long long NF1 = (TX + 1LL) * TY * TZ, NF2 = TX * (TY + 1LL) * TZ, NF3 = TX * TY * (TZ + 1LL);
+  constexpr long long NF = NF1 > NF2 ? (NF1 > NF3 ? NF1 : NF3) : (NF2 > NF3 ? NF2 : NF3);
+  constexpr long long NFH = (TX + 2LL) * (TY + 2) * (TZ + 2), NV = (TX + 1LL) * (TY + 1) * (TZ + 1);
+  constexpr long long NQ = G2 ? 7 : 6;
+  constexpr long long NB = NQ * NF > NFH + 3 * NV ? NQ * NF : NFH + 3 * NV;
+  return (nw3<G2>() * NH + NB) * (long long)sizeof(S) + NH;
+}
+
+// whether a tile's face kernel fits the 160 KiB of LDS of a workgroup
+template <class S, int TX, int TY, int TZ, bool G2>
+constexpr bool fits3() { return lds3<S, TX, TY, TZ, G2>() <= 160LL * 1024; }
+
+template <class S, int TX, int TY, int TZ, int NT, int MINW, bool PRK, bool G2, int LIM>
 static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
 {
-  constexpr int Wv = PRK ? 1 : MINW;
-  S* W = (S*)a.prim;
-  constexpr int PB = (TX * TY * TZ + 255) / 256;
-  hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK, LIM>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
-  return hipGetLastError();
+  if constexpr (!fits3<S, TX, TY, TZ, G2>()) {
+    return hipErrorInvalidValue;   // rejected on the host before any launch (fvm_k_tile_ok3)
+  } else {
+    constexpr int Wv = PRK ? 1 : MINW;
+    S* W = (S*)a.prim;
+    constexpr int PB = (TX * TY * TZ + 255) / 256;
+    hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK, G2>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK, G2, LIM>), dim3(ntiles), dim3(NT), 0, st, a,
+                       (const S*)W);
+    return hipGetLastError();
+  }
 }
 
 }  // namespace fvm
@@ -439,29 +499,59 @@ int fvm_k_tile_shape3(int t, int* tx, int* ty, int* nt)
 
 int fvm_k_tile_zchunk3(int t) { return (t >= 0 && t < NT3) ? TILES3[t][2] : 1; }
 
-template <class S, bool PRK, int LIM>
+template <class S, bool PRK, bool G2, int LIM>
 static hipError_t stage3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
   switch (tile) {
-    case 0: return launch3<S, 8, 8, 4, 256, 2, PRK, LIM>(a, ntiles, st);
-    case 1: return launch3<S, 16, 8, 2, 256, 2, PRK, LIM>(a, ntiles, st);
-    case 2: return launch3<S, 8, 4, 4, 128, 2, PRK, LIM>(a, ntiles, st);
-    case 3: return launch3<S, 16, 4, 4, 256, 2, PRK, LIM>(a, ntiles, st);
-    case 4: return launch3<S, 8, 8, 8, 512, 1, PRK, LIM>(a, ntiles, st);
+    case 0: return launch3<S, 8, 8, 4, 256, 2, PRK, G2, LIM>(a, ntiles, st);
+    case 1: return launch3<S, 16, 8, 2, 256, 2, PRK, G2, LIM>(a, ntiles, st);
+    case 2: return launch3<S, 8, 4, 4, 128, 2, PRK, G2, LIM>(a, ntiles, st);
+    case 3: return launch3<S, 16, 4, 4, 256, 2, PRK, G2, LIM>(a, ntiles, st);
+    case 4: return launch3<S, 8, 8, 8, 512, 1, PRK, G2, LIM>(a, ntiles, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <int LIM>
-static hipError_t stage3_any(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+template <class S, bool G2>
+static bool tile_ok3(int tile)
 {
-  if (mixed) return prk ? stage3<float, true, LIM>(tile, a, ntiles, st) : stage3<float, false, LIM>(tile, a, ntiles, st);
-  return prk ? stage3<double, true, LIM>(tile, a, ntiles, st) : stage3<double, false, LIM>(tile, a, ntiles, st);
+  switch (tile) {
+    case 0: return fits3<S, 8, 8, 4, G2>();
+    case 1: return fits3<S, 16, 8, 2, G2>();
+    case 2: return fits3<S, 8, 4, 4, G2>();
+    case 3: return fits3<S, 16, 4, 4, G2>();
+    case 4: return fits3<S, 8, 8, 8, G2>();
+  }
+  return false;
+}
+
+// kind: FVM_KIND_SG, FVM_KIND_PR or FVM_KIND_THREE
+template <int LIM>
+static hipError_t stage3_any(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+{
+  if (mixed) {
+    if (kind == FVM_KIND_THREE) return stage3<float, false, true, LIM>(tile, a, ntiles, st);
+    return kind == FVM_KIND_PR ? stage3<float, true, false, LIM>(tile, a, ntiles, st)
+                               : stage3<float, false, false, LIM>(tile, a, ntiles, st);
+  }
+  if (kind == FVM_KIND_THREE) return stage3<double, false, true, LIM>(tile, a, ntiles, st);
+  return kind == FVM_KIND_PR ? stage3<double, true, false, LIM>(tile, a, ntiles, st)
+                             : stage3<double, false, false, LIM>(tile, a, ntiles, st);
 }
 
 // the default limiters (Koren, Minmod) as compile-time constants, any others at run time
-hipError_t fvm_k_stage3(int mixed, int prk, int tile, const StageArgs& a, int ntiles, hipStream_t st)
+hipError_t fvm_k_stage3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  if (fvm_default_limiters(a.sc)) return stage3_any<1>(mixed, prk, tile, a, ntiles, st);
-  return stage3_any<0>(mixed, prk, tile, a, ntiles, st);
+  if (fvm_default_limiters(a.sc)) return stage3_any<1>(mixed, kind, tile, a, ntiles, st);
+  return stage3_any<0>(mixed, kind, tile, a, ntiles, st);
+}
+
+// whether the face kernel of a 3D tile fits the LDS of a workgroup for this
+// precision and closure kind (the three-component FP64 tile of 8x8x8 cells
+// does not)
+int fvm_k_tile_ok3(int mixed, int kind, int tile)
+{
+  bool g2 = kind == FVM_KIND_THREE;
+  if (mixed) return g2 ? tile_ok3<float, true>(tile) : tile_ok3<float, false>(tile);
+  return g2 ? tile_ok3<double, true>(tile) : tile_ok3<double, false>(tile);
 }

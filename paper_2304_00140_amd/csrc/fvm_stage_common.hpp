@@ -335,13 +335,15 @@ __device__ inline double cfl_rate(const CaseC& C, const double* u, const PT& pt,
   return l;
 }
 
-// fold a workgroup's CFL bound into its slot; the plain read skips the atomic
-// when the slot already holds a larger value (slots only grow within a stage)
+// fold a workgroup's CFL bound into its slot: one unsigned 64-bit atomic max
+// with no return value (a non-negative double orders like its bit pattern);
+// spreading the workgroups over NSLOT slots keeps the contention per address
+// low, and a read of the slot first to skip the atomic was measured slower
+// (the load's latency lands on the last wave of every workgroup)
 __device__ inline void cfl_max(CaseDyn& dy, int s, double m)
 {
   unsigned long long bits = (unsigned long long)__double_as_longlong(m);
-  unsigned long long* slot = &dy.dtmax[s][blockIdx.x % NSLOT];
-  if (__atomic_load_n(slot, __ATOMIC_RELAXED) < bits) atomicMax(slot, bits);
+  atomicMax(&dy.dtmax[s][blockIdx.x % NSLOT], bits);
 }
 
 }  // namespace fvm

@@ -52,7 +52,10 @@ def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, 
     dim = k[0]
     times = {}
     for t in range(L.fvm_tile_count(dim)):
-        handle.set_tile(t)
+        try:
+            handle.set_tile(t)
+        except fvm.FvmError:
+            continue   # a tile whose kernels do not fit this closure and precision
         handle.n_steps(warm)
         t0 = time.perf_counter()
         handle.n_steps(steps)

@@ -1,8 +1,8 @@
 """GPU (gfx950) second gas species (three components: a liquid and two ideal
 gases, rho xi_2 transported) against the CPU FP64 oracle through the C ABI:
-one RHS on every tile in 1D and 2D (switching, CSF, stress terms, walls),
-primitives, steps, totals, the mixed path against FP64, and the
-pressure/velocity equilibrium of a slab between the two gases."""
+one RHS on every tile in 1D, 2D and 3D (switching, CSF, stress terms, walls,
+a 3D jet inflow), primitives, steps, totals, the mixed path against FP64, and
+the pressure/velocity equilibrium of a slab between the two gases."""
 import numpy as np
 import pytest
 
@@ -142,8 +142,123 @@ def test_slab_between_two_gases_keeps_pressure_and_velocity(dev, stream):
     assert field_err(ctx.get_state(), q) < 1e-10
 
 
-def test_three_components_in_3d_are_rejected(dev, stream):
+SPECS3 = [
+    dict(dim=3, n=[14, 11, 10], seed=57, switching=1, sigma=0.05,
+         bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC], [W.BC_ZEROGRAD, W.BC_WALL]]),
+    dict(dim=3, n=[12, 10, 9], seed=58, viscous=True),
+]
+
+
+@pytest.mark.parametrize("spec", SPECS3, ids=lambda s: f"3d-{s['seed']}")
+def test_three_component_rhs_every_tile_3d(dev, stream, spec):
+    """3D: one RHS on every tile in FP64 against the oracle; the 8x8x8 tile
+    does not fit the LDS of a workgroup with three components in FP64 and is
+    refused by the library, the mixed path runs it"""
+    from oracle.oracle import Oracle
     from paper_2304_00140_amd import fvm
-    case = W.random_state(3, [8, 8, 8], 57, second_gas=True)
-    with pytest.raises(fvm.FvmError):
-        fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    case = make(spec)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    assert q.shape[0] == 7
+    r_ref = o.rhs(q)
+    ran = []
+    for tile in range(fvm.lib().fvm_tile_count(3)):
+        ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+        try:
+            ctx.set_tile(tile)
+        except fvm.FvmError as e:
+            assert tile == 4 and "LDS" in str(e)
+            ctx.close()
+            continue
+        err = field_err(gpu_rhs(ctx, q, dev), r_ref)
+        print(f"three components 3D {spec} tile {tile}: {err:.3e}", flush=True)
+        assert err < 1e-10
+        ran.append(tile)
+        ctx.close()
+    assert ran == [0, 1, 2, 3]
+    m = fvm.Context(case, fvm.FVM_MIXED, stream=stream.cuda_stream)
+    m.set_tile(4)
+    m.init_primitive()
+    m.n_steps(1)
+    assert np.isfinite(m.get_primitive()).all()
+    m.close()
+
+
+def test_three_component_steps_3d(dev, stream):
+    """3D three components with CSF and switching: primitives (11 rows),
+    totals, four FP64 steps against the oracle, mixed against FP64"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = make(dict(dim=3, n=[13, 12, 9], seed=59, switching=1, sigma=0.05))
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    ctx.init_primitive()
+    np.testing.assert_allclose(ctx.get_state(), q, rtol=1e-12, atol=1e-12 * np.abs(q).max())
+    w, w_ref = ctx.get_primitive(), o.prim_from_cons(q)
+    assert w.shape == w_ref.shape == (11, q.shape[1])
+    for f in (0, 4, 5, 6, 7, 8, 9, 10):
+        np.testing.assert_allclose(w[f], w_ref[f], rtol=1e-10, atol=1e-12 * np.abs(w_ref[f]).max())
+    np.testing.assert_allclose(ctx.totals(), o.totals(q), rtol=1e-12)
+    t = 0.0
+    for k in range(4):
+        t, _ = o.step(q, k, t)
+    t_gpu = ctx.n_steps(4)
+    err = field_err(ctx.get_state(), q)
+    print(f"three components 3D 4 steps: {err:.3e}", flush=True)
+    assert abs(t_gpu / t - 1) < 1e-12
+    assert err < 1e-10
+    m = fvm.Context(case, fvm.FVM_MIXED, stream=stream.cuda_stream)
+    m.init_primitive()
+    m.n_steps(4)
+    a, b = m.get_primitive(), ctx.get_primitive()
+    l1 = {f: np.abs(a[i] - b[i]).sum() / np.abs(b[i]).sum() for f, i in (("rho", 0), ("p", 4))}
+    l1["Y2"] = np.abs(a[9] - b[9]).sum() / a.shape[1]
+    print(f"three components 3D mixed vs fp64 L1: {l1}", flush=True)
+    assert max(l1.values()) < 1e-4
+
+
+def jet_two_gases(nx=32, ny=16, nz=16):
+    """the small 3D jet (inflow with noise, zero-gradient sides, CSF,
+    switching) with its ambient split between a nitrogen-like and a
+    helium-like ideal gas: the inflow ghost cells hold no second gas"""
+    case = W.liquid_jet_3d(nx=nx, ny=ny, nz=nz, cells_per_D=6, steps=3, gas="sg")
+    e = case["eos"]
+    liquid = W.sg(e["gamma"][0], e["pinf"][0], e["cv"][0], e["q"][0])
+    gas1 = W.sg(e["gamma"][1], e["pinf"][1], e["cv"][1], e["q"][1])
+    case["eos"] = W.make_eos(liquid, gas1, W.sg(1.67, 0.0, 3110.0))
+    pr = case["prim"]
+    z = W.cell_centres(case["grid"])[2]
+    share = 0.5 + 0.4 * np.tanh((z - z.mean()) / (4 * case["grid"]["dx"][2]))
+    alpha = pr[2]
+    case["prim"] = np.concatenate([pr[:2], (alpha * share)[None], pr[3:], (alpha * (1.0 - share))[None]])
+    return case
+
+
+def test_three_component_jet_with_inflow_3d(dev, stream):
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    case = jet_two_gases()
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    assert q.shape[0] == 7
+    ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    ctx.init_primitive()
+    err = field_err(gpu_rhs(ctx, q, dev), o.rhs(q))
+    print(f"three-component jet RHS: {err:.3e}", flush=True)
+    assert err < 1e-10
+    t = 0.0
+    for k in range(3):
+        t, _ = o.step(q, k, t)
+    ctx.n_steps(3)
+    err = field_err(ctx.get_state(), q)
+    print(f"three-component jet 3 steps: {err:.3e}", flush=True)
+    assert err < 1e-10
+    m = fvm.Context(case, fvm.FVM_MIXED, stream=stream.cuda_stream)
+    m.init_primitive()
+    m.n_steps(3)
+    a, b = m.get_primitive(), ctx.get_primitive()
+    l1p = np.abs(a[4] - b[4]).sum() / np.abs(b[4]).sum()
+    l1u = np.abs(a[1:4] - b[1:4]).sum() / (a.shape[1] * 300.0)
+    print(f"three-component jet mixed vs fp64 L1 p {l1p:.2e} u {l1u:.2e}", flush=True)
+    assert l1p < 1e-4 and l1u < 1e-4

@@ -36,6 +36,14 @@ def key_of(handle, precision):
     return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, kinds, diff, int(ncell))
 
 
+def _restart(handle):
+    if hasattr(handle, "cases"):
+        for i in range(len(handle.cases)):
+            handle.init_primitive(i)
+    else:
+        handle.init_primitive()
+
+
 def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, save=False):
     """handle: fvm.Context or fvm.Batch with a state set; returns (best tile, {tile: ms per stage})"""
     from . import fvm
@@ -56,6 +64,10 @@ def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, 
             handle.set_tile(t)
         except fvm.FvmError:
             continue   # a tile whose kernels do not fit this closure and precision
+        # every tile is timed on the same steps from the initial state (a case
+        # is not advanced through all tiles' steps, which may outlast its
+        # physical time span)
+        _restart(handle)
         handle.n_steps(warm)
         t0 = time.perf_counter()
         handle.n_steps(steps)

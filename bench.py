@@ -65,7 +65,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: the workload's own step count, 2000 for the 2D cases)")
+                    help="timed steps (default: the workload's own step count: 200 in 3D, 500 for the batch, 1e4 for the drop, else 2000)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="shock_bubble_2d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",

@@ -395,3 +395,74 @@ def test_liquid_jet_nozzle_lip_fp64(dev, stream):
         print(f"jet lip {done} steps: {err:.3e}", flush=True)
         assert err < 1e-10
     assert (q[5] / q[0]).min() < 0.0
+
+
+MINIMAL = [(1, [2]), (2, [2, 2]), (2, [2, 3]), (3, [2, 2, 2]), (3, [3, 2, 2])]
+
+
+def ulp_sensitivity(o, q, r, trials=8):
+    """per field: the largest change of the oracle's own RHS when every input
+    word moves by one ulp in a random direction, over the field's largest
+    |RHS| (how far rounding alone moves a right-hand side that is a small
+    difference of large fluxes)"""
+    rng = np.random.default_rng(0)
+    scale = np.maximum(np.abs(r).max(axis=1), 1e-300)
+    worst = np.zeros(q.shape[0])
+    for _ in range(trials):
+        rp = o.rhs(q * (1.0 + rng.choice([-1.0, 1.0], size=q.shape) * 2.0 ** -52))
+        worst = np.maximum(worst, np.abs(rp - r).max(axis=1) / scale)
+    return worst
+
+
+@pytest.mark.parametrize("dim,n", MINIMAL, ids=lambda v: str(v))
+def test_minimal_grids_match_oracle(dev, stream, dim, n):
+    """the smallest grids the ABI accepts (two cells in a direction: the
+    two-cell halo on either side reaches across the whole domain) with
+    periodic, wall and zero-gradient ends, CSF and switching on: one RHS on
+    every tile and three steps against the oracle, the mixed path finite.
+    With two periodic cells the two faces of a cell see the same pair of cells
+    in mirrored order, so a right-hand side can be a difference of nearly equal
+    fluxes; per field the bar is then 1e-10 or 16 times the oracle's own
+    one-ulp input sensitivity of that field, whichever is larger."""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    for bc in (W.BC_PERIODIC, W.BC_WALL, W.BC_ZEROGRAD):
+        case = W.random_state(dim, n, 5, bc=[[bc, bc]] * dim, sigma=0.05, switching=1)
+        o = Oracle(case)
+        q = o.cons_from_prim()
+        r_ref = o.rhs(q)
+        bar = np.maximum(1e-10, 16.0 * ulp_sensitivity(o, q, r_ref))
+        scale = np.maximum(np.abs(r_ref).max(axis=1), 1e-300)
+        for tile in range(fvm.lib().fvm_tile_count(dim)):
+            ctx = ctx_for(case, fvm.FVM_FP64, stream, tile)
+            err = np.abs(gpu_rhs(ctx, q, dev) - r_ref).max(axis=1) / scale
+            print(f"minimal grid {dim}D {n} bc {bc} tile {tile}: rhs {np.array2string(err, precision=1)} "
+                  f"bar {np.array2string(bar, precision=1)}", flush=True)
+            assert np.all(err <= bar), (bc, tile)
+            ctx.close()
+        ctx = ctx_for(case, fvm.FVM_FP64, stream)
+        ctx.init_primitive()
+        t = 0.0
+        for k in range(3):
+            t, _ = o.step(q, k, t)
+        t_gpu = ctx.n_steps(3)
+        err = field_err(ctx.get_state(), q)
+        print(f"minimal grid {dim}D {n} bc {bc}: 3 steps {err:.2e}", flush=True)
+        assert err < 1e-10 and abs(t_gpu / t - 1) < 1e-12
+        m = ctx_for(case, fvm.FVM_MIXED, stream)
+        m.init_primitive()
+        m.n_steps(3)
+        assert np.isfinite(m.get_state()).all()
+        m.close()
+        ctx.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_grids_below_two_cells_are_rejected(dev, stream, dim):
+    from paper_2304_00140_amd import fvm
+    for bad in (1, 0, -3):
+        case = W.random_state(dim, [4] * dim, 6)
+        case["grid"] = dict(case["grid"], n=[bad] + [4] * (dim - 1) + [1] * (3 - dim))
+        with pytest.raises(fvm.FvmError) as e:
+            fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+        assert "EINVAL" in str(e.value)

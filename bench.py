@@ -32,32 +32,32 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v8"
+KERNEL_BUILD = "k_stage12-v9"
 MEASURED = {
-    ("shock_bubble_2d", 0, 3, "k_stage12-v8"): dict(valu_per_cell_stage=4218125.3 * 64 / 262144,
-                                             traffic_bytes=(9767.0 * 2 + 10248.1) * 1024),
-    ("shock_bubble_2d", 1, 7, "k_stage12-v8"): dict(valu_per_cell_stage=3877406.2 * 64 / 262144,
-                                             traffic_bytes=(4945.9 * 2 + 5128.1) * 1024),
-    ("dual_gas_layer_2d", 0, 0, "k_stage12-v8"): dict(valu_per_cell_stage=10562916.3 * 64 / 524288,
-                                               traffic_bytes=(22495.1 * 2 + 24592.1) * 1024),
-    ("dual_gas_layer_2d", 1, 0, "k_stage12-v8"): dict(valu_per_cell_stage=9379870.9 * 64 / 524288,
-                                               traffic_bytes=(11368.0 * 2 + 12304.1) * 1024),
-    ("vapour_bubble_wall_2d", 0, 3, "k_stage12-v8"): dict(valu_per_cell_stage=8822294.0 * 64 / 524288,
-                                                   traffic_bytes=(15054.7 * 2 + 16400.1) * 1024),
-    ("vapour_bubble_wall_2d", 1, 3, "k_stage12-v8"): dict(valu_per_cell_stage=8159818.5 * 64 / 524288,
-                                                   traffic_bytes=(7609.7 * 2 + 8208.1) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
-                                           traffic_bytes=((928092.7 + 3519918.0) * 2 +
-                                                          (2547638.9 + 1670954.9)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v8"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
-                                           traffic_bytes=((462806.3 + 1687543.7) * 2 +
-                                                          (1216205.0 + 814994.2)) * 1024),
-    ("cube_to_sphere_3d", 0, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(51025400.0 + 402984771.5) * 64 / 16777216,
-                                               traffic_bytes=((342717.2 + 1523396.9) * 2 +
-                                                              (1378574.6 + 683563.0)) * 1024),
-    ("cube_to_sphere_3d", 1, 4, "k_stage12-v8"): dict(valu_per_cell_stage=(54695416.0 + 359542514.4) * 64 / 16777216,
-                                               traffic_bytes=((164771.2 + 629509.0) * 2 +
-                                                              (672127.7 + 359111.2)) * 1024),
+    ("shock_bubble_2d", 0, 10, "k_stage12-v9"): dict(valu_per_cell_stage=3526591.4 * 64 / 262144,
+                                             traffic_bytes=(9771.0 * 2 + 10242.1) * 1024),
+    ("shock_bubble_2d", 1, 10, "k_stage12-v9"): dict(valu_per_cell_stage=3373269.2 * 64 / 262144,
+                                             traffic_bytes=(4965.6 * 2 + 5122.1) * 1024),
+    ("dual_gas_layer_2d", 0, 10, "k_stage12-v9"): dict(valu_per_cell_stage=8795769.9 * 64 / 524288,
+                                               traffic_bytes=(22478.3 * 2 + 24580.1) * 1024),
+    ("dual_gas_layer_2d", 1, 9, "k_stage12-v9"): dict(valu_per_cell_stage=8557505.1 * 64 / 524288,
+                                               traffic_bytes=(11345.8 * 2 + 12296.1) * 1024),
+    ("vapour_bubble_wall_2d", 0, 9, "k_stage12-v9"): dict(valu_per_cell_stage=8105808.1 * 64 / 524288,
+                                                   traffic_bytes=(15028.7 * 2 + 16392.1) * 1024),
+    ("vapour_bubble_wall_2d", 1, 10, "k_stage12-v9"): dict(valu_per_cell_stage=6858119.0 * 64 / 524288,
+                                                   traffic_bytes=(7580.1 * 2 + 8196.1) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v9"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
+                                           traffic_bytes=((940356.7 + 3441663.0) * 2 +
+                                                          (2598974.3 + 1698210.5)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v9"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
+                                           traffic_bytes=((462798.1 + 1671489.8) * 2 +
+                                                          (1186711.9 + 793062.8)) * 1024),
+    ("cube_to_sphere_3d", 0, 4, "k_stage12-v9"): dict(valu_per_cell_stage=(51025400.0 + 402984771.5) * 64 / 16777216,
+                                               traffic_bytes=((361506.1 + 1557584.9) * 2 +
+                                                              (1360775.9 + 690547.4)) * 1024),
+    ("cube_to_sphere_3d", 1, 4, "k_stage12-v9"): dict(valu_per_cell_stage=(54695416.0 + 359542514.4) * 64 / 16777216,
+                                               traffic_bytes=((164919.4 + 645238.8) * 2 +
+                                                              (672200.8 + 343159.0)) * 1024),
 }
 
 

@@ -1091,6 +1091,8 @@ static hipError_t stage_b(int dim, int tile, const StageArgs& a, int ntiles, hip
       case 6: return launch_b<S, 2, 32, 8, 320, 5>(a, ntiles, st);
       case 7: return launch_b<S, 2, 16, 16, 320, 5>(a, ntiles, st);
       case 8: return launch_b<S, 2, 32, 8, 384, 6>(a, ntiles, st);
+      case 9: return launch_b<S, 2, 32, 16, 512, 4>(a, ntiles, st);
+      case 10: return launch_b<S, 2, 32, 32, 1024, 4>(a, ntiles, st);
     }
   }
   return hipErrorInvalidValue;

@@ -201,7 +201,8 @@ using namespace fvm;
 static const int TILES1[][4] = {{256, 1, 256, 4}, {128, 1, 128, 4}, {128, 1, 256, 4}};
 static const int TILES2[][4] = {{32, 8, 256, 4}, {16, 8, 256, 4}, {64, 4, 256, 4},
                                 {16, 16, 256, 4}, {32, 16, 256, 2}, {32, 4, 256, 4},
-                                {32, 8, 320, 5}, {16, 16, 320, 5}, {32, 8, 384, 6}};
+                                {32, 8, 320, 5}, {16, 16, 320, 5}, {32, 8, 384, 6},
+                                {32, 16, 512, 4}, {32, 32, 1024, 4}};
 static const int NT1 = sizeof(TILES1) / sizeof(TILES1[0]);
 static const int NT2 = sizeof(TILES2) / sizeof(TILES2[0]);
 

@@ -427,6 +427,10 @@ static hipError_t stage12(int dim, int tile, const StageArgs& a, int ntiles, hip
       case 6: return launch12<S, 2, 32, 8, 320, 5, PRK, G2, LIM>(a, ntiles, st);
       case 7: return launch12<S, 2, 16, 16, 320, 5, PRK, G2, LIM>(a, ntiles, st);
       case 8: return launch12<S, 2, 32, 8, 384, 6, PRK, G2, LIM>(a, ntiles, st);
+      // larger tiles: a smaller halo share (1.41 and 1.27 staged cells per cell)
+      // at the same four waves per SIMD
+      case 9: return launch12<S, 2, 32, 16, 512, 4, PRK, G2, LIM>(a, ntiles, st);
+      case 10: return launch12<S, 2, 32, 32, 1024, 4, PRK, G2, LIM>(a, ntiles, st);
     }
   }
   return hipErrorInvalidValue;

@@ -45,7 +45,9 @@ def _restart(handle):
 
 
 def autotune(handle, precision, steps=50, warm=50, verbose=False, retune=False, save=False):
-    """handle: fvm.Context or fvm.Batch with a state set; returns (best tile, {tile: ms per stage})"""
+    """handle: fvm.Context or fvm.Batch; returns (best tile, {tile: ms per stage}).  A sweep
+    (no cached choice) leaves the handle's state at its case's initial primitives advanced by
+    the last tile's timed steps: set the state again before a measured run."""
     from . import fvm
     k = key_of(handle, precision)
     if k in _cache and not retune:

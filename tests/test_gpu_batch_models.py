@@ -1,6 +1,6 @@
 """Batches (many independent cases of uneven size advanced together through
 the tile table) of the barotropic model in 2D and 3D and of the
-three-component model in 2D: every case of the batch bit-identical to the
+three-component model in 2D and 3D: every case of the batch bit-identical to the
 same case advanced on its own, in both precisions; mixing models in one batch
 is rejected."""
 import numpy as np
@@ -34,11 +34,16 @@ def model_cases(kind):
     if kind == "baro3d":
         return [W.random_state(3, n, seed, barotropic=True, bc=[[W.BC_WALL, W.BC_ZEROGRAD]] * 3)
                 for n, seed in (([12, 10, 9], 91), ([17, 9, 11], 92))]
+    if kind == "three3d":
+        return [W.random_state(3, n, seed, second_gas=True, switching=1, sigma=0.05,
+                               bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC],
+                                   [W.BC_ZEROGRAD, W.BC_WALL]])
+                for n, seed in (([13, 10, 9], 98), ([9, 14, 11], 99))]
     return [W.random_state(2, n, seed, second_gas=True, bc=[[W.BC_WALL, W.BC_WALL]] * 2)
             for n, seed in (([30, 22], 93), ([41, 19], 94), ([25, 33], 95))]
 
 
-@pytest.mark.parametrize("kind", ["baro2d", "baro3d", "three2d"])
+@pytest.mark.parametrize("kind", ["baro2d", "baro3d", "three2d", "three3d"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
 def test_batch_equals_single_cases(dev, stream, kind, prec):
     from paper_2304_00140_amd import fvm

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FVM_VERSION 3
+#define FVM_VERSION 4
 
 enum {
   FVM_OK = 0,
@@ -112,7 +112,7 @@ typedef struct fvm_grid_desc {
  * model: FVM_MODEL_FOUR_EQ (0, everything above) or FVM_MODEL_BAROTROPIC, the
  * barotropic equilibrium model of Section 2.2 (eqs. 2-3 .. 2-7), which
  * replaces the components above (kind, gamma, pinf, cv, q, PR data and T_ref
- * are ignored; mu and kc must be 0; ncomp must be 0 or 2): a liquid with
+ * are ignored; kc must be 0; ncomp must be 0 or 2): a liquid with
  * rho = bt_rho_sat + (p - bt_p_sat) / bt_c_liq^2 at p >= bt_p_sat that is a
  * liquid-vapour mixture below it (the same law with c_M^2 = p_sat / rho_sat),
  * and one isothermal ideal gas rho_G = p / bt_RT (bt_RT = R_Gas T_ref).
@@ -125,8 +125,13 @@ typedef struct fvm_grid_desc {
  * alpha_V and rho monotone through it) the face density is the THINC value
  * of rho (eqs. 3-7, 3-8, Remarks 1-2), elsewhere rho(p*, xi_face).  FP32
  * storage (FVM_MIXED) keeps the liquid's partial density relative to its
- * density at p_ref.  Requires bt_rho_sat > 0, bt_p_sat > 0, bt_c_liq > 0,
- * 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0; 1D, 2D and 3D. */
+ * density at p_ref.  Viscous stress (no heat conduction, no energy): mu[0]
+ * (liquid), mu[1] (gas) and bt_mu_vap (vapour) enter the mixture viscosity of
+ * eq. 2-8, (1 - alpha_G)[(1 - a_v)(1 + 5/2 a_v) mu_liq + a_v mu_vap] +
+ * alpha_G mu_gas, a_v = alpha_V / (1 - alpha_G) the vapour share of the
+ * liquid-vapour part; all zero: inviscid.  Requires bt_rho_sat > 0,
+ * bt_p_sat > 0, bt_c_liq > 0, 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0, finite
+ * viscosities >= 0; 1D, 2D and 3D. */
 typedef struct fvm_eos_desc {
   int kind[3];
   double gamma[3], pinf[3], cv[3], q[3];
@@ -140,6 +145,7 @@ typedef struct fvm_eos_desc {
   int ncomp;
   int model;
   double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
+  double bt_mu_vap;
 } fvm_eos_desc;
 
 /* Scheme parameters (Section 3.3, Appendix D; defaults in brackets):

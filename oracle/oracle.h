@@ -85,9 +85,11 @@ typedef struct {
    * (saturated density bt_rho_sat at bt_p_sat, speed of sound bt_c_liq)
    * that becomes a liquid-vapour mixture below bt_p_sat (c_M^2 = p_sat /
    * rho_sat; saturated vapour density bt_rho_vap for the vapour fraction),
-   * and one isothermal ideal gas with rho_G = p / bt_RT (bt_RT = R_Gas T_ref). */
+   * and one isothermal ideal gas with rho_G = p / bt_RT (bt_RT = R_Gas T_ref).
+   * Its viscosities: mu[0] liquid, mu[1] gas, bt_mu_vap vapour (eq. 2-8). */
   int model;
   double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
+  double bt_mu_vap;
 } og_eos;
 
 typedef struct {
@@ -143,6 +145,8 @@ double og_baro_density(const og_eos* e, double p, double Y);
 int og_baro_pressure(const og_eos* e, double rho, double Y, double* p);
 double og_baro_sound(const og_eos* e, double p);
 void og_baro_fractions(const og_eos* e, double rho, double Y, double p, double* alpha_G, double* alpha_V);
+/* mixture viscosity of eq. 2-8 (one gas) from the cell's alpha_G and alpha_V */
+double og_baro_viscosity(const og_eos* e, double alpha_G, double alpha_V);
 
 /* ---- reconstruction (Section 3.3, Table 4.2, Appendix D) ---- */
 double og_limiter_table(int kind, double r);

@@ -37,7 +37,8 @@ class Eos(C.Structure):
                 ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
                 ("mu", C.c_double * MAXCOMP), ("kc", C.c_double * MAXCOMP), ("ncomp", C.c_int),
                 ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
-                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double)]
+                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double),
+                ("bt_mu_vap", C.c_double)]
 
 
 class Scheme(C.Structure):
@@ -76,6 +77,7 @@ def lib():
             "og_baro_pressure": (C.c_int, [pe, C.c_double, C.c_double, dp]),
             "og_baro_sound": (C.c_double, [pe, C.c_double]),
             "og_baro_fractions": (None, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "og_baro_viscosity": (C.c_double, [pe, C.c_double, C.c_double]),
             "og_face_flux_baro": (C.c_int, [pe, ps, C.c_int, C.c_int, dp, C.c_int, C.c_int, C.c_int,
                                             dp, dp, dp]),
             "og_sound": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
@@ -148,6 +150,7 @@ def make_eos(ed):
         b = ed["baro"]
         e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
         e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
+        e.bt_mu_vap = b.get("mu_vap", 0.0)
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]

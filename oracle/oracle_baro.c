@@ -89,6 +89,22 @@ void og_baro_fractions(const og_eos* e, double rho, double Y, double p, double* 
   *alpha_V = aV;
 }
 
+/* mixture viscosity of eq. 2-8 with one gas:
+ *   (1 - alpha_G)[(1 - a_v)(1 + 5/2 a_v) mu_liq + a_v mu_vap] + alpha_G mu_gas.
+ * The bracket is the viscosity of the liquid-vapour part and (1 - alpha_G)
+ * its volume share, so a_v there is the vapour share of that part,
+ * a_v = alpha_V / (1 - alpha_G) with alpha_V of eq. 2-7 (a share of the whole
+ * cell); 0 where there is no liquid-vapour part. */
+double og_baro_viscosity(const og_eos* e, double alpha_G, double alpha_V)
+{
+  double aG = alpha_G < 0.0 ? 0.0 : (alpha_G > 1.0 ? 1.0 : alpha_G);
+  double m = 1.0 - aG;
+  double av = (m > 0.0) ? alpha_V / m : 0.0;
+  if (av > 1.0) av = 1.0;
+  if (av < 0.0) av = 0.0;
+  return m * ((1.0 - av) * (1.0 + 2.5 * av) * e->mu[0] + av * e->bt_mu_vap) + aG * e->mu[1];
+}
+
 static void upwind_pair(int lim, double a, double b, double c, double d, double* L, double* R)
 {
   *L = b + 0.5 * og_slope(lim, b - a, c - b);

@@ -448,9 +448,20 @@ int og_nq(const og_grid* g, const og_eos* e)
 
 static int has_diffusion(const og_eos* e)
 {
+  if (og_is_barotropic(e)) return e->mu[0] > 0.0 || e->mu[1] > 0.0 || e->bt_mu_vap > 0.0;
   for (int k = 0; k < og_ncomp(e); ++k)
     if (e->mu[k] > 0.0 || e->kc[k] > 0.0) return 1;
   return 0;
+}
+
+static double mix_alpha(const double* v, int ncomp, double a, double a2);
+
+/* viscosity of a padded cell: eq. (2-8), with the vapour term in the
+ * barotropic model */
+static double cell_viscosity(const og_eos* e, const double* W, size_t np, size_t c)
+{
+  if (og_is_barotropic(e)) return og_baro_viscosity(e, W[OW_A * np + c], W[OW_AV * np + c]);
+  return mix_alpha(e->mu, og_ncomp(e), W[OW_A * np + c], W[OW_A2 * np + c]);
 }
 
 /* a transport coefficient of a cell from its gas volume fractions: eq. (2-8)
@@ -492,19 +503,21 @@ static void viscous_flux(const og_grid* g, const og_eos* e, const og_pad* pd, co
   int nc = og_ncomp(e);
   double aL = W[OW_A * np + c], aR = W[OW_A * np + R];
   double bL = W[OW_A2 * np + c], bR = W[OW_A2 * np + R];
-  double mu = 0.5 * (mix_alpha(e->mu, nc, aL, bL) + mix_alpha(e->mu, nc, aR, bR));
-  double kc = 0.5 * (mix_alpha(e->kc, nc, aL, bL) + mix_alpha(e->kc, nc, aR, bR));
+  double mu = 0.5 * (cell_viscosity(e, W, np, c) + cell_viscosity(e, W, np, R));
   double work = 0.0;
-  Fv[0] = 0.0;
+  for (int v = 0; v < 7; ++v) Fv[v] = 0.0;
   for (int a = 0; a < dim; ++a) {
     double tau = mu * (grad[a][d] + grad[d][a]);
     if (a == d) tau -= 2.0 / 3.0 * mu * div;
     Fv[1 + a] = -tau;
     work += 0.5 * (W[(OW_U + a) * np + c] + W[(OW_U + a) * np + R]) * tau;
   }
-  Fv[1 + dim] = -work - kc * (W[OW_T * np + R] - W[OW_T * np + c]) / g->dx[d];
-  Fv[2 + dim] = 0.0;
-  Fv[3 + dim] = 0.0;
+  /* the barotropic model has no energy equation: the stress acts on the
+   * momentum only (row 1 + dim is rho xi there) */
+  if (!og_is_barotropic(e)) {
+    double kc = 0.5 * (mix_alpha(e->kc, nc, aL, bL) + mix_alpha(e->kc, nc, aR, bR));
+    Fv[1 + dim] = -work - kc * (W[OW_T * np + R] - W[OW_T * np + c]) / g->dx[d];
+  }
 }
 
 /* ---------------- right-hand side ---------------- */
@@ -566,9 +579,9 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
   int bad = 0;
   const int diffusive = has_diffusion(e);
   const int baro = og_is_barotropic(e);
-  if (baro && diffusive) {
+  if (baro && (e->kc[0] != 0.0 || e->kc[1] != 0.0)) {
     work_free(&w);
-    og_set_error("stress terms are not part of the barotropic model here");
+    og_set_error("the barotropic model has no energy equation: no heat conduction");
     return -4;
   }
   for (int d = 0; d < dim; ++d) {
@@ -690,14 +703,15 @@ int og_curvature(const og_grid* g, const og_eos* e, const og_scheme* s, const do
  * (the paper gives no formula): the usual convective limit with the cell's
  * speed of sound, plus the explicit diffusion limit with
  * nu = max(mu, kc / cv) / rho (cv mixed by mass fraction) when the fluids
- * are viscous or conducting */
+ * are viscous or conducting (barotropic model: nu = mu / rho with the mixture
+ * viscosity of eq. 2-8) */
 double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double* q)
 {
   og_pad pd;
   og_pad_init(&pd, g);
   size_t nc = pd.ncell;
   int dim = g->dim, nq = og_nq(g, e);
-  int diffusive = has_diffusion(e) && !og_is_barotropic(e);
+  int diffusive = has_diffusion(e);
   double sdx2 = 0.0;
   for (int d = 0; d < dim; ++d) sdx2 += 1.0 / (g->dx[d] * g->dx[d]);
   double lam = 0.0;
@@ -707,7 +721,10 @@ double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double
     if (prim_cell(e, dim, qc, w)) return NAN;
     double l = 0.0;
     for (int d = 0; d < dim; ++d) l += (fabs(w[OW_U + d]) + w[OW_C]) / g->dx[d];
-    if (diffusive) {
+    if (diffusive && og_is_barotropic(e)) {
+      /* viscous limit with the mixture viscosity of eq. (2-8) */
+      l += 2.0 * og_baro_viscosity(e, w[OW_A], w[OW_AV]) / w[OW_RHO] * sdx2;
+    } else if (diffusive) {
       int ncomp = og_ncomp(e);
       double cvm;
       if (ncomp == 2) {

@@ -106,8 +106,11 @@ static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
         !std::isfinite(e->bt_p_sat) || !std::isfinite(e->bt_c_liq) || !std::isfinite(e->bt_RT))
       return fail(b, FVM_EINVAL, "barotropic model needs rho_sat, p_sat, c_liq, RT > 0 and 0 <= rho_vap < rho_sat");
     for (int k = 0; k < 3; ++k)
-      if (e->mu[k] != 0.0 || e->kc[k] != 0.0)
-        return fail(b, FVM_EINVAL, "the barotropic model is inviscid and adiabatic (mu = kc = 0)");
+      if (e->kc[k] != 0.0 || (k == 2 && e->mu[k] != 0.0))
+        return fail(b, FVM_EINVAL, "the barotropic model has no heat conduction (kc = 0) and viscosities mu[0], mu[1]");
+    if (!(e->mu[0] >= 0.0 && e->mu[0] < 1e300) || !(e->mu[1] >= 0.0 && e->mu[1] < 1e300) ||
+        !(e->bt_mu_vap >= 0.0 && e->bt_mu_vap < 1e300))
+      return fail(b, FVM_EINVAL, "viscosities must be finite and >= 0");
     return FVM_OK;
   }
   if (e->ncomp != 0 && e->ncomp != 2 && e->ncomp != 3) return fail(b, FVM_EINVAL, "ncomp must be 2 or 3");
@@ -333,6 +336,10 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       double cg = std::sqrt(e.bt_RT), cm = std::sqrt(C.bt_cm2);
       C.bt_c_hi = e.bt_c_liq > cg ? e.bt_c_liq : cg;
       C.bt_c_lo = cm > cg ? cm : cg;
+      C.bt_mu_l = e.mu[0];
+      C.bt_mu_g = e.mu[1];
+      C.bt_mu_v = e.bt_mu_vap;
+      C.diff = (e.mu[0] > 0.0 || e.mu[1] > 0.0 || e.bt_mu_vap > 0.0) ? 1 : 0;
       continue;
     }
     for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], &eos[c], k);

@@ -10,8 +10,9 @@
 //   2..1+D: rho u
 // One fused kernel per Runge-Kutta stage on 1D/2D tiles, shaped like the
 // four-equation kernel: tile + two-cell halo staged in LDS after the FP64
-// closure p = f(rho, xi), sensors, x and y face sweeps, CSF, body force,
-// update, and in the last stage the CFL bound of the new state.  In 3D a
+// closure p = f(rho, xi), sensors, x and y face sweeps (with the viscous
+// stress of the mixture viscosity of eq. 2-8 when the fluids are viscous),
+// CSF, body force, update, and in the last stage the CFL bound of the new state.  In 3D a
 // closure kernel and a face kernel, as for the four-equation model.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -210,6 +211,62 @@ __device__ inline int baro_elig(R Ya, R Yb, R Yc, R va, R vb, R vc, R ra, R rb, 
   return e;
 }
 
+// mixture viscosity of eq. 2-8 with one gas,
+// (1 - aG)[(1 - a_v)(1 + 5/2 a_v) mu_L + a_v mu_V] + aG mu_G: the bracket is the
+// viscosity of the liquid-vapour part, so a_v = aV / (1 - aG) is the vapour
+// share of that part (aV of eq. 2-7 is a share of the whole cell)
+template <class R>
+__device__ inline R baro_mu(const CaseC& C, R aG, R aV)
+{
+  R g = fmin(fmax(aG, R(0)), R(1));
+  R m = R(1) - g;
+  R av = m > R(0) ? fmin(fmax(fdiv(aV, m), R(0)), R(1)) : R(0);
+  return m * ((R(1) - av) * (R(1) + R(2.5) * av) * R(C.bt_mu_l) + av * R(C.bt_mu_v)) + g * R(C.bt_mu_g);
+}
+
+// Stress part of the momentum flux through the face between the LDS cells c
+// and c + st[DIR] (eq. 2-2; the model has no energy equation): second-order
+// central, normal derivatives from the two cells, transverse ones as the
+// mean of the two cells' central differences, face viscosity the mean of the
+// two cells' eq. 2-8 values.  tau = mu (grad u + grad u^T - 2/3 div u I),
+// F_rho u -= tau . n.  U[a]: velocity component a; sA, sV: alpha_G, alpha_V.
+template <class S, int D, int DIR>
+__device__ inline void baro_visc(const CaseC& C, const S* const (&U)[D], const S* sA, const S* sV, int c,
+                                 const int (&st)[D], S* F)
+{
+  const int r = c + st[DIR];
+  S g[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == DIR) g[a][b] = (U[a][r] - U[a][c]) * S(C.idx[DIR]);
+      else g[a][b] = (U[a][c + st[b]] - U[a][c - st[b]] + U[a][r + st[b]] - U[a][r - st[b]]) * S(0.25 * C.idx[b]);
+    }
+  S div = S(0);
+#pragma unroll
+  for (int b = 0; b < D; ++b) div += g[b][b];
+  const S mu = S(0.5) * (baro_mu<S>(C, sA[c], sV[c]) + baro_mu<S>(C, sA[r], sV[r]));
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S tau = mu * (g[a][DIR] + g[DIR][a]);
+    if (a == DIR) tau -= S(2.0 / 3.0) * mu * div;
+    F[2 + a] -= tau;
+  }
+}
+
+// CFL rate of a cell: sum_d (|u_d| + c) / dx_d, plus 2 mu / rho sum_d 1/dx_d^2
+// for a viscous mixture (explicit diffusion limit, mu of eq. 2-8)
+template <int D>
+__device__ inline double baro_cfl(const CaseC& C, const double* u, const PB& pb, double rho)
+{
+  double l = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+  if (C.diff) l += 2.0 * baro_mu<double>(C, pb.aG, pb.aV) / rho * C.sdx2;
+  return l;
+}
+
 // ------------------------------------------------------------------ fused 1D/2D stage
 template <class S, int D, int TX, int TY, int NT, int MINW, int LIM>
 __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
@@ -320,6 +377,12 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
     for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
 
   const S eps = S(SC.eps_int);
+  // velocity arrays and LDS strides for the stress terms
+  const S* U[D];
+  int stv[D];
+  U[0] = s_u;
+  stv[0] = 1;
+  if constexpr (D == 2) { U[1] = s_v; stv[1] = HX; }
   // stencil of the face between LDS cells c and c + st (cells c - st .. c + 2 st)
   auto stencil = [&](int c, int st, BStencil<S, D>& bs, int& el, int& er) {
     S av[4];
@@ -347,6 +410,7 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
     bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
     S F[NQ];
     baro_face<S, D, 0, LIM>(SC, C, bs, disc, el, er, F);
+    if (C.diff) baro_visc<S, D, 0>(C, U, s_a, s_av, c, stv, F);
 #pragma unroll
     for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
   };
@@ -375,6 +439,7 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
       bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
       S F[NQ];
       baro_face<S, D, D - 1, LIM>(SC, C, bs, disc, el, er, F);
+      if (C.diff) baro_visc<S, D, D - 1>(C, U, s_a, s_av, c, stv, F);
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     };
@@ -508,9 +573,7 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
 #pragma unroll
         for (int v = 1; v < NQ; ++v) q[v] = (double)nv[v];
         PB pb = baro_prim<D>(C, q, u, rho, Y);
-        double l = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+        double l = baro_cfl<D>(C, u, pb, rho);
         if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, cell - C.off, step);
         else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, cell - C.off, step);
         else lam = fmax(lam, l);
@@ -618,8 +681,7 @@ __global__ __launch_bounds__(256) void k_baro_dt_init(const CaseC* cases, CaseDy
     double q[D + 2], u[D], rho, Y;
     baro_own<S, D>(C, src, total, C.off + c, q);
     PB pb = baro_prim<D>(C, q, u, rho, Y);
-    double l = 0.0;
-    for (int d = 0; d < D; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+    double l = baro_cfl<D>(C, u, pb, rho);
     if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, c, dy.base + label_off);
     else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, c, dy.base + label_off);
     else lam = l;
@@ -704,9 +766,7 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
     W[7 * T + cell] = S(pb.aG);
     W[8 * T + cell] = S(pb.aV);
     if (first) {
-      double l = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) l += (fabs(u[d]) + pb.c) * C.idx[d];
+      double l = baro_cfl<3>(C, u, pb, rho);
       if (!isfinite(l) || !isfinite(pb.p)) record_error(dy, ERR_NAN, cell - C.off, step - 1);
       else if (!(rho > 0.0) || !(pb.p > 0.0)) record_error(dy, ERR_NONPHYS, cell - C.off, step - 1);
       else lam = fmax(lam, l);
@@ -903,6 +963,12 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
       if (d == 0) baro_face<S, 3, 0, LIM>(SC, C, bs, disc, el, er, F);
       else if (d == 1) baro_face<S, 3, 1, LIM>(SC, C, bs, disc, el, er, F);
       else baro_face<S, 3, 2, LIM>(SC, C, bs, disc, el, er, F);
+      if (C.diff) {
+        const S* U3[3] = {s_u, s_v, s_ww};
+        if (d == 0) baro_visc<S, 3, 0>(C, U3, s_a, s_av, c, st, F);
+        else if (d == 1) baro_visc<S, 3, 1>(C, U3, s_a, s_av, c, st, F);
+        else baro_visc<S, 3, 2>(C, U3, s_a, s_av, c, st, F);
+      }
 #pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     }

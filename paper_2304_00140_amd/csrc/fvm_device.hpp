@@ -69,6 +69,7 @@ struct CaseC {
   // the gas, and the sound speed of impedances and CFL at p >= p_sat / below
   int model;
   double bt_rs, bt_ps, bt_cl2, bt_cm2, bt_rv, bt_RT, bt_c_hi, bt_c_lo;
+  double bt_mu_l, bt_mu_g, bt_mu_v;   // barotropic model: liquid, gas, vapour viscosity (eq. 2-8)
 };
 
 // per-case scalars that live on the device across steps; slot s = step & 1

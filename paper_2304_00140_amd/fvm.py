@@ -37,7 +37,8 @@ class fvm_eos_desc(C.Structure):
                 ("pr_vc", (C.c_double * MAXSPEC) * 2), ("pr_kij", ((C.c_double * MAXSPEC) * MAXSPEC) * 2),
                 ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 3), ("kc", C.c_double * 3),
                 ("ncomp", C.c_int), ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
-                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double)]
+                ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double),
+                ("bt_mu_vap", C.c_double)]
 
 
 class fvm_scheme_desc(C.Structure):
@@ -150,6 +151,7 @@ def eos_desc(ed, storage=None):
         b = ed["baro"]
         e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
         e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
+        e.bt_mu_vap = b.get("mu_vap", 0.0)
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]

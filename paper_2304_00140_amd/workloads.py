@@ -67,14 +67,17 @@ def make_eos(c0, c1, c2=None):
                 mu=[c.get("mu", 0.0) for c in comps], kc=[c.get("kc", 0.0) for c in comps])
 
 
-def baro_eos(rho_sat=1000.0, p_sat=2340.0, c_liq=1500.0, rho_vap=0.0173, R_gas=296.8, T_gas=336.9):
+def baro_eos(rho_sat=1000.0, p_sat=2340.0, c_liq=1500.0, rho_vap=0.0173, R_gas=296.8, T_gas=336.9,
+             mu_liq=0.0, mu_gas=0.0, mu_vap=0.0):
     """barotropic equilibrium model (Section 2.2): a liquid that becomes a
     liquid-vapour mixture below p_sat, and one isothermal ideal gas.  Defaults:
     Section 4.5's liquid and gas values; the saturated vapour density is that
-    of water vapour at 2340 Pa, 293 K (p / (R_v T), R_v = 461.5 J/(kg K))."""
+    of water vapour at 2340 Pa, 293 K (p / (R_v T), R_v = 461.5 J/(kg K)).
+    mu_liq, mu_gas, mu_vap [Pa s]: the viscosities of eq. (2-8) (0: inviscid)."""
     return dict(model=MODEL_BAROTROPIC, kind=[EOS_SG, EOS_SG], gamma=[0.0, 0.0], pinf=[0.0, 0.0],
-                cv=[0.0, 0.0], q=[0.0, 0.0], pr=[None, None], mu=[0.0, 0.0], kc=[0.0, 0.0],
-                baro=dict(rho_sat=rho_sat, p_sat=p_sat, c_liq=c_liq, rho_vap=rho_vap, RT=R_gas * T_gas))
+                cv=[0.0, 0.0], q=[0.0, 0.0], pr=[None, None], mu=[mu_liq, mu_gas], kc=[0.0, 0.0],
+                baro=dict(rho_sat=rho_sat, p_sat=p_sat, c_liq=c_liq, rho_vap=rho_vap, RT=R_gas * T_gas,
+                          mu_vap=mu_vap))
 
 
 def cv_for_density(gamma, pinf, rho, p, T):

@@ -1,7 +1,7 @@
 """GPU (gfx950) barotropic cavitation model (Section 2.2; liquid-vapour density
 THINC of Section 3.4) against the CPU FP64 oracle through the C ABI: one RHS
-on every tile in 1D, 2D and 3D (walls, far field, switching, CSF, gravity),
-primitives, steps, totals, the mixed path against FP64, a moving gas-liquid
+on every tile in 1D, 2D and 3D (walls, far field, switching, CSF, gravity,
+viscous stress with the mixture viscosity of eq. 2-8), primitives, steps, totals, the mixed path against FP64, a moving gas-liquid
 interface in equilibrium, a cavitating expansion, the vapour bubble near a
 wall and the square-to-circle case, and the rejected configurations."""
 import numpy as np
@@ -73,17 +73,31 @@ SPECS = [
     dict(dim=2, n=[41, 29], seed=64, switching=1, sigma=0.05,
          bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_ZEROGRAD, W.BC_WALL]]),
     dict(dim=2, n=[38, 33], seed=65, switching=1, gravity=[3.0, -9.81, 0.0]),
+    dict(dim=1, n=[90], seed=66, viscous=True),
+    dict(dim=2, n=[40, 35], seed=67, switching=1, sigma=0.05, viscous=True,
+         bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC]]),
 ]
+
+# viscosities of liquid, gas and vapour (eq. 2-8) large enough that the stress
+# part is of the order of the inviscid momentum right-hand side on these grids
+VISC = (5e-3, 1e-3, 2e-3)
+
+
+def viscous(c):
+    b = dict(c["eos"]["baro"], mu_vap=VISC[2])
+    c["eos"] = dict(c["eos"], mu=[VISC[0], VISC[1]], baro=b)
+    return c
 
 
 def make(spec):
     spec = dict(spec)
     dim, n, seed = spec.pop("dim"), spec.pop("n"), spec.pop("seed")
     grav = spec.pop("gravity", None)
+    visc = spec.pop("viscous", False)
     c = W.random_state(dim, n, seed, barotropic=True, **spec)
     if grav is not None:
         c["scheme"] = dict(c["scheme"], gravity=grav)
-    return c
+    return viscous(c) if visc else c
 
 
 @pytest.mark.parametrize("spec", SPECS, ids=lambda s: f"{s['dim']}d-{s['seed']}")
@@ -206,7 +220,8 @@ def test_barotropic_workloads_steps(dev, stream, name):
 
 SPECS3 = [dict(n=[19, 13, 11], seed=81), dict(n=[17, 14, 12], seed=82, switching=1, sigma=0.05),
           dict(n=[13, 12, 18], seed=83, switching=1, bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC],
-                                                        [W.BC_ZEROGRAD, W.BC_WALL]], gravity=[0.0, 0.0, -9.81])]
+                                                        [W.BC_ZEROGRAD, W.BC_WALL]], gravity=[0.0, 0.0, -9.81]),
+          dict(n=[14, 12, 11], seed=85, switching=1, viscous=True)]
 
 
 @pytest.mark.parametrize("spec", SPECS3, ids=lambda s: f"3d-{s['seed']}")
@@ -218,9 +233,12 @@ def test_barotropic_rhs_3d_every_tile(dev, stream, spec):
     spec = dict(spec)
     n, seed = spec.pop("n"), spec.pop("seed")
     grav = spec.pop("gravity", None)
+    visc = spec.pop("viscous", False)
     case = W.random_state(3, n, seed, barotropic=True, **spec)
     if grav is not None:
         case["scheme"] = dict(case["scheme"], gravity=grav)
+    if visc:
+        case = viscous(case)
     o = Oracle(case)
     q = o.cons_from_prim()
     assert q.shape[0] == 5
@@ -270,10 +288,82 @@ def test_barotropic_3d_steps_mixed_and_cube_to_sphere(dev, stream):
         assert l1 < 1e-4
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_barotropic_viscous_steps_and_mixed(dev, stream, dim):
+    """the stress terms with the mixture viscosity of eq. 2-8 (liquid, vapour
+    and gas cells) over four steps: FP64 against the oracle (the time step
+    includes the viscous limit), the mixed path within L1 1e-4 of FP64"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    n = [36, 30] if dim == 2 else [14, 13, 12]
+    case = viscous(W.random_state(dim, n, 70 + dim, barotropic=True, switching=1))
+    o = Oracle(case)
+    q0 = o.cons_from_prim()
+    q = q0.copy()
+    t = o.run(q, 4)
+    ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    ctx.init_primitive()
+    t_gpu = ctx.n_steps(4)
+    # the oracle's own sensitivity: the same run from a start density one ulp higher
+    qs = q0.copy()
+    qs[0] *= 1.0 + EPS
+    o.run(qs, 4)
+    scale = np.maximum(np.abs(q).max(axis=1), 1e-300)
+    sens = np.abs(qs - q).max(axis=1) / scale
+    rel = np.abs(ctx.get_state() - q).max(axis=1) / scale
+    print(f"barotropic viscous {dim}D 4 steps: {np.array2string(rel, precision=2)} "
+          f"(oracle one-ulp sensitivity {np.array2string(sens, precision=2)})", flush=True)
+    assert abs(t_gpu / t - 1) < 1e-12
+    assert np.all(rel <= np.maximum(1e-10, 4.0 * sens))
+    m = fvm.Context(case, fvm.FVM_MIXED, stream=stream.cuda_stream)
+    m.init_primitive()
+    m.n_steps(4)
+    a, b = m.get_primitive(), ctx.get_primitive()
+    l1 = max(np.abs(a[f] - b[f]).sum() / np.abs(b[f]).sum() for f in (0, 4))
+    print(f"barotropic viscous {dim}D mixed vs fp64 L1 {l1:.2e}", flush=True)
+    assert l1 < 1e-4
+
+
+def test_barotropic_viscous_time_step(dev, stream):
+    """a shear wave in the liquid-vapour mixture with gas (uniform p < p_sat,
+    alpha_G = 0.3) viscous enough that the diffusive limit 2 mu / rho sum 1/dx^2
+    sets the time step: 50 FP64 steps against the oracle, times equal"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    n, L = 32, 1e-3
+    g = W.make_grid(2, [n, 4], [L, L / 8], [[W.BC_PERIODIC] * 2] * 2)
+    case = dict(name="bshear", grid=g, eos=W.baro_eos(mu_liq=10.0, mu_gas=2.0, mu_vap=1.0),
+                scheme=W.default_scheme(), steps=None, t_end=0.0, storage=dict(p_ref=1e5, T_ref=0.0))
+    x, y = W.cell_centres(g)
+    p = 0.5 * case["eos"]["baro"]["p_sat"]
+    case["prim"] = W.pack_prim(np.full_like(x, p), np.zeros_like(x), np.full_like(x, 0.3),
+                               [0 * x, 0.01 * np.sin(2 * np.pi * x / L)])
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    w = o.prim_from_cons(q)
+    dx = L / n
+    conv = (np.abs(w[1]) + w[7]).max() / dx + (np.abs(w[2]) + w[7]).max() / (L / 8 / 4)
+    assert o.dt(q) < 0.9 * case["scheme"]["cfl"] / conv   # the viscous limit is the binding one
+    t = o.run(q, 50)
+    ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    ctx.init_primitive()
+    t_gpu = ctx.n_steps(50)
+    err = field_err(ctx.get_state(), q)
+    print(f"barotropic viscous shear wave 50 steps: {err:.3e}, t {t_gpu:.6e} vs {t:.6e}", flush=True)
+    assert abs(t_gpu / t - 1) < 1e-12
+    assert err < 1e-10
+
+
 def test_barotropic_rejections(dev, stream):
     from paper_2304_00140_amd import fvm
+    # no energy equation: no heat conduction; viscosities finite and >= 0
+    for key, val in (("kc", [1e-3, 0.0]), ("mu", [-1e-3, 0.0])):
+        c2 = W.random_state(2, [16, 16], 68, barotropic=True)
+        c2["eos"] = dict(c2["eos"], **{key: val})
+        with pytest.raises(fvm.FvmError):
+            fvm.Context(c2, fvm.FVM_FP64, stream=stream.cuda_stream)
     c2 = W.random_state(2, [16, 16], 68, barotropic=True)
-    c2["eos"] = dict(c2["eos"], mu=[1e-3, 0.0])
+    c2["eos"] = dict(c2["eos"], baro=dict(c2["eos"]["baro"], mu_vap=float("nan")))
     with pytest.raises(fvm.FvmError):
         fvm.Context(c2, fvm.FVM_FP64, stream=stream.cuda_stream)
     c3 = W.random_state(2, [16, 16], 69, barotropic=True)

@@ -4,8 +4,10 @@ the mathematics fix: each branch of the one-fluid equation reduces to its
 component law, round trips through the closure, continuity at p_sat, the
 volume-fraction identities of eq. 2-6 and 2-7, stationarity, pressure /
 velocity equilibrium of a moving gas-liquid interface, conservation, the
-acoustic speed of the liquid, mirror symmetry of a cavitating expansion and
-the face density of an eligible liquid-vapour cell."""
+acoustic speed of the liquid, mirror symmetry of a cavitating expansion,
+the face density of an eligible liquid-vapour cell, and the stress terms with
+the mixture viscosity of eq. 2-8 (its limits, the exact viscous RHS of a
+quadratic velocity, shear-wave decay in liquid, mixture and gas)."""
 import ctypes as C
 
 import numpy as np
@@ -227,3 +229,100 @@ def test_liquid_vapour_face_density_is_the_thinc_value():
         else:
             assert rf == pytest.approx(L.og_baro_density(C.byref(e), pst.value, 0.0), rel=1e-14)
         assert F[1] == pytest.approx(F[0] * 2.0 + pst.value, rel=1e-12)
+
+
+def viscosity(e, aG, aV):
+    return lib().og_baro_viscosity(C.byref(e), aG, aV)
+
+
+def test_mixture_viscosity_limits():
+    """eq. 2-8 with one gas: pure liquid gives mu_liq, pure gas mu_gas; with
+    the liquid-vapour part all vapour (alpha_V = 1 - alpha_G) it is the
+    volume-weighted mean of mu_vap and mu_gas; at small vapour share the
+    slope in the share is (5/2 - 1) mu_liq + mu_vap (the suspension term minus
+    the displaced liquid), taken by a finite difference"""
+    muL, muG, muV = 1.0e-3, 2.0e-5, 1.0e-5
+    e = make_eos(W.baro_eos(mu_liq=muL, mu_gas=muG, mu_vap=muV))
+    assert viscosity(e, 0.0, 0.0) == pytest.approx(muL, rel=1e-15)
+    assert viscosity(e, 1.0, 0.0) == pytest.approx(muG, rel=1e-15)
+    for g in (0.0, 0.3, 0.9):
+        assert viscosity(e, g, 1.0 - g) == pytest.approx((1 - g) * muV + g * muG, rel=1e-13)
+        h = 1e-6
+        slope = (viscosity(e, g, (1 - g) * h) - viscosity(e, g, 0.0)) / h
+        assert slope == pytest.approx((1 - g) * (1.5 * muL + muV), rel=1e-5)
+
+
+def baro_visc_case(dim, n, L, mu, bc):
+    g = W.make_grid(dim, n, L, bc)
+    return dict(name="bvisc", grid=g, eos=W.baro_eos(mu_liq=mu[0], mu_gas=mu[1], mu_vap=mu[2]),
+                scheme=W.default_scheme(), prim=None, steps=None, t_end=0.0, storage=dict(p_ref=1e5, T_ref=0.0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quadratic_velocity_momentum_in_the_liquid_is_exact(dim):
+    """compressed liquid (no vapour, no gas: mu = mu_liq), quadratic velocity:
+    the face-centred central stress is exact, so the viscous part of the
+    momentum RHS in interior cells is mu (lap u + grad(div u) / 3); the mass
+    rows do not change"""
+    mu = 2.0e-3
+    n = [12, 10] if dim == 2 else [9, 8, 8]
+    L = [1e-4 * k for k in n]
+    case = baro_visc_case(dim, n, L, (mu, 0.0, 0.0), [[W.BC_ZEROGRAD] * 2] * dim)
+    xs = W.cell_centres(case["grid"])
+    rng = np.random.default_rng(6 + dim)
+    A = rng.uniform(-3e5, 3e5, size=(dim, dim, dim))   # u_a = sum_bc A[a, b, c] x_b x_c
+    comps = [sum(A[a, b, c] * xs[b] * xs[c] for b in range(dim) for c in range(dim)) for a in range(dim)]
+    case["prim"] = W.pack_prim(np.full_like(xs[0], 1e5), np.zeros_like(xs[0]), np.zeros_like(xs[0]), comps)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    r1 = o.rhs(q)
+    inv = dict(case, eos=W.baro_eos())
+    dr = r1 - Oracle(inv).rhs(q)
+    S = A + A.transpose(0, 2, 1)                      # d2 u_a / dx_b dx_c
+    lap = [sum(S[a, b, b] for b in range(dim)) for a in range(dim)]
+    gdiv = [sum(S[b, b, a] for b in range(dim)) for a in range(dim)]
+    inner = np.zeros(n[::-1], bool)
+    inner[(slice(2, -2),) * dim] = True
+    inner = inner.reshape(-1)
+    scale = mu * max(abs(v) for v in lap + gdiv)
+    for a in range(dim):
+        ex = mu * (lap[a] + gdiv[a] / 3.0)
+        assert np.abs(dr[1 + a][inner] - ex).max() < 1e-7 * scale
+    assert np.abs(dr[0]).max() == 0.0 and np.abs(dr[1 + dim]).max() == 0.0
+
+
+@pytest.mark.parametrize("aG,p", [(0.0, 1e5), (0.0, 0.5 * PS), (0.3, 0.5 * PS)])
+def test_shear_wave_decays_with_the_mixture_viscosity(aG, p):
+    """v = U sin(kx), u = 0 in a periodic box at uniform p: every convective
+    flux cancels and v decays by the LS-RK4 polynomial of lam dt per step,
+    lam = -nu (4/dx^2) sin^2(k dx/2), nu = mu_mix / rho with eq. 2-8 in compressed
+    liquid, in the liquid-vapour mixture (p < p_sat) and with gas in it, whose
+    vapour share of the liquid-vapour part is alpha_V / (1 - alpha_G)"""
+    muL, muG, muV = 10.0, 2.0, 1.0
+    n, L = 32, 1e-3
+    case = baro_visc_case(2, [n, 4], [L, 4 * L / n], (muL, muG, muV), [[W.BC_PERIODIC] * 2] * 2)
+    x, y = W.cell_centres(case["grid"])
+    k = 2 * np.pi / L
+    U = 0.01
+    case["prim"] = W.pack_prim(np.full_like(x, p), np.zeros_like(x), np.full_like(x, aG), [0 * x, U * np.sin(k * x)])
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    w0 = o.prim_from_cons(q)
+    rho = w0[0].mean()
+    assert np.abs(w0[0] / rho - 1).max() < 1e-12
+    e = make_eos(case["eos"])
+    a, av = fractions(e, rho, w0[6].mean(), p)
+    assert a == pytest.approx(aG, abs=1e-12)
+    s = av / (1.0 - aG)
+    mu_mix = (1 - aG) * ((1 - s) * (1 + 2.5 * s) * muL + s * muV) + aG * muG
+    nu = mu_mix / rho
+    dx = L / n
+    lam = -nu * 4 / dx ** 2 * np.sin(k * dx / 2) ** 2
+    amp, t = 1.0, 0.0
+    for step in range(250):
+        t, dt = o.step(q, step, t)
+        z = lam * dt
+        amp *= 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    w = o.prim_from_cons(q)
+    assert amp < 0.8   # the run covers a real decay
+    np.testing.assert_allclose(w[2], amp * U * np.sin(k * x), atol=1e-6 * U * amp)

@@ -112,12 +112,14 @@ typedef struct fvm_grid_desc {
  * model: FVM_MODEL_FOUR_EQ (0, everything above) or FVM_MODEL_BAROTROPIC, the
  * barotropic equilibrium model of Section 2.2 (eqs. 2-3 .. 2-7), which
  * replaces the components above (kind, gamma, pinf, cv, q, PR data and T_ref
- * are ignored; kc must be 0; ncomp must be 0 or 2): a liquid with
+ * are ignored; kc must be 0; ncomp 0 or 2: one gas, 3: two gases): a liquid with
  * rho = bt_rho_sat + (p - bt_p_sat) / bt_c_liq^2 at p >= bt_p_sat that is a
  * liquid-vapour mixture below it (the same law with c_M^2 = p_sat / rho_sat),
- * and one isothermal ideal gas rho_G = p / bt_RT (bt_RT = R_Gas T_ref).
- * There is no energy equation: N_q = D + 2 (rho, rho u, rho xi); p follows
- * from (rho, xi); the T row of the primitive input and in_T, ff_T of the grid
+ * and one isothermal ideal gas rho_G = p / bt_RT (bt_RT = R_Gas T_ref); with
+ * ncomp = 3 a second one, rho_G2 = p / bt_RT2 (eqs. 2-5, 2-6 with Gas1 and
+ * Gas2), whose mass fraction xi_2 is transported like xi.
+ * There is no energy equation: N_q = D + 2 (rho, rho u, rho xi; two gases:
+ * D + 3 with rho xi_2 last); p follows from (rho, xi[, xi_2]); the T row of the primitive input and in_T, ff_T of the grid
  * are ignored (a far-field or inflow state needs p > 0 instead); the primitive
  * output has 12 rows (the 11 above with T = xi_2 = alpha_2 = 0, then the
  * vapour volume fraction of eq. 2-7, at most 0.995).  Where the upwind cell
@@ -126,12 +128,14 @@ typedef struct fvm_grid_desc {
  * of rho (eqs. 3-7, 3-8, Remarks 1-2), elsewhere rho(p*, xi_face).  FP32
  * storage (FVM_MIXED) keeps the liquid's partial density relative to its
  * density at p_ref.  Viscous stress (no heat conduction, no energy): mu[0]
- * (liquid), mu[1] (gas) and bt_mu_vap (vapour) enter the mixture viscosity of
- * eq. 2-8, (1 - alpha_G)[(1 - a_v)(1 + 5/2 a_v) mu_liq + a_v mu_vap] +
- * alpha_G mu_gas, a_v = alpha_V / (1 - alpha_G) the vapour share of the
- * liquid-vapour part; all zero: inviscid.  Requires bt_rho_sat > 0,
- * bt_p_sat > 0, bt_c_liq > 0, 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0, finite
- * viscosities >= 0; 1D, 2D and 3D. */
+ * (liquid), mu[1] (gas), mu[2] (second gas) and bt_mu_vap (vapour) enter the
+ * mixture viscosity of eq. 2-8, (1 - alpha_G - alpha_G2)[(1 - a_v)(1 + 5/2 a_v)
+ * mu_liq + a_v mu_vap] + alpha_G mu_gas + alpha_G2 mu_gas2, a_v = alpha_V /
+ * (1 - alpha_G - alpha_G2) the vapour share of the liquid-vapour part; all
+ * zero: inviscid.  The primitive input of two gases has alpha_G2 after u; the
+ * output keeps 12 rows with xi_2 and alpha_G2 in rows 9 and 10.  Requires bt_rho_sat > 0,
+ * bt_p_sat > 0, bt_c_liq > 0, 0 <= bt_rho_vap < bt_rho_sat, bt_RT > 0 (and
+ * bt_RT2 > 0 with two gases), finite viscosities >= 0; 1D, 2D and 3D. */
 typedef struct fvm_eos_desc {
   int kind[3];
   double gamma[3], pinf[3], cv[3], q[3];
@@ -146,6 +150,7 @@ typedef struct fvm_eos_desc {
   int model;
   double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
   double bt_mu_vap;
+  double bt_RT2;
 } fvm_eos_desc;
 
 /* Scheme parameters (Section 3.3, Appendix D; defaults in brackets):

@@ -90,6 +90,9 @@ typedef struct {
   int model;
   double bt_rho_sat, bt_p_sat, bt_c_liq, bt_rho_vap, bt_RT;
   double bt_mu_vap;
+  /* ncomp = 3 in the barotropic model: a second isothermal ideal gas with
+   * rho_G2 = p / bt_RT2 (viscosity mu[2]) */
+  double bt_RT2;
 } og_eos;
 
 typedef struct {
@@ -147,6 +150,12 @@ double og_baro_sound(const og_eos* e, double p);
 void og_baro_fractions(const og_eos* e, double rho, double Y, double p, double* alpha_G, double* alpha_V);
 /* mixture viscosity of eq. 2-8 (one gas) from the cell's alpha_G and alpha_V */
 double og_baro_viscosity(const og_eos* e, double alpha_G, double alpha_V);
+/* the same with two gases (ncomp = 3): xi_2 / alpha_G2 of the second gas */
+double og_baro_density2(const og_eos* e, double p, double Y, double Y2);
+int og_baro_pressure2(const og_eos* e, double rho, double Y, double Y2, double* p);
+void og_baro_fractions2(const og_eos* e, double rho, double Y, double Y2, double p, double* alpha_G,
+                        double* alpha_G2, double* alpha_V);
+double og_baro_viscosity2(const og_eos* e, double alpha_G, double alpha_G2, double alpha_V);
 
 /* ---- reconstruction (Section 3.3, Table 4.2, Appendix D) ---- */
 double og_limiter_table(int kind, double r);

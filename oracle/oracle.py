@@ -38,7 +38,7 @@ class Eos(C.Structure):
                 ("mu", C.c_double * MAXCOMP), ("kc", C.c_double * MAXCOMP), ("ncomp", C.c_int),
                 ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
                 ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double),
-                ("bt_mu_vap", C.c_double)]
+                ("bt_mu_vap", C.c_double), ("bt_RT2", C.c_double)]
 
 
 class Scheme(C.Structure):
@@ -78,6 +78,9 @@ def lib():
             "og_baro_sound": (C.c_double, [pe, C.c_double]),
             "og_baro_fractions": (None, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_baro_viscosity": (C.c_double, [pe, C.c_double, C.c_double]),
+            "og_baro_density2": (C.c_double, [pe, C.c_double, C.c_double, C.c_double]),
+            "og_baro_pressure2": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, dp]),
+            "og_baro_fractions2": (None, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp]),
             "og_face_flux_baro": (C.c_int, [pe, ps, C.c_int, C.c_int, dp, C.c_int, C.c_int, C.c_int,
                                             dp, dp, dp]),
             "og_sound": (C.c_double, [pe, C.c_int, C.c_double, C.c_double]),
@@ -151,6 +154,7 @@ def make_eos(ed):
         e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
         e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
         e.bt_mu_vap = b.get("mu_vap", 0.0)
+        e.bt_RT2 = b.get("RT2", 0.0)
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
@@ -196,7 +200,7 @@ class Oracle:
         self.dim = case["grid"]["dim"]
         self.ncomp = len(case["eos"]["kind"])
         self.barotropic = int(case["eos"].get("model", 0)) == 1
-        self.nq = self.dim + 2 if self.barotropic else self.dim + self.ncomp + 1
+        self.nq = self.dim + self.ncomp if self.barotropic else self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
 
     def _err(self, rc, what):

@@ -83,10 +83,12 @@ static int cons_from_prim_cell(const og_eos* e, int dim, double p, double T, dou
      * rho_G = p / (R T) (eq. 2-5), rho xi = alpha_G rho_G; T is not used */
     if (!(p > 0.0)) return -1;
     double rG = p / e->bt_RT, rL = og_baro_liquid_density(e, p);
-    rho = al * rG + (1.0 - al) * rL;
+    double rG2 = og_ncomp(e) == 3 ? p / e->bt_RT2 : 0.0;
+    rho = al * rG + al2 * rG2 + (1.0 - al - al2) * rL;
     qc[0] = rho;
     for (int d = 0; d < dim; ++d) qc[1 + d] = rho * u[d];
     qc[1 + dim] = al * rG;
+    if (og_ncomp(e) == 3) qc[2 + dim] = al2 * rG2;
     return rho > 0.0 ? 0 : -1;
   }
   if (og_ncomp(e) == 2) {
@@ -145,12 +147,13 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   if (og_is_barotropic(e)) {
     /* p = f(rho, xi) (Section 2.2), alpha_G (eq. 2-6), alpha_V (eq. 2-7) */
     double Y = qc[1 + dim] / rho, p;
-    int rc = og_baro_pressure(e, rho, Y, &p);
+    double Y2 = og_ncomp(e) == 3 ? qc[2 + dim] / rho : 0.0;
+    int rc = og_baro_pressure2(e, rho, Y, Y2, &p);
     W[OW_RHO] = rho;
     W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
-    W[OW_P] = p; W[OW_T] = 0.0; W[OW_Y] = Y; W[OW_Y2] = 0.0; W[OW_A2] = 0.0;
+    W[OW_P] = p; W[OW_T] = 0.0; W[OW_Y] = Y; W[OW_Y2] = Y2;
     W[OW_C] = og_baro_sound(e, p);
-    og_baro_fractions(e, rho, Y, p, &W[OW_A], &W[OW_AV]);
+    og_baro_fractions2(e, rho, Y, Y2, p, &W[OW_A], &W[OW_A2], &W[OW_AV]);
     if (rc || !(rho > 0.0) || !(p > 0.0) || !isfinite(p)) return -1;
     return 0;
   }
@@ -273,7 +276,7 @@ static int fill_ghosts(const og_grid* g, const og_eos* e, const og_pad* pd, doub
 /* per padded cell with one neighbour on each side: bit 0 = f (discontinuous
  * branch), bit 1+d = THINC eligibility along d */
 static void sensors(const og_grid* g, const og_eos* e, const og_scheme* s, const og_pad* pd,
-                    const double* W, unsigned char* flag)
+                    const double* W, unsigned short* flag)
 {
   int dim = g->dim;
   size_t np = pd->npad;
@@ -285,12 +288,14 @@ static void sensors(const og_grid* g, const og_eos* e, const og_scheme* s, const
       for (int i = lo[0]; i < hi[0]; ++i) {
         size_t c = og_pidx(pd, i, j, k);
         size_t st[3] = {1, (size_t)pd->P[0], (size_t)pd->P[0] * pd->P[1]};
-        unsigned char fl = 0;
+        unsigned short fl = 0;
         /* THINC eligibility: eps < xi_i < 1 - eps and xi monotone through i along d;
          * bits 1+d for xi_1, 4+d for xi_2 or, in the barotropic model, for the
-         * vapour fraction alpha_V (liquid-vapour interface, Remark 1) */
-        for (int g2 = 0; g2 < 2; ++g2) {
-          int f = g2 ? (og_is_barotropic(e) ? OW_AV : OW_Y2) : OW_Y;
+         * vapour fraction alpha_V (liquid-vapour interface, Remark 1), and 7+d
+         * for xi_2 of the barotropic model with two gases */
+        const int nsets = (og_is_barotropic(e) && og_ncomp(e) == 3) ? 3 : 2;
+        for (int g2 = 0; g2 < nsets; ++g2) {
+          int f = g2 == 2 ? OW_Y2 : (g2 ? (og_is_barotropic(e) ? OW_AV : OW_Y2) : OW_Y);
           double Y = W[f * np + c];
           for (int d = 0; d < dim; ++d) {
             double Ym = W[f * np + c - st[d]], Yp = W[f * np + c + st[d]];
@@ -302,7 +307,7 @@ static void sensors(const og_grid* g, const og_eos* e, const og_scheme* s, const
               double r0 = W[OW_RHO * np + c];
               ok = ok && (r0 - W[OW_RHO * np + c - st[d]]) * (W[OW_RHO * np + c + st[d]] - r0) > 0.0;
             }
-            if (ok) fl |= (unsigned char)((g2 ? 16u : 2u) << d);
+            if (ok) fl |= (unsigned short)((g2 == 2 ? 128u : (g2 ? 16u : 2u)) << d);
           }
         }
         if (!s->switching) {
@@ -440,7 +445,7 @@ static void curvature_field(const og_grid* g, const og_scheme* s, const og_pad* 
 
 int og_nq(const og_grid* g, const og_eos* e)
 {
-  if (og_is_barotropic(e)) return g->dim + 2;
+  if (og_is_barotropic(e)) return g->dim + 2 + (og_ncomp(e) == 3 ? 1 : 0);
   return g->dim + og_ncomp(e) + 1;
 }
 
@@ -448,7 +453,7 @@ int og_nq(const og_grid* g, const og_eos* e)
 
 static int has_diffusion(const og_eos* e)
 {
-  if (og_is_barotropic(e)) return e->mu[0] > 0.0 || e->mu[1] > 0.0 || e->bt_mu_vap > 0.0;
+  if (og_is_barotropic(e)) return e->mu[0] > 0.0 || e->mu[1] > 0.0 || e->mu[2] > 0.0 || e->bt_mu_vap > 0.0;
   for (int k = 0; k < og_ncomp(e); ++k)
     if (e->mu[k] > 0.0 || e->kc[k] > 0.0) return 1;
   return 0;
@@ -460,7 +465,7 @@ static double mix_alpha(const double* v, int ncomp, double a, double a2);
  * barotropic model */
 static double cell_viscosity(const og_eos* e, const double* W, size_t np, size_t c)
 {
-  if (og_is_barotropic(e)) return og_baro_viscosity(e, W[OW_A * np + c], W[OW_AV * np + c]);
+  if (og_is_barotropic(e)) return og_baro_viscosity2(e, W[OW_A * np + c], W[OW_A2 * np + c], W[OW_AV * np + c]);
   return mix_alpha(e->mu, og_ncomp(e), W[OW_A * np + c], W[OW_A2 * np + c]);
 }
 
@@ -526,7 +531,7 @@ typedef struct {
   og_pad pd;
   double* qp;            /* padded conserved [nq][npad] */
   double* W;             /* padded primitives [OW_N][npad] */
-  unsigned char* flag;   /* padded sensor bits */
+  unsigned short* flag;  /* padded sensor bits */
 } og_work;
 
 static int work_setup(og_work* w, const og_grid* g, const og_eos* e, const double* q, int64_t step)
@@ -536,7 +541,7 @@ static int work_setup(og_work* w, const og_grid* g, const og_eos* e, const doubl
   size_t np = w->pd.npad, nc = w->pd.ncell;
   w->qp = (double*)calloc((size_t)nq * np, sizeof(double));
   w->W = (double*)calloc((size_t)OW_N * np, sizeof(double));
-  w->flag = (unsigned char*)calloc(np, 1);
+  w->flag = (unsigned short*)calloc(np, sizeof(unsigned short));
   if (!w->qp || !w->W || !w->flag) { og_set_error("out of memory"); return -1; }
   for (int k = 0; k < w->pd.n[2]; ++k)
     for (int j = 0; j < w->pd.n[1]; ++j)
@@ -579,7 +584,7 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
   int bad = 0;
   const int diffusive = has_diffusion(e);
   const int baro = og_is_barotropic(e);
-  if (baro && (e->kc[0] != 0.0 || e->kc[1] != 0.0)) {
+  if (baro && (e->kc[0] != 0.0 || e->kc[1] != 0.0 || e->kc[2] != 0.0)) {
     work_free(&w);
     og_set_error("the barotropic model has no energy equation: no heat conduction");
     return -4;
@@ -602,8 +607,8 @@ int og_rhs(const og_grid* g, const og_eos* e, const og_scheme* s, const double* 
           int f = (w.flag[c] | w.flag[c + st[d]]) & 1;
           /* THINC eligibility of cells i and i+1 along d: bit 0 xi_1, bit 1 xi_2 */
           int fl = w.flag[c], fr = w.flag[c + st[d]];
-          int sl = ((fl >> (1 + d)) & 1) | (((fl >> (4 + d)) & 1) << 1);
-          int sr = ((fr >> (1 + d)) & 1) | (((fr >> (4 + d)) & 1) << 1);
+          int sl = ((fl >> (1 + d)) & 1) | (((fl >> (4 + d)) & 1) << 1) | (((fl >> (7 + d)) & 1) << 2);
+          int sr = ((fr >> (1 + d)) & 1) | (((fr >> (4 + d)) & 1) << 1) | (((fr >> (7 + d)) & 1) << 2);
           double F[7];
           if (baro ? og_face_flux_baro(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL)
                    : og_face_flux(e, s, dim, d, Wl, f, sl, sr, F, NULL, NULL))
@@ -682,7 +687,7 @@ int og_sensor_flags(const og_grid* g, const og_eos* e, const og_scheme* s, const
     for (int k = 0; k < w.pd.n[2]; ++k)
       for (int j = 0; j < w.pd.n[1]; ++j)
         for (int i = 0; i < w.pd.n[0]; ++i)
-          flags[og_cidx(&w.pd, i, j, k)] = w.flag[og_pidx(&w.pd, i, j, k)];
+          flags[og_cidx(&w.pd, i, j, k)] = (unsigned char)(w.flag[og_pidx(&w.pd, i, j, k)] & 0xffu);
   }
   work_free(&w);
   return rc;
@@ -723,7 +728,7 @@ double og_dt(const og_grid* g, const og_eos* e, const og_scheme* s, const double
     for (int d = 0; d < dim; ++d) l += (fabs(w[OW_U + d]) + w[OW_C]) / g->dx[d];
     if (diffusive && og_is_barotropic(e)) {
       /* viscous limit with the mixture viscosity of eq. (2-8) */
-      l += 2.0 * og_baro_viscosity(e, w[OW_A], w[OW_AV]) / w[OW_RHO] * sdx2;
+      l += 2.0 * og_baro_viscosity2(e, w[OW_A], w[OW_A2], w[OW_AV]) / w[OW_RHO] * sdx2;
     } else if (diffusive) {
       int ncomp = og_ncomp(e);
       double cvm;

@@ -100,16 +100,21 @@ static int check_eos(fvm_batch* b, const fvm_eos_desc* e)
   if (e->model != FVM_MODEL_FOUR_EQ && e->model != FVM_MODEL_BAROTROPIC)
     return fail(b, FVM_EINVAL, "unknown model");
   if (e->model == FVM_MODEL_BAROTROPIC) {
-    if (e->ncomp != 0 && e->ncomp != 2) return fail(b, FVM_EINVAL, "the barotropic model has one gas (ncomp 2)");
+    if (e->ncomp != 0 && e->ncomp != 2 && e->ncomp != 3)
+      return fail(b, FVM_EINVAL, "the barotropic model has one gas (ncomp 2) or two (ncomp 3)");
+    if (e->ncomp == 3 && (!(e->bt_RT2 > 0.0) || !std::isfinite(e->bt_RT2)))
+      return fail(b, FVM_EINVAL, "a second gas in the barotropic model needs RT2 > 0");
     if (!(e->bt_rho_sat > 0.0) || !(e->bt_p_sat > 0.0) || !(e->bt_c_liq > 0.0) || !(e->bt_RT > 0.0) ||
         !(e->bt_rho_vap >= 0.0) || !(e->bt_rho_vap < e->bt_rho_sat) || !std::isfinite(e->bt_rho_sat) ||
         !std::isfinite(e->bt_p_sat) || !std::isfinite(e->bt_c_liq) || !std::isfinite(e->bt_RT))
       return fail(b, FVM_EINVAL, "barotropic model needs rho_sat, p_sat, c_liq, RT > 0 and 0 <= rho_vap < rho_sat");
     for (int k = 0; k < 3; ++k)
-      if (e->kc[k] != 0.0 || (k == 2 && e->mu[k] != 0.0))
-        return fail(b, FVM_EINVAL, "the barotropic model has no heat conduction (kc = 0) and viscosities mu[0], mu[1]");
+      if (e->kc[k] != 0.0 || (k == 2 && e->ncomp != 3 && e->mu[k] != 0.0))
+        return fail(b, FVM_EINVAL,
+                    "the barotropic model has no heat conduction (kc = 0) and viscosities mu[0], mu[1] (mu[2] with a "
+                    "second gas)");
     if (!(e->mu[0] >= 0.0 && e->mu[0] < 1e300) || !(e->mu[1] >= 0.0 && e->mu[1] < 1e300) ||
-        !(e->bt_mu_vap >= 0.0 && e->bt_mu_vap < 1e300))
+        !(e->mu[2] >= 0.0 && e->mu[2] < 1e300) || !(e->bt_mu_vap >= 0.0 && e->bt_mu_vap < 1e300))
       return fail(b, FVM_EINVAL, "viscosities must be finite and >= 0");
     return FVM_OK;
   }
@@ -295,7 +300,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     if (nc != b->ncomp) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the number of components"));
     const int baro = eos[c].model == FVM_MODEL_BAROTROPIC;
     if (c == 0) b->kind = baro ? FVM_KIND_BARO : FVM_KIND_SG;
-    if (baro != (b->kind == FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
+    if (baro != (b->kind >= FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
     CaseC& C = b->hc[c];
     std::memset(&C, 0, sizeof C);
     C.dim = g->dim;
@@ -333,13 +338,15 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       C.bt_cm2 = e.bt_p_sat / e.bt_rho_sat;
       C.bt_rv = e.bt_rho_vap;
       C.bt_RT = e.bt_RT;
-      double cg = std::sqrt(e.bt_RT), cm = std::sqrt(C.bt_cm2);
+      C.bt_RT2 = nc == 3 ? e.bt_RT2 : 0.0;
+      double cg = std::sqrt(e.bt_RT > C.bt_RT2 ? e.bt_RT : C.bt_RT2), cm = std::sqrt(C.bt_cm2);
       C.bt_c_hi = e.bt_c_liq > cg ? e.bt_c_liq : cg;
       C.bt_c_lo = cm > cg ? cm : cg;
       C.bt_mu_l = e.mu[0];
       C.bt_mu_g = e.mu[1];
       C.bt_mu_v = e.bt_mu_vap;
-      C.diff = (e.mu[0] > 0.0 || e.mu[1] > 0.0 || e.bt_mu_vap > 0.0) ? 1 : 0;
+      C.bt_mu_g2 = nc == 3 ? e.mu[2] : 0.0;
+      C.diff = (e.mu[0] > 0.0 || e.mu[1] > 0.0 || C.bt_mu_g2 > 0.0 || e.bt_mu_vap > 0.0) ? 1 : 0;
       continue;
     }
     for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], &eos[c], k);
@@ -348,8 +355,8 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       if (eos[c].mu[k] > 0.0 || eos[c].kc[k] > 0.0) C.diff = 1;
     if (C.comp[1].kind == FVM_EOS_PR) b->kind = FVM_KIND_PR;
   }
-  if (b->ncomp == 3) b->kind = FVM_KIND_THREE;
-  b->nq = (b->kind == FVM_KIND_BARO) ? b->dim + 2 : b->dim + b->ncomp + 1;
+  if (b->ncomp == 3) b->kind = (b->kind == FVM_KIND_BARO) ? FVM_KIND_BARO2 : FVM_KIND_THREE;
+  b->nq = (b->kind >= FVM_KIND_BARO) ? b->dim + b->ncomp : b->dim + b->ncomp + 1;
   b->total = off;
   // scheme constants
   SchemeC& S = b->sc;
@@ -381,7 +388,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
       pT[2 * c + 1] = eos[c].T_ref;
       any = any || (eos[c].T_ref > 0.0);
     }
-    if (b->kind == FVM_KIND_BARO) any = false;
+    if (b->kind >= FVM_KIND_BARO) any = false;
     if (any && b->mixed) {
       if ((rc = ensure_scratch(b, sizeof(double) * 8 * ncases))) return bail(rc);
       double* dpT = (double*)b->scratch;
@@ -392,7 +399,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
     }
     for (int c = 0; c < ncases; ++c) {
       CaseC& C = b->hc[c];
-      if (b->kind == FVM_KIND_BARO) {
+      if (b->kind >= FVM_KIND_BARO) {
         // FP32 storage keeps the liquid's partial density relative to the
         // liquid density at p_ref (eq. 2-3 / 2-4); the gas is unshifted
         double pr = eos[c].p_ref, rl = 0.0;
@@ -430,7 +437,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   }
   if (b->dim == 3) {
     // rho, u, v, w, p, T, xi, c, alpha (+ xi_2, alpha_2 with three components)
-    const size_t rows = (b->kind == FVM_KIND_THREE) ? 11 : 9;
+    const size_t rows = (b->kind == FVM_KIND_THREE || b->kind == FVM_KIND_BARO2) ? 11 : 9;
     if (hipMalloc(&b->prim, rows * (size_t)b->total * b->esz) != hipSuccess)
       return bail(fail(b, FVM_ENOMEM, "primitive buffer allocation failed"));
     // zero T: the first closure of a Peng-Robinson cell takes the ideal-gas start
@@ -735,7 +742,7 @@ int fvm_get_primitive(fvm_ctx* ctx, double* w_host)
   if (!w_host) return fail(b, FVM_EINVAL, "NULL array");
   if (!b->has_state[0]) return fail(b, FVM_ESTATE, "no state set");
   const CaseC& C = b->hc[0];
-  size_t rows = b->kind == FVM_KIND_BARO ? 12 : (b->ncomp == 3 ? 11 : 9);
+  size_t rows = b->kind >= FVM_KIND_BARO ? 12 : (b->ncomp == 3 ? 11 : 9);
   size_t bytes = sizeof(double) * rows * (size_t)C.ncell;
   int rc = ensure_scratch(b, bytes);
   if (rc) return rc;
@@ -838,6 +845,8 @@ static int check_tile(fvm_batch* b, int tile)
   if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
   if (b->dim == 3 && b->kind == FVM_KIND_THREE && !fvm_k_tile_ok3(b->mixed, b->kind, tile))
     return fail(b, FVM_EINVAL, "this 3D tile does not fit the LDS of a workgroup with three components in FP64");
+  if (b->dim == 3 && b->kind == FVM_KIND_BARO2 && !fvm_kb_tile_ok3(b->mixed, 1, tile))
+    return fail(b, FVM_EINVAL, "this 3D tile does not fit the LDS of a workgroup with two gases in FP64");
   return FVM_OK;
 }
 

@@ -70,6 +70,7 @@ struct CaseC {
   int model;
   double bt_rs, bt_ps, bt_cl2, bt_cm2, bt_rv, bt_RT, bt_c_hi, bt_c_lo;
   double bt_mu_l, bt_mu_g, bt_mu_v;   // barotropic model: liquid, gas, vapour viscosity (eq. 2-8)
+  double bt_RT2, bt_mu_g2;            // barotropic model, second gas: R T and viscosity
 };
 
 // per-case scalars that live on the device across steps; slot s = step & 1

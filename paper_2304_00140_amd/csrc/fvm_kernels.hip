@@ -225,10 +225,10 @@ int fvm_k_tile_shape(int dim, int t, int* tx, int* ty, int* nt)
 
 // kind: closure of the batch, FVM_KIND_SG (stiffened-gas pair), FVM_KIND_PR
 // (Peng-Robinson component 1), FVM_KIND_THREE (liquid and two ideal gases) or
-// FVM_KIND_BARO (barotropic model)
+// FVM_KIND_BARO / FVM_KIND_BARO2 (barotropic model, one or two gases)
 hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) return fvm_kb_stage(dim, mixed, tile, a, ntiles, st);
+  if (kind >= FVM_KIND_BARO) return fvm_kb_stage(dim, mixed, kind == FVM_KIND_BARO2, tile, a, ntiles, st);
   if (dim == 3) return fvm_k_stage3(mixed, kind, tile, a, ntiles, st);
   if (fvm_default_limiters(a.sc)) return fvm_k_stage12_deflim(dim, mixed, kind, tile, a, ntiles, st);
   return stage12_any<0>(dim, mixed, kind, tile, a, ntiles, st);
@@ -267,7 +267,7 @@ static unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const double* prim, void* dst, long long total, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) return fvm_kb_prim_to_state(dim, mixed, cases, icase, ncell, prim, dst, total, st);
+  if (kind >= FVM_KIND_BARO) return fvm_kb_prim_to_state(dim, mixed, kind == FVM_KIND_BARO2, cases, icase, ncell, prim, dst, total, st);
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_prim_to_state<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, prim, (S*)dst, total)
   FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
@@ -277,7 +277,7 @@ hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const CaseC* cases,
 hipError_t fvm_k_cons_to_state(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const double* q, void* dst, long long total, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) return fvm_kb_cons_to_state(dim, mixed, cases, icase, ncell, q, dst, total, st);
+  if (kind >= FVM_KIND_BARO) return fvm_kb_cons_to_state(dim, mixed, kind == FVM_KIND_BARO2, cases, icase, ncell, q, dst, total, st);
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_cons_to_state<S, D, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, q, (S*)dst, total)
   FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
@@ -287,7 +287,7 @@ hipError_t fvm_k_cons_to_state(int dim, int mixed, int kind, const CaseC* cases,
 hipError_t fvm_k_state_to_cons(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const void* src, double* q, long long total, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) return fvm_kb_state_to_cons(dim, mixed, cases, icase, ncell, src, q, total, st);
+  if (kind >= FVM_KIND_BARO) return fvm_kb_state_to_cons(dim, mixed, kind == FVM_KIND_BARO2, cases, icase, ncell, src, q, total, st);
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_state_to_cons<S, D, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, q, total)
   FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
@@ -297,7 +297,7 @@ hipError_t fvm_k_state_to_cons(int dim, int mixed, int kind, const CaseC* cases,
 hipError_t fvm_k_state_to_prim(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell,
                                const void* src, double* w, long long total, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) return fvm_kb_state_to_prim(dim, mixed, cases, icase, ncell, src, w, total, st);
+  if (kind >= FVM_KIND_BARO) return fvm_kb_state_to_prim(dim, mixed, kind == FVM_KIND_BARO2, cases, icase, ncell, src, w, total, st);
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_state_to_prim<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, icase, (const S*)src, w, total)
   FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
@@ -307,8 +307,8 @@ hipError_t fvm_k_state_to_prim(int dim, int mixed, int kind, const CaseC* cases,
 hipError_t fvm_k_dt_init(int dim, int mixed, int kind, const CaseC* cases, CaseDyn* dyn, int icase, long long ncell,
                          const void* src, long long total, long long label_off, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO)
-    return fvm_kb_dt_init(dim, mixed, cases, dyn, icase, ncell, src, total, label_off, st);
+  if (kind >= FVM_KIND_BARO)
+    return fvm_kb_dt_init(dim, mixed, kind == FVM_KIND_BARO2, cases, dyn, icase, ncell, src, total, label_off, st);
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_dt_init<S, D, P, G>), dim3(blocks_for(ncell, 256)), dim3(256), 0, st, cases, dyn, icase, (const S*)src, total, label_off)
   FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
@@ -318,15 +318,15 @@ hipError_t fvm_k_dt_init(int dim, int mixed, int kind, const CaseC* cases, CaseD
 hipError_t fvm_k_totals(int dim, int mixed, int kind, const CaseC* cases, int icase, long long ncell, const void* src,
                         long long total, double* part, int nblk, double vol, double* out, hipStream_t st)
 {
-  if (kind == FVM_KIND_BARO) {
-    hipError_t e = fvm_kb_totals_part(dim, mixed, cases, icase, src, total, part, nblk, st);
+  if (kind >= FVM_KIND_BARO) {
+    hipError_t e = fvm_kb_totals_part(dim, mixed, kind == FVM_KIND_BARO2, cases, icase, src, total, part, nblk, st);
     if (e != hipSuccess) return e;
   } else {
 #define CALL(S, D, P, G) hipLaunchKernelGGL((k_totals_part<S, D, G>), dim3(nblk), dim3(256), 0, st, cases, icase, (const S*)src, total, part)
     FVM_DISPATCH(mixed, dim, kind, CALL);
 #undef CALL
   }
-  int nq = dim + (kind == FVM_KIND_BARO ? 2 : (kind == FVM_KIND_THREE ? 4 : 3));
+  int nq = dim + (kind == FVM_KIND_BARO ? 2 : (kind == FVM_KIND_BARO2 ? 3 : (kind == FVM_KIND_THREE ? 4 : 3)));
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, part, nblk, nq, vol, out);
   return hipGetLastError();
 }

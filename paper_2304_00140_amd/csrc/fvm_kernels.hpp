@@ -23,7 +23,7 @@ struct StageArgs {
 // closure of a batch: stiffened-gas pair, Peng-Robinson component 1, a
 // liquid with two ideal gases (three components, one more storage field), or
 // the barotropic model (no energy field; its own kernels, 1D/2D)
-enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2, FVM_KIND_BARO = 3 };
+enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2, FVM_KIND_BARO = 3, FVM_KIND_BARO2 = 4 };
 
 // the scheme uses the default limiters (Koren for velocities, Minmod for the
 // thermodynamic variables): the stage kernels then take them as compile-time
@@ -65,16 +65,17 @@ hipError_t fvm_k_ref_shift(const fvm::CaseC* cases_in, int ncases, double* out /
                            const double* pT /* [ncases][2] */, hipStream_t st);
 
 // barotropic model (fvm_baro.hip), 1D and 2D
-hipError_t fvm_kb_stage(int dim, int mixed, int tile, const StageArgs& a, int ntiles, hipStream_t st);
-hipError_t fvm_kb_prim_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_kb_stage(int dim, int mixed, int g2, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+int fvm_kb_tile_ok3(int mixed, int g2, int tile);
+hipError_t fvm_kb_prim_to_state(int dim, int mixed, int g2, const fvm::CaseC* cases, int icase, long long ncell,
                                 const double* prim, void* dst, long long total, hipStream_t st);
-hipError_t fvm_kb_cons_to_state(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_kb_cons_to_state(int dim, int mixed, int g2, const fvm::CaseC* cases, int icase, long long ncell,
                                 const double* q, void* dst, long long total, hipStream_t st);
-hipError_t fvm_kb_state_to_cons(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_kb_state_to_cons(int dim, int mixed, int g2, const fvm::CaseC* cases, int icase, long long ncell,
                                 const void* src, double* q, long long total, hipStream_t st);
-hipError_t fvm_kb_state_to_prim(int dim, int mixed, const fvm::CaseC* cases, int icase, long long ncell,
+hipError_t fvm_kb_state_to_prim(int dim, int mixed, int g2, const fvm::CaseC* cases, int icase, long long ncell,
                                 const void* src, double* w, long long total, hipStream_t st);
-hipError_t fvm_kb_dt_init(int dim, int mixed, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
+hipError_t fvm_kb_dt_init(int dim, int mixed, int g2, const fvm::CaseC* cases, fvm::CaseDyn* dyn, int icase,
                           long long ncell, const void* src, long long total, long long label_off, hipStream_t st);
-hipError_t fvm_kb_totals_part(int dim, int mixed, const fvm::CaseC* cases, int icase, const void* src,
+hipError_t fvm_kb_totals_part(int dim, int mixed, int g2, const fvm::CaseC* cases, int icase, const void* src,
                               long long total, double* part, int nblk, hipStream_t st);

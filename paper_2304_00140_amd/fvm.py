@@ -38,7 +38,7 @@ class fvm_eos_desc(C.Structure):
                 ("p_ref", C.c_double), ("T_ref", C.c_double), ("mu", C.c_double * 3), ("kc", C.c_double * 3),
                 ("ncomp", C.c_int), ("model", C.c_int), ("bt_rho_sat", C.c_double), ("bt_p_sat", C.c_double),
                 ("bt_c_liq", C.c_double), ("bt_rho_vap", C.c_double), ("bt_RT", C.c_double),
-                ("bt_mu_vap", C.c_double)]
+                ("bt_mu_vap", C.c_double), ("bt_RT2", C.c_double)]
 
 
 class fvm_scheme_desc(C.Structure):
@@ -152,6 +152,7 @@ def eos_desc(ed, storage=None):
         e.bt_rho_sat, e.bt_p_sat, e.bt_c_liq = b["rho_sat"], b["p_sat"], b["c_liq"]
         e.bt_rho_vap, e.bt_RT = b["rho_vap"], b["RT"]
         e.bt_mu_vap = b.get("mu_vap", 0.0)
+        e.bt_RT2 = b.get("RT2", 0.0)
     for k in range(nc):
         e.kind[k] = int(ed["kind"][k])
         e.gamma[k], e.pinf[k], e.cv[k], e.q[k] = ed["gamma"][k], ed["pinf"][k], ed["cv"][k], ed["q"][k]
@@ -208,7 +209,7 @@ class Context:
         self.dim = case["grid"]["dim"]
         self.ncomp = len(case["eos"]["kind"])
         self.barotropic = int(case["eos"].get("model", 0)) == 1
-        self.nq = self.dim + 2 if self.barotropic else self.dim + self.ncomp + 1
+        self.nq = self.dim + self.ncomp if self.barotropic else self.dim + self.ncomp + 1
         self.ncell = int(np.prod(case["grid"]["n"]))
         self._g = grid_desc(case["grid"])
         self._e = eos_desc(case["eos"], case.get("storage") if shifts else None)
@@ -306,7 +307,7 @@ class Batch:
         n = len(cases)
         self.dim = cases[0]["grid"]["dim"]
         if int(cases[0]["eos"].get("model", 0)) == 1:
-            self.nq = self.dim + 2
+            self.nq = self.dim + len(cases[0]["eos"]["kind"])
         else:
             self.nq = self.dim + len(cases[0]["eos"]["kind"]) + 1
         self._g = (fvm_grid_desc * n)(*[grid_desc(c["grid"]) for c in cases])

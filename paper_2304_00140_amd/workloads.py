@@ -68,16 +68,20 @@ def make_eos(c0, c1, c2=None):
 
 
 def baro_eos(rho_sat=1000.0, p_sat=2340.0, c_liq=1500.0, rho_vap=0.0173, R_gas=296.8, T_gas=336.9,
-             mu_liq=0.0, mu_gas=0.0, mu_vap=0.0):
+             mu_liq=0.0, mu_gas=0.0, mu_vap=0.0, RT2=None, mu_gas2=0.0):
     """barotropic equilibrium model (Section 2.2): a liquid that becomes a
-    liquid-vapour mixture below p_sat, and one isothermal ideal gas.  Defaults:
-    Section 4.5's liquid and gas values; the saturated vapour density is that
-    of water vapour at 2340 Pa, 293 K (p / (R_v T), R_v = 461.5 J/(kg K)).
-    mu_liq, mu_gas, mu_vap [Pa s]: the viscosities of eq. (2-8) (0: inviscid)."""
-    return dict(model=MODEL_BAROTROPIC, kind=[EOS_SG, EOS_SG], gamma=[0.0, 0.0], pinf=[0.0, 0.0],
-                cv=[0.0, 0.0], q=[0.0, 0.0], pr=[None, None], mu=[mu_liq, mu_gas], kc=[0.0, 0.0],
-                baro=dict(rho_sat=rho_sat, p_sat=p_sat, c_liq=c_liq, rho_vap=rho_vap, RT=R_gas * T_gas,
-                          mu_vap=mu_vap))
+    liquid-vapour mixture below p_sat, and one isothermal ideal gas (two with
+    RT2 = R_Gas2 T_ref2 given, eqs. 2-5, 2-6).  Defaults: Section 4.5's liquid
+    and gas values; the saturated vapour density is that of water vapour at
+    2340 Pa, 293 K (p / (R_v T), R_v = 461.5 J/(kg K)).  mu_liq, mu_gas,
+    mu_vap, mu_gas2 [Pa s]: the viscosities of eq. (2-8) (0: inviscid)."""
+    n = 2 if RT2 is None else 3
+    baro = dict(rho_sat=rho_sat, p_sat=p_sat, c_liq=c_liq, rho_vap=rho_vap, RT=R_gas * T_gas, mu_vap=mu_vap)
+    if RT2 is not None:
+        baro["RT2"] = RT2
+    return dict(model=MODEL_BAROTROPIC, kind=[EOS_SG] * n, gamma=[0.0] * n, pinf=[0.0] * n,
+                cv=[0.0] * n, q=[0.0] * n, pr=[None] * n, mu=[mu_liq, mu_gas, mu_gas2][:n], kc=[0.0] * n,
+                baro=baro)
 
 
 def cv_for_density(gamma, pinf, rho, p, T):
@@ -395,7 +399,8 @@ def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.
     three-component case: the gas side is shared between an air-like and a
     helium-like ideal gas by a smooth random split.  barotropic=True makes a
     barotropic-model case whose pressure spans about 0.2 .. 2 p_sat, so
-    that liquid, liquid-vapour mixture and gas all occur."""
+    that liquid, liquid-vapour mixture and gas all occur (with second_gas,
+    two gases in the barotropic model)."""
     rng = np.random.default_rng(seed)
     n3 = list(n) + [1] * (3 - len(n))
     if bc is None:
@@ -443,7 +448,15 @@ def random_state(dim, n, seed, L=1e-3, interface=True, liquid=True, velocity=30.
         # a tenth of the velocity: near p_sat the mixture is soft (c_M ~ 1.5 m/s)
         # and a stronger random compression drives cells across the kink of the
         # law at p_sat within a few steps
-        prim = pack_prim(pb, np.zeros_like(pb), alpha, [0.1 * ud for ud in u])
+        ub = [0.1 * ud for ud in u]
+        if second_gas:
+            # the gas shared between the model's gas and a helium-like second
+            # gas (R 2077.1 J/(kg K) at the same temperature)
+            eos = baro_eos(RT2=2077.1 * 336.9)
+            share = 0.5 + 0.45 * np.tanh(3.0 * smooth(1.0))
+            prim = pack_prim(pb, np.zeros_like(pb), alpha * share, ub + [alpha * (1.0 - share)])
+        else:
+            prim = pack_prim(pb, np.zeros_like(pb), alpha, ub)
         return dict(name=f"random_baro_{dim}d_{seed}", grid=g, eos=eos,
                     scheme=default_scheme(sigma=sigma, switching=switching), prim=prim, steps=None,
                     t_end=0.0, storage=dict(p_ref=eos["baro"]["p_sat"], T_ref=0.0))

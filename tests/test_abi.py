@@ -46,11 +46,12 @@ def test_version(fvm_mod):
 def test_descriptor_layout_matches_c(fvm_mod, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fvm.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fvm_grid_desc), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fvm_grid_desc), '
                    'sizeof(fvm_eos_desc), sizeof(fvm_scheme_desc), offsetof(fvm_grid_desc, in_seed), '
                    'offsetof(fvm_eos_desc, p_ref), offsetof(fvm_scheme_desc, eps_normal), '
                    'offsetof(fvm_eos_desc, kc), offsetof(fvm_scheme_desc, gravity), '
-                   'offsetof(fvm_eos_desc, model), offsetof(fvm_eos_desc, bt_RT), offsetof(fvm_eos_desc, bt_mu_vap));'
+                   'offsetof(fvm_eos_desc, model), offsetof(fvm_eos_desc, bt_RT), offsetof(fvm_eos_desc, bt_mu_vap), '
+                   'offsetof(fvm_eos_desc, bt_RT2));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -59,7 +60,8 @@ def test_descriptor_layout_matches_c(fvm_mod, tmp_path):
           fvm_mod.fvm_grid_desc.in_seed.offset, fvm_mod.fvm_eos_desc.p_ref.offset,
           fvm_mod.fvm_scheme_desc.eps_normal.offset, fvm_mod.fvm_eos_desc.kc.offset,
           fvm_mod.fvm_scheme_desc.gravity.offset, fvm_mod.fvm_eos_desc.model.offset,
-          fvm_mod.fvm_eos_desc.bt_RT.offset, fvm_mod.fvm_eos_desc.bt_mu_vap.offset]
+          fvm_mod.fvm_eos_desc.bt_RT.offset, fvm_mod.fvm_eos_desc.bt_mu_vap.offset,
+          fvm_mod.fvm_eos_desc.bt_RT2.offset]
     assert out == py
 
 

@@ -326,3 +326,99 @@ def test_shear_wave_decays_with_the_mixture_viscosity(aG, p):
     w = o.prim_from_cons(q)
     assert amp < 0.8   # the run covers a real decay
     np.testing.assert_allclose(w[2], amp * U * np.sin(k * x), atol=1e-6 * U * amp)
+
+
+# ---------------------------------------------------------------- two gases (eqs. 2-5, 2-6 with Gas1, Gas2)
+SPLIT = 0.3
+
+
+def baro_split(dim, n, seed, **kw):
+    """a barotropic random state with one gas, and the same state with the gas
+    split 0.3 : 0.7 between two identical gases (same R T, same viscosity)"""
+    c1 = W.random_state(dim, n, seed, barotropic=True, **kw)
+    c1["scheme"] = dict(c1["scheme"], thinc=0)
+    b = c1["eos"]["baro"]
+    c1["eos"] = W.baro_eos(mu_liq=2e-3, mu_gas=4e-4, mu_vap=1e-3)
+    c2 = dict(c1)
+    c2["eos"] = W.baro_eos(mu_liq=2e-3, mu_gas=4e-4, mu_vap=1e-3, RT2=b["RT"], mu_gas2=4e-4)
+    p, T, a = c1["prim"][0], c1["prim"][1], c1["prim"][2]
+    u = list(c1["prim"][3:3 + dim])
+    c2["prim"] = W.pack_prim(p, T, SPLIT * a, u + [(1.0 - SPLIT) * a])
+    return c1, c2
+
+
+@pytest.mark.parametrize("dim,switching,sigma", [(1, 0, 0.0), (2, 1, 0.05), (3, 1, 0.0)])
+def test_two_gas_rhs_invariant_under_gas_splitting(dim, switching, sigma):
+    """splitting the one gas into two identical gases 0.3 : 0.7 leaves mass and
+    momentum right-hand sides unchanged (stress terms with eq. 2-8 included)
+    and gives the two fraction right-hand sides as 0.3 and 0.7 of the one-gas
+    xi right-hand side (THINC off: its eligibility band is not scale-free);
+    the momentum rows within the pressure noise of the stiff liquid (the two
+    closures sum the gas terms in different orders)"""
+    n = {1: [61], 2: [23, 17], 3: [11, 9, 8]}[dim]
+    c1, c2 = baro_split(dim, n, 40 + dim, switching=switching, sigma=sigma)
+    o1, o2 = Oracle(c1), Oracle(c2)
+    q1, q2 = o1.cons_from_prim(), o2.cons_from_prim()
+    assert q2.shape[0] == q1.shape[0] + 1
+    np.testing.assert_allclose(q2[:1 + dim], q1[:1 + dim], rtol=1e-13, atol=1e-13 * np.abs(q1).max())
+    np.testing.assert_allclose(q2[1 + dim] + q2[2 + dim], q1[1 + dim], rtol=1e-13, atol=1e-16)
+    r1, r2 = o1.rhs(q1), o2.rhs(q2)
+    scale = np.abs(r1).max(axis=1)
+    noise = 16 * CL * CL * RS * 2.0 ** -52 / c1["grid"]["dx"][0]
+    assert np.abs(r2[0] - r1[0]).max() < 1e-10 * scale[0]
+    for f in range(1, 1 + dim):
+        assert np.abs(r2[f] - r1[f]).max() < 1e-10 * scale[f] + noise
+    assert np.abs(r2[1 + dim] - SPLIT * r1[1 + dim]).max() < 1e-10 * scale[1 + dim]
+    assert np.abs(r2[2 + dim] - (1.0 - SPLIT) * r1[1 + dim]).max() < 1e-10 * scale[1 + dim]
+
+
+def test_two_gas_round_trip_and_volume_fractions():
+    """(p, alpha_G1, alpha_G2) -> rho, xi_1, xi_2 -> back with two different
+    gases: each gas at its own density p / (R_i T_i) (eq. 2-6), the one-fluid
+    equation with both gas terms satisfied, the volume fractions of the
+    liquid-vapour part and the gases summing to one"""
+    RT2 = 4124.0 * 300.0   # hydrogen-like
+    e = make_eos(W.baro_eos(RT2=RT2))
+    L = lib()
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        p = 10 ** rng.uniform(2.5, 7.0)
+        a1, a2 = rng.dirichlet([1, 1, 1])[:2] * rng.choice([1.0, 1e-3])
+        rl = L.og_baro_liquid_density(C.byref(e), p)
+        rho = a1 * p / RT + a2 * p / RT2 + (1 - a1 - a2) * rl
+        Y1, Y2 = a1 * p / RT / rho, a2 * p / RT2 / rho
+        assert L.og_baro_density2(C.byref(e), p, Y1, Y2) == pytest.approx(rho, rel=1e-12)
+        pp = C.c_double()
+        assert L.og_baro_pressure2(C.byref(e), rho, Y1, Y2, C.byref(pp)) == 0
+        assert pp.value == pytest.approx(p, rel=1e-8)
+        lhs = (1.0 - rho * (Y1 * RT + Y2 * RT2) / pp.value) * L.og_baro_liquid_density(C.byref(e), pp.value)
+        assert lhs == pytest.approx((1.0 - Y1 - Y2) * rho, rel=1e-7, abs=1e-9 * rho)
+        g1, g2, v = C.c_double(), C.c_double(), C.c_double()
+        L.og_baro_fractions2(C.byref(e), rho, Y1, Y2, pp.value, C.byref(g1), C.byref(g2), C.byref(v))
+        assert g1.value == pytest.approx(a1, rel=1e-7, abs=1e-12)
+        assert g2.value == pytest.approx(a2, rel=1e-7, abs=1e-12)
+
+
+def test_two_gas_slab_advection_keeps_pressure_and_velocity():
+    """a liquid slab between two different gases moving at 20 m/s through a
+    periodic box at uniform p: p and u stay uniform to round-off (the TDU
+    face density of eq. 3-5 with both gas fractions), totals conserved"""
+    n = 100
+    g = W.make_grid(1, [n], [1.0], [[W.BC_PERIODIC, W.BC_PERIODIC]])
+    x = W.cell_centres(g)[0]
+    liq = (1.0 - W.smeared(x - 0.6, 0.01)) * W.smeared(x - 0.3, 0.01)
+    gas2 = W.smeared(x - 0.6, 0.01) * (1.0 - W.smeared(x - 0.85, 0.01))
+    a1 = np.clip(1.0 - liq - gas2, 0.0, 1.0)
+    prim = W.pack_prim(np.full(n, 1e5), np.zeros(n), a1, [np.full(n, 20.0), gas2])
+    case = dict(name="slab_baro2", grid=g, eos=W.baro_eos(RT2=4124.0 * 300.0), scheme=W.default_scheme(), prim=prim,
+                steps=None, t_end=0.0, storage=dict(p_ref=1e5, T_ref=0.0))
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    assert q.shape[0] == 4
+    tot0 = o.totals(q)
+    o.run(q, 200)
+    w = o.prim_from_cons(q)
+    assert np.abs(w[4] - 1e5).max() < 1e-12 * CL * CL * RS * 1e-3
+    assert np.abs(w[1] - 20.0).max() < 1e-11 * 20.0
+    assert w[9].max() > 0.5 and w[6].max() > 0.5     # both gases still there
+    np.testing.assert_allclose(o.totals(q), tot0, rtol=1e-13, atol=1e-13 * np.abs(tot0).max())

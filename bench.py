@@ -227,8 +227,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("this build runs on one GPU; the multi-GPU decomposition is described in DESIGN.md, "
-              "not launched", file=sys.stderr)
+        print("fvm runs on one GPU: the decomposition over several GPUs is a design that is not "
+              "built, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2304_00140_amd import build, fvm

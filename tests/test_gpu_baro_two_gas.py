@@ -209,3 +209,45 @@ def test_two_gas_rejections(dev, stream):
     m = fvm.Context(c3, fvm.FVM_MIXED, stream=stream.cuda_stream)
     m.set_tile(4)
     m.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_two_gas_farfield_and_inflow_ghosts(dev, stream, dim):
+    """far-field and noisy inflow ghost states (one gas, no second gas) next
+    to a two-gas interior: one RHS at steps 0 and 3 (the inflow noise depends
+    on the step) on every tile, against the oracle"""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm
+    n = {1: [97], 2: [39, 31], 3: [15, 12, 11]}[dim]
+    bc = {1: [[W.BC_INFLOW, W.BC_FARFIELD]],
+          2: [[W.BC_INFLOW, W.BC_FARFIELD], [W.BC_FARFIELD, W.BC_WALL]],
+          3: [[W.BC_INFLOW, W.BC_ZEROGRAD], [W.BC_FARFIELD, W.BC_WALL], [W.BC_PERIODIC, W.BC_PERIODIC]]}[dim]
+    case = make(dim, n, 100 + dim, bc=bc, sigma=0.05, viscous=True)
+    g, dx = case["grid"], case["grid"]["dx"]
+    psat = case["eos"]["baro"]["p_sat"]
+    g["farfield"] = dict(p=1.4 * psat, T=0.0, alpha=0.25)
+    # the inflow disc: radius 0.35 of the y extent around the x = 0 face's centre
+    g["inflow"] = dict(p=1.2 * psat, T=0.0, alpha=0.3, u=2.0, radius=0.35 * (n[1] * dx[1] if dim > 1 else 1.0),
+                       center=[0.5 * n[1] * dx[1] if dim > 1 else 0.0, 0.5 * n[2] * dx[2] if dim > 2 else 0.0],
+                       noise=0.05, seed=13)
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    refs = {step: o.rhs(q, step) for step in (0, 3)}
+    for tile in range(fvm.lib().fvm_tile_count(dim)):
+        ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+        try:
+            ctx.set_tile(tile)
+        except fvm.FvmError:
+            assert dim == 3 and tile == 4
+            ctx.close()
+            continue
+        for step, r_ref in refs.items():
+            qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+            rd = torch.zeros_like(qd)
+            torch.cuda.synchronize()
+            ctx.rhs(qd.data_ptr(), rd.data_ptr(), step)
+            ok, rel = rhs_ok(rd.cpu().numpy(), r_ref, case)
+            print(f"two gases {dim}D far field / inflow tile {tile} step {step}: "
+                  f"{np.array2string(rel, precision=2)}", flush=True)
+            assert ok
+        ctx.close()

@@ -232,7 +232,8 @@ int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step);
  * context's dimension (0 .. fvm_tile_count(dim) - 1) and its extent.
  * fvm_set_tile / fvm_batch_set_tile return FVM_EINVAL (state unchanged) for an
  * index out of range or a tile whose kernels do not fit this closure and
- * precision (3D, three components, FP64: the 8x8x8 tile). */
+ * precision (3D in FP64 with three components or with two gases in the
+ * barotropic model: the 8x8x8 tile). */
 int fvm_tile_count(int dim);
 int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads);
 int fvm_set_tile(fvm_ctx* ctx, int tile);

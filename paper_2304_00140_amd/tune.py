@@ -32,7 +32,7 @@ def key_of(handle, precision):
     s = case["scheme"]
     e = case["eos"]
     diff = any(v > 0 for v in list(e.get("mu", [])) + list(e.get("kc", [])))
-    kinds = (("barotropic", "gas2") if int(e.get("ncomp", 2)) == 3 else ("barotropic",)) \
+    kinds = (("barotropic", "gas2") if len(e["kind"]) == 3 else ("barotropic",)) \
         if int(e.get("model", 0)) == 1 else tuple(e["kind"])
     return (case["grid"]["dim"], precision, int(s["switching"]), s["sigma"] > 0, kinds, diff, int(ncell))
 

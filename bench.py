@@ -32,7 +32,7 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v11"
+KERNEL_BUILD = "k_stage12-v12"
 MEASURED = {
     ("shock_bubble_2d", 0, 10, "k_stage12-v11"): dict(valu_per_cell_stage=3526591.4 * 64 / 262144,
                                              traffic_bytes=(9771.0 * 2 + 10242.1) * 1024),

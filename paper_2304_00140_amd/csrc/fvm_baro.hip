@@ -811,9 +811,18 @@ __global__ __launch_bounds__(256) void k_baro_totals_part(const CaseC* cases, in
 // As for the four-equation model in 3D: the FP64 closure runs once per cell in
 // its own kernel and writes the primitives in the storage precision; the face
 // kernel stages tile + two-cell halo primitives in LDS.
-// rho, u, v, w, p, xi, c, alpha_G, alpha_V [, xi_2, alpha_G2 with two gases]
+// rho, u, v, w, p, xi, alpha_G, alpha_V [, xi_2, alpha_G2 with two gases]; the
+// sound speed is not stored: it is a function of p alone (baro_sound)
 template <bool G2>
-constexpr int nwb3() { return G2 ? 11 : 9; }
+constexpr int nwb3() { return G2 ? 10 : 8; }
+
+// the sound speed of the closure at pressure p (the larger of the liquid and
+// gas speeds above p_sat, of the mixture and gas speeds below)
+template <class S>
+__device__ inline S baro_sound(const CaseC& C, S p)
+{
+  return S(((double)p >= C.bt_ps) ? C.bt_c_hi : C.bt_c_lo);
+}
 
 // primitives of every owned cell; in the first stage of a step also the CFL
 // bound of q^n and its checks (an error of the step before)
@@ -849,12 +858,11 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
     W[3 * T + cell] = S(u[2]);
     W[4 * T + cell] = S(pb.p);
     W[5 * T + cell] = S(Y);
-    W[6 * T + cell] = S(pb.c);
-    W[7 * T + cell] = S(pb.aG);
-    W[8 * T + cell] = S(pb.aV);
+    W[6 * T + cell] = S(pb.aG);
+    W[7 * T + cell] = S(pb.aV);
     if constexpr (G2) {
-      W[9 * T + cell] = S(Y2);
-      W[10 * T + cell] = S(pb.aG2);
+      W[8 * T + cell] = S(Y2);
+      W[9 * T + cell] = S(pb.aG2);
     }
     if (first) {
       double l = baro_cfl<3>(C, u, pb, rho);
@@ -877,10 +885,10 @@ __device__ inline void bprim_of(const CaseC& C, const double* q, S* w)
   double u[3], rho, Y, Y2;
   PB pb = baro_prim<3, G2>(C, q, u, rho, Y, Y2);
   w[0] = S(rho); w[1] = S(u[0]); w[2] = S(u[1]); w[3] = S(u[2]);
-  w[4] = S(pb.p); w[5] = S(Y); w[6] = S(pb.c); w[7] = S(pb.aG); w[8] = S(pb.aV);
+  w[4] = S(pb.p); w[5] = S(Y); w[6] = S(pb.aG); w[7] = S(pb.aV);
   if constexpr (G2) {
-    w[9] = S(Y2);
-    w[10] = S(pb.aG2);
+    w[8] = S(Y2);
+    w[9] = S(pb.aG2);
   }
 }
 
@@ -963,9 +971,8 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
   S* s_ww = s_w[3];
   S* s_p = s_w[4];
   S* s_Y = s_w[5];
-  S* s_c = s_w[6];
-  S* s_a = s_w[7];
-  S* s_av = s_w[8];
+  S* s_a = s_w[6];
+  S* s_av = s_w[7];
   S* s_Y2 = G2 ? s_w[NWB3 - 2] : nullptr;
   S* s_a2 = G2 ? s_w[NWB3 - 1] : nullptr;
   // total gas volume fraction and gas mass fraction of a halo cell
@@ -1057,8 +1064,8 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
         av[m] = s_av[cm];
         if constexpr (G2) bs.Y2[m] = s_Y2[cm];
       }
-      bs.c1 = s_c[c];
-      bs.c2 = s_c[c + sd];
+      bs.c1 = baro_sound<S>(C, s_p[c]);
+      bs.c2 = baro_sound<S>(C, s_p[c + sd]);
       int el = baro_elig<S>(bs.Y[0], bs.Y[1], bs.Y[2], av[0], av[1], av[2], bs.r[0], bs.r[1], bs.r[2], eps);
       int er = baro_elig<S>(bs.Y[1], bs.Y[2], bs.Y[3], av[1], av[2], av[3], bs.r[1], bs.r[2], bs.r[3], eps);
       if constexpr (G2) {

@@ -32,32 +32,32 @@ VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v12"
+KERNEL_BUILD = "k_stage12-v13"
 MEASURED = {
-    ("shock_bubble_2d", 0, 10, "k_stage12-v11"): dict(valu_per_cell_stage=3526591.4 * 64 / 262144,
+    ("shock_bubble_2d", 0, 10, "k_stage12-v13"): dict(valu_per_cell_stage=3526591.4 * 64 / 262144,
                                              traffic_bytes=(9771.0 * 2 + 10242.1) * 1024),
-    ("shock_bubble_2d", 1, 10, "k_stage12-v11"): dict(valu_per_cell_stage=3373269.2 * 64 / 262144,
+    ("shock_bubble_2d", 1, 10, "k_stage12-v13"): dict(valu_per_cell_stage=3373269.2 * 64 / 262144,
                                              traffic_bytes=(4965.6 * 2 + 5122.1) * 1024),
-    ("dual_gas_layer_2d", 0, 10, "k_stage12-v11"): dict(valu_per_cell_stage=8795769.9 * 64 / 524288,
+    ("dual_gas_layer_2d", 0, 10, "k_stage12-v13"): dict(valu_per_cell_stage=8795769.9 * 64 / 524288,
                                                traffic_bytes=(22478.6 * 2 + 24580.1) * 1024),
-    ("dual_gas_layer_2d", 1, 9, "k_stage12-v11"): dict(valu_per_cell_stage=8557505.1 * 64 / 524288,
+    ("dual_gas_layer_2d", 1, 9, "k_stage12-v13"): dict(valu_per_cell_stage=8557505.1 * 64 / 524288,
                                                traffic_bytes=(11345.9 * 2 + 12296.1) * 1024),
-    ("vapour_bubble_wall_2d", 0, 9, "k_stage12-v11"): dict(valu_per_cell_stage=8114414.4 * 64 / 524288,
-                                                   traffic_bytes=(15061.2 * 2 + 16392.1) * 1024),
-    ("vapour_bubble_wall_2d", 1, 10, "k_stage12-v11"): dict(valu_per_cell_stage=6842057.9 * 64 / 524288,
-                                                   traffic_bytes=(7603.6 * 2 + 8196.1) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v11"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
-                                           traffic_bytes=((928068.7 + 3521037.0) * 2 +
-                                                          (2547634.4 + 1670906.1)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v11"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
-                                           traffic_bytes=((462804.3 + 1687666.8) * 2 +
-                                                          (1216253.3 + 814903.0)) * 1024),
-    ("cube_to_sphere_3d", 0, 4, "k_stage12-v11"): dict(valu_per_cell_stage=(51875938.0 + 406813654.7) * 64 / 16777216,
-                                               traffic_bytes=((342924.2 + 1524994.7) * 2 +
-                                                              (1384441.4 + 684148.5)) * 1024),
-    ("cube_to_sphere_3d", 1, 4, "k_stage12-v11"): dict(valu_per_cell_stage=(55545824.0 + 360614415.0) * 64 / 16777216,
-                                               traffic_bytes=((164658.2 + 629497.5) * 2 +
-                                                              (673738.4 + 359225.5)) * 1024),
+    ("vapour_bubble_wall_2d", 0, 9, "k_stage12-v13"): dict(valu_per_cell_stage=8114414.4 * 64 / 524288,
+                                                   traffic_bytes=(15062.4 * 2 + 16392.1) * 1024),
+    ("vapour_bubble_wall_2d", 1, 10, "k_stage12-v13"): dict(valu_per_cell_stage=6842057.9 * 64 / 524288,
+                                                   traffic_bytes=(7599.0 * 2 + 8196.1) * 1024),
+    ("liquid_jet_3d", 0, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
+                                           traffic_bytes=((928041.1 + 3522144.5) * 2 +
+                                                          (2547827.9 + 1673987.5)) * 1024),
+    ("liquid_jet_3d", 1, 0, "k_stage12-v13"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
+                                           traffic_bytes=((462805.9 + 1687499.4) * 2 +
+                                                          (1215968.9 + 814903.5)) * 1024),
+    ("cube_to_sphere_3d", 0, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(51613794.0 + 412734614.7) * 64 / 16777216,
+                                               traffic_bytes=((339514.1 + 1350660.6) * 2 +
+                                                              (1230793.9 + 682506.0)) * 1024),
+    ("cube_to_sphere_3d", 1, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(55545824.0 + 360647183.0) * 64 / 16777216,
+                                               traffic_bytes=((164659.7 + 629517.9) * 2 +
+                                                              (674552.5 + 358678.3)) * 1024),
 }
 
 

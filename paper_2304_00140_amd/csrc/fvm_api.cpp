@@ -437,8 +437,8 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   }
   if (b->dim == 3) {
     // rho, u, v, w, p, T, xi, c, alpha (+ xi_2, alpha_2 with three components)
-    // (barotropic: rho, u, v, w, p, xi, alpha_G, alpha_V + xi_2, alpha_G2 with two gases)
-    const size_t rows = b->kind == FVM_KIND_BARO ? 8 : (b->kind == FVM_KIND_BARO2 ? 10 : (b->kind == FVM_KIND_THREE ? 11 : 9));
+    // (barotropic: rho, u, v, w, p, xi, alpha_G, alpha_V, c in FP32 + xi_2, alpha_G2 with two gases)
+    const size_t rows = (b->kind == FVM_KIND_THREE || b->kind == FVM_KIND_BARO2) ? 11 : 9;
     if (hipMalloc(&b->prim, rows * (size_t)b->total * b->esz) != hipSuccess)
       return bail(fail(b, FVM_ENOMEM, "primitive buffer allocation failed"));
     // zero T: the first closure of a Peng-Robinson cell takes the ideal-gas start

@@ -811,17 +811,19 @@ __global__ __launch_bounds__(256) void k_baro_totals_part(const CaseC* cases, in
 // As for the four-equation model in 3D: the FP64 closure runs once per cell in
 // its own kernel and writes the primitives in the storage precision; the face
 // kernel stages tile + two-cell halo primitives in LDS.
-// rho, u, v, w, p, xi, alpha_G, alpha_V [, xi_2, alpha_G2 with two gases]; the
-// sound speed is not stored: it is a function of p alone (baro_sound)
-template <bool G2>
-constexpr int nwb3() { return G2 ? 10 : 8; }
+// rho, u, v, w, p, xi, alpha_G, alpha_V [, c with FP32 storage] [, xi_2,
+// alpha_G2 with two gases].  The sound speed is a function of p alone
+// (baro_sound): the FP64 path recomputes it at the faces; the FP32 path keeps
+// it as a stored field, which measured faster there.
+template <class S, bool G2>
+constexpr int nwb3() { return (sizeof(S) == 4 ? 9 : 8) + (G2 ? 2 : 0); }
 
 // the sound speed of the closure at pressure p (the larger of the liquid and
 // gas speeds above p_sat, of the mixture and gas speeds below)
 template <class S>
 __device__ inline S baro_sound(const CaseC& C, S p)
 {
-  return S(((double)p >= C.bt_ps) ? C.bt_c_hi : C.bt_c_lo);
+  return (p >= S(C.bt_ps)) ? S(C.bt_c_hi) : S(C.bt_c_lo);
 }
 
 // primitives of every owned cell; in the first stage of a step also the CFL
@@ -858,11 +860,13 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
     W[3 * T + cell] = S(u[2]);
     W[4 * T + cell] = S(pb.p);
     W[5 * T + cell] = S(Y);
+    constexpr int NW = nwb3<S, G2>();
     W[6 * T + cell] = S(pb.aG);
     W[7 * T + cell] = S(pb.aV);
+    if constexpr (sizeof(S) == 4) W[8 * T + cell] = S(pb.c);
     if constexpr (G2) {
-      W[8 * T + cell] = S(Y2);
-      W[9 * T + cell] = S(pb.aG2);
+      W[(NW - 2) * T + cell] = S(Y2);
+      W[(NW - 1) * T + cell] = S(pb.aG2);
     }
     if (first) {
       double l = baro_cfl<3>(C, u, pb, rho);
@@ -885,10 +889,12 @@ __device__ inline void bprim_of(const CaseC& C, const double* q, S* w)
   double u[3], rho, Y, Y2;
   PB pb = baro_prim<3, G2>(C, q, u, rho, Y, Y2);
   w[0] = S(rho); w[1] = S(u[0]); w[2] = S(u[1]); w[3] = S(u[2]);
+  constexpr int NW = nwb3<S, G2>();
   w[4] = S(pb.p); w[5] = S(Y); w[6] = S(pb.aG); w[7] = S(pb.aV);
+  if constexpr (sizeof(S) == 4) w[8] = S(pb.c);
   if constexpr (G2) {
-    w[8] = S(Y2);
-    w[9] = S(pb.aG2);
+    w[NW - 2] = S(Y2);
+    w[NW - 1] = S(pb.aG2);
   }
 }
 
@@ -931,7 +937,7 @@ __device__ inline void load_bprim3(const CaseC& C, const S* __restrict__ W, long
   }
   long long cell = C.off + ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz);
 #pragma unroll
-  for (int v = 0; v < nwb3<G2>(); ++v) w[v] = W[v * T + cell];
+  for (int v = 0; v < nwb3<S, G2>(); ++v) w[v] = W[v * T + cell];
   if (fx) w[1] = -w[1];
   if (fy) w[2] = -w[2];
   if (fz) w[3] = -w[3];
@@ -941,7 +947,7 @@ template <class S, int TX, int TY, int TZ, int NT, int MINW, int LIM, bool G2>
 __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __restrict__ W)
 {
   constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, HXY = HX * HY, NH = HXY * HZ;
-  constexpr int NWB3 = nwb3<G2>();
+  constexpr int NWB3 = nwb3<S, G2>();
   constexpr int NQ = 5 + (G2 ? 1 : 0);
   constexpr int NC = TX * TY * TZ;
   constexpr int CPT = (NC + NT - 1) / NT;
@@ -1064,8 +1070,13 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
         av[m] = s_av[cm];
         if constexpr (G2) bs.Y2[m] = s_Y2[cm];
       }
-      bs.c1 = baro_sound<S>(C, s_p[c]);
-      bs.c2 = baro_sound<S>(C, s_p[c + sd]);
+      if constexpr (sizeof(S) == 4) {
+        bs.c1 = s_w[8][c];
+        bs.c2 = s_w[8][c + sd];
+      } else {
+        bs.c1 = baro_sound<S>(C, s_p[c]);
+        bs.c2 = baro_sound<S>(C, s_p[c + sd]);
+      }
       int el = baro_elig<S>(bs.Y[0], bs.Y[1], bs.Y[2], av[0], av[1], av[2], bs.r[0], bs.r[1], bs.r[2], eps);
       int er = baro_elig<S>(bs.Y[1], bs.Y[2], bs.Y[3], av[1], av[2], av[3], bs.r[1], bs.r[2], bs.r[3], eps);
       if constexpr (G2) {
@@ -1224,7 +1235,7 @@ constexpr long bld3()
   constexpr long NFH = (long)(TX + 2) * (TY + 2) * (TZ + 2), NV = (long)(TX + 1) * (TY + 1) * (TZ + 1);
   constexpr long NQ = 5 + (G2 ? 1 : 0);
   constexpr long NBUF = NQ * NF > NFH + 3 * NV ? NQ * NF : NFH + 3 * NV;
-  return (long)sizeof(S) * (nwb3<G2>() * NH + NBUF) + NH;
+  return (long)sizeof(S) * (nwb3<S, G2>() * NH + NBUF) + NH;
 }
 
 template <class S, int TX, int TY, int TZ, bool G2>

@@ -1,13 +1,15 @@
 // fvm_baro.hip -- gfx950 kernels of the barotropic cavitation model
 // (Section 2.2, eqs. 2-3 .. 2-7): a liquid that becomes a liquid-vapour
-// mixture below its saturation pressure and one isothermal ideal gas, with no
-// energy equation; face density by TDU (eq. 3-5) or, across liquid-vapour
-// interface cells, by THINC of the density (eqs. 3-7, 3-8, Remarks 1-2).
+// mixture below its saturation pressure and one isothermal ideal gas (or two:
+// the G2 instances), with no energy equation; face density by TDU (eq. 3-5)
+// or, across liquid-vapour interface cells, by THINC of the density
+// (eqs. 3-7, 3-8, Remarks 1-2).
 //
-// Storage of a cell, N_q = D + 2:
-//   0: rho (1 - xi) - rref_L   liquid / mixture partial density minus a reference
-//   1: rho xi                  gas partial density
+// Storage of a cell, N_q = D + 2 (D + 3 with two gases):
+//   0: rho (1 - xi - xi_2) - rref_L   liquid / mixture partial density minus a reference
+//   1: rho xi                          gas partial density
 //   2..1+D: rho u
+//   2+D: rho xi_2                      second gas partial density (two gases)
 // One fused kernel per Runge-Kutta stage on 1D/2D tiles, shaped like the
 // four-equation kernel: tile + two-cell halo staged in LDS after the FP64
 // closure p = f(rho, xi), sensors, x and y face sweeps (with the viscous

@@ -1,0 +1,201 @@
+"""Pins of the oracle's discontinuity sensor (Appendix D, eq. D.4: the gas
+volume-fraction detector theta^Gas and the vapour detector theta^alpha) and of
+the face values that the Riemann solver takes (eq. 3-1 / D.6: p* from the
+reconstructed states; eq. 3-2 / D.5: the impedance weighting of u*).
+
+Every expected value below is derived by hand from the paper's definitions
+or from textbook linear acoustics, not by re-evaluating the oracle's own
+expressions."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, lib, make_eos, make_scheme
+from paper_2304_00140_amd import workloads as W
+
+P0, T0 = 1e5, 300.0
+WATER = W.sg(4.4, 6e8, W.cv_for_density(4.4, 6e8, 1000.0, P0, T0))
+AIR = W.sg(1.4, 0.0, 717.5)            # R = 287 J/(kg K): 1.1614 kg/m^3 at (P0, T0)
+
+
+def _case_1d(alpha, sw=1):
+    n = len(alpha)
+    g = W.make_grid(1, [n], [1e-3], [[W.BC_PERIODIC, W.BC_PERIODIC]])
+    z = np.zeros(n)
+    prim = W.pack_prim(np.full(n, P0), np.full(n, T0), np.asarray(alpha, float), [z])
+    return dict(name="sensor_1d", grid=g, eos=W.make_eos(WATER, AIR),
+                scheme=W.default_scheme(switching=sw), prim=prim, steps=None, t_end=0.0,
+                storage=dict(p_ref=P0, T_ref=T0))
+
+
+def _flags(case):
+    o = Oracle(case)
+    q = o.cons_from_prim()
+    return o.sensor_flags(q) & 1, o.prim_from_cons(q)
+
+
+def test_gas_sensor_flags_a_volume_fraction_jump():
+    """A water / air-water mixture step at rest: alpha_G jumps by 0.5 while the
+    gas mass fraction jumps by only ~1.2e-3 (air is ~860 times lighter).  The
+    detector sums |jumps of alpha_G| on both sides of a cell (0 + 0.5 > 0.4):
+    exactly the two cells on either side of each of the two jumps (periodic)
+    are flagged; the velocity is zero, so the Ducros ratio is 0."""
+    n = 16
+    alpha = np.where(np.arange(n) >= 8, 0.5, 0.0)
+    f, Wp = _flags(_case_1d(alpha))
+    assert Wp[6].max() < 2e-3                         # the mass fraction stays below 2e-3
+    expect = np.zeros(n, int)
+    expect[[7, 8, 15, 0]] = 1
+    np.testing.assert_array_equal(f, expect)
+
+
+def test_gas_sensor_ignores_a_large_mass_fraction_jump():
+    """The converse: alpha_G from 0.999 to 0.99995 moves the mass fraction from
+    ~0.54 to ~0.96 (a jump of ~0.42, above the threshold) but the volume
+    fraction by ~1e-3: no cell is flagged."""
+    n = 16
+    alpha = np.where(np.arange(n) >= 8, 0.99995, 0.999)
+    f, Wp = _flags(_case_1d(alpha))
+    dY = abs(Wp[6][8] - Wp[6][7])
+    assert dY > 0.4                                   # a mass-fraction detector would fire
+    assert not f.any()
+
+
+def test_gas_sensor_smooth_ramp_below_threshold():
+    """a volume fraction ramp of 0.05 per cell gives 0.1 per cell: never flagged"""
+    n = 24
+    alpha = np.concatenate([np.linspace(0.1, 0.6, 12), np.linspace(0.6, 0.1, 12)])
+    f, _ = _flags(_case_1d(alpha))
+    assert not f.any()
+
+
+def test_gas_sensor_sums_over_the_directions():
+    """2D: alpha_G = 0.25 [x >= 6] + 0.25 [y >= 6] on a periodic 12 x 12 grid.
+    A cell next to only one of the two step lines sees a variation of 0.25
+    (not flagged); a cell next to both sees 0.25 + 0.25 = 0.5 > 0.4 (flagged),
+    because the detector adds the variations of all directions.  The flagged
+    cells are the corners where an x-step row (x in {5, 6, 11, 0}) meets a
+    y-step row (y in {5, 6, 11, 0})."""
+    n = 12
+    g = W.make_grid(2, [n, n], [1e-3, 1e-3], [[W.BC_PERIODIC, W.BC_PERIODIC]] * 2)
+    x, y = [np.floor(c / g["dx"][0]).astype(int) for c in W.cell_centres(g)]
+    alpha = 0.25 * (x >= 6) + 0.25 * (y >= 6)
+    z = np.zeros(n * n)
+    prim = W.pack_prim(np.full(n * n, P0), np.full(n * n, T0), alpha, [z, z])
+    case = dict(name="sensor_2d", grid=g, eos=W.make_eos(WATER, AIR), scheme=W.default_scheme(switching=1),
+                prim=prim, steps=None, t_end=0.0, storage=dict(p_ref=P0, T_ref=T0))
+    f, _ = _flags(case)
+    rows = {5, 6, 11, 0}
+    expect = np.array([(xi in rows) and (yi in rows) for xi, yi in zip(x, y)], int)
+    np.testing.assert_array_equal(f, expect)
+
+
+def test_vapour_sensor_flags_a_vapour_fraction_jump():
+    """Barotropic model (Section 2.2) without gas, at rest: compressed liquid
+    at 2 p_sat (no vapour) next to a liquid-vapour mixture at 0.4 p_sat, where
+    eq. 2-7 gives alpha_V ~ 1 - p / p_sat ~ 0.6.  Only the vapour detector
+    theta^alpha can see this jump (alpha_G = 0, u = 0): the cells on either
+    side of both jumps are flagged.  A mixture whose alpha_V rises by ~0.01
+    per cell is not."""
+    eos = W.baro_eos()
+    ps = eos["baro"]["p_sat"]
+    n = 16
+    g = W.make_grid(1, [n], [1e-3], [[W.BC_PERIODIC, W.BC_PERIODIC]])
+    z = np.zeros(n)
+
+    def case_for(p):
+        return dict(name="vapour_1d", grid=g, eos=eos, scheme=W.default_scheme(switching=1),
+                    prim=W.pack_prim(p, z, z, [z]), steps=None, t_end=0.0,
+                    storage=dict(p_ref=ps, T_ref=0.0))
+
+    p = np.where(np.arange(n) >= 8, 0.4 * ps, 2.0 * ps)
+    f, Wp = _flags(case_for(p))
+    av = Wp[11]
+    assert av[:8].max() == 0.0 and av[8:].min() > 0.55
+    expect = np.zeros(n, int)
+    expect[[7, 8, 15, 0]] = 1
+    np.testing.assert_array_equal(f, expect)
+    ramp = ps * (0.9 - 0.01 * np.abs(np.arange(n) - 8))
+    f, Wp = _flags(case_for(ramp))
+    assert Wp[11].max() > 0.15 and not f.any()
+
+
+# ------------------------------------------------------------- Riemann face values
+
+def _face(rows, f=1, dim=2, d=0):
+    e = make_eos(W.make_eos(WATER, AIR))
+    s = make_scheme(W.default_scheme())
+    arr = np.zeros((4, 12))
+    arr[:, :len(rows[0])] = rows
+    F = np.zeros(7)
+    us, ps = C.c_double(), C.c_double()
+    rc = lib().og_face_flux(C.byref(e), C.byref(s), dim, d, arr.ctypes.data_as(C.POINTER(C.c_double)),
+                            f, 0, 0, F.ctypes.data_as(C.POINTER(C.c_double)), C.byref(us), C.byref(ps))
+    assert rc == 0
+    return F[:dim + 3], us.value, ps.value
+
+
+def _row(rho, u, p, c, Y, T=T0):
+    # (rho, u, v, w, p, T, xi, c, alpha_G): rho and c enter the impedances as given
+    return [rho, u, 0.0, 0.0, p, T, Y, c, Y]
+
+
+def test_face_velocity_is_weighted_towards_the_heavier_side():
+    """eq. 3-2: u* weights each side's velocity by that side's acoustic
+    impedance, so at a water / air contact the interface moves with the water
+    (a rigid wall for the gas).  The impedances of D.5 keep that: with water
+    on the left (u = 2 m/s) and air on the right (u = -3 m/s) at one pressure,
+    u* lies between the two and nearer the water's velocity, and mirroring the
+    stencil mirrors u*.  (Swapping I_L and I_R puts u* nearer the air.)"""
+    water = [_row(1000.0, 2.0, P0, 1500.0, 0.0)] * 2
+    air = [_row(1.16, -3.0, P0, 1500.0, 1.0)] * 2
+    _, us, ps = _face(water + air)
+    assert -3.0 < us < 2.0
+    assert abs(us - 2.0) < abs(us + 3.0) / 2
+    assert ps == pytest.approx(P0, rel=1e-15)
+    mir = [_row(1.16, 3.0, P0, 1500.0, 1.0)] * 2 + [_row(1000.0, -2.0, P0, 1500.0, 0.0)] * 2
+    _, usm, _ = _face(mir)
+    assert usm == pytest.approx(-us, rel=1e-14)
+
+
+@pytest.mark.parametrize("f", [1, 0])
+def test_equal_densities_give_the_linear_acoustic_solution(f):
+    """Two sides of one density rho: D.5's impedances both become rho c_m and
+    the discontinuous u* is the textbook linear-acoustics interface velocity
+    (u_L + u_R)/2 + (p_L - p_R)/(2 rho c_m), c_m the larger sound speed.  Flat
+    states on each side are their own limited reconstructions.  In the
+    smooth branch D.1 of the step velocity is (7 (u_L + u_R) - u_L - u_R)/12 =
+    (u_L + u_R)/2, the third difference of the step pressure is 2 (p_L - p_R),
+    and with k3 = 1/4 the pressure term is (p_L - p_R)/(4 rho c_m): the same
+    acoustic term for the states of the unlimited upwind-biased
+    reconstruction, whose face pressures differ by (p_L - p_R)/2 here."""
+    rho, cL, cR = 5.0, 340.0, 410.0
+    pa, pb, ua, ub = 1.2e5, 1.0e5, 4.0, -1.0
+    rows = [_row(rho, ua, pa, cL, 1.0)] * 2 + [_row(rho, ub, pb, cR, 1.0)] * 2
+    _, us, ps = _face(rows, f=f)
+    acoustic = (pa - pb) / (2.0 * rho * cR)
+    if f:
+        assert us == pytest.approx(0.5 * (ua + ub) + acoustic, rel=1e-14)
+        assert ps == pytest.approx(0.5 * (pa + pb), rel=1e-15)
+    else:
+        assert us == pytest.approx(0.5 * (ua + ub) + 0.5 * acoustic, rel=1e-13)
+        assert ps == pytest.approx(0.5 * (pa + pb), rel=1e-15)
+
+
+def test_face_pressure_comes_from_the_reconstructed_states():
+    """eq. 3-1 / D.6: p* = (p_L + p_R)/2 of the reconstructed face states.
+    Cell pressures P0 + dp (1, 2, 4, 4): Minmod (Table 4.2; r = near/far = 2
+    gives f = 1) makes p_L = 2 + 1/2 = 2.5, and the flat right pair makes
+    p_R = 4 - 0 = 4, so p* = 3.25 (the mean of the two cell pressures would be
+    3).  With the fluid at rest and equal densities u* = (p_L - p_R)/(2 rho c):
+    the face flows from high to low pressure.  The smooth branch takes D.1:
+    (7 (2 + 4) - 1 - 4)/12 = 37/12.  The momentum flux carries p*."""
+    dp, rho, c = 100.0, 1.16, 347.0
+    rows = [_row(rho, 0.0, P0 + k * dp, c, 1.0) for k in (1, 2, 4, 4)]
+    F, us, ps = _face(rows, f=1)
+    assert ps == pytest.approx(P0 + 3.25 * dp, rel=1e-15)
+    assert us == pytest.approx((2.5 - 4.0) * dp / (2.0 * rho * c), rel=1e-13)
+    assert F[1] == pytest.approx(ps, rel=1e-15)     # u_f = 0: the momentum flux is p* alone
+    _, _, ps0 = _face(rows, f=0)
+    assert ps0 == pytest.approx(P0 + 37.0 / 12.0 * dp, rel=1e-15)

@@ -41,6 +41,12 @@ def field_err(a, b):
     return (np.abs(a - b).max(axis=1) / scale).max()
 
 
+def field_errs(a, b):
+    """max |a - b| per field over max |b| per field, one value per field"""
+    scale = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return np.abs(a - b).max(axis=1) / scale
+
+
 def gpu_rhs(ctx, q, dev, step=0):
     qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
     rd = torch.zeros_like(qd)
@@ -308,8 +314,17 @@ def test_peng_robinson_gas_matches_oracle(dev, stream, dim):
     w, w_ref = ctx.get_primitive(), o.prim_from_cons(q)
     np.testing.assert_allclose(w[4], w_ref[4], rtol=1e-10, atol=1e-10 * 1e5)
     np.testing.assert_allclose(w[5], w_ref[5], rtol=1e-10)
+    print(f"PR {dim}d sound speed: {np.abs(w[7] / w_ref[7] - 1).max():.3e}", flush=True)
     np.testing.assert_allclose(w[7], w_ref[7], rtol=1e-9)
-    assert field_err(gpu_rhs(ctx, q, dev), o.rhs(q)) < 1e-9
+    r_ref = o.rhs(q)
+    err = field_errs(gpu_rhs(ctx, q, dev), r_ref)
+    # the bar per field: 1e-10, or four times the oracle's own change under a
+    # one-ulp perturbation of its input where that is larger (the stiff
+    # liquid's pressure, and with it the momentum rows, is fixed only to
+    # rounding of p + p_inf ~ 6e8 Pa)
+    sens = ulp_sensitivity(o, q, r_ref)
+    print(f"PR {dim}d rhs: {err} one-ulp sensitivity {sens}", flush=True)
+    assert np.all(err < np.maximum(1e-10, 4.0 * sens))
     t = 0.0
     for k in range(3):
         t, _ = o.step(q, k, t)
@@ -330,7 +345,9 @@ def test_liquid_jet_small_fp64_and_mixed(dev, stream):
     ctx = ctx_for(case, fvm.FVM_FP64, stream)
     ctx.init_primitive()
     np.testing.assert_allclose(ctx.get_state(), q, rtol=1e-12, atol=1e-12 * np.abs(q).max())
-    assert field_err(gpu_rhs(ctx, q, dev, 0), o.rhs(q, 0)) < 1e-9
+    err = field_err(gpu_rhs(ctx, q, dev, 0), o.rhs(q, 0))
+    print(f"jet rhs: {err:.3e}", flush=True)
+    assert err < 1e-10
     t = 0.0
     for k in range(3):
         t, _ = o.step(q, k, t)
@@ -370,7 +387,9 @@ def test_mass_fraction_outside_unit_interval(dev, stream, gas, dim):
     w, w_ref = ctx.get_primitive(), o.prim_from_cons(q)
     for f in (4, 5, 7, 8):
         np.testing.assert_allclose(w[f], w_ref[f], rtol=1e-10, atol=1e-10 * np.abs(w_ref[f]).max())
-    assert field_err(gpu_rhs(ctx, q, dev), o.rhs(q)) < 1e-9
+    err = field_err(gpu_rhs(ctx, q, dev), o.rhs(q))
+    print(f"outside [0, 1] {gas} {dim}d rhs: {err:.3e}", flush=True)
+    assert err < 1e-10
 
 
 def test_liquid_jet_nozzle_lip_fp64(dev, stream):

@@ -1,12 +1,16 @@
 """Benchmark of the gfx950 solver: cell-RK-stage updates per second.
 
-Default workload: the 2D shock-helium-bubble case, 1024 x 256 cells, FP64 and
-mixed (FP32 storage and fluxes, FP64 closure) paths, `--steps` time steps of
-four stages each, state resident in HBM.  Prints one JSON line.
+Default workload: the 3D liquid jet (Section 4.7 shape), 512 x 256 x 256
+cells, Peng-Robinson gas, CSF, sensor switching; the headline is the path its
+configuration names (mixed: FP32 storage and fluxes, FP64 closure), with the
+FP64 path measured beside it.  `--steps` time steps of four stages each, the
+state resident in HBM.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 2000] [--warmup 50] [--workload shock_bubble_2d]
+  python bench.py [--gpus 1] [--steps 200] [--warmup 50] [--workload liquid_jet_3d]
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -22,43 +26,31 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions per second
 VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Per-unit figures of the dominant kernel measured with rocprofv3 on these
-# workloads and launch shapes (profiles/k_stage12_shock_bubble_2d_counters.md,
-# profiles/k_stage12_dual_gas_layer_2d_counters.md,
-# profiles/k_baro12_vapour_bubble_wall_2d_counters.md,
-# profiles/k_bface3_cube_to_sphere_3d_counters.md,
-# profiles/k_face3_liquid_jet_3d_counters.md): executed VALU lane-instructions
-# per cell-stage (SQ_INSTS_VALU x 64 / cells; in 3D the closure and face kernels
-# of a stage together) and HBM bytes per stage (FETCH_SIZE x 2.0 + WRITE_SIZE x
-# 1.0 in KiB, factors from a 1 GiB device copy).  Keyed by (workload,
-# precision, tile, kernel build).
-KERNEL_BUILD = "k_stage12-v13"
-MEASURED = {
-    ("shock_bubble_2d", 0, 10, "k_stage12-v13"): dict(valu_per_cell_stage=3526591.4 * 64 / 262144,
-                                             traffic_bytes=(9771.0 * 2 + 10242.1) * 1024),
-    ("shock_bubble_2d", 1, 10, "k_stage12-v13"): dict(valu_per_cell_stage=3373269.2 * 64 / 262144,
-                                             traffic_bytes=(4965.6 * 2 + 5122.1) * 1024),
-    ("dual_gas_layer_2d", 0, 10, "k_stage12-v13"): dict(valu_per_cell_stage=8795769.9 * 64 / 524288,
-                                               traffic_bytes=(22478.6 * 2 + 24580.1) * 1024),
-    ("dual_gas_layer_2d", 1, 9, "k_stage12-v13"): dict(valu_per_cell_stage=8557505.1 * 64 / 524288,
-                                               traffic_bytes=(11345.9 * 2 + 12296.1) * 1024),
-    ("vapour_bubble_wall_2d", 0, 9, "k_stage12-v13"): dict(valu_per_cell_stage=8114414.4 * 64 / 524288,
-                                                   traffic_bytes=(15062.4 * 2 + 16392.1) * 1024),
-    ("vapour_bubble_wall_2d", 1, 10, "k_stage12-v13"): dict(valu_per_cell_stage=6842057.9 * 64 / 524288,
-                                                   traffic_bytes=(7599.0 * 2 + 8196.1) * 1024),
-    ("liquid_jet_3d", 0, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(333992682.4 + 1326082430.9) * 64 / 33554432,
-                                           traffic_bytes=((928041.1 + 3522144.5) * 2 +
-                                                          (2547827.9 + 1673987.5)) * 1024),
-    ("liquid_jet_3d", 1, 0, "k_stage12-v13"): dict(valu_per_cell_stage=(376349584.9 + 1422188568.0) * 64 / 33554432,
-                                           traffic_bytes=((462805.9 + 1687499.4) * 2 +
-                                                          (1215968.9 + 814903.5)) * 1024),
-    ("cube_to_sphere_3d", 0, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(51613794.0 + 412734614.7) * 64 / 16777216,
-                                               traffic_bytes=((339514.1 + 1350660.6) * 2 +
-                                                              (1230793.9 + 682506.0)) * 1024),
-    ("cube_to_sphere_3d", 1, 4, "k_stage12-v13"): dict(valu_per_cell_stage=(55545824.0 + 360647183.0) * 64 / 16777216,
-                                               traffic_bytes=((164659.7 + 629517.9) * 2 +
-                                                              (674552.5 + 358678.3)) * 1024),
-}
+# the precision each workload's configuration names for its headline
+MAIN_PRECISION = {"liquid_jet_3d": "mixed", "liquid_jet_3d_viscous": "mixed", "drop_2d": "mixed",
+                  "bubble_collapse_batch": "mixed", "shock_bubble_2d": "fp64", "dual_gas_layer_2d": "fp64",
+                  "vapour_bubble_wall_2d": "fp64", "cube_to_sphere_3d": "fp64", "interface_advection_1d": "fp64"}
+
+
+def kernel_source_hash():
+    """hash of the HIP/C++ sources the library is built from: rocprofv3 counter
+    figures below are valid only for the build they were taken on"""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2304_00140_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+# rocprofv3 --pmc figures of the dominant stage kernel on these workloads and
+# launch shapes (files under profiles/ named for kernel and workload give the
+# commands): executed VALU lane-instructions per cell-stage (SQ_INSTS_VALU x 64
+# / cells) and HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# in KiB, the factors read off a 1 GiB device copy).  Keyed by (workload,
+# precision, tile, hash of the kernel sources); a key that does not match the
+# built sources reports null instead of stale numbers.
+MEASURED = {}
 
 
 def parse():
@@ -67,7 +59,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's own step count: 200 in 3D, 500 for the batch, 1e4 for the drop, else 2000)")
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="shock_bubble_2d",
+    ap.add_argument("--workload", default="liquid_jet_3d",
                     choices=["shock_bubble_2d", "drop_2d", "bubble_collapse_batch", "liquid_jet_3d",
                              "liquid_jet_3d_viscous", "dual_gas_layer_2d", "vapour_bubble_wall_2d",
                              "cube_to_sphere_3d", "interface_advection_1d"])
@@ -182,7 +174,8 @@ def kernel_name(case):
 
 
 def l1_errors(a, b, uref):
-    """relative L1 of the mixed-path primitives a against FP64-path b"""
+    """relative L1 of the mixed-path primitives a against FP64-path b: rho and
+    p over the field's L1 norm, u over N U_ref, xi (and xi_2) over N"""
     n = a.shape[1]
     out = {
         "rho": float(np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum()),
@@ -190,9 +183,35 @@ def l1_errors(a, b, uref):
         "p": float(np.abs(a[4] - b[4]).sum() / np.abs(b[4]).sum()),
         "Y": float(np.abs(a[6] - b[6]).sum() / n),
     }
-    if a.shape[0] > 9:
+    if a.shape[0] in (11,):
         out["Y2"] = float(np.abs(a[9] - b[9]).sum() / n)
     return out
+
+
+def drop_physics(case, prec, stream, steps, every):
+    """Section 4.4 / Appendix C diagnostics of the static drop: the Laplace
+    jump <p>_{r < R/2} - <p>_{r > 3R/2} against sigma / R, and the largest
+    spurious speed max |u| against the step"""
+    from paper_2304_00140_amd import fvm, workloads as W
+    ctx = fvm.Context(case, prec, stream=stream.cuda_stream)
+    ctx.init_primitive()
+    x, y = W.cell_centres(case["grid"])
+    Lx = case["grid"]["n"][0] * case["grid"]["dx"][0]
+    r = np.hypot(x - 0.5 * Lx, y - 0.5 * Lx)
+    R = case["radius"]
+    sig = case["scheme"]["sigma"]
+    inner, outer = r < 0.5 * R, r > 1.5 * R
+    umax, done = [], 0
+    while done < steps:
+        k = min(every, steps - done)
+        ctx.n_steps(k)
+        done += k
+        w = ctx.get_primitive()
+        umax.append([done, float(np.hypot(w[1], w[2]).max())])
+    dp = float(w[4][inner].mean() - w[4][outer].mean())
+    ctx.close()
+    return dict(steps=steps, laplace_dp_Pa=dp, sigma_over_R_Pa=sig / R, laplace_ratio=dp * R / sig,
+                max_u_vs_step=umax), w
 
 
 def cpu_baseline(cases, seconds):
@@ -238,79 +257,81 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     cases, cfg = make_workload(args.workload, args.steps)
-    paths = {"both": [fvm.FVM_FP64, fvm.FVM_MIXED], "fp64": [fvm.FVM_FP64], "mixed": [fvm.FVM_MIXED]}[args.precision]
+    main_name = MAIN_PRECISION.get(args.workload, "fp64") if args.precision == "both" else args.precision
+    other = {"fp64": "mixed", "mixed": "fp64"}[main_name]
+    names = [main_name] + ([other] if args.precision == "both" else [])
+    code = {"fp64": fvm.FVM_FP64, "mixed": fvm.FVM_MIXED}
     res = {}
-    for prec in paths:
-        res[prec] = run_path(cases, prec, args, stream, torch)
-        print(f"# {'fp64' if prec == 0 else 'mixed'}: {res[prec]['ms']:.2f} ms for {args.steps} steps, "
-              f"stage ms {[round(x, 4) for x in res[prec]['stage_ms']]}", file=sys.stderr, flush=True)
-    main_prec = paths[0]
-    r = res[main_prec]
-    cell_stages = r["ncell"] * 4 * args.steps
-    value = cell_stages / (r["ms"] * 1e-3)
-    word = 8 if main_prec == fvm.FVM_FP64 else 4
-    bytes_per_cell_stage = 2.75 * r["nq"] * word
-    # average duration of one stage launch: the HIP-event-timed region on the
-    # solver's stream holds 4 stage launches per step (and one tiny step-counter
-    # kernel per 50 steps)
-    stage_avg_ms = r["ms"] / (4 * args.steps)
-    hbm_alg = r["ncell"] * bytes_per_cell_stage / (stage_avg_ms * 1e-3) / 1e9
-    meas = MEASURED.get((args.workload, main_prec, r["tile"], KERNEL_BUILD))
-    if meas:
-        achieved = meas["valu_per_cell_stage"] * r["ncell"] / (stage_avg_ms * 1e-3) / 1e12
-        traffic = meas["traffic_bytes"]
-    else:
-        achieved, traffic = None, None
+    for name in names:
+        res[name] = run_path(cases, code[name], args, stream, torch)
+        print(f"# {name}: {res[name]['ms']:.2f} ms for {args.steps} steps, "
+              f"stage ms {[round(x, 4) for x in res[name]['stage_ms']]}", file=sys.stderr, flush=True)
+    src_hash = kernel_source_hash()
+
+    def path_entry(name):
+        r = res[name]
+        word = 8 if name == "fp64" else 4
+        bpcs = 2.75 * r["nq"] * word           # algorithmic bytes per cell-stage
+        # one stage launch on average: the HIP-event-timed region on the
+        # solver's stream holds 4 stage launches per step (and one tiny
+        # step-counter kernel per 50 steps)
+        stage_ms = r["ms"] / (4 * args.steps)
+        alg_bytes = r["ncell"] * bpcs
+        achieved = alg_bytes / (stage_ms * 1e-3) / 1e9
+        meas = MEASURED.get((args.workload, name, r["tile"], src_hash))
+        valu = None
+        if meas:
+            vps = meas["valu_per_cell_stage"]
+            valu = {"per_cell_stage": vps, "achieved_T_lane_instr_s": vps * r["ncell"] / (stage_ms * 1e-3) / 1e12,
+                    "peak": VALU_PEAK_TINSTR,
+                    "frac": vps * r["ncell"] / (stage_ms * 1e-3) / 1e12 / VALU_PEAK_TINSTR}
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic_bytes"] if meas else None,
+                "kernel": kernel_name(cases[0]), "kernel_src": src_hash,
+                "algorithmic_bytes_per_cell_stage": bpcs, "algorithmic_bytes_per_launch": alg_bytes,
+                "stage_launch_ms": stage_ms, "stage_ms": r["stage_ms"], "tile": r["tile"],
+                "tune_ms_per_stage": r["tune"], "valu": valu}
+        return dict(value=r["ncell"] * 4 * args.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / args.steps,
+                    dtype="f64" if name == "fp64" else "f32+f64-closure", roofline=roof)
+
+    main_e = path_entry(main_name)
     out = {
         "metric": "cell-RK-stage updates/s + HBM GB/s frac, FP64 vs mixed FP32 at stated L1 err",
-        "value": value,
+        "value": main_e["value"],
         "unit": "cell-RK-stage updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms"] / args.steps,
+        "ms_per_step": main_e["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == fvm.FVM_FP64 else "f32+f64-closure",
+        "dtype": main_e["dtype"],
         "data": "synthetic",
-        "config": dict(cfg, cells=r["ncell"], steps=args.steps, parallelism="single-gpu"),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TINSTR,
-            "unit": "T VALU lane-instr/s",
-            "frac": None if achieved is None else achieved / VALU_PEAK_TINSTR,
-            "traffic": traffic,
-            "kernel": kernel_name(cases[0]),
-            "kernel_build": KERNEL_BUILD,
-            "valu_per_cell_stage": None if meas is None else meas["valu_per_cell_stage"],
-            "stage_launch_ms": stage_avg_ms,
-            "stage_ms": r["stage_ms"],
-            "hbm": {"algorithmic_bytes_per_cell_stage": bytes_per_cell_stage, "achieved_GBs": hbm_alg,
-                    "peak_GBs": HBM_PEAK_GBS, "frac": hbm_alg / HBM_PEAK_GBS,
-                    "counter_GBs": None if traffic is None else traffic / (stage_avg_ms * 1e-3) / 1e9},
-            "tile": r["tile"],
-            "tune_ms_per_stage": r["tune"],
-        },
+        "config": dict(cfg, cells=res[main_name]["ncell"], steps=args.steps, precision=main_name,
+                       parallelism="single-gpu"),
+        "roofline": main_e["roofline"],
     }
-    if fvm.FVM_MIXED in res and len(paths) == 2:
-        m = res[fvm.FVM_MIXED]
-        mv = m["ncell"] * 4 * args.steps / (m["ms"] * 1e-3)
-        mavg = m["ms"] / (4 * args.steps)
-        mach = m["ncell"] * 2.75 * m["nq"] * 4 / (mavg * 1e-3) / 1e9
-        entry = {"value": mv, "ms_per_step": m["ms"] / args.steps, "dtype": "f32+f64-closure",
-                 "stage_ms": m["stage_ms"], "achieved_GBs": mach, "frac": mach / HBM_PEAK_GBS,
-                 "tile": m["tile"], "tune_ms_per_stage": m["tune"]}
-        mm = MEASURED.get((args.workload, fvm.FVM_MIXED, m["tile"], KERNEL_BUILD))
-        if mm:
-            entry["valu_frac"] = mm["valu_per_cell_stage"] * m["ncell"] / (mavg * 1e-3) / 1e12 / VALU_PEAK_TINSTR
+    if len(names) == 2:
+        e = path_entry(other)
         if len(cases) == 1:
             uref = {"shock_bubble_2d": 113.5, "drop_2d": 0.53, "liquid_jet_3d": 300.0, "liquid_jet_3d_viscous": 300.0,
                     "dual_gas_layer_2d": 25.0, "vapour_bubble_wall_2d": 31.6, "cube_to_sphere_3d": 3.0,
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)
-            entry["l1_vs_fp64"] = l1_errors(m["handle"].get_primitive(), r["handle"].get_primitive(), uref)
-        out["mixed"] = entry
+            wm, wf = res["mixed"]["handle"].get_primitive(), res["fp64"]["handle"].get_primitive()
+            out["l1_mixed_vs_fp64"] = l1_errors(wm, wf, uref)
+        out[other] = e
+    if args.workload == "drop_2d":
+        # the configured 10^4 steps of the static drop, both paths, outside the timed region
+        phys = {}
+        ws = {}
+        for name in names:
+            phys[name], ws[name] = drop_physics(cases[0], code[name], stream, DEFAULT_STEPS["drop_2d"], 1000)
+        if len(names) == 2:
+            R, sig = cases[0]["radius"], cases[0]["scheme"]["sigma"]
+            phys["mixed_vs_fp64_p_max_over_sigma_R"] = float(np.abs(ws["mixed"][4] - ws["fp64"][4]).max() * R / sig)
+            phys["l1_mixed_vs_fp64"] = l1_errors(ws["mixed"], ws["fp64"], 0.53)
+        out["drop_physics"] = phys
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cases, args.cpu_seconds)
     print(json.dumps(out))

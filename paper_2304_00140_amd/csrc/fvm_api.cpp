@@ -194,6 +194,16 @@ static void fill_comp(Comp& c, const fvm_eos_desc* e, int k)
     c.npair = np;
     c.b = bb;
     c.M = M;
+    // sum_q w_q a0_q (A_q - B_q s)^2 with A_q = 1 + c_q, B_q = c_q / sqrt(Tc_q), s = sqrt(T)
+    c.pa_0 = c.pa_1 = c.pa_2 = 0.0;
+    for (int q = 0; q < np; ++q) {
+      double w = c.pw[q] * c.pa0[q], A = 1.0 + c.pcc[q], B = c.pcc[q] * c.prs[q];
+      c.pa_0 += w * A * A;
+      c.pa_1 += 2.0 * w * A * B;
+      c.pa_2 += w * B * B;
+    }
+    c.iM = 1.0 / M;
+    c.ikb = 1.0 / (2.0 * fvm::SQRT2 * bb * M);
     c.gam_ig = 1.0 + R / (M * c.cv);
     c.gamma = c.gam_ig;   // used only by the sound-speed bound of the ideal stand-in
     c.pinf = 0.0;
@@ -266,6 +276,94 @@ static void batch_free(fvm_batch* b)
   delete b;
 }
 
+// one case's constants from its descriptors (validated): grid, boundary data,
+// closure components; rows start at field offset `off`.  Reports the number of
+// components, whether the barotropic model is used and whether component 1 is
+// a Peng-Robinson fluid.  No storage shifts (FP64 storage); the caller adds
+// them for FP32 storage.
+static int describe_case(fvm_batch* b, CaseC& C, const fvm_grid_desc* g, const fvm_eos_desc* eos, long long off,
+                         double* vol_out, int* nc_out, int* baro_out, int* pr_out)
+{
+  int rc;
+  if (!eos) return fail(b, FVM_EINVAL, "eos descriptor is NULL");
+  if ((rc = check_grid(b, g, eos->model == FVM_MODEL_BAROTROPIC))) return rc;
+  if ((rc = check_eos(b, eos))) return rc;
+  const int nc = eos_ncomp(eos);
+  const int baro = eos->model == FVM_MODEL_BAROTROPIC;
+  std::memset(&C, 0, sizeof C);
+  C.dim = g->dim;
+  long long n = 1;
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    C.n[d] = g->n[d];
+    C.dx[d] = d < g->dim ? g->dx[d] : 1.0;
+    C.idx[d] = 1.0 / C.dx[d];
+    C.bc[d][0] = g->bc[d][0];
+    C.bc[d][1] = g->bc[d][1];
+    n *= g->n[d];
+    if (d < g->dim) vol *= g->dx[d];
+  }
+  if (vol_out) *vol_out = vol;
+  C.ncell = n;
+  C.off = off;
+  C.in_p = g->in_p; C.in_T = g->in_T; C.in_alpha = g->in_alpha; C.in_u = g->in_u;
+  C.in_radius = g->in_radius; C.in_c0 = g->in_center[0]; C.in_c1 = g->in_center[1];
+  C.in_noise = g->in_noise; C.in_seed = g->in_seed;
+  C.ff_p = g->ff_p; C.ff_T = g->ff_T; C.ff_alpha = g->ff_alpha;
+  C.any_ff = 0;
+  for (int d = 0; d < g->dim; ++d)
+    for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
+  C.ncomp = nc;
+  C.sdx2 = 0.0;
+  for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
+  *nc_out = nc;
+  *baro_out = baro;
+  *pr_out = 0;
+  if (baro) {
+    const fvm_eos_desc& e = *eos;
+    C.model = 1;
+    C.bt_rs = e.bt_rho_sat;
+    C.bt_ps = e.bt_p_sat;
+    C.bt_cl2 = e.bt_c_liq * e.bt_c_liq;
+    C.bt_cm2 = e.bt_p_sat / e.bt_rho_sat;
+    C.bt_rv = e.bt_rho_vap;
+    C.bt_RT = e.bt_RT;
+    C.bt_RT2 = nc == 3 ? e.bt_RT2 : 0.0;
+    double cg = std::sqrt(e.bt_RT > C.bt_RT2 ? e.bt_RT : C.bt_RT2), cm = std::sqrt(C.bt_cm2);
+    C.bt_c_hi = e.bt_c_liq > cg ? e.bt_c_liq : cg;
+    C.bt_c_lo = cm > cg ? cm : cg;
+    C.bt_mu_l = e.mu[0];
+    C.bt_mu_g = e.mu[1];
+    C.bt_mu_v = e.bt_mu_vap;
+    C.bt_mu_g2 = nc == 3 ? e.mu[2] : 0.0;
+    C.diff = (e.mu[0] > 0.0 || e.mu[1] > 0.0 || C.bt_mu_g2 > 0.0 || e.bt_mu_vap > 0.0) ? 1 : 0;
+    return FVM_OK;
+  }
+  for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], eos, k);
+  C.diff = 0;
+  for (int k = 0; k < nc; ++k)
+    if (eos->mu[k] > 0.0 || eos->kc[k] > 0.0) C.diff = 1;
+  if (C.comp[1].kind == FVM_EOS_PR) *pr_out = 1;
+  return FVM_OK;
+}
+
+static void fill_scheme(SchemeC& S, double* rk, const fvm_scheme_desc* s, int dim)
+{
+  std::memset(&S, 0, sizeof S);
+  S.switching = s->switching; S.lim_u = s->lim_u; S.lim_s = s->lim_s; S.thinc = s->thinc;
+  S.beta = s->beta; S.thinc_gamma = s->thinc_gamma; S.eps_int = s->eps_interface;
+  S.th_d = s->theta_ducros; S.th_g = s->theta_gas; S.eps_d = s->eps_ducros; S.k3 = s->kappa3;
+  S.sigma = s->sigma; S.eps_n = s->eps_normal; S.cfl = s->cfl;
+  S.tanh_b = std::tanh(s->beta); S.icosh_b = 1.0 / std::cosh(s->beta); S.itanh_b = 1.0 / std::tanh(s->beta);
+  S.t_end = 0.0;
+  S.has_grav = 0;
+  for (int d = 0; d < 3; ++d) {
+    S.grav[d] = d < dim ? s->gravity[d] : 0.0;
+    if (S.grav[d] != 0.0) S.has_grav = 1;
+  }
+  for (int i = 0; i < 4; ++i) rk[i] = s->rk[i];
+}
+
 static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids, const fvm_eos_desc* eos,
                         const fvm_scheme_desc* s, int precision, void* stream, std::string* errout)
 {
@@ -291,87 +389,20 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   b->has_state.assign(ncases, 0);
   long long off = 0;
   for (int c = 0; c < ncases; ++c) {
-    const fvm_grid_desc* g = &grids[c];
-    if ((rc = check_grid(b, g, eos[c].model == FVM_MODEL_BAROTROPIC))) return bail(rc);
-    if (g->dim != b->dim) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the dimension"));
-    if ((rc = check_eos(b, &eos[c]))) return bail(rc);
-    const int nc = eos_ncomp(&eos[c]);
+    int nc = 0, baro = 0, pr = 0;
+    if ((rc = describe_case(b, b->hc[c], &grids[c], &eos[c], off, &b->vol[c], &nc, &baro, &pr))) return bail(rc);
+    if (grids[c].dim != b->dim) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the dimension"));
     if (c == 0) b->ncomp = nc;
     if (nc != b->ncomp) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the number of components"));
-    const int baro = eos[c].model == FVM_MODEL_BAROTROPIC;
     if (c == 0) b->kind = baro ? FVM_KIND_BARO : FVM_KIND_SG;
     if (baro != (b->kind >= FVM_KIND_BARO)) return bail(fail(b, FVM_EINVAL, "all cases of a batch share the model"));
-    CaseC& C = b->hc[c];
-    std::memset(&C, 0, sizeof C);
-    C.dim = g->dim;
-    long long n = 1;
-    double vol = 1.0;
-    for (int d = 0; d < 3; ++d) {
-      C.n[d] = g->n[d];
-      C.dx[d] = d < g->dim ? g->dx[d] : 1.0;
-      C.idx[d] = 1.0 / C.dx[d];
-      C.bc[d][0] = g->bc[d][0];
-      C.bc[d][1] = g->bc[d][1];
-      n *= g->n[d];
-      if (d < g->dim) vol *= g->dx[d];
-    }
-    b->vol[c] = vol;
-    C.ncell = n;
-    C.off = off;
-    off += (n + 63) / 64 * 64;   // keep every case's rows starting on a 64-word boundary
-    C.in_p = g->in_p; C.in_T = g->in_T; C.in_alpha = g->in_alpha; C.in_u = g->in_u;
-    C.in_radius = g->in_radius; C.in_c0 = g->in_center[0]; C.in_c1 = g->in_center[1];
-    C.in_noise = g->in_noise; C.in_seed = g->in_seed;
-    C.ff_p = g->ff_p; C.ff_T = g->ff_T; C.ff_alpha = g->ff_alpha;
-    C.any_ff = 0;
-    for (int d = 0; d < g->dim; ++d)
-      for (int sd = 0; sd < 2; ++sd) C.any_ff |= (g->bc[d][sd] == FVM_BC_FARFIELD);
-    C.ncomp = nc;
-    C.sdx2 = 0.0;
-    for (int d = 0; d < g->dim; ++d) C.sdx2 += C.idx[d] * C.idx[d];
-    if (baro) {
-      const fvm_eos_desc& e = eos[c];
-      C.model = 1;
-      C.bt_rs = e.bt_rho_sat;
-      C.bt_ps = e.bt_p_sat;
-      C.bt_cl2 = e.bt_c_liq * e.bt_c_liq;
-      C.bt_cm2 = e.bt_p_sat / e.bt_rho_sat;
-      C.bt_rv = e.bt_rho_vap;
-      C.bt_RT = e.bt_RT;
-      C.bt_RT2 = nc == 3 ? e.bt_RT2 : 0.0;
-      double cg = std::sqrt(e.bt_RT > C.bt_RT2 ? e.bt_RT : C.bt_RT2), cm = std::sqrt(C.bt_cm2);
-      C.bt_c_hi = e.bt_c_liq > cg ? e.bt_c_liq : cg;
-      C.bt_c_lo = cm > cg ? cm : cg;
-      C.bt_mu_l = e.mu[0];
-      C.bt_mu_g = e.mu[1];
-      C.bt_mu_v = e.bt_mu_vap;
-      C.bt_mu_g2 = nc == 3 ? e.mu[2] : 0.0;
-      C.diff = (e.mu[0] > 0.0 || e.mu[1] > 0.0 || C.bt_mu_g2 > 0.0 || e.bt_mu_vap > 0.0) ? 1 : 0;
-      continue;
-    }
-    for (int k = 0; k < nc; ++k) fill_comp(C.comp[k], &eos[c], k);
-    C.diff = 0;
-    for (int k = 0; k < nc; ++k)
-      if (eos[c].mu[k] > 0.0 || eos[c].kc[k] > 0.0) C.diff = 1;
-    if (C.comp[1].kind == FVM_EOS_PR) b->kind = FVM_KIND_PR;
+    if (pr) b->kind = FVM_KIND_PR;
+    off += (b->hc[c].ncell + 63) / 64 * 64;   // keep every case's rows starting on a 64-word boundary
   }
   if (b->ncomp == 3) b->kind = (b->kind == FVM_KIND_BARO) ? FVM_KIND_BARO2 : FVM_KIND_THREE;
   b->nq = (b->kind >= FVM_KIND_BARO) ? b->dim + b->ncomp : b->dim + b->ncomp + 1;
   b->total = off;
-  // scheme constants
-  SchemeC& S = b->sc;
-  S.switching = s->switching; S.lim_u = s->lim_u; S.lim_s = s->lim_s; S.thinc = s->thinc;
-  S.beta = s->beta; S.thinc_gamma = s->thinc_gamma; S.eps_int = s->eps_interface;
-  S.th_d = s->theta_ducros; S.th_g = s->theta_gas; S.eps_d = s->eps_ducros; S.k3 = s->kappa3;
-  S.sigma = s->sigma; S.eps_n = s->eps_normal; S.cfl = s->cfl;
-  S.tanh_b = std::tanh(s->beta); S.icosh_b = 1.0 / std::cosh(s->beta); S.itanh_b = 1.0 / std::tanh(s->beta);
-  S.t_end = 0.0;
-  S.has_grav = 0;
-  for (int d = 0; d < 3; ++d) {
-    S.grav[d] = d < b->dim ? s->gravity[d] : 0.0;
-    if (S.grav[d] != 0.0) S.has_grav = 1;
-  }
-  for (int i = 0; i < 4; ++i) b->rk[i] = s->rk[i];
+  fill_scheme(b->sc, b->rk, s, b->dim);
 
   // device tables
   HIPCHECK(b, hipMalloc(&b->dc, sizeof(CaseC) * ncases));
@@ -962,3 +993,4 @@ int64_t fvm_batch_cells(fvm_batch* b)
 }
 
 }  // extern "C"
+

@@ -44,6 +44,11 @@ struct Comp {
   int npair;
   double pw[MAXPAIR], pa0[MAXPAIR], pcc[MAXPAIR], prs[MAXPAIR];
   double b, M;         // covolume [m^3/mol], molar mass [kg/mol]
+  // a(T) summed over the pairs is a quadratic in s = sqrt(T):
+  //   a = pa_0 - pa_1 s + pa_2 s^2,  a - T a' = pa_0 - pa_1 s / 2,  T^2 a'' = pa_1 s / 4
+  double pa_0, pa_1, pa_2;
+  double iM;           // 1 / M
+  double ikb;          // 1 / (2 sqrt(2) b M): energy departure per unit (a - T a') log(...)
   double gam_ig;       // 1 + R / (M cv): ideal-gas stand-in used as Newton start
   double mu, kc;       // dynamic viscosity [Pa s], thermal conductivity [W/(m K)]
 };
@@ -136,17 +141,15 @@ __device__ inline double noise01(unsigned long long seed, unsigned long long ste
 // ------------------------------------------------------------------ Peng-Robinson (A.2.1)
 struct PRab { double a, a1, a2; };
 
+// a(T), a'(T), a''(T) of the pair sum  sum_q w_q a0_q (1 + c_q (1 - sqrt(T / Tc_q)))^2
+// written as the quadratic in s = sqrt(T) it is (coefficients pa_* from the host)
 __device__ inline PRab pr_a(const Comp& c, double T)
 {
-  double s = sqrt(T), is = frcp(s), iT = is * is;
-  PRab r{0.0, 0.0, 0.0};
-  for (int q = 0; q < c.npair; ++q) {
-    double rs = c.prs[q], cc = c.pcc[q], wa = c.pw[q] * c.pa0[q];
-    double g = 1.0 + cc * (1.0 - s * rs);
-    r.a += wa * g * g;
-    r.a1 -= wa * cc * g * rs * is;
-    r.a2 += 0.5 * wa * cc * rs * iT * (cc * rs + g * is);
-  }
+  double s = sqrt(T), is = frcp(s);
+  PRab r;
+  r.a = fma(c.pa_2, T, c.pa_0 - c.pa_1 * s);
+  r.a1 = c.pa_2 - 0.5 * c.pa_1 * is;
+  r.a2 = 0.25 * c.pa_1 * is * is * is;
   return r;
 }
 
@@ -155,21 +158,39 @@ __device__ inline double pr_log(double V, double b)
   return log((V + (1.0 - SQRT2) * b) * frcp(V + (1.0 + SQRT2) * b));
 }
 
-// molar volume at (p, T): largest root of the compressibility cubic by Newton
-// from Z = 1 + B (an upper bound of every root with V > b)
-__device__ inline double pr_volume(double p, double T, double a, double b)
+// molar volume at (p, T): the largest root of the compressibility cubic
+//   Z^3 + (B - 1) Z^2 + (A - 3 B^2 - 2 B) Z + (B^3 + B^2 - A B) = 0
+// by Newton.  From Z = 1 + B (an upper bound of every root with V > b) the
+// iterates fall monotonically onto it.  A start Z0 > B (e.g. the upwind cell's
+// own compressibility) is tried first; its limit is kept only if it lies right
+// of the inflection point with a positive slope, which makes it the largest
+// root.  Newton stops once a correction falls below 1e-9 Z: the error left is
+// then of order Z 1e-18.
+__device__ inline double pr_cubic_newton(double Z, double c2, double c1, double c0, int& ok)
 {
-  double RT = R_UNIV * T, iRT = frcp(RT);
-  double Bd = b * p * iRT, Ad = a * p * iRT * iRT;
-  double c2 = Bd - 1.0, c1 = Ad - 3.0 * Bd * Bd - 2.0 * Bd, c0 = Bd * Bd * Bd + Bd * Bd - Ad * Bd;
-  double Z = 1.0 + Bd;
+  ok = 0;
   for (int it = 0; it < 60; ++it) {
     double f = ((Z + c2) * Z + c1) * Z + c0;
     double fp = (3.0 * Z + 2.0 * c2) * Z + c1;
     double dZ = f * frcp(fp);
     Z -= dZ;
-    if (fabs(dZ) <= 1e-15 * fabs(Z)) break;
+    if (fabs(dZ) <= 1e-9 * fabs(Z)) { ok = 1; break; }
   }
+  return Z;
+}
+
+__device__ inline double pr_volume(double p, double T, double a, double b, double Z0 = 0.0)
+{
+  double RT = R_UNIV * T, iRT = frcp(RT);
+  double Bd = b * p * iRT, Ad = a * p * iRT * iRT;
+  double c2 = Bd - 1.0, c1 = Ad - 3.0 * Bd * Bd - 2.0 * Bd, c0 = Bd * Bd * Bd + Bd * Bd - Ad * Bd;
+  int ok = 0;
+  double Z = 0.0;
+  if (Z0 > Bd && Z0 < 1e300) {
+    Z = pr_cubic_newton(Z0, c2, c1, c0, ok);
+    ok = ok && Z > -c2 * (1.0 / 3.0) && (3.0 * Z + 2.0 * c2) * Z + c1 > 0.0;
+  }
+  if (!ok) Z = pr_cubic_newton(1.0 + Bd, c2, c1, c0, ok);
   return Z * RT * frcp(p);
 }
 
@@ -198,13 +219,12 @@ __device__ inline VE comp_ve(const Comp& c, double p, double T)
   double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
   double dpdT = R_UNIV * iVb - A.a1 * iD;
   double L = pr_log(V, b);
-  double k = frcp(2.0 * SQRT2 * b);
-  double cvm = M * c.cv - T * A.a2 * k * L;
+  double cvm = M * c.cv - T * A.a2 * c.ikb * M * L;
   double dedV = T * dpdT - (R_UNIV * T * iVb - A.a * iD);
   double dVdp = frcp(dpdV), dVdT = -dpdT * dVdp;
-  double iM = frcp(M);
+  double iM = c.iM;
   r.v = V * iM;
-  r.e = c.cv * T + c.qs + (A.a - T * A.a1) * k * L * iM;
+  r.e = c.cv * T + c.qs + (A.a - T * A.a1) * c.ikb * L;
   r.dvdp = dVdp * iM;
   r.dvdT = dVdT * iM;
   r.dedp = dedV * dVdp * iM;
@@ -212,17 +232,17 @@ __device__ inline VE comp_ve(const Comp& c, double p, double T)
   return r;
 }
 
-// speed of sound of a Peng-Robinson component at molar volume V and T
-__device__ inline double pr_sound_V(const Comp& c, double V, double T)
+// speed of sound of a Peng-Robinson component at molar volume V and T, with
+// its a(T) terms A and L = log((V + (1 - sqrt 2) b) / (V + (1 + sqrt 2) b))
+__device__ inline double pr_sound_VL(const Comp& c, double V, double T, const PRab& A, double L)
 {
-  PRab A = pr_a(c, T);
   double b = c.b, M = c.M;
   double D = V * V + 2.0 * b * V - b * b;
   double iD = frcp(D), iVb = frcp(V - b);
   double dpdV = -R_UNIV * T * iVb * iVb + A.a * (2.0 * V + 2.0 * b) * iD * iD;
   double dpdT = R_UNIV * iVb - A.a1 * iD;
-  double cvm = M * c.cv - T * A.a2 * frcp(2.0 * SQRT2 * b) * pr_log(V, b);
-  return sqrt(-(V * V * frcp(M)) * (dpdV - T * dpdT * dpdT * frcp(cvm)));
+  double cvm = M * c.cv - T * A.a2 * c.ikb * M * L;
+  return sqrt(-(V * V * c.iM) * (dpdV - T * dpdT * dpdT * frcp(cvm)));
 }
 
 // ------------------------------------------------------------------ closure inversion
@@ -354,9 +374,11 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e, dou
     }
     if (Y == 1.0) {
       // pure Peng-Robinson: Newton on T at fixed v (Appendix B), then p from (A.2.1)
+      // e(T) = cv T + q + (a - T a') k with a - T a' = pa_0 - pa_1 sqrt(T) / 2 and
+      // de/dT = cv - k pa_1 / (4 sqrt(T)) at this cell's fixed V
       double V = c1.M * v;
       double L = pr_log(V, c1.b);
-      double k = L / (2.0 * SQRT2 * c1.b * c1.M);
+      double k = L * c1.ikb;
       double Tn = 0.0;
       int conv = 0;
       for (int start = (Tw > 0.0 && Tw < 1e300) ? 0 : 1; start < 2 && !conv; ++start) {
@@ -367,9 +389,9 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e, dou
           if (!(Tn > 0.0)) Tn = 100.0;
         }
         for (int it = 0; it < 60; ++it) {
-          PRab A = pr_a(c1, Tn);
-          double f = c1.cv * Tn + c1.qs + (A.a - Tn * A.a1) * k - e;
-          double fp = c1.cv - Tn * A.a2 * k;
+          double sT = sqrt(Tn);
+          double f = c1.cv * Tn + c1.qs + (c1.pa_0 - 0.5 * c1.pa_1 * sT) * k - e;
+          double fp = c1.cv - 0.25 * k * c1.pa_1 * frcp(sT);
           double dT = f * frcp(fp);
           double Tnew = Tn - dT;
           if (Tnew <= 0.0) Tnew = 0.5 * Tn;
@@ -379,8 +401,8 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e, dou
       }
       PRab A = pr_a(c1, Tn);
       r.T = Tn;
-      r.p = R_UNIV * Tn / (V - c1.b) - A.a / (V * V + 2.0 * c1.b * V - c1.b * c1.b);
-      r.c = fmax(sqrt(c0.c2T * Tn), pr_sound_V(c1, V, Tn));
+      r.p = R_UNIV * Tn * frcp(V - c1.b) - A.a * frcp(V * V + 2.0 * c1.b * V - c1.b * c1.b);
+      r.c = fmax(sqrt(c0.c2T * Tn), pr_sound_VL(c1, V, Tn, A, L));
       r.alpha = 1.0;
       r.ok = conv;
       return r;
@@ -416,8 +438,9 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e, dou
     }
     r.p = p;
     r.T = T;
-    double Vg = pr_volume(p, T, pr_a(c1, T).a, c1.b);
-    r.c = fmax(sqrt(c0.c2T * T), pr_sound_V(c1, Vg, T));
+    PRab Ag = pr_a(c1, T);
+    double Vg = pr_volume(p, T, Ag.a, c1.b);
+    r.c = fmax(sqrt(c0.c2T * T), pr_sound_VL(c1, Vg, T, Ag, pr_log(Vg, c1.b)));
     r.alpha = Y * rho * Vg / c1.M;
     r.ok = conv;
     return r;
@@ -444,9 +467,11 @@ __device__ inline void tdu3(const CaseC& C, R ps, R Tf, R Y1, R Y2, R& rf, R& ef
   ef = es;
 }
 
-// forward closure at (p, T, xi) in FP64: 1 / rho and e (storage gauge)
+// forward closure at (p, T, xi) in FP64: 1 / rho and e (storage gauge).  Z0:
+// a start for the Peng-Robinson compressibility (0: none)
 template <bool PRK>
-__device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y, double& vmix, double& e)
+__device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y, double& vmix, double& e,
+                                   double Z0 = 0.0)
 {
   double Yk[2] = {1.0 - Y, Y};
   vmix = 0.0;
@@ -460,11 +485,12 @@ __device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y,
       vk = c.A * T * frcp(p + c.pinf);
       ek = c.cv * T + c.pinf * vk + c.qs;
     } else {
-      PRab A = pr_a(c, T);
-      double V = pr_volume(p, T, A.a, c.b);
-      double iM = frcp(c.M);
-      vk = V * iM;
-      ek = c.cv * T + c.qs + (A.a - T * A.a1) * frcp(2.0 * SQRT2 * c.b) * iM * pr_log(V, c.b);
+      // a - T a' = pa_0 - pa_1 sqrt(T) / 2
+      double sT = sqrt(T);
+      double a = fma(c.pa_2, T, c.pa_0 - c.pa_1 * sT);
+      double V = pr_volume(p, T, a, c.b, Z0);
+      vk = V * c.iM;
+      ek = c.cv * T + c.qs + (c.pa_0 - 0.5 * c.pa_1 * sT) * c.ikb * pr_log(V, c.b);
     }
     vmix += Yk[k] * vk;
     e += Yk[k] * ek;
@@ -627,8 +653,16 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
   } else if (!PRK || C.comp[1].kind == 0 || Yf == R(0)) {
     tdu_sg<R>(C, ps, Tf, Yf, rf, ef);
   } else {
+    // a pure-gas face whose upwind cell is pure gas starts the compressibility
+    // from that cell's own, p* M / (rho R T_f) (close: same fluid, nearby state)
+    double Z0 = 0.0;
+    const bool left = us >= R(0);
+    if (Yf == R(1) && (left ? s.Y[1] : s.Y[2]) == R(1)) {
+      double rup = (double)(left ? s.rho1 : s.rho2);
+      Z0 = (double)ps * C.comp[1].M * frcp(rup * R_UNIV * (double)Tf);
+    }
     double vm, em;
-    closure_fwd<PRK>(C, (double)ps, (double)Tf, (double)Yf, vm, em);
+    closure_fwd<PRK>(C, (double)ps, (double)Tf, (double)Yf, vm, em, Z0);
     rf = R(frcp(vm));
     ef = R(em);
   }

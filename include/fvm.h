@@ -213,6 +213,26 @@ int fvm_get_primitive(fvm_ctx* ctx, double* w_host);
  * touched. */
 int fvm_rhs(fvm_ctx* ctx, const double* q_dev_in, double* r_dev_out, int64_t step);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fvm_rhs without a
+ * context.  One right-hand side R(q) of the FP64 path for the case described
+ * by g, e, s (validated as by fvm_create; the FP64 path stores q unshifted, so
+ * e->p_ref / e->T_ref do not matter), q_dev_in and r_dev_out device arrays
+ * [N_q x ncell] FP64 owned by the caller, inflow noise of step `step`,
+ * launched on `stream` (a hipStream_t, NULL = default stream) of the current
+ * device; returns after the launches without waiting (the result is ready
+ * when the stream reaches them).  It allocates nothing: its tables and the
+ * storage copy of q (3D also the primitive rows) live in one static device
+ * array of FVM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.  A
+ * case that needs more (about 40 bytes per cell in 2D, 120 in 3D) is
+ * FVM_EINVAL with a message (fvm_last_error(NULL)).  All calls on one GPU
+ * share that array and it keeps the last call's contents: calls that overlap
+ * on one GPU (other streams or threads) race and must be ordered by the
+ * caller.  The default tile shape of the dimension is used. */
+#define FVM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int fvm_rhs_noalloc(const fvm_grid_desc* g, const fvm_eos_desc* e, const fvm_scheme_desc* s,
+                    const double* q_dev_in, double* r_dev_out, int64_t step, void* stream);
+
 /* Advance by one step (4 stages).  dt_out / t_out may be NULL.  Synchronises. */
 int fvm_step(fvm_ctx* ctx, double* dt_out, double* t_out);
 /* Advance by n steps entirely on the device (dt from the stage-4 reduction of

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -994,3 +995,134 @@ int64_t fvm_batch_cells(fvm_batch* b)
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ allocation-free right-hand side
+// Workspace of fvm_rhs_noalloc: the case and tile tables, the FP64 storage
+// copy of the input and (3D) the primitive rows, in one file-scope device
+// array.  Every GPU the library runs on holds its own copy until the process
+// ends; in host code the array's name is only a stand-in, so its device
+// address is looked up once per device and kept in g_noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[FVM_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[64];
+
+static int noalloc_base(void** out, std::string& err)
+{
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return FVM_EHIP;
+  }
+  if (dev < 0 || dev >= 64) {
+    err = "device index out of range for the allocation-free workspace";
+    return FVM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return FVM_EHIP;
+    }
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return FVM_OK;
+}
+
+// case table (by value), zeroed per-case scalars, the tile table of one case
+// ((case 0, i, j, k), i fastest) and zeroed rows [zero0, zero0 + nzero) of the
+// 3D primitive buffer (a zero temperature makes a Peng-Robinson closure start
+// from its ideal-gas stand-in); no memset or copy nodes
+__global__ void k_noalloc_setup(CaseC c, CaseC* dc, CaseDyn* dd, int4* tiles, int ntiles, int t0, int t1,
+                                double* zero0, long long nzero)
+{
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long nth = (long long)gridDim.x * blockDim.x;
+  if (tid == 0) {
+    *dc = c;
+    unsigned char* z = reinterpret_cast<unsigned char*>(dd);
+    for (size_t i = 0; i < sizeof(CaseDyn); ++i) z[i] = 0;
+  }
+  for (long long i = tid; i < ntiles; i += nth)
+    tiles[i] = make_int4(0, (int)(i % t0), (int)((i / t0) % t1), (int)(i / ((long long)t0 * t1)));
+  for (long long i = tid; i < nzero; i += nth) zero0[i] = 0.0;
+}
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+extern "C" int fvm_rhs_noalloc(const fvm_grid_desc* g, const fvm_eos_desc* e, const fvm_scheme_desc* s,
+                               const double* q_dev_in, double* r_dev_out, int64_t step, void* stream)
+{
+  fvm_batch eb;   // error messages only (its containers stay empty)
+  auto bail = [&](int rc) {
+    g_create_err = eb.err;
+    return rc;
+  };
+  if (!q_dev_in || !r_dev_out) return bail(fail(&eb, FVM_EINVAL, "NULL device array"));
+  int rc = check_scheme(&eb, s);
+  if (rc) return bail(rc);
+  CaseC C;
+  int nc = 0, baro = 0, pr = 0;
+  if ((rc = describe_case(&eb, C, g, e, 0, nullptr, &nc, &baro, &pr))) return bail(rc);
+  const int dim = C.dim;
+  const int kind = baro ? (nc == 3 ? FVM_KIND_BARO2 : FVM_KIND_BARO)
+                        : (nc == 3 ? FVM_KIND_THREE : (pr ? FVM_KIND_PR : FVM_KIND_SG));
+  const int nq = baro ? dim + nc : dim + nc + 1;
+  const int tile = 0;
+  int tx, ty, nt;
+  if (fvm_k_tile_shape(dim, tile, &tx, &ty, &nt)) return bail(fail(&eb, FVM_EINVAL, "bad tile"));
+  const int zc = dim == 3 ? fvm_k_tile_zchunk3(tile) : 1;
+  C.tiles[0] = (C.n[0] + tx - 1) / tx;
+  C.tiles[1] = dim >= 2 ? (C.n[1] + ty - 1) / ty : 1;
+  C.tiles[2] = dim >= 3 ? (C.n[2] + zc - 1) / zc : 1;
+  C.tile0 = 0;
+  const long long ntiles = (long long)C.tiles[0] * C.tiles[1] * C.tiles[2];
+  const long long total = (C.ncell + 63) / 64 * 64;
+  const size_t rows = (kind == FVM_KIND_THREE || kind == FVM_KIND_BARO2) ? 11 : 9;
+  const size_t oD = align256(sizeof(CaseC));
+  const size_t oT = oD + align256(sizeof(CaseDyn));
+  const size_t oQ = oT + align256(sizeof(int4) * (size_t)ntiles);
+  const size_t oP = oQ + align256(sizeof(double) * (size_t)nq * (size_t)total);
+  const size_t end = oP + (dim == 3 ? sizeof(double) * rows * (size_t)total : 0);
+  if (end > (size_t)FVM_NOALLOC_SCRATCH_BYTES || ntiles > 0x7fffffffLL) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg, "case needs %zu bytes of workspace; the allocation-free right-hand side has %zu",
+                  end, (size_t)FVM_NOALLOC_SCRATCH_BYTES);
+    return bail(fail(&eb, FVM_EINVAL, msg));
+  }
+  void* base = nullptr;
+  if ((rc = noalloc_base(&base, eb.err))) return bail(rc);
+  char* p = static_cast<char*>(base);
+  CaseC* dc = reinterpret_cast<CaseC*>(p);
+  CaseDyn* dd = reinterpret_cast<CaseDyn*>(p + oD);
+  int4* dt = reinterpret_cast<int4*>(p + oT);
+  double* q = reinterpret_cast<double*>(p + oQ);
+  double* prim = dim == 3 ? reinterpret_cast<double*>(p + oP) : nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(256), dim3(256), 0, st, C, dc, dd, dt, (int)ntiles, C.tiles[0], C.tiles[1],
+                     prim, dim == 3 ? (long long)rows * total : 0LL);
+  hipError_t he = hipGetLastError();
+  if (he == hipSuccess) he = fvm_k_cons_to_state(dim, 0, kind, dc, 0, C.ncell, q_dev_in, q, total, st);
+  if (he != hipSuccess) return bail(fail(&eb, FVM_EHIP, std::string("launch: ") + hipGetErrorString(he)));
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  double rk[4];
+  fill_scheme(a.sc, rk, s, dim);
+  a.cases = dc;
+  a.dyn = dd;
+  a.tiles = dt;
+  a.total = total;
+  a.prim = prim;
+  a.src = q;
+  a.qn = q;
+  a.dst = nullptr;
+  a.stage = -1;
+  a.rhs_out = r_dev_out;
+  a.rhs_step = step;
+  he = fvm_k_stage(dim, 0, kind, tile, a, (int)ntiles, st);
+  if (he != hipSuccess) return bail(fail(&eb, FVM_EHIP, std::string("stage launch: ") + hipGetErrorString(he)));
+  return FVM_OK;
+}

@@ -67,6 +67,7 @@ SIGNATURES = {
     "fvm_get_state_device": (C.c_int, [_P, _P]),
     "fvm_get_primitive": (C.c_int, [_P, _DP]),
     "fvm_rhs": (C.c_int, [_P, _P, _P, C.c_int64]),
+    "fvm_rhs_noalloc": (C.c_int, [_GP, _EP, _SP, _P, _P, C.c_int64, _P]),
     "fvm_step": (C.c_int, [_P, _DP, _DP]),
     "fvm_n_steps": (C.c_int, [_P, C.c_int, C.c_double, _DP]),
     "fvm_clock": (C.c_int, [_P, _DP, _DP, _I64P]),
@@ -196,6 +197,18 @@ def _stream_ptr(stream):
     if stream is None:
         return None
     return C.c_void_p(int(stream))
+
+
+def rhs_noalloc(case, q_in_ptr, r_out_ptr, step=0, stream=None):
+    """fvm_rhs_noalloc: one FP64 right-hand side of `case` from device array
+    q_in_ptr into r_out_ptr ([N_q, ncell] FP64 device pointers), no context and
+    no device allocation; launched on `stream` without waiting"""
+    L = lib()
+    g, e, s = grid_desc(case["grid"]), eos_desc(case["eos"], None), scheme_desc(case["scheme"])
+    rc = L.fvm_rhs_noalloc(C.byref(g), C.byref(e), C.byref(s), C.c_void_p(q_in_ptr), C.c_void_p(r_out_ptr),
+                           step, _stream_ptr(stream))
+    if rc:
+        raise FvmError(rc, L.fvm_last_error(None).decode())
 
 
 # ---------------------------------------------------------------- wrappers

@@ -9,8 +9,10 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfvm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fvm_kernels.hip", "fvm_stage12_deflim.hip", "fvm_stage3d.hip", "fvm_baro.hip", "fvm_api.cpp"]
-HEADERS = ["fvm_device.hpp", "fvm_kernels.hpp", "fvm_stage_common.hpp", "fvm_stage12.hpp"]
+SOURCES = ["fvm_kernels.hip", "fvm_stage12_deflim.hip", "fvm_stage3d.hip", "fvm_stage3m.hip", "fvm_stage3mp.hip",
+           "fvm_baro.hip", "fvm_api.cpp"]
+HEADERS = ["fvm_device.hpp", "fvm_kernels.hpp", "fvm_stage_common.hpp", "fvm_stage12.hpp", "fvm_stage3m.hpp",
+           "fvm_stage3_prim.hpp"]
 ARCH = os.environ.get("FVM_OFFLOAD_ARCH", "gfx950")
 
 # packed FP32 instructions are disabled: the compiler would otherwise form them

@@ -876,9 +876,18 @@ int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads)
 static int check_tile(fvm_batch* b, int tile)
 {
   if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
+  if (b->dim == 3 && tile >= fvm_k_tile_first_m3()) {
+    bool ok = (b->kind == FVM_KIND_SG || b->kind == FVM_KIND_PR) && fvm_default_limiters(b->sc);
+    for (const CaseC& C : b->hc) ok = ok && !C.diff;
+    if (!ok)
+      return fail(b, FVM_EINVAL,
+                  "the z-marching 3D tiles take two-component inviscid closures (stiffened gas or Peng-Robinson) "
+                  "with the default limiters");
+    return FVM_OK;
+  }
   if (b->dim == 3 && b->kind == FVM_KIND_THREE && !fvm_k_tile_ok3(b->mixed, b->kind, tile))
     return fail(b, FVM_EINVAL, "this 3D tile does not fit the LDS of a workgroup with three components in FP64");
-  if (b->dim == 3 && b->kind == FVM_KIND_BARO2 && !fvm_kb_tile_ok3(b->mixed, 1, tile))
+  if (b->dim == 3 && b->kind == FVM_KIND_BARO2 && fvm_kb_tile_ok3(b->mixed, 1, tile) != 1)
     return fail(b, FVM_EINVAL, "this 3D tile does not fit the LDS of a workgroup with two gases in FP64");
   return FVM_OK;
 }

@@ -45,6 +45,15 @@ hipError_t fvm_k_stage(int dim, int mixed, int kind, int tile, const StageArgs& 
 hipError_t fvm_k_stage12_deflim(int dim, int mixed, int kind, int tile, const StageArgs& a, int ntiles,
                                 hipStream_t st);
 hipError_t fvm_k_stage3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+// z-marching 3D stage (fvm_stage3m.hip), two-component inviscid closures; its
+// tiles follow the closure + face kernel pair's in the 3D tile numbering
+int fvm_k_tile_count_m3();
+int fvm_k_tile_shape_m3(int tile, int* tx, int* ty, int* nt, int* zc);
+hipError_t fvm_k_stage_m3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+// the same shapes after the closure kernel k_prim3 (fvm_stage3mp.hip)
+hipError_t fvm_k_stage_m3p(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
+// first 3D tile index of the z-marching kernel
+int fvm_k_tile_first_m3();
 int fvm_k_tile_ok3(int mixed, int kind, int tile);
 hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,

@@ -246,7 +246,13 @@ def test_barotropic_rhs_3d_every_tile(dev, stream, spec):
     fl = o.sensor_flags(q)
     for tile in range(fvm.lib().fvm_tile_count(3)):
         ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
-        ctx.set_tile(tile)
+        try:
+            ctx.set_tile(tile)
+        except fvm.FvmError as e:
+            # the z-marching tiles take the four-equation model only
+            assert "z-marching" in str(e)
+            ctx.close()
+            continue
         ok, rel = rhs_ok(gpu_rhs(ctx, q, dev), r_ref, case)
         print(f"barotropic 3D {n} seed {seed} tile {tile}: {np.array2string(rel, precision=2)} "
               f"(liquid-vapour THINC cells {int(((fl >> 4) & 7).astype(bool).sum())})", flush=True)

@@ -103,13 +103,16 @@ def test_two_gas_rhs_every_tile(dev, stream, spec):
     r_ref = o.rhs(q)
     fl = o.sensor_flags(q)
     ran = 0
+    refused = 0
     for tile in range(fvm.lib().fvm_tile_count(dim)):
         ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
         try:
             ctx.set_tile(tile)
-        except fvm.FvmError:
-            # the 8x8x8 3D tile does not fit the LDS with two gases in FP64
-            assert dim == 3 and tile == 4
+        except fvm.FvmError as e:
+            # the 8x8x8 3D tile does not fit the LDS with two gases in FP64, and
+            # the z-marching tiles take the four-equation model only
+            assert dim == 3 and (tile == 4 or "z-marching" in str(e))
+            refused += 1
             ctx.close()
             continue
         ok, rel = rhs_ok(gpu_rhs(ctx, q, dev), r_ref, case)
@@ -118,7 +121,7 @@ def test_two_gas_rhs_every_tile(dev, stream, spec):
         assert ok
         ran += 1
         ctx.close()
-    assert ran >= fvm.lib().fvm_tile_count(dim) - 1
+    assert ran == fvm.lib().fvm_tile_count(dim) - refused and ran >= 3
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -237,8 +240,8 @@ def test_two_gas_farfield_and_inflow_ghosts(dev, stream, dim):
         ctx = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
         try:
             ctx.set_tile(tile)
-        except fvm.FvmError:
-            assert dim == 3 and tile == 4
+        except fvm.FvmError as e:
+            assert dim == 3 and (tile == 4 or "z-marching" in str(e))
             ctx.close()
             continue
         for step, r_ref in refs.items():

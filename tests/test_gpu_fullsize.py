@@ -53,8 +53,18 @@ def bench_context(case, prec, stream):
     return h, tile
 
 
-def l1(a, b):
-    return max(np.abs(a[f] - b[f]).sum() / np.abs(b[f]).sum() for f in (0, 4))
+def l1_fields(a, b, uref):
+    """relative L1 of mixed-path primitives a against FP64-path b per field:
+    rho and p over the field's L1 norm, the velocity over N U_ref, xi (and xi_2
+    with three components) over N"""
+    n = a.shape[1]
+    out = {"rho": np.abs(a[0] - b[0]).sum() / np.abs(b[0]).sum(),
+           "u": np.abs(a[1:4] - b[1:4]).sum() / (n * uref),
+           "p": np.abs(a[4] - b[4]).sum() / np.abs(b[4]).sum(),
+           "Y": np.abs(a[6] - b[6]).sum() / n}
+    if a.shape[0] == 11:
+        out["Y2"] = np.abs(a[9] - b[9]).sum() / n
+    return out
 
 
 FULL_2D = {"shock_bubble_2d": lambda s: W.shock_bubble_2d(1024, 256, s),
@@ -79,9 +89,9 @@ def test_2d_workload_full_size(dev, stream, name, steps, uref):
     assert err < 1e-10
     m, mtile = bench_context(case, fvm.FVM_MIXED, stream)
     m.n_steps(steps)
-    e1 = l1(m.get_primitive(), h.get_primitive())
-    print(f"{name} mixed (tile {mtile}) vs fp64 L1 rho/p: {e1:.2e}", flush=True)
-    assert e1 < 1e-4
+    e1 = l1_fields(m.get_primitive(), h.get_primitive(), uref)
+    print(f"{name} mixed (tile {mtile}) vs fp64 L1 {e1}", flush=True)
+    assert max(e1.values()) < 1e-4
 
 
 def test_bubble_collapse_batch_full_size(dev, stream):
@@ -165,6 +175,82 @@ def test_liquid_jet_full_size_sampled_windows(dev, stream, viscous):
     del qd, rd
     mx, mtile = bench_context(case, fvm.FVM_MIXED, stream)
     mx.n_steps(20)
-    e1 = l1(mx.get_primitive(), h.get_primitive())
-    print(f"jet mixed (tile {mtile}) vs fp64 L1 rho/p: {e1:.2e}", flush=True)
-    assert e1 < 1e-4
+    e1 = l1_fields(mx.get_primitive(), h.get_primitive(), 300.0)
+    print(f"jet mixed (tile {mtile}) vs fp64 L1 {e1}", flush=True)
+    assert max(e1.values()) < 1e-4
+
+
+def test_shock_bubble_mixed_at_its_configured_length(dev, stream):
+    """the shock-bubble configuration's 2000 steps: the mixed path against the
+    FP64 path in rho, u (U_ref = 113.5 m/s), p and xi.  The Richtmyer-Meshkov
+    roll-up of the bubble amplifies small differences: the FP64 path started
+    from its own initial state rounded to FP32 is measured beside it as the
+    dynamics' own response to a rounding-sized perturbation.  Bar per field:
+    1e-4, or twice that measured sensitivity where larger."""
+    from paper_2304_00140_amd import fvm
+    case = W.shock_bubble_2d(1024, 256, 2000)
+    h, htile = bench_context(case, fvm.FVM_FP64, stream)
+    m, _ = bench_context(case, fvm.FVM_MIXED, stream)
+    g = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    g.set_tile(htile)
+    g.set_state(h.get_state().astype(np.float32).astype(np.float64))
+    for c in (h, m, g):
+        c.n_steps(2000)
+    wf = h.get_primitive()
+    e = l1_fields(m.get_primitive(), wf, 113.5)
+    es = l1_fields(g.get_primitive(), wf, 113.5)
+    print(f"shock-bubble 2000 steps mixed vs fp64 L1 {e}; fp64 from FP32-rounded start {es}", flush=True)
+    for f in e:
+        assert e[f] <= max(1e-4, 2.0 * es[f]), f
+
+
+def test_drop_at_its_configured_length(dev, stream):
+    """the static drop's 10^4 steps (Section 4.4, Appendix C).
+    Physics, both paths: the Laplace jump <p>_{r<R/2} - <p>_{r>3R/2}, sampled
+    every 500 steps, averages to sigma / R within 15 % (it rings with the
+    acoustic waves the smeared start sends out), and the spurious speed
+    max |u| is reported against the step.
+    Precision: the discrete drop is not stationary (max |u| grows by about
+    0.014 m/s per 1000 steps in FP64) and that motion amplifies differences:
+    the FP64 path started from its own initial state rounded to FP32 (a
+    one-time relative change of ~3e-8) drifts from the unperturbed FP64 path
+    to ~8e-3 in u by 10^4 steps.  The mixed path, which rounds at every stage,
+    is held to 1e-4 per field up to 100 steps; at 10^4 steps to 2e-4 in rho,
+    p and xi and, in u, to twice the FP64 path's drift from the rounded
+    start; the pressure difference is also reported in units of sigma / R."""
+    from paper_2304_00140_amd import fvm
+    case = W.drop_2d(256, 10000)
+    R, sig = case["radius"], case["scheme"]["sigma"]
+    x, y = W.cell_centres(case["grid"])
+    Lx = case["grid"]["n"][0] * case["grid"]["dx"][0]
+    r = np.hypot(x - 0.5 * Lx, y - 0.5 * Lx)
+    inner, outer = r < 0.5 * R, r > 1.5 * R
+    h, htile = bench_context(case, fvm.FVM_FP64, stream)
+    m, _ = bench_context(case, fvm.FVM_MIXED, stream)
+    g = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    g.set_tile(htile)
+    g.set_state(h.get_state().astype(np.float32).astype(np.float64))
+    jumps = {"fp64": [], "mixed": []}
+    done = 0
+    for target in [100] + list(range(500, 10001, 500)):
+        for c in (h, m, g):
+            c.n_steps(target - done)
+        done = target
+        wf, wm, wg = h.get_primitive(), m.get_primitive(), g.get_primitive()
+        for name, w in (("fp64", wf), ("mixed", wm)):
+            jumps[name].append(w[4][inner].mean() - w[4][outer].mean())
+        em, es = l1_fields(wm, wf, 0.53), l1_fields(wg, wf, 0.53)
+        if target == 100:
+            print(f"drop 100 steps mixed vs fp64 L1 {em}", flush=True)
+            assert max(em.values()) < 1e-4
+        if target % 2500 == 0:
+            print(f"drop {target} steps: mixed vs fp64 {em}, p max {np.abs(wm[4] - wf[4]).max() * R / sig:.3f} "
+                  f"sigma/R; fp64 from FP32-rounded start {es}; max|u| fp64 {np.hypot(wf[1], wf[2]).max():.4f} "
+                  f"mixed {np.hypot(wm[1], wm[2]).max():.4f}", flush=True)
+    for f in ("rho", "p", "Y"):
+        assert em[f] < 2e-4, f
+    assert em["u"] <= 2.0 * es["u"]
+    for name in jumps:
+        ratio = np.mean(jumps[name]) * R / sig
+        print(f"drop {name}: mean Laplace jump {ratio:.4f} sigma/R (last {jumps[name][-1] * R / sig:.4f})", flush=True)
+        assert 0.85 < ratio < 1.15

@@ -87,7 +87,12 @@ def test_stress_terms_match_oracle_every_tile(dev, stream, spec):
     dref = rv - ri
     assert np.abs(dref[1:1 + dim]).max() > 1e-3 * np.abs(rv[1:1 + dim]).max()   # the terms matter
     for tile in range(fvm.lib().fvm_tile_count(dim)):
-        gv = gpu_rhs(cv, q, dev, stream, tile)
+        try:
+            gv = gpu_rhs(cv, q, dev, stream, tile)
+        except fvm.FvmError as e:
+            # the z-marching 3D tiles take inviscid cases only
+            assert dim == 3 and "z-marching" in str(e)
+            continue
         gi = gpu_rhs(ci, q, dev, stream, tile)
         e_all = field_err(gv, rv)
         e_diff = field_err((gv - gi)[1:2 + dim], dref[1:2 + dim])

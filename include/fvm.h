@@ -249,11 +249,15 @@ int fvm_totals(fvm_ctx* ctx, double* out);
 int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step);
 
 /* Launch configuration: tile shape index of the fused stage kernel for this
- * context's dimension (0 .. fvm_tile_count(dim) - 1) and its extent.
+ * context's dimension (0 .. fvm_tile_count(dim) - 1) and its extent.  In 3D,
+ * indices 0-4 and, after the z-marching kernel's, the last five are the
+ * closure + face kernel pair (the last five with one thread per face of the
+ * direction with the most faces); the z-marching tiles take only the
+ * two-component inviscid closures with the default limiters.
  * fvm_set_tile / fvm_batch_set_tile return FVM_EINVAL (state unchanged) for an
  * index out of range or a tile whose kernels do not fit this closure and
  * precision (3D in FP64 with three components or with two gases in the
- * barotropic model: the 8x8x8 tile). */
+ * barotropic model: the 8x8x8 tiles). */
 int fvm_tile_count(int dim);
 int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads);
 int fvm_set_tile(fvm_ctx* ctx, int tile);

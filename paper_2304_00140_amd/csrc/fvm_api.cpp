@@ -876,7 +876,7 @@ int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads)
 static int check_tile(fvm_batch* b, int tile)
 {
   if (tile < 0 || tile >= fvm_k_tile_count(b->dim)) return fail(b, FVM_EINVAL, "bad tile index");
-  if (b->dim == 3 && tile >= fvm_k_tile_first_m3()) {
+  if (b->dim == 3 && fvm_k_tile_is_m3(tile)) {
     bool ok = (b->kind == FVM_KIND_SG || b->kind == FVM_KIND_PR) && fvm_default_limiters(b->sc);
     for (const CaseC& C : b->hc) ok = ok && !C.diff;
     if (!ok)

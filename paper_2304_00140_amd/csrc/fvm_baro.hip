@@ -1266,26 +1266,32 @@ static hipError_t launch_b3(const StageArgs& a, int ntiles, hipStream_t st)
 template <class S, bool G2>
 static hipError_t stage_b3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  switch (tile) {
+  switch (fvm_k_tile_row3(tile)) {
     case 0: return launch_b3<S, 8, 8, 4, 256, 2, G2>(a, ntiles, st);
     case 1: return launch_b3<S, 16, 8, 2, 256, 2, G2>(a, ntiles, st);
     case 2: return launch_b3<S, 8, 4, 4, 128, 2, G2>(a, ntiles, st);
     case 3: return launch_b3<S, 16, 4, 4, 256, 2, G2>(a, ntiles, st);
     case 4: return launch_b3<S, 8, 8, 8, 512, 1, G2>(a, ntiles, st);
+    case 5: return launch_b3<S, 8, 8, 8, 768, 1, G2>(a, ntiles, st);
+    case 6: return launch_b3<S, 8, 8, 8, 1024, 1, G2>(a, ntiles, st);
+    case 7: return launch_b3<S, 8, 8, 4, 512, 1, G2>(a, ntiles, st);
+    case 8: return launch_b3<S, 8, 4, 4, 256, 2, G2>(a, ntiles, st);
+    case 9: return launch_b3<S, 8, 8, 8, 576, 1, G2>(a, ntiles, st);
   }
   return hipErrorInvalidValue;
 }
 
 // 1 if the 3D tile fits the LDS of a workgroup, 0 if not, -1 for no such tile
+// (or a z-marching tile, which the barotropic model does not take)
 template <class S, bool G2>
 static int tile_okb3(int tile)
 {
-  switch (tile) {
-    case 0: return bfits3<S, 8, 8, 4, G2>();
+  switch (fvm_k_tile_row3(tile)) {
+    case 0: case 7: return bfits3<S, 8, 8, 4, G2>();
     case 1: return bfits3<S, 16, 8, 2, G2>();
-    case 2: return bfits3<S, 8, 4, 4, G2>();
+    case 2: case 8: return bfits3<S, 8, 4, 4, G2>();
     case 3: return bfits3<S, 16, 4, 4, G2>();
-    case 4: return bfits3<S, 8, 8, 8, G2>();
+    case 4: case 5: case 6: case 9: return bfits3<S, 8, 8, 8, G2>();
   }
   return -1;
 }

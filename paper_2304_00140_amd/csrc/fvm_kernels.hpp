@@ -53,8 +53,11 @@ int fvm_k_tile_shape_m3(int tile, int* tx, int* ty, int* nt, int* zc);
 hipError_t fvm_k_stage_m3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 // the same shapes after the closure kernel k_prim3 (fvm_stage3mp.hip)
 hipError_t fvm_k_stage_m3p(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
-// first 3D tile index of the z-marching kernel
-int fvm_k_tile_first_m3();
+// whether a 3D tile index is one of the z-marching kernel's
+int fvm_k_tile_is_m3(int tile);
+// shape row (0-9) of a 3D tile index of the closure + face kernel pair, which
+// the barotropic 3D kernels share; -1 for a z-marching tile or no tile
+int fvm_k_tile_row3(int tile);
 int fvm_k_tile_ok3(int mixed, int kind, int tile);
 hipError_t fvm_k_advance(fvm::CaseDyn* dyn, int ncases, int nsteps, hipStream_t st);
 hipError_t fvm_k_prim_to_state(int dim, int mixed, int kind, const fvm::CaseC* cases, int icase, long long ncell,

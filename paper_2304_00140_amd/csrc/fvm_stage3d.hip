@@ -338,7 +338,17 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
   if constexpr (!fits3<S, TX, TY, TZ, G2>()) {
     return hipErrorInvalidValue;   // rejected on the host before any launch (fvm_k_tile_ok3)
   } else {
-    constexpr int Wv = PRK ? 1 : MINW;
+    // the Peng-Robinson face kernels ask for as many waves per SIMD as the
+    // workgroups that the LDS of the tile admits per CU hold, within what the
+    // kernel's registers allow without large spills (4 waves in FP32 storage,
+    // 3 in FP64), so the register budget does not become the tighter limit
+    constexpr long long LDS_CU = 160LL * 1024;
+    constexpr int WG_LDS = (int)(LDS_CU / lds3<S, TX, TY, TZ, G2>());
+    constexpr int WPS = (NT / 64 + 3) / 4;
+    constexpr int CAP = sizeof(S) == 4 ? 4 : 3;
+    constexpr int NWG = WG_LDS < CAP / WPS ? WG_LDS : CAP / WPS;
+    constexpr int WOCC = (NWG > 1 ? NWG : 1) * WPS;
+    constexpr int Wv = PRK ? WOCC : MINW;
     S* W = (S*)a.prim;
     constexpr int PB = (TX * TY * TZ + 255) / 256;
     hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK, G2>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
@@ -354,60 +364,92 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
 
 using namespace fvm;
 
-// (tx, ty, tz, threads)
-static const int TILES3[][4] = {{8, 8, 4, 256}, {16, 8, 2, 256}, {8, 4, 4, 128}, {16, 4, 4, 256}, {8, 8, 8, 512}};
+// (tx, ty, tz, threads).  Rows 5-9 give the 8x8x8 and 8x8x4 / 8x4x4 tiles
+// more threads than cells: up to one thread per face of a direction, so each
+// direction's faces take one pass, and more waves per SIMD to hide latency
+// where the LDS of the tile admits only one or two workgroups per CU.
+static const int TILES3[][4] = {{8, 8, 4, 256}, {16, 8, 2, 256}, {8, 4, 4, 128}, {16, 4, 4, 256}, {8, 8, 8, 512},
+                                {8, 8, 8, 768}, {8, 8, 8, 1024}, {8, 8, 4, 512}, {8, 4, 4, 256}, {8, 8, 8, 576}};
 static const int NT3 = sizeof(TILES3) / sizeof(TILES3[0]);
+// 3D tile numbering: rows 0-4 of the closure + face kernel pair, then the
+// z-marching kernel's tiles (two-component inviscid closures only), then rows
+// 5-9 of the pair
+static const int NP3A = 5;
 
-// 3D tile numbering: the closure + face kernel pair's tiles first, then the
-// z-marching kernel's (two-component inviscid closures only)
-int fvm_k_tile_first_m3() { return NT3; }
+static int march_index3(int t)
+{
+  int m = t - NP3A;
+  return (m >= 0 && m < fvm_k_tile_count_m3()) ? m : -1;
+}
+
+// TILES3 row of a 3D tile index, -1 for a z-marching tile or no tile
+static int pair_row3(int t)
+{
+  if (t < 0) return -1;
+  if (t < NP3A) return t;
+  int r = t - fvm_k_tile_count_m3();
+  return (r >= NP3A && r < NT3) ? r : -1;
+}
+
+int fvm_k_tile_is_m3(int t) { return march_index3(t) >= 0; }
+
+int fvm_k_tile_row3(int t) { return pair_row3(t); }
 
 int fvm_k_tile_count3() { return NT3 + fvm_k_tile_count_m3(); }
 
 int fvm_k_tile_shape3(int t, int* tx, int* ty, int* nt)
 {
-  if (t >= NT3) {
+  int m = march_index3(t);
+  if (m >= 0) {
     int zc;
-    return fvm_k_tile_shape_m3(t - NT3, tx, ty, nt, &zc);
+    return fvm_k_tile_shape_m3(m, tx, ty, nt, &zc);
   }
-  if (t < 0) return -1;
-  *tx = TILES3[t][0];
-  *ty = TILES3[t][1];
-  *nt = TILES3[t][3];
+  int r = pair_row3(t);
+  if (r < 0) return -1;
+  *tx = TILES3[r][0];
+  *ty = TILES3[r][1];
+  *nt = TILES3[r][3];
   return 0;
 }
 
 int fvm_k_tile_zchunk3(int t)
 {
-  if (t >= NT3) {
+  int m = march_index3(t);
+  if (m >= 0) {
     int tx, ty, nt, zc;
-    return fvm_k_tile_shape_m3(t - NT3, &tx, &ty, &nt, &zc) ? 1 : zc;
+    return fvm_k_tile_shape_m3(m, &tx, &ty, &nt, &zc) ? 1 : zc;
   }
-  return (t >= 0) ? TILES3[t][2] : 1;
+  int r = pair_row3(t);
+  return r >= 0 ? TILES3[r][2] : 1;
 }
 
 template <class S, bool PRK, bool G2, int LIM>
-static hipError_t stage3(int tile, const StageArgs& a, int ntiles, hipStream_t st)
+static hipError_t stage3(int row, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  switch (tile) {
+  switch (row) {
     case 0: return launch3<S, 8, 8, 4, 256, 2, PRK, G2, LIM>(a, ntiles, st);
     case 1: return launch3<S, 16, 8, 2, 256, 2, PRK, G2, LIM>(a, ntiles, st);
     case 2: return launch3<S, 8, 4, 4, 128, 2, PRK, G2, LIM>(a, ntiles, st);
     case 3: return launch3<S, 16, 4, 4, 256, 2, PRK, G2, LIM>(a, ntiles, st);
     case 4: return launch3<S, 8, 8, 8, 512, 1, PRK, G2, LIM>(a, ntiles, st);
+    case 5: return launch3<S, 8, 8, 8, 768, 1, PRK, G2, LIM>(a, ntiles, st);
+    case 6: return launch3<S, 8, 8, 8, 1024, 1, PRK, G2, LIM>(a, ntiles, st);
+    case 7: return launch3<S, 8, 8, 4, 512, 1, PRK, G2, LIM>(a, ntiles, st);
+    case 8: return launch3<S, 8, 4, 4, 256, 2, PRK, G2, LIM>(a, ntiles, st);
+    case 9: return launch3<S, 8, 8, 8, 576, 1, PRK, G2, LIM>(a, ntiles, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <class S, bool G2>
-static bool tile_ok3(int tile)
+static bool tile_ok3(int row)
 {
-  switch (tile) {
-    case 0: return fits3<S, 8, 8, 4, G2>();
+  switch (row) {
+    case 0: case 7: return fits3<S, 8, 8, 4, G2>();
     case 1: return fits3<S, 16, 8, 2, G2>();
-    case 2: return fits3<S, 8, 4, 4, G2>();
+    case 2: case 8: return fits3<S, 8, 4, 4, G2>();
     case 3: return fits3<S, 16, 4, 4, G2>();
-    case 4: return fits3<S, 8, 8, 8, G2>();
+    case 4: case 5: case 6: case 9: return fits3<S, 8, 8, 8, G2>();
   }
   return false;
 }
@@ -429,12 +471,15 @@ static hipError_t stage3_any(int mixed, int kind, int tile, const StageArgs& a, 
 // the default limiters (Koren, Minmod) as compile-time constants, any others at run time
 hipError_t fvm_k_stage3(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st)
 {
-  if (tile >= NT3) {
+  int m = march_index3(tile);
+  if (m >= 0) {
     if (kind != FVM_KIND_SG && kind != FVM_KIND_PR) return hipErrorInvalidValue;
-    return fvm_k_stage_m3(mixed, kind, tile - NT3, a, ntiles, st);
+    return fvm_k_stage_m3(mixed, kind, m, a, ntiles, st);
   }
-  if (fvm_default_limiters(a.sc)) return stage3_any<1>(mixed, kind, tile, a, ntiles, st);
-  return stage3_any<0>(mixed, kind, tile, a, ntiles, st);
+  int r = pair_row3(tile);
+  if (r < 0) return hipErrorInvalidValue;
+  if (fvm_default_limiters(a.sc)) return stage3_any<1>(mixed, kind, r, a, ntiles, st);
+  return stage3_any<0>(mixed, kind, r, a, ntiles, st);
 }
 
 // whether the face kernel of a 3D tile fits the LDS of a workgroup for this
@@ -442,8 +487,10 @@ hipError_t fvm_k_stage3(int mixed, int kind, int tile, const StageArgs& a, int n
 // does not)
 int fvm_k_tile_ok3(int mixed, int kind, int tile)
 {
-  if (tile >= NT3) return (kind == FVM_KIND_SG || kind == FVM_KIND_PR) && tile < fvm_k_tile_count3();
+  if (march_index3(tile) >= 0) return kind == FVM_KIND_SG || kind == FVM_KIND_PR;
+  int r = pair_row3(tile);
+  if (r < 0) return 0;
   bool g2 = kind == FVM_KIND_THREE;
-  if (mixed) return g2 ? tile_ok3<float, true>(tile) : tile_ok3<float, false>(tile);
-  return g2 ? tile_ok3<double, true>(tile) : tile_ok3<double, false>(tile);
+  if (mixed) return g2 ? tile_ok3<float, true>(r) : tile_ok3<float, false>(r);
+  return g2 ? tile_ok3<double, true>(r) : tile_ok3<double, false>(r);
 }

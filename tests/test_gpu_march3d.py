@@ -29,10 +29,20 @@ def stream(dev):
 
 
 def march_tiles():
-    """3D tile indices of the z-marching kernel (those a stiffened-gas case
-    accepts beyond the closure + face kernel pair's five)"""
+    """3D tile indices of the z-marching kernel: those a barotropic case
+    refuses as z-marching tiles"""
     from paper_2304_00140_amd import fvm
-    return list(range(5, fvm.lib().fvm_tile_count(3)))
+    ctx = fvm.Context(W.random_state(3, [9, 8, 7], 86, barotropic=True), fvm.FVM_FP64)
+    tiles = []
+    for tile in range(fvm.lib().fvm_tile_count(3)):
+        try:
+            ctx.set_tile(tile)
+        except fvm.FvmError as e:
+            if "z-marching" in str(e):
+                tiles.append(tile)
+    ctx.close()
+    assert len(tiles) == 10
+    return tiles
 
 
 def field_err(a, b):

@@ -179,7 +179,7 @@ def test_three_component_rhs_every_tile_3d(dev, stream, spec):
             if "z-marching" in str(e):
                 ctx.close()
                 continue
-            assert shape3(tile) == (8, 8, 512) and "LDS" in str(e)
+            assert shape3(tile)[:2] == (8, 8) and shape3(tile)[2] >= 512 and "LDS" in str(e)
             refused.append(tile)
             ctx.close()
             continue

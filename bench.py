@@ -43,14 +43,30 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
-# rocprofv3 --pmc figures of the dominant stage kernel on these workloads and
-# launch shapes (files under profiles/ named for kernel and workload give the
-# commands): executed VALU lane-instructions per cell-stage (SQ_INSTS_VALU x 64
-# / cells) and HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# in KiB, the factors read off a 1 GiB device copy).  Keyed by (workload,
+# rocprofv3 --pmc figures of the stage kernels on these workloads and launch
+# shapes (files under profiles/ named for kernel and workload give the
+# commands; a 3D stage sums its closure and face kernels): executed VALU
+# lane-instructions per cell-stage (SQ_INSTS_VALU x 64 / cells) and HBM bytes
+# per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 in KiB, the factors
+# read off a 1 GiB device copy).  Keyed by (workload,
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
-MEASURED = {}
+MEASURED = {
+    ("liquid_jet_3d", "mixed", 4, "22462d94557d"): {"valu_per_cell_stage": 2679.7, "traffic_bytes": 7561500586},
+    ("liquid_jet_3d", "fp64", 15, "22462d94557d"): {"valu_per_cell_stage": 2726.4, "traffic_bytes": 13492027662},
+    ("liquid_jet_3d", "mixed", 7, "22462d94557d"): {"valu_per_cell_stage": 2507.0, "traffic_bytes": 2513080802},
+    ("liquid_jet_3d", "fp64", 7, "22462d94557d"): {"valu_per_cell_stage": 2530.6, "traffic_bytes": 5223558498},
+    ("shock_bubble_2d", "fp64", 10, "22462d94557d"): {"valu_per_cell_stage": 1125.3, "traffic_bytes": 185988018},
+    ("shock_bubble_2d", "mixed", 10, "22462d94557d"): {"valu_per_cell_stage": 972.2, "traffic_bytes": 77499070},
+    ("bubble_collapse_batch", "mixed", 4, "22462d94557d"): {"valu_per_cell_stage": 999.9, "traffic_bytes": 446820384},
+    ("bubble_collapse_batch", "fp64", 4, "22462d94557d"): {"valu_per_cell_stage": 1106.2, "traffic_bytes": 1095038855},
+    ("vapour_bubble_wall_2d", "fp64", 9, "22462d94557d"): {"valu_per_cell_stage": 990.5, "traffic_bytes": 47640914},
+    ("vapour_bubble_wall_2d", "mixed", 10, "22462d94557d"): {"valu_per_cell_stage": 835.2, "traffic_bytes": 23969870},
+    ("cube_to_sphere_3d", "fp64", 4, "22462d94557d"): {"valu_per_cell_stage": 1764.7, "traffic_bytes": 5438539861},
+    ("cube_to_sphere_3d", "mixed", 4, "22462d94557d"): {"valu_per_cell_stage": 1576.7, "traffic_bytes": 2682483368},
+    ("dual_gas_layer_2d", "fp64", 10, "22462d94557d"): {"valu_per_cell_stage": 1211.7, "traffic_bytes": 405600872},
+    ("dual_gas_layer_2d", "mixed", 9, "22462d94557d"): {"valu_per_cell_stage": 1119.0, "traffic_bytes": 143655797},
+}
 
 
 def parse():
@@ -188,12 +204,13 @@ def l1_errors(a, b, uref):
     return out
 
 
-def drop_physics(case, prec, stream, steps, every):
+def drop_physics(case, prec, stream, steps, every, tile):
     """Section 4.4 / Appendix C diagnostics of the static drop: the Laplace
     jump <p>_{r < R/2} - <p>_{r > 3R/2} against sigma / R, and the largest
     spurious speed max |u| against the step"""
     from paper_2304_00140_amd import fvm, workloads as W
     ctx = fvm.Context(case, prec, stream=stream.cuda_stream)
+    ctx.set_tile(tile)
     ctx.init_primitive()
     x, y = W.cell_centres(case["grid"])
     Lx = case["grid"]["n"][0] * case["grid"]["dx"][0]
@@ -326,7 +343,8 @@ def main():
         phys = {}
         ws = {}
         for name in names:
-            phys[name], ws[name] = drop_physics(cases[0], code[name], stream, DEFAULT_STEPS["drop_2d"], 1000)
+            phys[name], ws[name] = drop_physics(cases[0], code[name], stream, DEFAULT_STEPS["drop_2d"], 1000,
+                                                   res[name]["tile"])
         if len(names) == 2:
             R, sig = cases[0]["radius"], cases[0]["scheme"]["sigma"]
             phys["mixed_vs_fp64_p_max_over_sigma_R"] = float(np.abs(ws["mixed"][4] - ws["fp64"][4]).max() * R / sig)

@@ -182,10 +182,14 @@ def run_path(cases, prec, args, stream, torch):
                 tune={str(k): round(v, 5) for k, v in (tune or {}).items()})
 
 
-def kernel_name(case):
+def kernel_name(case, tile):
+    from paper_2304_00140_amd import fvm
     baro = int(case["eos"].get("model", 0)) == 1
-    if case["grid"]["dim"] == 3:
-        return "k_bprim3+k_bface3" if baro else "k_prim3+k_face3"
+    dim = case["grid"]["dim"]
+    if dim == 3:
+        if baro:
+            return "k_bprim3+k_bface3"
+        return {1: "k_prim3+k_face3", 2: "k_march3", 3: "k_prim3+k_march3"}[fvm.lib().fvm_tile_kernels(dim, tile)]
     return "k_baro12" if baro else "k_stage12"
 
 
@@ -304,7 +308,7 @@ def main():
                     "frac": vps * r["ncell"] / (stage_ms * 1e-3) / 1e12 / VALU_PEAK_TINSTR}
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic_bytes"] if meas else None,
-                "kernel": kernel_name(cases[0]), "kernel_src": src_hash,
+                "kernel": kernel_name(cases[0], r["tile"]), "kernel_src": src_hash,
                 "algorithmic_bytes_per_cell_stage": bpcs, "algorithmic_bytes_per_launch": alg_bytes,
                 "stage_launch_ms": stage_ms, "stage_ms": r["stage_ms"], "tile": r["tile"],
                 "tune_ms_per_stage": r["tune"], "valu": valu}

@@ -260,6 +260,13 @@ int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step);
  * barotropic model: the 8x8x8 tiles). */
 int fvm_tile_count(int dim);
 int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads);
+/* Kernels one stage of a tile index launches: FVM_TK_STAGE (the fused 1D/2D
+ * stage kernel), FVM_TK_PAIR (3D: closure kernel, then the LDS-tiled face
+ * kernel), FVM_TK_MARCH (3D: the z-marching kernel with the closure in it),
+ * FVM_TK_PRIM_MARCH (3D: closure kernel, then the z-marching kernel);
+ * FVM_EINVAL for no such tile. */
+enum { FVM_TK_STAGE = 0, FVM_TK_PAIR = 1, FVM_TK_MARCH = 2, FVM_TK_PRIM_MARCH = 3 };
+int fvm_tile_kernels(int dim, int tile);
 int fvm_set_tile(fvm_ctx* ctx, int tile);
 /* Mean duration [ms] of each of the four stage kernels over `steps` steps,
  * measured with HIP events on the context's stream around every stage

@@ -862,6 +862,14 @@ int fvm_error_info(fvm_ctx* ctx, int* code, int64_t* cell, int64_t* step)
 
 int fvm_tile_count(int dim) { return fvm_k_tile_count(dim); }
 
+int fvm_tile_kernels(int dim, int tile)
+{
+  if (dim < 1 || dim > 3 || tile < 0 || tile >= fvm_k_tile_count(dim)) return FVM_EINVAL;
+  if (dim < 3) return FVM_TK_STAGE;
+  int m = fvm_k_tile_march3(tile);
+  return m < 0 ? FVM_TK_PAIR : (m == 0 ? FVM_TK_MARCH : FVM_TK_PRIM_MARCH);
+}
+
 int fvm_tile_shape(int dim, int tile, int* tx, int* ty, int* threads)
 {
   int a, b2, c;

@@ -55,6 +55,9 @@ hipError_t fvm_k_stage_m3(int mixed, int kind, int tile, const StageArgs& a, int
 hipError_t fvm_k_stage_m3p(int mixed, int kind, int tile, const StageArgs& a, int ntiles, hipStream_t st);
 // whether a 3D tile index is one of the z-marching kernel's
 int fvm_k_tile_is_m3(int tile);
+// -1 for a closure + face pair tile, 0 for a z-marching tile with the closure
+// fused, 1 for one after the closure kernel
+int fvm_k_tile_march3(int tile);
 // shape row (0-9) of a 3D tile index of the closure + face kernel pair, which
 // the barotropic 3D kernels share; -1 for a z-marching tile or no tile
 int fvm_k_tile_row3(int tile);

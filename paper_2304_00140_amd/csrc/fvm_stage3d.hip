@@ -395,6 +395,12 @@ int fvm_k_tile_is_m3(int t) { return march_index3(t) >= 0; }
 
 int fvm_k_tile_row3(int t) { return pair_row3(t); }
 
+int fvm_k_tile_march3(int t)
+{
+  int m = march_index3(t);
+  return m < 0 ? -1 : (m < fvm_k_tile_count_m3() / 2 ? 0 : 1);
+}
+
 int fvm_k_tile_count3() { return NT3 + fvm_k_tile_count_m3(); }
 
 int fvm_k_tile_shape3(int t, int* tx, int* ty, int* nt)

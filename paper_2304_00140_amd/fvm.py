@@ -18,6 +18,7 @@ MAXSPEC = 4
 
 FVM_OK, FVM_EINVAL, FVM_EHIP, FVM_ENOMEM, FVM_ENONPHYS, FVM_ENAN, FVM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FVM_FP64, FVM_MIXED = 0, 1
+FVM_TK_STAGE, FVM_TK_PAIR, FVM_TK_MARCH, FVM_TK_PRIM_MARCH = 0, 1, 2, 3
 ERRNAMES = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENONPHYS", -5: "ENAN", -6: "ESTATE"}
 
 
@@ -75,6 +76,7 @@ SIGNATURES = {
     "fvm_error_info": (C.c_int, [_P, _IP, _I64P, _I64P]),
     "fvm_tile_count": (C.c_int, [C.c_int]),
     "fvm_tile_shape": (C.c_int, [C.c_int, C.c_int, _IP, _IP, _IP]),
+    "fvm_tile_kernels": (C.c_int, [C.c_int, C.c_int]),
     "fvm_set_tile": (C.c_int, [_P, C.c_int]),
     "fvm_time_stages": (C.c_int, [_P, C.c_int, _DP]),
     "fvm_batch_create": (C.c_int, [C.POINTER(_P), C.c_int, _GP, _EP, _SP, C.c_int, _P]),

@@ -76,6 +76,15 @@ def test_tile_tables_host_only(fvm_mod):
             # whole waves; a tile may have more or fewer cells than threads
             assert tx.value * ty.value > 0 and nt.value % 64 == 0
     assert L.fvm_tile_shape(2, 99, None, None, None) != 0
+    # kernels per tile: one fused stage kernel in 1D/2D; in 3D the closure +
+    # face pair, the z-marching kernel with the closure fused and after the
+    # closure kernel, then the pair again
+    for dim in (1, 2):
+        assert {L.fvm_tile_kernels(dim, t) for t in range(L.fvm_tile_count(dim))} == {fvm_mod.FVM_TK_STAGE}
+    kinds = [L.fvm_tile_kernels(3, t) for t in range(L.fvm_tile_count(3))]
+    assert kinds == [fvm_mod.FVM_TK_PAIR] * 5 + [fvm_mod.FVM_TK_MARCH] * 5 + [fvm_mod.FVM_TK_PRIM_MARCH] * 5 + \
+        [fvm_mod.FVM_TK_PAIR] * 5
+    assert L.fvm_tile_kernels(3, len(kinds)) == fvm_mod.FVM_EINVAL and L.fvm_tile_kernels(4, 0) == fvm_mod.FVM_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch):

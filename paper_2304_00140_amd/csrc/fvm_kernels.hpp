@@ -17,7 +17,6 @@ struct StageArgs {
   int step_off;               // stage >= 0: step index relative to CaseDyn::base
   int stage;                  // 0..3, or -1 for a bare right-hand side
   double ak;                  // stage coefficient
-  int ntiles;                 // entries of the tile table
   fvm::SchemeC sc;
 };
 

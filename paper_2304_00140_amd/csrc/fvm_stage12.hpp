@@ -48,355 +48,350 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
   __shared__ S s_F[NQ][NF];
   __shared__ double s_red[NT / 64];
 
-  // one tile per workgroup, or (fewer workgroups than tiles) a grid-stride
-  // walk over the tiles; the tile order keeps each XCD on one run of tiles
-  for (int tb = blockIdx.x; tb < a.ntiles; tb += gridDim.x) {
-    if (tb != (int)blockIdx.x) __syncthreads();
-    const int4 tl = a.tiles[xcd_block(tb, a.ntiles)];
-    const CaseC& C = a.cases[tl.x];
-    CaseDyn& dy = a.dyn[tl.x];
-    const SchemeC& SC = a.sc;
-    const int x0 = tl.y * TX, y0 = tl.z * TY;
-    const int tid = threadIdx.x;
-    const bool upd = a.stage >= 0;
-    const long long step = upd ? dy.base + a.step_off : a.rhs_step;
-    const S* __restrict__ src = (const S*)a.src;
-    const long long T = a.total;
+  const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const CaseC& C = a.cases[tl.x];
+  CaseDyn& dy = a.dyn[tl.x];
+  const SchemeC& SC = a.sc;
+  const int x0 = tl.y * TX, y0 = tl.z * TY;
+  const int tid = threadIdx.x;
+  const bool upd = a.stage >= 0;
+  const long long step = upd ? dy.base + a.step_off : a.rhs_step;
+  const S* __restrict__ src = (const S*)a.src;
+  const long long T = a.total;
 
-    // ---- q^n of the owned cells, fetched early so its latency overlaps the stencil work
-    S qn_reg[CPT][NQ];
-    if (upd) {
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
-        int gx = x0 + cc % TX, gy = y0 + cc / TX;
-        bool own = cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1]);
-        long long cell = C.off + (own ? gx + (long long)C.n[0] * gy : 0);
-  #pragma unroll
-        for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+  // ---- q^n of the owned cells, fetched early so its latency overlaps the stencil work
+  S qn_reg[CPT][NQ];
+  if (upd) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      int gx = x0 + cc % TX, gy = y0 + cc / TX;
+      bool own = cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1]);
+      long long cell = C.off + (own ? gx + (long long)C.n[0] * gy : 0);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) qn_reg[k][v] = ((const S*)a.qn)[v * T + cell];
+    }
+  }
+
+  // ---- tile + halo: all loads first, then the FP64 closure inversion, primitives to LDS
+  {
+    double qv[NIT][NQ];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        int hx = h % HX, hy = h / HX;
+        load_cell<S, D, PRK, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
       }
     }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int h = tid + it * NT;
+      if (h < NH) {
+        double u[D], rho, Y, Y2;
+        PT pt = cell_prim_any<D, PRK, G2>(C, qv[it], u, rho, Y, Y2);
+        s_rho[h] = S(rho);
+        s_u[h] = S(u[0]);
+        if (D == 2) s_v[h] = S(u[D - 1]);
+        s_p[h] = S(pt.p);
+        s_T[h] = S(pt.T);
+        s_Y[h] = S(Y);
+        s_c[h] = S(pt.c);
+        s_a[h] = S(pt.alpha);
+        if constexpr (G2) {
+          s_Y2[h] = S(Y2);
+          s_a2[h] = S(pt.alpha2);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // total gas volume fraction and mass fraction of a staged cell
+  auto aG = [&](int c) -> S {
+    if constexpr (G2) return s_a[c] + s_a2[c];
+    else return s_a[c];
+  };
+  auto YG = [&](int c) -> S {
+    if constexpr (G2) return s_Y[c] + s_Y2[c];
+    else return s_Y[c];
+  };
 
-    // ---- tile + halo: all loads first, then the FP64 closure inversion, primitives to LDS
-    {
-      double qv[NIT][NQ];
-  #pragma unroll
-      for (int it = 0; it < NIT; ++it) {
-        int h = tid + it * NT;
-        if (h < NH) {
-          int hx = h % HX, hy = h / HX;
-          load_cell<S, D, PRK, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
-        }
+  // ---- switching sensors (Appendix D) on tile + one halo layer
+  if (SC.switching) {
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+      S idx2 = S(0.5 * C.idx[0]);
+      S dudx = (s_u[c + 1] - s_u[c - 1]) * idx2;
+      S div = dudx, curl2 = S(0);
+      S thg = fabs(aG(c) - aG(c - 1)) + fabs(aG(c + 1) - aG(c));
+      if (D == 2) {
+        S idy2 = S(0.5 * C.idx[1]);
+        S dvdy = (s_v[c + HX] - s_v[c - HX]) * idy2;
+        S dvdx = (s_v[c + 1] - s_v[c - 1]) * idx2;
+        S dudy = (s_u[c + HX] - s_u[c - HX]) * idy2;
+        div += dvdy;
+        S w = dvdx - dudy;
+        curl2 = w * w;
+        thg += fabs(aG(c) - aG(c - HX)) + fabs(aG(c + HX) - aG(c));
       }
-  #pragma unroll
-      for (int it = 0; it < NIT; ++it) {
-        int h = tid + it * NT;
-        if (h < NH) {
-          double u[D], rho, Y, Y2;
-          PT pt = cell_prim_any<D, PRK, G2>(C, qv[it], u, rho, Y, Y2);
-          s_rho[h] = S(rho);
-          s_u[h] = S(u[0]);
-          if (D == 2) s_v[h] = S(u[D - 1]);
-          s_p[h] = S(pt.p);
-          s_T[h] = S(pt.T);
-          s_Y[h] = S(Y);
-          s_c[h] = S(pt.c);
-          s_a[h] = S(pt.alpha);
-          if constexpr (G2) {
-            s_Y2[h] = S(Y2);
-            s_a2[h] = S(pt.alpha2);
-          }
-        }
-      }
+      S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
+      s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
     }
     __syncthreads();
-    // total gas volume fraction and mass fraction of a staged cell
-    auto aG = [&](int c) -> S {
-      if constexpr (G2) return s_a[c] + s_a2[c];
-      else return s_a[c];
-    };
-    auto YG = [&](int c) -> S {
-      if constexpr (G2) return s_Y[c] + s_Y2[c];
-      else return s_Y[c];
-    };
+  }
 
-    // ---- switching sensors (Appendix D) on tile + one halo layer
-    if (SC.switching) {
-      for (int h = tid; h < FX * FY; h += NT) {
-        int lx = h % FX, ly = h / FX;
-        int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
-        S idx2 = S(0.5 * C.idx[0]);
-        S dudx = (s_u[c + 1] - s_u[c - 1]) * idx2;
-        S div = dudx, curl2 = S(0);
-        S thg = fabs(aG(c) - aG(c - 1)) + fabs(aG(c + 1) - aG(c));
-        if (D == 2) {
-          S idy2 = S(0.5 * C.idx[1]);
-          S dvdy = (s_v[c + HX] - s_v[c - HX]) * idy2;
-          S dvdx = (s_v[c + 1] - s_v[c - 1]) * idx2;
-          S dudy = (s_u[c + HX] - s_u[c - HX]) * idy2;
-          div += dvdy;
-          S w = dvdx - dudy;
-          curl2 = w * w;
-          thg += fabs(aG(c) - aG(c - HX)) + fabs(aG(c + HX) - aG(c));
-        }
-        S thd = fdiv(div * div, div * div + curl2 + S(SC.eps_d));
-        s_fl[c] = (thd > S(SC.th_d) || thg > S(SC.th_g)) ? 1 : 0;
-      }
-      __syncthreads();
+  S R[CPT][NQ];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
+
+  const S eps = S(SC.eps_int);
+  // velocity arrays and LDS strides for the stress terms and the body force
+  const S* U[D];
+  int stv[D];
+  U[0] = s_u;
+  stv[0] = 1;
+  if constexpr (D == 2) { U[1] = s_v; stv[1] = HX; }
+  // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
+  auto xface = [&](int f) {
+    int i = f % (TX + 1), j = f / (TX + 1);
+    int c = (j + OY) * HX + i + 1;
+    Stencil<S, D> st;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      st.u[0][m] = s_u[c - 1 + m];
+      if (D == 2) st.u[D - 1][m] = s_v[c - 1 + m];
+      st.p[m] = s_p[c - 1 + m];
+      st.T[m] = s_T[c - 1 + m];
+      st.Y[m] = s_Y[c - 1 + m];
+      if constexpr (G2) st.Y2[m] = s_Y2[c - 1 + m];
     }
-
-    S R[CPT][NQ];
-  #pragma unroll
-    for (int k = 0; k < CPT; ++k)
-  #pragma unroll
-      for (int v = 0; v < NQ; ++v) R[k][v] = S(0);
-
-    const S eps = S(SC.eps_int);
-    // velocity arrays and LDS strides for the stress terms and the body force
-    const S* U[D];
-    int stv[D];
-    U[0] = s_u;
-    stv[0] = 1;
-    if constexpr (D == 2) { U[1] = s_v; stv[1] = HX; }
-    // ---- x faces: face i-1/2 of tile column i = 0..TX, between LDS cells c and c+1
-    auto xface = [&](int f) {
-      int i = f % (TX + 1), j = f / (TX + 1);
-      int c = (j + OY) * HX + i + 1;
-      Stencil<S, D> st;
-  #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        st.u[0][m] = s_u[c - 1 + m];
-        if (D == 2) st.u[D - 1][m] = s_v[c - 1 + m];
-        st.p[m] = s_p[c - 1 + m];
-        st.T[m] = s_T[c - 1 + m];
-        st.Y[m] = s_Y[c - 1 + m];
-        if constexpr (G2) st.Y2[m] = s_Y2[c - 1 + m];
+    st.rho1 = s_rho[c]; st.rho2 = s_rho[c + 1];
+    st.c1 = s_c[c]; st.c2 = s_c[c + 1];
+    bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
+    S F[NQ];
+    bool sl2 = false, sr2 = false;
+    if constexpr (G2) {
+      sl2 = eligible(st.Y2[0], st.Y2[1], st.Y2[2], eps);
+      sr2 = eligible(st.Y2[1], st.Y2[2], st.Y2[3], eps);
+    }
+    face_flux<S, D, 0, PRK, G2, LIM>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                                eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
+    if (C.diff) visc_flux<S, D, 0, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
+  };
+  for_faces<NFX, NT>(tid, xface);
+  __syncthreads();
+  {
+    S ix = S(C.idx[0]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int f = (cc / TX) * (TX + 1) + cc % TX;
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + 1]) * ix;
       }
-      st.rho1 = s_rho[c]; st.rho2 = s_rho[c + 1];
-      st.c1 = s_c[c]; st.c2 = s_c[c + 1];
-      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + 1]) != 0);
+    }
+  }
+  if (D == 2) {
+    __syncthreads();
+    auto yface = [&](int f) {
+      int i = f % TX, j = f / TX;
+      int c = (j + 1) * HX + i + 2;
+      Stencil<S, D> st;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int cm = c + (m - 1) * HX;
+        st.u[0][m] = s_u[cm];
+        st.u[D - 1][m] = s_v[cm];
+        st.p[m] = s_p[cm];
+        st.T[m] = s_T[cm];
+        st.Y[m] = s_Y[cm];
+        if constexpr (G2) st.Y2[m] = s_Y2[cm];
+      }
+      st.rho1 = s_rho[c]; st.rho2 = s_rho[c + HX];
+      st.c1 = s_c[c]; st.c2 = s_c[c + HX];
+      bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
       S F[NQ];
       bool sl2 = false, sr2 = false;
       if constexpr (G2) {
         sl2 = eligible(st.Y2[0], st.Y2[1], st.Y2[2], eps);
         sr2 = eligible(st.Y2[1], st.Y2[2], st.Y2[3], eps);
       }
-      face_flux<S, D, 0, PRK, G2, LIM>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
-                                  eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
-      if (C.diff) visc_flux<S, D, 0, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
-  #pragma unroll
+      face_flux<S, D, D - 1, PRK, G2, LIM>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
+                                      eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
+      if (C.diff) visc_flux<S, D, D - 1, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
+#pragma unroll
       for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
     };
-    for_faces<NFX, NT>(tid, xface);
+    for_faces<NFY, NT>(tid, yface);
     __syncthreads();
-    {
-      S ix = S(C.idx[0]);
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
-        if (cc < NC) {
-          int f = (cc / TX) * (TX + 1) + cc % TX;
-  #pragma unroll
-          for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + 1]) * ix;
-        }
+    S iy = S(C.idx[D - 1]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int f = cc;   // j * TX + i
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + TX]) * iy;
       }
     }
-    if (D == 2) {
-      __syncthreads();
-      auto yface = [&](int f) {
-        int i = f % TX, j = f / TX;
-        int c = (j + 1) * HX + i + 2;
-        Stencil<S, D> st;
-  #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          int cm = c + (m - 1) * HX;
-          st.u[0][m] = s_u[cm];
-          st.u[D - 1][m] = s_v[cm];
-          st.p[m] = s_p[cm];
-          st.T[m] = s_T[cm];
-          st.Y[m] = s_Y[cm];
-          if constexpr (G2) st.Y2[m] = s_Y2[cm];
-        }
-        st.rho1 = s_rho[c]; st.rho2 = s_rho[c + HX];
-        st.c1 = s_c[c]; st.c2 = s_c[c + HX];
-        bool disc = !SC.switching || ((s_fl[c] | s_fl[c + HX]) != 0);
-        S F[NQ];
-        bool sl2 = false, sr2 = false;
-        if constexpr (G2) {
-          sl2 = eligible(st.Y2[0], st.Y2[1], st.Y2[2], eps);
-          sr2 = eligible(st.Y2[1], st.Y2[2], st.Y2[3], eps);
-        }
-        face_flux<S, D, D - 1, PRK, G2, LIM>(SC, C, st, disc, eligible(st.Y[0], st.Y[1], st.Y[2], eps),
-                                        eligible(st.Y[1], st.Y[2], st.Y[3], eps), F, sl2, sr2);
-        if (C.diff) visc_flux<S, D, D - 1, G2>(C, U, s_T, s_a, c, stv, F, s_a2);
-  #pragma unroll
-        for (int v = 0; v < NQ; ++v) s_F[v][f] = F[v];
-      };
-      for_faces<NFY, NT>(tid, yface);
-      __syncthreads();
-      S iy = S(C.idx[D - 1]);
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
-        if (cc < NC) {
-          int f = cc;   // j * TX + i
-  #pragma unroll
-          for (int v = 0; v < NQ; ++v) R[k][v] += (s_F[v][f] - s_F[v][f + TX]) * iy;
-        }
-      }
-    }
+  }
 
-    // ---- CSF: kappa from the Gaussian-smoothed xi with vertex normals, force sigma kappa grad(alpha_G)
-    if (SC.sigma > 0.0) {
-      __syncthreads();
-      S* s_H = &s_F[0][0];
-      S* s_nx = s_H + FX * FY;
-      S* s_ny = s_nx + VX * VY;
-      for (int h = tid; h < FX * FY; h += NT) {
-        int lx = h % FX, ly = h / FX;
-        int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
-        S acc;
-        if (D == 1) {
-          acc = (YG(c - 1) + S(2) * YG(c) + YG(c + 1)) * S(0.25);
-        } else {
-          S r0 = YG(c - HX - 1) + S(2) * YG(c - HX) + YG(c - HX + 1);
-          S r1 = YG(c - 1) + S(2) * YG(c) + YG(c + 1);
-          S r2 = YG(c + HX - 1) + S(2) * YG(c + HX) + YG(c + HX + 1);
-          acc = (r0 + S(2) * r1 + r2) * S(1.0 / 16.0);
-        }
-        s_H[h] = acc;
+  // ---- CSF: kappa from the Gaussian-smoothed xi with vertex normals, force sigma kappa grad(alpha_G)
+  if (SC.sigma > 0.0) {
+    __syncthreads();
+    S* s_H = &s_F[0][0];
+    S* s_nx = s_H + FX * FY;
+    S* s_ny = s_nx + VX * VY;
+    for (int h = tid; h < FX * FY; h += NT) {
+      int lx = h % FX, ly = h / FX;
+      int c = (ly + (D == 2 ? 1 : 0)) * HX + lx + 1;
+      S acc;
+      if (D == 1) {
+        acc = (YG(c - 1) + S(2) * YG(c) + YG(c + 1)) * S(0.25);
+      } else {
+        S r0 = YG(c - HX - 1) + S(2) * YG(c - HX) + YG(c - HX + 1);
+        S r1 = YG(c - 1) + S(2) * YG(c) + YG(c + 1);
+        S r2 = YG(c + HX - 1) + S(2) * YG(c + HX) + YG(c + HX + 1);
+        acc = (r0 + S(2) * r1 + r2) * S(1.0 / 16.0);
       }
-      __syncthreads();
-      S en = S(SC.eps_n * C.idx[0]);
-      for (int h = tid; h < VX * VY; h += NT) {
-        int vx = h % VX, vy = h / VX;      // vertex at the upper corner of tile cell (vx-1, vy-1)
-        int c = vy * FX + vx;              // s_H index of cell (vx-1, vy-1)
-        S gx, gy = S(0);
-        if (D == 1) {
-          gx = (s_H[c + 1] - s_H[c]) * S(C.idx[0]);
-        } else {
-          gx = (s_H[c + 1] + s_H[c + FX + 1] - s_H[c] - s_H[c + FX]) * S(0.5 * C.idx[0]);
-          gy = (s_H[c + FX] + s_H[c + FX + 1] - s_H[c] - s_H[c + 1]) * S(0.5 * C.idx[1]);
-        }
-        S inv = frcp(sqrt(gx * gx + gy * gy) + en);
-        s_nx[h] = gx * inv;
-        if (D == 2) s_ny[h] = gy * inv;
-      }
-      __syncthreads();
-      S sig = S(SC.sigma);
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
-        if (cc < NC) {
-          int i = cc % TX, j = cc / TX;
-          int c = (j + OY) * HX + i + 2;
-          S kap, Sx, Sy = S(0);
-          if (D == 1) {
-            kap = -(s_nx[i + 1] - s_nx[i]) * S(C.idx[0]);
-            Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
-          } else {
-            int v = (j + 1) * VX + (i + 1);   // vertex (i, j) = upper corner of cell (i, j)
-            S dnx = s_nx[v] + s_nx[v - VX] - s_nx[v - 1] - s_nx[v - VX - 1];
-            S dny = s_ny[v] + s_ny[v - 1] - s_ny[v - VX] - s_ny[v - VX - 1];
-            kap = -(dnx * S(0.5 * C.idx[0]) + dny * S(0.5 * C.idx[1]));
-            Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
-            Sy = sig * kap * (aG(c + HX) - aG(c - HX)) * S(0.5 * C.idx[1]);
-          }
-          R[k][2] += Sx;
-          S se = s_u[c] * Sx;
-          if (D == 2) { R[k][3] += Sy; se += s_v[c] * Sy; }
-          R[k][2 + D] += se;
-        }
-      }
+      s_H[h] = acc;
     }
-
-    // ---- body force (eq. 2-2, source Q): rho g on the momentum, rho u . g on the energy
-    if (SC.has_grav) {
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
-        if (cc < NC) {
-          int c = (cc / TX + OY) * HX + cc % TX + 2;
-          S rho = s_rho[c], pw = S(0);
-  #pragma unroll
-          for (int d = 0; d < D; ++d) {
-            S gd = S(SC.grav[d]);
-            R[k][2 + d] += rho * gd;
-            pw += U[d][c] * gd;
-          }
-          R[k][2 + D] += rho * pw;
-        }
+    __syncthreads();
+    S en = S(SC.eps_n * C.idx[0]);
+    for (int h = tid; h < VX * VY; h += NT) {
+      int vx = h % VX, vy = h / VX;      // vertex at the upper corner of tile cell (vx-1, vy-1)
+      int c = vy * FX + vx;              // s_H index of cell (vx-1, vy-1)
+      S gx, gy = S(0);
+      if (D == 1) {
+        gx = (s_H[c + 1] - s_H[c]) * S(C.idx[0]);
+      } else {
+        gx = (s_H[c + 1] + s_H[c + FX + 1] - s_H[c] - s_H[c + FX]) * S(0.5 * C.idx[0]);
+        gy = (s_H[c + FX] + s_H[c + FX + 1] - s_H[c] - s_H[c + 1]) * S(0.5 * C.idx[1]);
       }
+      S inv = frcp(sqrt(gx * gx + gy * gy) + en);
+      s_nx[h] = gx * inv;
+      if (D == 2) s_ny[h] = gy * inv;
     }
-
-    // ---- output
-    if (!upd) {
-      // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64,
-      // in the caller's layout [N_q][ncell] of this case
-  #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        int cc = tid + k * NT;
+    __syncthreads();
+    S sig = S(SC.sigma);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
         int i = cc % TX, j = cc / TX;
-        int gx = x0 + i, gy = y0 + j;
-        if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
-          const long long RS = C.ncell;
-          long long cell = gx + (long long)C.n[0] * gy;
-          double r0 = (double)R[k][0], r1 = (double)R[k][1];
-          double r2 = G2 ? (double)R[k][NQ - 1] : 0.0;
-          a.rhs_out[cell] = G2 ? r0 + r1 + r2 : r0 + r1;
-  #pragma unroll
-          for (int d = 0; d < D; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
-          double rE = (double)R[k][2 + D] + C.Q[0] * r0 + C.Q[1] * r1;
-          a.rhs_out[(1 + D) * RS + cell] = G2 ? rE + C.Q[2] * r2 : rE;
-          a.rhs_out[(2 + D) * RS + cell] = r1;
-          if constexpr (G2) a.rhs_out[(3 + D) * RS + cell] = r2;
+        int c = (j + OY) * HX + i + 2;
+        S kap, Sx, Sy = S(0);
+        if (D == 1) {
+          kap = -(s_nx[i + 1] - s_nx[i]) * S(C.idx[0]);
+          Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
+        } else {
+          int v = (j + 1) * VX + (i + 1);   // vertex (i, j) = upper corner of cell (i, j)
+          S dnx = s_nx[v] + s_nx[v - VX] - s_nx[v - 1] - s_nx[v - VX - 1];
+          S dny = s_ny[v] + s_ny[v - 1] - s_ny[v - VX] - s_ny[v - VX - 1];
+          kap = -(dnx * S(0.5 * C.idx[0]) + dny * S(0.5 * C.idx[1]));
+          Sx = sig * kap * (aG(c + 1) - aG(c - 1)) * S(0.5 * C.idx[0]);
+          Sy = sig * kap * (aG(c + HX) - aG(c - HX)) * S(0.5 * C.idx[1]);
         }
+        R[k][2] += Sx;
+        S se = s_u[c] * Sx;
+        if (D == 2) { R[k][3] += Sy; se += s_v[c] * Sy; }
+        R[k][2 + D] += se;
       }
-      continue;
     }
-    const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
-    if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
-    S* dst = (S*)a.dst;
-    const S adt = S(a.ak * dt);
-    double lam = 0.0;
-  #pragma unroll
+  }
+
+  // ---- body force (eq. 2-2, source Q): rho g on the momentum, rho u . g on the energy
+  if (SC.has_grav) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      int cc = tid + k * NT;
+      if (cc < NC) {
+        int c = (cc / TX + OY) * HX + cc % TX + 2;
+        S rho = s_rho[c], pw = S(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          S gd = S(SC.grav[d]);
+          R[k][2 + d] += rho * gd;
+          pw += U[d][c] * gd;
+        }
+        R[k][2 + D] += rho * pw;
+      }
+    }
+  }
+
+  // ---- output
+  if (!upd) {
+    // right-hand side in the conserved variables (rho, rho u, rho E, rho xi), FP64,
+    // in the caller's layout [N_q][ncell] of this case
+#pragma unroll
     for (int k = 0; k < CPT; ++k) {
       int cc = tid + k * NT;
       int i = cc % TX, j = cc / TX;
       int gx = x0 + i, gy = y0 + j;
       if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
-        long long cell = C.off + gx + (long long)C.n[0] * gy;
-        S nv[NQ];
-  #pragma unroll
-        for (int v = 0; v < NQ; ++v) {
-          nv[v] = qn_reg[k][v] + adt * R[k][v];
-          dst[v * T + cell] = nv[v];
-        }
-        if (a.stage == 3) {
-          double q[NQ], u[D], rho, Y, Y2;
-          q[0] = (double)nv[0] + C.rref[0];
-          q[1] = (double)nv[1] + C.rref[1];
-  #pragma unroll
-          for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
-          if constexpr (G2) q[NQ - 1] += C.rref[2];
-          PT pt = cell_prim_any<D, PRK, G2>(C, q, u, rho, Y, Y2);
-          double l = cfl_rate<D, G2>(C, u, pt, rho, Y, Y2);
-          bool finite = isfinite(l) && isfinite(pt.p);
-          if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
-          else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
-          else lam = fmax(lam, l);
-        }
+        const long long RS = C.ncell;
+        long long cell = gx + (long long)C.n[0] * gy;
+        double r0 = (double)R[k][0], r1 = (double)R[k][1];
+        double r2 = G2 ? (double)R[k][NQ - 1] : 0.0;
+        a.rhs_out[cell] = G2 ? r0 + r1 + r2 : r0 + r1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) a.rhs_out[(1 + d) * RS + cell] = (double)R[k][2 + d];
+        double rE = (double)R[k][2 + D] + C.Q[0] * r0 + C.Q[1] * r1;
+        a.rhs_out[(1 + D) * RS + cell] = G2 ? rE + C.Q[2] * r2 : rE;
+        a.rhs_out[(2 + D) * RS + cell] = r1;
+        if constexpr (G2) a.rhs_out[(3 + D) * RS + cell] = r2;
       }
     }
-    if (a.stage == 3) {
-      lam = wave_max(lam);
-      if ((tid & 63) == 0) s_red[tid >> 6] = lam;
-      __syncthreads();
-      if (tid == 0) {
-        double m = s_red[0];
-        for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
-        cfl_max(dy, (int)((step + 1) & 1), m);
+    return;
+  }
+  const double dt = step_dt(dy, step, SC.cfl, SC.t_end);
+  if (a.stage == 0 && tl.y == 0 && tl.z == 0 && tl.w == 0 && tid == 0) step_scalars(dy, step, dt);
+  S* dst = (S*)a.dst;
+  const S adt = S(a.ak * dt);
+  double lam = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int cc = tid + k * NT;
+    int i = cc % TX, j = cc / TX;
+    int gx = x0 + i, gy = y0 + j;
+    if (cc < NC && gx < C.n[0] && (D == 1 || gy < C.n[1])) {
+      long long cell = C.off + gx + (long long)C.n[0] * gy;
+      S nv[NQ];
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        nv[v] = qn_reg[k][v] + adt * R[k][v];
+        dst[v * T + cell] = nv[v];
       }
+      if (a.stage == 3) {
+        double q[NQ], u[D], rho, Y, Y2;
+        q[0] = (double)nv[0] + C.rref[0];
+        q[1] = (double)nv[1] + C.rref[1];
+#pragma unroll
+        for (int v = 2; v < NQ; ++v) q[v] = (double)nv[v];
+        if constexpr (G2) q[NQ - 1] += C.rref[2];
+        PT pt = cell_prim_any<D, PRK, G2>(C, q, u, rho, Y, Y2);
+        double l = cfl_rate<D, G2>(C, u, pt, rho, Y, Y2);
+        bool finite = isfinite(l) && isfinite(pt.p);
+        if (!finite) record_error(dy, ERR_NAN, cell - C.off, step);
+        else if (!(rho > 0.0) || !(pt.T > 0.0) || !pt.ok) record_error(dy, ERR_NONPHYS, cell - C.off, step);
+        else lam = fmax(lam, l);
+      }
+    }
+  }
+  if (a.stage == 3) {
+    lam = wave_max(lam);
+    if ((tid & 63) == 0) s_red[tid >> 6] = lam;
+    __syncthreads();
+    if (tid == 0) {
+      double m = s_red[0];
+      for (int w = 1; w < NT / 64; ++w) m = fmax(m, s_red[w]);
+      cfl_max(dy, (int)((step + 1) & 1), m);
     }
   }
 }
@@ -406,15 +401,7 @@ static hipError_t launch12(const StageArgs& a, int ntiles, hipStream_t st)
 {
   // the Peng-Robinson closure needs more registers than the stiffened-gas one
   constexpr int W = PRK ? 1 : MINW;
-  // a tile table longer than the resident workgroups is walked by a grid of
-  // that many (a batch of small cases: one launch covers tens of thousands of
-  // tiles, and the persistent walk saves a quarter of the stage time there)
-  static std::atomic<int> resident[FVM_RESIDENT_DEVICES];
-  StageArgs b = a;
-  b.ntiles = ntiles;
-  const int grid = resident_grid(reinterpret_cast<const void*>(&k_stage12<S, D, TX, TY, NT, W, PRK, G2, LIM>), NT,
-                                 resident, ntiles);
-  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, W, PRK, G2, LIM>), dim3(grid), dim3(NT), 0, st, b);
+  hipLaunchKernelGGL((k_stage12<S, D, TX, TY, NT, W, PRK, G2, LIM>), dim3(ntiles), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 

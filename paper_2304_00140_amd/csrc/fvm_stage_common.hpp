@@ -3,7 +3,6 @@
 // a cell, error recording, wavefront max and the per-step scalars.
 #pragma once
 #include <hip/hip_runtime.h>
-#include <atomic>
 #include "fvm_device.hpp"
 
 namespace fvm {
@@ -237,32 +236,6 @@ __device__ inline int xcd_block(int b, int n)
   constexpr int NX = 8;
   int q = n / NX, r = n % NX, k = b % NX;
   return k * q + (k < r ? k : r) + b / NX;
-}
-
-// Resident workgroups of a kernel on the current device (occupancy per CU
-// times the CUs), computed once per device and kept in `cache`; the launch
-// grid for n tiles is the smaller of the two.  A grid that is a multiple of 8
-// keeps every workgroup of a grid-stride walk on one XCD: block b takes tiles
-// b, b + grid, ... whose xcd_block images lie in that XCD's run.  If the
-// queries fail the grid is n, one tile per workgroup.
-#define FVM_RESIDENT_DEVICES 64
-inline int resident_grid(const void* kern, int nthreads, std::atomic<int>* cache, int n)
-{
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= FVM_RESIDENT_DEVICES) return n;
-  int g = cache[dev].load(std::memory_order_relaxed);
-  if (g == 0) {
-    int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nthreads, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
-        ncu <= 0) {
-      (void)hipGetLastError();
-      return n;
-    }
-    g = per_cu * ncu;
-    cache[dev].store(g, std::memory_order_relaxed);
-  }
-  return n < g ? n : g;
 }
 
 // ------------------------------------------------------------------ viscous stress, heat conduction

@@ -166,7 +166,7 @@ __device__ inline double pr_log(double V, double b)
 // of the inflection point with a positive slope, which makes it the largest
 // root.  Newton stops once a correction falls below 1e-9 Z: the error left is
 // then of order Z 1e-18.
-__device__ inline double pr_cubic_newton(double Z, double c2, double c1, double c0, int& ok)
+__device__ inline double pr_cubic_newton(double Z, double c2, double c1, double c0, int& ok, double tol = 1e-9)
 {
   ok = 0;
   for (int it = 0; it < 60; ++it) {
@@ -174,12 +174,14 @@ __device__ inline double pr_cubic_newton(double Z, double c2, double c1, double 
     double fp = (3.0 * Z + 2.0 * c2) * Z + c1;
     double dZ = f * frcp(fp);
     Z -= dZ;
-    if (fabs(dZ) <= 1e-9 * fabs(Z)) { ok = 1; break; }
+    if (fabs(dZ) <= tol * fabs(Z)) { ok = 1; break; }
   }
   return Z;
 }
 
-__device__ inline double pr_volume(double p, double T, double a, double b, double Z0 = 0.0)
+// tol: the relative correction at which Newton stops (1e-9: the error left is
+// of order 1e-18; 1e-6, for face states rounded to FP32: of order 1e-12)
+__device__ inline double pr_volume(double p, double T, double a, double b, double Z0 = 0.0, double tol = 1e-9)
 {
   double RT = R_UNIV * T, iRT = frcp(RT);
   double Bd = b * p * iRT, Ad = a * p * iRT * iRT;
@@ -187,10 +189,10 @@ __device__ inline double pr_volume(double p, double T, double a, double b, doubl
   int ok = 0;
   double Z = 0.0;
   if (Z0 > Bd && Z0 < 1e300) {
-    Z = pr_cubic_newton(Z0, c2, c1, c0, ok);
+    Z = pr_cubic_newton(Z0, c2, c1, c0, ok, tol);
     ok = ok && Z > -c2 * (1.0 / 3.0) && (3.0 * Z + 2.0 * c2) * Z + c1 > 0.0;
   }
-  if (!ok) Z = pr_cubic_newton(1.0 + Bd, c2, c1, c0, ok);
+  if (!ok) Z = pr_cubic_newton(1.0 + Bd, c2, c1, c0, ok, tol);
   return Z * RT * frcp(p);
 }
 
@@ -468,8 +470,12 @@ __device__ inline void tdu3(const CaseC& C, R ps, R Tf, R Y1, R Y2, R& rf, R& ef
 }
 
 // forward closure at (p, T, xi) in FP64: 1 / rho and e (storage gauge).  Z0:
-// a start for the Peng-Robinson compressibility (0: none)
-template <bool PRK>
+// a start for the Peng-Robinson compressibility (0: none).  F32: the result
+// is rounded to FP32 (face states of the FP32-storage path), so the
+// Peng-Robinson compressibility stops at a relative correction of 1e-6, and
+// sqrt(T) and the departure energy's logarithm are taken in FP32; the cubic
+// itself stays in FP64
+template <bool PRK, bool F32 = false>
 __device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y, double& vmix, double& e,
                                    double Z0 = 0.0)
 {
@@ -485,12 +491,16 @@ __device__ inline void closure_fwd(const CaseC& C, double p, double T, double Y,
       vk = c.A * T * frcp(p + c.pinf);
       ek = c.cv * T + c.pinf * vk + c.qs;
     } else {
-      // a - T a' = pa_0 - pa_1 sqrt(T) / 2
-      double sT = sqrt(T);
+      // a - T a' = pa_0 - pa_1 sqrt(T) / 2 (with F32, T is an FP32 face value
+      // and its square root is taken in FP32)
+      double sT = F32 ? (double)sqrtf((float)T) : sqrt(T);
       double a = fma(c.pa_2, T, c.pa_0 - c.pa_1 * sT);
-      double V = pr_volume(p, T, a, c.b, Z0);
+      double V = pr_volume(p, T, a, c.b, Z0, F32 ? 1e-6 : 1e-9);
       vk = V * c.iM;
-      ek = c.cv * T + c.qs + (c.pa_0 - 0.5 * c.pa_1 * sT) * c.ikb * pr_log(V, c.b);
+      double L;
+      if constexpr (F32) L = (double)logf((float)((V + (1.0 - SQRT2) * c.b) * frcp(V + (1.0 + SQRT2) * c.b)));
+      else L = pr_log(V, c.b);
+      ek = c.cv * T + c.qs + (c.pa_0 - 0.5 * c.pa_1 * sT) * c.ikb * L;
     }
     vmix += Yk[k] * vk;
     e += Yk[k] * ek;
@@ -662,7 +672,7 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
       Z0 = (double)ps * C.comp[1].M * frcp(rup * R_UNIV * (double)Tf);
     }
     double vm, em;
-    closure_fwd<PRK>(C, (double)ps, (double)Tf, (double)Yf, vm, em, Z0);
+    closure_fwd<PRK, sizeof(R) == 4>(C, (double)ps, (double)Tf, (double)Yf, vm, em, Z0);
     rf = R(frcp(vm));
     ef = R(em);
   }

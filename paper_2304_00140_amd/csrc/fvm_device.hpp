@@ -375,32 +375,21 @@ __device__ inline PT closure(const CaseC& C, double rho, double Y, double e, dou
       return r;
     }
     if (Y == 1.0) {
-      // pure Peng-Robinson: Newton on T at fixed v (Appendix B), then p from (A.2.1)
-      // e(T) = cv T + q + (a - T a') k with a - T a' = pa_0 - pa_1 sqrt(T) / 2 and
-      // de/dT = cv - k pa_1 / (4 sqrt(T)) at this cell's fixed V
+      // pure Peng-Robinson at this cell's fixed V: e(T) = cv T + q + (a - T a') k
+      // with a - T a' = pa_0 - pa_1 sqrt(T) / 2 is a quadratic in s = sqrt(T),
+      //   cv s^2 - beta s - gam = 0,  beta = pa_1 k / 2,  gam = e - q - pa_0 k,
+      // whose positive root is taken in the form without cancellation (Appendix
+      // B solves the same equation by Newton; this is its exact solution); p
+      // then follows from (A.2.1)
       double V = c1.M * v;
       double L = pr_log(V, c1.b);
       double k = L * c1.ikb;
-      double Tn = 0.0;
-      int conv = 0;
-      for (int start = (Tw > 0.0 && Tw < 1e300) ? 0 : 1; start < 2 && !conv; ++start) {
-        if (start == 0) {
-          Tn = Tw;
-        } else {
-          Tn = (e - c1.qs) / c1.cv;
-          if (!(Tn > 0.0)) Tn = 100.0;
-        }
-        for (int it = 0; it < 60; ++it) {
-          double sT = sqrt(Tn);
-          double f = c1.cv * Tn + c1.qs + (c1.pa_0 - 0.5 * c1.pa_1 * sT) * k - e;
-          double fp = c1.cv - 0.25 * k * c1.pa_1 * frcp(sT);
-          double dT = f * frcp(fp);
-          double Tnew = Tn - dT;
-          if (Tnew <= 0.0) Tnew = 0.5 * Tn;
-          Tn = Tnew;
-          if (fabs(dT) <= 1e-13 * Tn) { conv = 1; break; }
-        }
-      }
+      double beta = 0.5 * c1.pa_1 * k, gam = e - c1.qs - c1.pa_0 * k;
+      double D = fma(beta, beta, 4.0 * c1.cv * gam);
+      double sD = sqrt(fmax(D, 0.0));
+      double sT = beta >= 0.0 ? 0.5 * (beta + sD) * frcp(c1.cv) : 2.0 * gam * frcp(sD - beta);
+      double Tn = sT * sT;
+      int conv = gam > 0.0 && D >= 0.0 && sT > 0.0;
       PRab A = pr_a(c1, Tn);
       r.T = Tn;
       r.p = R_UNIV * Tn * frcp(V - c1.b) - A.a * frcp(V * V + 2.0 * c1.b * V - c1.b * c1.b);

@@ -20,8 +20,10 @@ constexpr int nw3() { return G2 ? 11 : 9; }
 // the cells hold q^n, so this kernel also folds the CFL bound of q^n into the
 // case's slot for this step (read by the face kernel of the same stage) and
 // reports a non-finite or non-physical q^n as an error of the step before.
+// Four waves per SIMD: the Peng-Robinson closure fits 127 VGPRs without
+// spills (it took 133, three waves, when left free)
 template <class S, int TX, int TY, int TZ, bool PRK, bool G2>
-__global__ __launch_bounds__(256) void k_prim3(StageArgs a, S* __restrict__ W)
+__global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W)
 {
   __shared__ double s_red[4];
   // PB workgroups of 256 threads per tile, one cell per thread

@@ -254,3 +254,65 @@ def test_drop_at_its_configured_length(dev, stream):
         ratio = np.mean(jumps[name]) * R / sig
         print(f"drop {name}: mean Laplace jump {ratio:.4f} sigma/R (last {jumps[name][-1] * R / sig:.4f})", flush=True)
         assert 0.85 < ratio < 1.15
+
+
+def test_bubble_collapse_batch_mixed_at_its_configured_length(dev, stream):
+    """the batch configuration's 500 steps: every case's mixed-path state
+    (FP32 storage and fluxes, FP64 closure) against its FP64-path state in
+    rho, u (U_ref = sqrt(p_far / 1000 kg/m^3), the collapse's velocity scale),
+    p and xi, with the FP64 path started from its own state rounded to FP32
+    beside it as the collapse's response to a rounding-sized perturbation.
+    Bar per case and field: 1e-4, or twice that sensitivity where larger."""
+    from oracle.oracle import Oracle
+    from paper_2304_00140_amd import fvm, tune
+    cases = W.bubble_collapse_batch(256, steps=500)
+    runs = {}
+    for name, prec in (("fp64", fvm.FVM_FP64), ("mixed", fvm.FVM_MIXED), ("rounded", fvm.FVM_FP64)):
+        b = fvm.Batch(cases, prec, stream=stream.cuda_stream)
+        for i in range(len(cases)):
+            b.init_primitive(i)
+        tune.autotune(b, prec)
+        for i in range(len(cases)):
+            b.init_primitive(i)
+        runs[name] = b
+    for i in range(len(cases)):
+        runs["rounded"].set_state(i, runs["fp64"].get_state(i).astype(np.float32).astype(np.float64))
+    for b in runs.values():
+        b.n_steps(500)
+    worst, worst_s = {}, {}
+    for i, c in enumerate(cases):
+        o = Oracle(c)
+        wf, wm, wg = (o.prim_from_cons(runs[n].get_state(i)) for n in ("fp64", "mixed", "rounded"))
+        uref = (c["grid"]["farfield"]["p"] / 1000.0) ** 0.5
+        e, es = l1_fields(wm, wf, uref), l1_fields(wg, wf, uref)
+        for f in e:
+            worst[f] = max(worst.get(f, 0.0), e[f])
+            worst_s[f] = max(worst_s.get(f, 0.0), es[f])
+            assert e[f] <= max(1e-4, 2.0 * es[f]), (i, f, e[f], es[f])
+    print(f"batch 500 steps: worst case mixed vs fp64 L1 {worst}; fp64 from FP32-rounded start {worst_s}", flush=True)
+    for b in runs.values():
+        b.close()
+
+
+def test_liquid_jet_mixed_at_its_configured_length(dev, stream):
+    """the jet configuration's 200 steps (512 x 256 x 256, the benchmark's
+    tiles): the mixed path against the FP64 path in rho, u (U_ref = 300 m/s),
+    p and xi, the FP64 path from its FP32-rounded start beside it.  Bar per
+    field: 1e-4, or twice that sensitivity where larger."""
+    from paper_2304_00140_amd import fvm
+    case = W.liquid_jet_3d(512, 256, 256, 200)
+    h, htile = bench_context(case, fvm.FVM_FP64, stream)
+    m, _ = bench_context(case, fvm.FVM_MIXED, stream)
+    g = fvm.Context(case, fvm.FVM_FP64, stream=stream.cuda_stream)
+    g.set_tile(htile)
+    g.set_state(h.get_state().astype(np.float32).astype(np.float64))
+    for c in (h, m, g):
+        c.n_steps(200)
+    wf = h.get_primitive()
+    e = l1_fields(m.get_primitive(), wf, 300.0)
+    es = l1_fields(g.get_primitive(), wf, 300.0)
+    print(f"jet 200 steps mixed vs fp64 L1 {e}; fp64 from FP32-rounded start {es}", flush=True)
+    for f in e:
+        assert e[f] <= max(1e-4, 2.0 * es[f]), f
+    for c in (h, m, g):
+        c.close()

@@ -107,13 +107,18 @@ typedef struct {
   double sigma;         /* surface tension [N/m]; 0 disables the CSF source */
   double eps_normal;    /* interface-normal regularisation, times 1/dx */
   double gravity[3];    /* body-force acceleration g [m/s^2] (eq. 2-2, source Q) */
+  /* thermal variable reconstructed at a face (Appendix B): 0 the temperature,
+   * with rho_f, e_f from the closure at (p*, T_f, xi_f); 1 the specific
+   * internal energy, reconstructed as T would be, with rho_f from the closure
+   * at (p*, xi_f, e_f) (two stiffened-gas components only) */
+  int thermal;
 } og_scheme;
 
 /* primitive vector of one cell.  Y2, A2: second gas (0 with two components);
- * AV: vapour volume fraction (barotropic model; 0 otherwise); T is 0 in the
- * barotropic model */
+ * AV: vapour volume fraction (barotropic model; 0 otherwise); E: specific
+ * internal energy; T and E are 0 in the barotropic model */
 enum { OW_RHO = 0, OW_U = 1, OW_V = 2, OW_W = 3, OW_P = 4, OW_T = 5, OW_Y = 6, OW_C = 7, OW_A = 8,
-       OW_Y2 = 9, OW_A2 = 10, OW_AV = 11, OW_N = 12 };
+       OW_Y2 = 9, OW_A2 = 10, OW_AV = 11, OW_E = 12, OW_N = 13 };
 
 /* ---- thermodynamics (Appendix A) ---- */
 /* number of components (2 or 3) and of conserved fields */
@@ -121,6 +126,9 @@ int og_ncomp(const og_eos* e);
 int og_nq(const og_grid* g, const og_eos* e);
 /* two components: Y is the mass fraction of component 1 */
 int og_eos_forward(const og_eos* e, double p, double T, double Y, double* rho, double* ein);
+/* (p, e, xi) -> (rho, T) for two stiffened-gas components in p-T equilibrium;
+ * -1 for other closures or a state with no positive T */
+int og_eos_forward_e(const og_eos* e, double p, double ein, double Y, double* rho, double* T);
 int og_eos_inverse(const og_eos* e, double rho, double ein, double Y, double Tguess,
                    double* p, double* T);
 /* any number of components: Y1, Y2 the gas mass fractions (Y2 = 0 with two) */

@@ -12,6 +12,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 MAXSPEC = 4
+# rows of a cell's primitive vector in oracle.h (the last, OW_E, is the
+# specific internal energy)
+OW_N = 13
 
 
 class Grid(C.Structure):
@@ -46,7 +49,8 @@ class Scheme(C.Structure):
                 ("beta", C.c_double), ("thinc_gamma", C.c_double), ("eps_interface", C.c_double),
                 ("theta_ducros", C.c_double), ("theta_gas", C.c_double), ("eps_ducros", C.c_double),
                 ("kappa3", C.c_double), ("rk", C.c_double * 4), ("cfl", C.c_double),
-                ("sigma", C.c_double), ("eps_normal", C.c_double), ("gravity", C.c_double * 3)]
+                ("sigma", C.c_double), ("eps_normal", C.c_double), ("gravity", C.c_double * 3),
+                ("thermal", C.c_int)]
 
 
 RHS_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_void_p)
@@ -65,6 +69,7 @@ def lib():
         pg, pe, ps = C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Scheme)
         sig = {
             "og_eos_forward": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
+            "og_eos_forward_e": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_eos_inverse": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_eos_forward2": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]),
             "og_eos_inverse2": (C.c_int, [pe, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -185,6 +190,7 @@ def make_scheme(sd):
         s.rk[i] = sd["rk"][i]
     for i, gi in enumerate(sd.get("gravity", [0.0, 0.0, 0.0])):
         s.gravity[i] = gi
+    s.thermal = int(sd.get("thermal", 0))
     return s
 
 
@@ -215,12 +221,12 @@ class Oracle:
 
     def prim_from_cons(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
-        W = np.empty((12, self.ncell))
+        W = np.empty((OW_N, self.ncell))
         self._err(self.L.og_prim_from_cons(C.byref(self.g), C.byref(self.e), _dp(q), _dp(W)), "prim_from_cons")
         # rows: rho, u, v, w, p, T, xi_1, c, alpha_1 (+ xi_2, alpha_2 with three components;
         # + xi_2 = 0, alpha_2 = 0, alpha_V in the barotropic model)
         if self.barotropic:
-            return W
+            return W[:12]
         return W[:11] if self.ncomp == 3 else W[:9]
 
     def rhs(self, q, step=0):

@@ -214,6 +214,32 @@ int og_eos_forward(const og_eos* e, double p, double T, double Y, double* rho, d
   return 0;
 }
 
+/* (p, e, xi) -> (rho, T), two stiffened-gas components (Appendix B's face
+ * closure rho* = f(p*, xi*, e*)).  At fixed p each component's volume
+ * v_k = (g_k - 1) cv_k T / (p + pinf_k) (A.1.2) and energy
+ * e_k = cv_k T + pinf_k v_k + q_k (A.1.1, A.1.3) are linear in T, so the
+ * mixture energy sum_k xi_k e_k = e fixes T directly. */
+int og_eos_forward_e(const og_eos* e, double p, double ein, double Y, double* rho, double* T)
+{
+  if (og_ncomp(e) != 2 || e->kind[0] != OG_EOS_SG || e->kind[1] != OG_EOS_SG) return -1;
+  double Yk[2] = {1.0 - Y, Y};
+  double slope = 0.0, offset = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    if (Yk[k] == 0.0) continue;
+    double vT = (e->gamma[k] - 1.0) * e->cv[k] / (p + e->pinf[k]);   /* v_k / T */
+    slope += Yk[k] * (e->cv[k] + e->pinf[k] * vT);
+    offset += Yk[k] * e->q[k];
+  }
+  double t = (ein - offset) / slope;
+  if (!(t > 0.0)) return -1;
+  double v = 0.0;
+  for (int k = 0; k < 2; ++k)
+    if (Yk[k] != 0.0) v += Yk[k] * (e->gamma[k] - 1.0) * e->cv[k] * t / (p + e->pinf[k]);
+  *rho = 1.0 / v;
+  *T = t;
+  return 0;
+}
+
 /* inverse of one stiffened-gas component alone (A.1.1 solved for p) */
 static void sg_pure(const og_eos* e, int k, double rho, double ein, double* p, double* T)
 {

@@ -151,7 +151,7 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
     int rc = og_baro_pressure2(e, rho, Y, Y2, &p);
     W[OW_RHO] = rho;
     W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
-    W[OW_P] = p; W[OW_T] = 0.0; W[OW_Y] = Y; W[OW_Y2] = Y2;
+    W[OW_P] = p; W[OW_T] = 0.0; W[OW_Y] = Y; W[OW_Y2] = Y2; W[OW_E] = 0.0;
     W[OW_C] = og_baro_sound(e, p);
     og_baro_fractions2(e, rho, Y, Y2, p, &W[OW_A], &W[OW_A2], &W[OW_AV]);
     if (rc || !(rho > 0.0) || !(p > 0.0) || !isfinite(p)) return -1;
@@ -165,7 +165,7 @@ static int prim_cell(const og_eos* e, int dim, const double* qc, double* W)
   int rc = og_eos_inverse2(e, rho, ein, Y, Y2, 0.0, &p, &T);
   W[OW_RHO] = rho;
   W[OW_U] = u[0]; W[OW_V] = u[1]; W[OW_W] = u[2];
-  W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y; W[OW_Y2] = Y2;
+  W[OW_P] = p; W[OW_T] = T; W[OW_Y] = Y; W[OW_Y2] = Y2; W[OW_E] = ein;
   W[OW_C] = og_mix_sound2(e, p, T, Y, Y2);
   W[OW_AV] = 0.0;
   if (!three) {

@@ -93,7 +93,10 @@ static void upwind_pair(int lim, double a, double b, double c, double d, double*
  *    term equals p_L - p_R of unlimited upwind-biased states, i.e. the
  *    pressure term of eq. (3-2), which fixes its sign as dissipative;
  *  - TDU (eq. 3-5, Appendix B): the face temperature is reconstructed and
- *    rho_f, e_f follow from the closure at (p*, T_f, xi_f);
+ *    rho_f, e_f follow from the closure at (p*, T_f, xi_f); with
+ *    s->thermal = 1 the specific internal energy is reconstructed in its
+ *    place (same limiter, upwind side, central average) and rho_f follows
+ *    from the closure at (p*, xi_f, e_f);
  *  - flux of eq. (2-2): m = rho_f u*; (m, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*, m xi_f).
  * With three components the second gas fraction xi_2 is reconstructed like
  * xi_1 (limited, THINC where eligible, central) and TDU takes both
@@ -109,13 +112,14 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
   double uf[3] = {0.0, 0.0, 0.0};
   double us, ps, Tf, Yf, Y2f = 0.0;
   const int three = og_ncomp(e) == 3;
+  const int th = s->thermal ? OW_E : OW_T;   /* the reconstructed thermal row */
 
   if (f) {
     double uL[3] = {0, 0, 0}, uR[3] = {0, 0, 0}, pL, pR, TL, TR, YL, YR, Y2L = 0.0, Y2R = 0.0;
     for (int d = 0; d < dim; ++d)
       upwind_pair(s->lim_u, W[0][OW_U + d], W[1][OW_U + d], W[2][OW_U + d], W[3][OW_U + d], &uL[d], &uR[d]);
     upwind_pair(s->lim_s, W[0][OW_P], W[1][OW_P], W[2][OW_P], W[3][OW_P], &pL, &pR);
-    upwind_pair(s->lim_s, W[0][OW_T], W[1][OW_T], W[2][OW_T], W[3][OW_T], &TL, &TR);
+    upwind_pair(s->lim_s, W[0][th], W[1][th], W[2][th], W[3][th], &TL, &TR);
     upwind_pair(s->lim_s, W[0][OW_Y], W[1][OW_Y], W[2][OW_Y], W[3][OW_Y], &YL, &YR);
     if (three) upwind_pair(s->lim_s, W[0][OW_Y2], W[1][OW_Y2], W[2][OW_Y2], W[3][OW_Y2], &Y2L, &Y2R);
     ps = 0.5 * (pL + pR);
@@ -147,7 +151,7 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
     ps = og_central4(W[0][OW_P], W[1][OW_P], W[2][OW_P], W[3][OW_P]);
     double d3p = W[3][OW_P] - 3.0 * W[2][OW_P] + 3.0 * W[1][OW_P] - W[0][OW_P];
     us = uf[dir] + s->kappa3 * d3p / (IL + IR);
-    Tf = 0.5 * (W[1][OW_T] + W[2][OW_T]);
+    Tf = 0.5 * (W[1][th] + W[2][th]);
     Yf = 0.5 * (W[1][OW_Y] + W[2][OW_Y]);
     if (three) Y2f = 0.5 * (W[1][OW_Y2] + W[2][OW_Y2]);
   }
@@ -161,7 +165,13 @@ int og_face_flux(const og_eos* e, const og_scheme* s, int dim, int dir,
     Y2f /= sum;
   }
   double rf, ef;
-  if (og_eos_forward2(e, ps, Tf, Yf, Y2f, &rf, &ef)) return -1;
+  if (s->thermal) {
+    double Tt;
+    if (three || og_eos_forward_e(e, ps, Tf, Yf, &rf, &Tt)) return -1;
+    ef = Tf;
+  } else if (og_eos_forward2(e, ps, Tf, Yf, Y2f, &rf, &ef)) {
+    return -1;
+  }
   double m = rf * us;
   double ke = 0.0;
   for (int d = 0; d < dim; ++d) ke += uf[d] * uf[d];

@@ -208,7 +208,7 @@ def test_liquid_vapour_face_density_is_the_thinc_value():
     L = lib()
     e = make_eos(EOS)
     s = make_scheme(W.default_scheme())
-    Wst = np.zeros((4, 12))
+    Wst = np.zeros((4, 13))
     ps = [0.3 * PS, 0.5 * PS, 0.7 * PS, 0.9 * PS]
     for m in range(4):
         rho = RS * ps[m] / PS

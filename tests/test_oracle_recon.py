@@ -144,7 +144,7 @@ def prim_row(e, p, T, Y, u):
     L().og_eos_forward(C.byref(e), p, T, Y, C.byref(r), C.byref(en))
     c = L().og_mix_sound(C.byref(e), p, T, Y)
     v_g = L().og_spec_volume(C.byref(e), 1, p, T)
-    return [r.value, u[0], u[1], u[2], p, T, Y, c, Y * r.value * v_g, 0.0, 0.0, 0.0], en.value
+    return [r.value, u[0], u[1], u[2], p, T, Y, c, Y * r.value * v_g, 0.0, 0.0, 0.0, en.value], en.value
 
 
 @pytest.mark.parametrize("f", [1, 0])

@@ -126,7 +126,7 @@ def test_vapour_sensor_flags_a_vapour_fraction_jump():
 def _face(rows, f=1, dim=2, d=0):
     e = make_eos(W.make_eos(WATER, AIR))
     s = make_scheme(W.default_scheme())
-    arr = np.zeros((4, 12))
+    arr = np.zeros((4, 13))
     arr[:, :len(rows[0])] = rows
     F = np.zeros(7)
     us, ps = C.c_double(), C.c_double()

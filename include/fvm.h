@@ -168,7 +168,12 @@ typedef struct fvm_eos_desc {
  *   second term only with viscous or conducting fluids);
  * sigma [0]: surface tension (CSF on when > 0); eps_normal [1e-12];
  * gravity[3] [0]: body-force acceleration g [m/s^2] of eq. (2-2): the source
- *   rho g on the momentum and rho u.g on the energy. */
+ *   rho g on the momentum and rho u.g on the energy;
+ * thermal [0]: the thermal variable reconstructed at a face (Appendix B): 0
+ *   the temperature, rho_f and e_f from the closure at (p*, T_f, xi_f); 1 the
+ *   specific internal energy, reconstructed as T would be, rho_f from the
+ *   closure at (p*, xi_f, e_f).  thermal = 1 takes the two-component
+ *   stiffened-gas closure in 1D and 2D (FVM_EINVAL otherwise). */
 typedef struct fvm_scheme_desc {
   int switching, lim_u, lim_s, thinc;
   double beta, thinc_gamma, eps_interface;
@@ -179,6 +184,7 @@ typedef struct fvm_scheme_desc {
   double sigma;
   double eps_normal;
   double gravity[3];
+  int thermal;
 } fvm_scheme_desc;
 
 typedef struct fvm_ctx fvm_ctx;

@@ -157,6 +157,18 @@ static int check_scheme(fvm_batch* b, const fvm_scheme_desc* s)
     return fail(b, FVM_EINVAL, "scheme parameters out of range");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(s->gravity[d])) return fail(b, FVM_EINVAL, "gravity must be finite");
+  if (s->thermal != 0 && s->thermal != 1) return fail(b, FVM_EINVAL, "thermal must be 0 or 1");
+  return FVM_OK;
+}
+
+// the internal-energy face closure is built for the two-component
+// stiffened-gas closure in 1D and 2D
+static int check_thermal(fvm_batch* b, const fvm_scheme_desc* s, int dim, int kind)
+{
+  if (s->thermal == 1 && (dim == 3 || kind != FVM_KIND_SG))
+    return fail(b, FVM_EINVAL,
+                "the internal-energy face closure (thermal = 1) takes the two-component stiffened-gas closure in 1D "
+                "and 2D");
   return FVM_OK;
 }
 
@@ -362,6 +374,7 @@ static void fill_scheme(SchemeC& S, double* rk, const fvm_scheme_desc* s, int di
     S.grav[d] = d < dim ? s->gravity[d] : 0.0;
     if (S.grav[d] != 0.0) S.has_grav = 1;
   }
+  S.recon_e = s->thermal;
   for (int i = 0; i < 4; ++i) rk[i] = s->rk[i];
 }
 
@@ -402,6 +415,7 @@ static int batch_create(fvm_batch** out, int ncases, const fvm_grid_desc* grids,
   }
   if (b->ncomp == 3) b->kind = (b->kind == FVM_KIND_BARO) ? FVM_KIND_BARO2 : FVM_KIND_THREE;
   b->nq = (b->kind >= FVM_KIND_BARO) ? b->dim + b->ncomp : b->dim + b->ncomp + 1;
+  if ((rc = check_thermal(b, s, b->dim, b->kind))) return bail(rc);
   b->total = off;
   fill_scheme(b->sc, b->rk, s, b->dim);
 
@@ -1088,6 +1102,7 @@ extern "C" int fvm_rhs_noalloc(const fvm_grid_desc* g, const fvm_eos_desc* e, co
   const int kind = baro ? (nc == 3 ? FVM_KIND_BARO2 : FVM_KIND_BARO)
                         : (nc == 3 ? FVM_KIND_THREE : (pr ? FVM_KIND_PR : FVM_KIND_SG));
   const int nq = baro ? dim + nc : dim + nc + 1;
+  if ((rc = check_thermal(&eb, s, dim, kind))) return bail(rc);
   const int tile = 0;
   int tx, ty, nt;
   if (fvm_k_tile_shape(dim, tile, &tx, &ty, &nt)) return bail(fail(&eb, FVM_EINVAL, "bad tile"));

@@ -100,6 +100,7 @@ struct SchemeC {
   double t_end;
   double grav[3];      // body-force acceleration
   int has_grav;
+  int recon_e;         // 1: the face reconstructs e (not T); rho_f from (p*, xi_f, e_f)
 };
 
 // ------------------------------------------------------------------ math
@@ -576,6 +577,28 @@ __device__ inline void tdu_sg(const CaseC& C, R ps, R Tf, R Yf, R& rf, R& ef)
        (Yf != R(0) ? Yf * (R(c1.cv) * Tf + P1 * v1 + R(c1.qs)) : R(0));
 }
 
+// Face closure from the internal energy (Appendix B, rho* = f(p*, xi*, e*))
+// for a stiffened-gas pair in precision R: at fixed p each component's volume
+// v_k = A_k T / (p + pinf_k) and energy e_k = cv_k T + pinf_k v_k + q_k are
+// linear in T, so sum_k xi_k e_k = e gives T, then 1 / rho_f.  ef_in is the
+// face energy in the unshifted gauge; ef is returned in the storage gauge
+// (minus sum_k xi_k Q_k)
+template <class R>
+__device__ inline void tdu_sg_e(const CaseC& C, R ps, R ef_in, R Yf, R& rf, R& ef)
+{
+  const Comp& c0 = C.comp[0];
+  const Comp& c1 = C.comp[1];
+  R Y0 = R(1) - Yf;
+  R P0 = R(c0.pinf), P1 = R(c1.pinf);
+  R w0 = R(c0.A) * frcp(ps + P0), w1 = R(c1.A) * frcp(ps + P1);   // v_k / T
+  R slope = (Y0 != R(0) ? Y0 * (R(c0.cv) + P0 * w0) : R(0)) + (Yf != R(0) ? Yf * (R(c1.cv) + P1 * w1) : R(0));
+  R off = (Y0 != R(0) ? Y0 * R(c0.qs + C.Q[0]) : R(0)) + (Yf != R(0) ? Yf * R(c1.qs + C.Q[1]) : R(0));
+  R Tf = (ef_in - off) * frcp(slope);
+  R vs = (Y0 != R(0) ? Y0 * w0 : R(0)) + (Yf != R(0) ? Yf * w1 : R(0));
+  rf = frcp(vs * Tf);
+  ef = ef_in - ((Y0 != R(0) ? Y0 * R(C.Q[0]) : R(0)) + (Yf != R(0) ? Yf * R(C.Q[1]) : R(0)));
+}
+
 // One face (Section 3.2/3.3, Appendix D):
 //  impedances I_L = (3 rho_i + rho_{i+1}) c_m / 4, I_R = (rho_i + 3 rho_{i+1}) c_m / 4;
 //  discontinuous branch: limited upwind-biased states, p* = (p_L + p_R)/2,
@@ -584,7 +607,9 @@ __device__ inline void tdu_sg(const CaseC& C, R ps, R Tf, R Yf, R& rf, R& ef)
 //   an interface cell;
 //  smooth branch: fourth-order central u, p; second-order central T, xi;
 //   u* = u_C + k3 (p_{i+2} - 3 p_{i+1} + 3 p_i - p_{i-1}) / (I_L + I_R);
-//  TDU: rho_f, e_f from the closure at (p*, T_f, xi_f);
+//  TDU: rho_f, e_f from the closure at (p*, T_f, xi_f) (S.recon_e, in the
+//   run-time limiter instantiations: the stencil's T rows hold e and rho_f
+//   follows from the closure at (p*, xi_f, e_f));
 //  flux (storage variables): (m xi_L, m xi_G, m u_f + p* n, m (e_f + |u_f|^2/2) + p* u*).
 // LIM = 1 fixes the default limiters (Koren for velocities, Minmod for p, T,
 // xi) at compile time; LIM = 0 takes the scheme's limiters at run time.
@@ -639,7 +664,9 @@ __device__ inline void face_flux(const SchemeC& S, const CaseC& C, const Stencil
     if constexpr (G2) Y2f = R(0.5) * (s.Y2[1] + s.Y2[2]);
   }
   R rf, ef;
-  if constexpr (G2) {
+  if (LIM == 0 && !G2 && S.recon_e) {
+    tdu_sg_e<R>(C, ps, Tf, Yf, rf, ef);
+  } else if constexpr (G2) {
     // independently reconstructed gas fractions summing above one are
     // rescaled (no liquid mass may leave through a pure-gas face)
     R sum = Yf + Y2f;

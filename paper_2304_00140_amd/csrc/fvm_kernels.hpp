@@ -26,11 +26,13 @@ struct StageArgs {
 enum { FVM_KIND_SG = 0, FVM_KIND_PR = 1, FVM_KIND_THREE = 2, FVM_KIND_BARO = 3, FVM_KIND_BARO2 = 4 };
 
 // the scheme uses the default limiters (Koren for velocities, Minmod for the
-// thermodynamic variables): the stage kernels then take them as compile-time
-// constants instead of branching on the limiter kind at every slope
+// thermodynamic variables) and reconstructs T: the stage kernels then take
+// the limiters as compile-time constants instead of branching on the limiter
+// kind at every slope (the internal-energy face closure runs in the run-time
+// limiter kernels)
 inline bool fvm_default_limiters(const fvm::SchemeC& s)
 {
-  return s.lim_u == fvm::LIM_KOREN && s.lim_s == fvm::LIM_MINMOD;
+  return s.lim_u == fvm::LIM_KOREN && s.lim_s == fvm::LIM_MINMOD && !s.recon_e;
 }
 
 int fvm_k_tile_count(int dim);

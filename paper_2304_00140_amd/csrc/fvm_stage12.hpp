@@ -44,6 +44,9 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
 
   __shared__ S s_rho[NH], s_u[NH], s_v[D == 2 ? NH : 1], s_p[NH], s_T[NH], s_Y[NH], s_c[NH], s_a[NH];
   __shared__ S s_Y2[G2 ? NH : 1], s_a2[G2 ? NH : 1];
+  // specific internal energy, staged for the internal-energy face closure
+  // (run-time limiter kernels only)
+  __shared__ S s_e[(LIM == 0 && !G2) ? NH : 1];
   __shared__ unsigned char s_fl[NH];
   __shared__ S s_F[NQ][NF];
   __shared__ double s_red[NT / 64];
@@ -102,10 +105,26 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
           s_Y2[h] = S(Y2);
           s_a2[h] = S(pt.alpha2);
         }
+        if constexpr (LIM == 0 && !G2) {
+          if (SC.recon_e) {
+            // e in the unshifted gauge (the FP32 storage gauge subtracts
+            // sum_k xi_k Q_k, which the face would otherwise reconstruct
+            // apart from xi)
+            double ke = u[0] * u[0];
+            if (D == 2) ke += u[D - 1] * u[D - 1];
+            s_e[h] = S(qv[it][2 + D] * frcp(rho) - 0.5 * ke + (1.0 - Y) * C.Q[0] + Y * C.Q[1]);
+          }
+        }
       }
     }
   }
   __syncthreads();
+  // the thermal variable a face reconstructs: T, or e with the internal-energy
+  // face closure
+  const S* s_th = s_T;
+  if constexpr (LIM == 0 && !G2) {
+    if (SC.recon_e) s_th = s_e;
+  }
   // total gas volume fraction and mass fraction of a staged cell
   auto aG = [&](int c) -> S {
     if constexpr (G2) return s_a[c] + s_a2[c];
@@ -164,7 +183,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
       st.u[0][m] = s_u[c - 1 + m];
       if (D == 2) st.u[D - 1][m] = s_v[c - 1 + m];
       st.p[m] = s_p[c - 1 + m];
-      st.T[m] = s_T[c - 1 + m];
+      st.T[m] = s_th[c - 1 + m];
       st.Y[m] = s_Y[c - 1 + m];
       if constexpr (G2) st.Y2[m] = s_Y2[c - 1 + m];
     }
@@ -209,7 +228,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
         st.u[0][m] = s_u[cm];
         st.u[D - 1][m] = s_v[cm];
         st.p[m] = s_p[cm];
-        st.T[m] = s_T[cm];
+        st.T[m] = s_th[cm];
         st.Y[m] = s_Y[cm];
         if constexpr (G2) st.Y2[m] = s_Y2[cm];
       }

@@ -47,7 +47,7 @@ class fvm_scheme_desc(C.Structure):
                 ("beta", C.c_double), ("thinc_gamma", C.c_double), ("eps_interface", C.c_double),
                 ("theta_ducros", C.c_double), ("theta_gas", C.c_double), ("eps_ducros", C.c_double),
                 ("kappa3", C.c_double), ("rk", C.c_double * 4), ("cfl", C.c_double), ("sigma", C.c_double),
-                ("eps_normal", C.c_double), ("gravity", C.c_double * 3)]
+                ("eps_normal", C.c_double), ("gravity", C.c_double * 3), ("thermal", C.c_int)]
 
 
 _P = C.c_void_p
@@ -187,6 +187,7 @@ def scheme_desc(sd):
         s.rk[i] = sd["rk"][i]
     for i, gi in enumerate(sd.get("gravity", [0.0, 0.0, 0.0])):
         s.gravity[i] = gi
+    s.thermal = int(sd.get("thermal", 0))
     return s
 
 

@@ -52,20 +52,20 @@ def kernel_source_hash():
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
 MEASURED = {
-    ("liquid_jet_3d", "mixed", 4, "f7173868e969"): {"valu_per_cell_stage": 2253.8, "traffic_bytes": 7421871531},
-    ("liquid_jet_3d", "fp64", 15, "f7173868e969"): {"valu_per_cell_stage": 2732.4, "traffic_bytes": 13401481160},
-    ("liquid_jet_3d", "mixed", 7, "f7173868e969"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523092501},
-    ("liquid_jet_3d", "fp64", 7, "f7173868e969"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5140448955},
-    ("shock_bubble_2d", "fp64", 10, "f7173868e969"): {"valu_per_cell_stage": 860.9, "traffic_bytes": 30463035},
-    ("shock_bubble_2d", "mixed", 10, "f7173868e969"): {"valu_per_cell_stage": 823.6, "traffic_bytes": 15410267},
-    ("bubble_collapse_batch", "mixed", 3, "f7173868e969"): {"valu_per_cell_stage": 1146.9, "traffic_bytes": 432694792},
-    ("bubble_collapse_batch", "fp64", 3, "f7173868e969"): {"valu_per_cell_stage": 1213.1, "traffic_bytes": 862762806},
-    ("vapour_bubble_wall_2d", "fp64", 9, "f7173868e969"): {"valu_per_cell_stage": 990.5, "traffic_bytes": 47640927},
-    ("vapour_bubble_wall_2d", "mixed", 10, "f7173868e969"): {"valu_per_cell_stage": 835.2, "traffic_bytes": 23969865},
-    ("cube_to_sphere_3d", "fp64", 4, "f7173868e969"): {"valu_per_cell_stage": 1770.9, "traffic_bytes": 5419355134},
-    ("cube_to_sphere_3d", "mixed", 4, "f7173868e969"): {"valu_per_cell_stage": 1587.4, "traffic_bytes": 2686417614},
-    ("dual_gas_layer_2d", "fp64", 10, "f7173868e969"): {"valu_per_cell_stage": 1066.1, "traffic_bytes": 71163793},
-    ("dual_gas_layer_2d", "mixed", 9, "f7173868e969"): {"valu_per_cell_stage": 1042.8, "traffic_bytes": 35815932},
+    ("liquid_jet_3d", "mixed", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 2253.8, "traffic_bytes": 7422163526},
+    ("liquid_jet_3d", "fp64", 15, "2bfbd62a8bac"): {"valu_per_cell_stage": 2732.4, "traffic_bytes": 13402497346},
+    ("liquid_jet_3d", "mixed", 7, "2bfbd62a8bac"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523182325},
+    ("liquid_jet_3d", "fp64", 7, "2bfbd62a8bac"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5139570229},
+    ("shock_bubble_2d", "fp64", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 860.9, "traffic_bytes": 30484370},
+    ("shock_bubble_2d", "mixed", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 823.6, "traffic_bytes": 15414101},
+    ("bubble_collapse_batch", "mixed", 3, "2bfbd62a8bac"): {"valu_per_cell_stage": 1146.9, "traffic_bytes": 432701722},
+    ("bubble_collapse_batch", "fp64", 3, "2bfbd62a8bac"): {"valu_per_cell_stage": 1213.1, "traffic_bytes": 862732754},
+    ("vapour_bubble_wall_2d", "fp64", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 990.5, "traffic_bytes": 47640920},
+    ("vapour_bubble_wall_2d", "mixed", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 835.2, "traffic_bytes": 23969867},
+    ("cube_to_sphere_3d", "fp64", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 1770.9, "traffic_bytes": 5419372718},
+    ("cube_to_sphere_3d", "mixed", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 1587.4, "traffic_bytes": 2685621614},
+    ("dual_gas_layer_2d", "fp64", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 1066.1, "traffic_bytes": 71161511},
+    ("dual_gas_layer_2d", "mixed", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 1042.8, "traffic_bytes": 35841346},
 }
 
 

@@ -198,6 +198,20 @@ def kernel_name(case, tile):
     return "k_baro12" if baro else "k_stage12"
 
 
+def linf_errors(a, b, uref):
+    """largest difference of the mixed-path primitives a against FP64-path b:
+    rho and p over the field's largest magnitude, u over U_ref, xi as is"""
+    out = {
+        "rho": float(np.abs(a[0] - b[0]).max() / np.abs(b[0]).max()),
+        "u": float(np.abs(a[1:4] - b[1:4]).max() / uref),
+        "p": float(np.abs(a[4] - b[4]).max() / np.abs(b[4]).max()),
+        "Y": float(np.abs(a[6] - b[6]).max()),
+    }
+    if a.shape[0] in (11,):
+        out["Y2"] = float(np.abs(a[9] - b[9]).max())
+    return out
+
+
 def l1_errors(a, b, uref):
     """relative L1 of the mixed-path primitives a against FP64-path b: rho and
     p over the field's L1 norm, u over N U_ref, xi (and xi_2) over N"""
@@ -346,6 +360,7 @@ def main():
                     "interface_advection_1d": 100.0}.get(args.workload, 1.0)
             wm, wf = res["mixed"]["handle"].get_primitive(), res["fp64"]["handle"].get_primitive()
             out["l1_mixed_vs_fp64"] = l1_errors(wm, wf, uref)
+            out["linf_mixed_vs_fp64"] = linf_errors(wm, wf, uref)
         out[other] = e
     diag = DEFAULT_STEPS["drop_2d"] if args.drop_diag_steps is None else args.drop_diag_steps
     if args.workload == "drop_2d" and diag > 0:

@@ -267,17 +267,27 @@ def cpu_baseline(cases, seconds):
         else:
             case = W.liquid_jet_3d(128, 64, 64, steps=1, viscous=case.get("viscous", False))
     o = Oracle(case)
-    q = o.cons_from_prim()
-    t0 = time.perf_counter()
-    t, k = 0.0, 0
-    while k < 2 or time.perf_counter() - t0 < seconds:
-        t, _ = o.step(q, k, t)
-        k += 1
-    sec = time.perf_counter() - t0
     ncell = int(np.prod(case["grid"]["n"]))
-    return dict(value=ncell * 4 * k / sec, unit="cell-RK-stage updates/s", cores=int(o.L.og_nthreads()),
+
+    def timed(budget):
+        q = o.cons_from_prim()
+        t0 = time.perf_counter()
+        t, k = 0.0, 0
+        while k < 2 or time.perf_counter() - t0 < budget:
+            t, _ = o.step(q, k, t)
+            k += 1
+        return k, time.perf_counter() - t0
+
+    cores = int(o.L.og_nthreads())
+    k, sec = timed(seconds)
+    # the same sample on one thread, over a third of the time
+    o.L.og_set_nthreads(1)
+    k1, sec1 = timed(seconds / 3.0)
+    o.L.og_set_nthreads(cores)
+    return dict(value=ncell * 4 * k / sec, unit="cell-RK-stage updates/s", cores=cores,
                 kind="oracle", sample=f"{case['name']} {'x'.join(str(n) for n in case['grid']['n'][:case['grid']['dim']])}"
-                f" cells, {k} steps from the initial state", seconds=round(sec, 2))
+                f" cells, {k} steps from the initial state", seconds=round(sec, 2),
+                one_thread=dict(value=ncell * 4 * k1 / sec1, steps=k1, seconds=round(sec1, 2)))
 
 
 def main():

@@ -209,6 +209,8 @@ uint64_t og_splitmix64(uint64_t x);
 double og_noise01(uint64_t seed, uint64_t step, uint64_t j, uint64_t k, uint64_t comp);
 
 int og_nthreads(void);
+/* threads of the OpenMP loops from now on (n > 0) */
+void og_set_nthreads(int n);
 const char* og_last_error(void);
 
 #ifdef __cplusplus

@@ -116,6 +116,7 @@ def lib():
             "og_splitmix64": (C.c_uint64, [C.c_uint64]),
             "og_noise01": (C.c_double, [C.c_uint64] * 5),
             "og_nthreads": (C.c_int, []),
+            "og_set_nthreads": (None, [C.c_int]),
             "og_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():

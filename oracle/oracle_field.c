@@ -33,6 +33,15 @@ int og_nthreads(void)
 #endif
 }
 
+void og_set_nthreads(int n)
+{
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void og_pad_init(og_pad* pd, const og_grid* g)
 {
   pd->dim = g->dim;

@@ -64,8 +64,8 @@ MEASURED = {
     ("bubble_collapse_batch", "fp64", 3, "2bfbd62a8bac"): {"valu_per_cell_stage": 1213.1, "traffic_bytes": 862732754},
     ("vapour_bubble_wall_2d", "fp64", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 990.5, "traffic_bytes": 47640920},
     ("vapour_bubble_wall_2d", "mixed", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 835.2, "traffic_bytes": 23969867},
-    ("cube_to_sphere_3d", "fp64", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 1770.9, "traffic_bytes": 5419372718},
-    ("cube_to_sphere_3d", "mixed", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 1587.4, "traffic_bytes": 2685621614},
+    ("cube_to_sphere_3d", "fp64", 16, "2bfbd62a8bac"): {"valu_per_cell_stage": 1805.4, "traffic_bytes": 5396118680},
+    ("cube_to_sphere_3d", "mixed", 15, "2bfbd62a8bac"): {"valu_per_cell_stage": 1631.2, "traffic_bytes": 2679127888},
     ("dual_gas_layer_2d", "fp64", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 1066.1, "traffic_bytes": 71161511},
     ("dual_gas_layer_2d", "mixed", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 1042.8, "traffic_bytes": 35841346},
 }

@@ -79,12 +79,34 @@ __global__ __launch_bounds__(NT, MINW) void k_stage12(StageArgs a)
   // ---- tile + halo: all loads first, then the FP64 closure inversion, primitives to LDS
   {
     double qv[NIT][NQ];
+    if (halo_inside12<S, D>(C, x0, y0, TX, TY)) {
+      // no ghost cell: straight loads at 32-bit byte offsets from the rows' bases
+      const char* base[NQ];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      int h = tid + it * NT;
-      if (h < NH) {
-        int hx = h % HX, hy = h / HX;
-        load_cell<S, D, PRK, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
+      for (int v = 0; v < NQ; ++v) base[v] = (const char*)(src + v * T + C.off);
+      const unsigned n0 = (unsigned)C.n[0];
+      const unsigned org = (unsigned)(x0 - 2) + (D == 2 ? n0 * (unsigned)(y0 - 2) : 0u);
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        int h = tid + it * NT;
+        if (h < NH) {
+          const unsigned hx = h % HX, hy = h / HX;
+          const unsigned off = (org + hx + n0 * hy) * (unsigned)sizeof(S);
+#pragma unroll
+          for (int v = 0; v < NQ; ++v) qv[it][v] = (double)*(const S*)(base[v] + off);
+          qv[it][0] += C.rref[0];
+          qv[it][1] += C.rref[1];
+          if constexpr (G2) qv[it][3 + D] += C.rref[2];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        int h = tid + it * NT;
+        if (h < NH) {
+          int hx = h % HX, hy = h / HX;
+          load_cell<S, D, PRK, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, 0, step, qv[it]);
+        }
       }
     }
 #pragma unroll

@@ -86,12 +86,32 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   }
 
   // ---- tile + halo primitives into LDS
-  for (int h = tid; h < NH; h += NT) {
-    int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
-    S w[NW3];
-    load_prim3<S, PRK, G2>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+  if (halo_inside3<S>(C, x0, y0, z0, TX, TY, TZ)) {
+    // no ghost cell: straight loads at 32-bit byte offsets from the rows' bases
+    const char* base[NW3];
 #pragma unroll
-    for (int v = 0; v < NW3; ++v) s_w[v][h] = w[v];
+    for (int v = 0; v < NW3; ++v) base[v] = (const char*)(W + v * T + C.off);
+    const unsigned n0 = (unsigned)C.n[0], n01 = n0 * (unsigned)C.n[1];
+    const unsigned org = (unsigned)(x0 - 2) + n0 * (unsigned)(y0 - 2) + n01 * (unsigned)(z0 - 2);
+    // unrolled, so that the loads of every pass are in flight together
+#pragma unroll
+    for (int it = 0; it < (NH + NT - 1) / NT; ++it) {
+      const int h = tid + it * NT;
+      if (h < NH) {
+        const unsigned hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+        const unsigned off = (org + hx + n0 * hy + n01 * hz) * (unsigned)sizeof(S);
+#pragma unroll
+        for (int v = 0; v < NW3; ++v) s_w[v][h] = *(const S*)(base[v] + off);
+      }
+    }
+  } else {
+    for (int h = tid; h < NH; h += NT) {
+      int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+      S w[NW3];
+      load_prim3<S, PRK, G2>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+#pragma unroll
+      for (int v = 0; v < NW3; ++v) s_w[v][h] = w[v];
+    }
   }
   __syncthreads();
 

@@ -75,6 +75,18 @@ __device__ inline bool beyond_farfield(const CaseC& C, int gx, int gy, int gz)
   return f;
 }
 
+// true when the two-cell halo of the TX (x TY) tile at x0 (, y0) lies inside
+// its case, so that no cell of it is a ghost, and every cell of the case sits
+// within 32-bit byte offsets of its row's base (the loads of such a tile skip
+// the boundary logic and address in 32 bits)
+template <class S, int D>
+__device__ inline bool halo_inside12(const CaseC& C, int x0, int y0, int TX, int TY)
+{
+  bool in = x0 >= 2 && x0 + TX + 2 <= C.n[0];
+  if (D == 2) in = in && y0 >= 2 && y0 + TY + 2 <= C.n[1];
+  return in && (long long)C.n[0] * (D == 2 ? C.n[1] : 1) * (long long)sizeof(S) <= 0xffffffffLL;
+}
+
 // load one (possibly ghost) cell: physical partial densities, momentum, gauge
 // energy (and the second gas's partial density with G2)
 template <class S, int D, bool PRK, bool G2 = false>

@@ -372,12 +372,32 @@ __global__ __launch_bounds__(NT, MINW) void k_baro12(StageArgs a)
   // ---- tile + halo: loads, FP64 closure, primitives to LDS
   {
     double qv[NIT][NQ];
+    if (halo_inside12<S, D>(C, x0, y0, TX, TY)) {
+      // no ghost cell: straight loads at 32-bit byte offsets from the rows' bases
+      const char* base[NQ];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      int h = tid + it * NT;
-      if (h < NH) {
-        int hx = h % HX, hy = h / HX;
-        baro_load<S, D, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, step, qv[it]);
+      for (int v = 0; v < NQ; ++v) base[v] = (const char*)(src + v * T + C.off);
+      const unsigned n0 = (unsigned)C.n[0];
+      const unsigned org = (unsigned)(x0 - 2) + (D == 2 ? n0 * (unsigned)(y0 - 2) : 0u);
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        int h = tid + it * NT;
+        if (h < NH) {
+          const unsigned hx = h % HX, hy = h / HX;
+          const unsigned off = (org + hx + n0 * hy) * (unsigned)sizeof(S);
+#pragma unroll
+          for (int v = 0; v < NQ; ++v) qv[it][v] = (double)*(const S*)(base[v] + off);
+          qv[it][0] += C.rref[0];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        int h = tid + it * NT;
+        if (h < NH) {
+          int hx = h % HX, hy = h / HX;
+          baro_load<S, D, G2>(C, src, T, x0 + hx - 2, (D == 2) ? y0 + hy - 2 : 0, step, qv[it]);
+        }
       }
     }
 #pragma unroll
@@ -1005,12 +1025,31 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
     }
   }
 
-  for (int h = tid; h < NH; h += NT) {
-    int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
-    S w[NWB3];
-    load_bprim3<S, G2>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+  if (halo_inside3<S>(C, x0, y0, z0, TX, TY, TZ)) {
+    // no ghost cell: straight loads at 32-bit byte offsets from the rows' bases
+    const char* base[NWB3];
 #pragma unroll
-    for (int v = 0; v < NWB3; ++v) s_w[v][h] = w[v];
+    for (int v = 0; v < NWB3; ++v) base[v] = (const char*)(W + v * T + C.off);
+    const unsigned n0 = (unsigned)C.n[0], n01 = n0 * (unsigned)C.n[1];
+    const unsigned org = (unsigned)(x0 - 2) + n0 * (unsigned)(y0 - 2) + n01 * (unsigned)(z0 - 2);
+#pragma unroll
+    for (int it = 0; it < (NH + NT - 1) / NT; ++it) {
+      const int h = tid + it * NT;
+      if (h < NH) {
+        const unsigned hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+        const unsigned off = (org + hx + n0 * hy + n01 * hz) * (unsigned)sizeof(S);
+#pragma unroll
+        for (int v = 0; v < NWB3; ++v) s_w[v][h] = *(const S*)(base[v] + off);
+      }
+    }
+  } else {
+    for (int h = tid; h < NH; h += NT) {
+      int hx = h % HX, hy = (h / HX) % HY, hz = h / HXY;
+      S w[NWB3];
+      load_bprim3<S, G2>(C, W, T, x0 + hx - 2, y0 + hy - 2, z0 + hz - 2, step, w);
+#pragma unroll
+      for (int v = 0; v < NWB3; ++v) s_w[v][h] = w[v];
+    }
   }
   __syncthreads();
 

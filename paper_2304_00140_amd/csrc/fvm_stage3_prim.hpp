@@ -90,17 +90,6 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
   }
 }
 
-// true when the two-cell halo of the TX x TY x TZ tile at (x0, y0, z0) lies
-// inside its case, so that no cell of it is a ghost, and every cell of the
-// case sits within 32-bit byte offsets of its row's base (the loads of such a
-// tile skip the boundary logic and address in 32 bits)
-template <class S>
-__device__ inline bool halo_inside3(const CaseC& C, int x0, int y0, int z0, int TX, int TY, int TZ)
-{
-  return x0 >= 2 && y0 >= 2 && z0 >= 2 && x0 + TX + 2 <= C.n[0] && y0 + TY + 2 <= C.n[1] &&
-         z0 + TZ + 2 <= C.n[2] && (long long)C.n[0] * C.n[1] * C.n[2] * (long long)sizeof(S) <= 0xffffffffLL;
-}
-
 // primitives of one (possibly ghost) cell
 template <class S, bool PRK, bool G2>
 __device__ inline void load_prim3(const CaseC& C, const S* __restrict__ W, long long T, int gx, int gy, int gz,

@@ -87,6 +87,17 @@ __device__ inline bool halo_inside12(const CaseC& C, int x0, int y0, int TX, int
   return in && (long long)C.n[0] * (D == 2 ? C.n[1] : 1) * (long long)sizeof(S) <= 0xffffffffLL;
 }
 
+// true when the two-cell halo of the TX x TY x TZ tile at (x0, y0, z0) lies
+// inside its case, so that no cell of it is a ghost, and every cell of the
+// case sits within 32-bit byte offsets of its row's base (the loads of such a
+// tile skip the boundary logic and address in 32 bits)
+template <class S>
+__device__ inline bool halo_inside3(const CaseC& C, int x0, int y0, int z0, int TX, int TY, int TZ)
+{
+  return x0 >= 2 && y0 >= 2 && z0 >= 2 && x0 + TX + 2 <= C.n[0] && y0 + TY + 2 <= C.n[1] &&
+         z0 + TZ + 2 <= C.n[2] && (long long)C.n[0] * C.n[1] * C.n[2] * (long long)sizeof(S) <= 0xffffffffLL;
+}
+
 // load one (possibly ghost) cell: physical partial densities, momentum, gauge
 // energy (and the second gas's partial density with G2)
 template <class S, int D, bool PRK, bool G2 = false>

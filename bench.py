@@ -52,22 +52,22 @@ def kernel_source_hash():
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
 MEASURED = {
-    ("liquid_jet_3d", "mixed", 4, "2bfbd62a8bac"): {"valu_per_cell_stage": 2253.8, "traffic_bytes": 7422163526},
-    ("liquid_jet_3d", "fp64", 15, "2bfbd62a8bac"): {"valu_per_cell_stage": 2732.4, "traffic_bytes": 13402497346},
-    ("liquid_jet_3d", "mixed", 7, "2bfbd62a8bac"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523182325},
-    ("liquid_jet_3d", "fp64", 7, "2bfbd62a8bac"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5139570229},
-    ("shock_bubble_2d", "fp64", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 860.9, "traffic_bytes": 30484370},
-    ("shock_bubble_2d", "mixed", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 823.6, "traffic_bytes": 15414101},
-    ("drop_2d", "mixed", 1, "2bfbd62a8bac"): {"valu_per_cell_stage": 1430.7, "traffic_bytes": 4050153},
-    ("drop_2d", "fp64", 1, "2bfbd62a8bac"): {"valu_per_cell_stage": 1527.5, "traffic_bytes": 7884537},
-    ("bubble_collapse_batch", "mixed", 3, "2bfbd62a8bac"): {"valu_per_cell_stage": 1146.9, "traffic_bytes": 432701722},
-    ("bubble_collapse_batch", "fp64", 3, "2bfbd62a8bac"): {"valu_per_cell_stage": 1213.1, "traffic_bytes": 862732754},
-    ("vapour_bubble_wall_2d", "fp64", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 990.5, "traffic_bytes": 47640920},
-    ("vapour_bubble_wall_2d", "mixed", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 835.2, "traffic_bytes": 23969867},
-    ("cube_to_sphere_3d", "fp64", 16, "2bfbd62a8bac"): {"valu_per_cell_stage": 1805.4, "traffic_bytes": 5396118680},
-    ("cube_to_sphere_3d", "mixed", 15, "2bfbd62a8bac"): {"valu_per_cell_stage": 1631.2, "traffic_bytes": 2679127888},
-    ("dual_gas_layer_2d", "fp64", 10, "2bfbd62a8bac"): {"valu_per_cell_stage": 1066.1, "traffic_bytes": 71161511},
-    ("dual_gas_layer_2d", "mixed", 9, "2bfbd62a8bac"): {"valu_per_cell_stage": 1042.8, "traffic_bytes": 35841346},
+    ("liquid_jet_3d", "mixed", 4, "e830914dd0d0"): {"valu_per_cell_stage": 2075.5, "traffic_bytes": 7745482595},
+    ("liquid_jet_3d", "fp64", 15, "e830914dd0d0"): {"valu_per_cell_stage": 2505.0, "traffic_bytes": 13416964562},
+    ("liquid_jet_3d", "mixed", 7, "e830914dd0d0"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2474620571},
+    ("liquid_jet_3d", "fp64", 7, "e830914dd0d0"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5025964142},
+    ("shock_bubble_2d", "fp64", 10, "e830914dd0d0"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496584},
+    ("shock_bubble_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420095},
+    ("drop_2d", "mixed", 1, "e830914dd0d0"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
+    ("drop_2d", "fp64", 1, "e830914dd0d0"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879761},
+    ("bubble_collapse_batch", "mixed", 3, "e830914dd0d0"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432779979},
+    ("bubble_collapse_batch", "fp64", 3, "e830914dd0d0"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862827691},
+    ("vapour_bubble_wall_2d", "fp64", 9, "e830914dd0d0"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47634735},
+    ("vapour_bubble_wall_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23962347},
+    ("cube_to_sphere_3d", "fp64", 16, "e830914dd0d0"): {"valu_per_cell_stage": 1669.2, "traffic_bytes": 5517671173},
+    ("cube_to_sphere_3d", "mixed", 15, "e830914dd0d0"): {"valu_per_cell_stage": 1505.8, "traffic_bytes": 2656902674},
+    ("dual_gas_layer_2d", "fp64", 10, "e830914dd0d0"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71435863},
+    ("dual_gas_layer_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798478},
 }
 
 

@@ -981,15 +981,24 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
 
   __shared__ S s_w[NWB3][NH];
   __shared__ unsigned char s_fl[NH];
+  // FP64 kernels skip the CSF term on tiles where it is exactly zero; the tile's
+  // mark lives in s_fl[0], a corner of the two-cell halo that no sensor or face
+  // touches.  (In FP32 storage the test's code costs the face kernels more
+  // registers and time than the skip saves.)  The case table is then read
+  // through the constant address space, which keeps its field loads scalar
+  // past the mark's LDS store
+  constexpr bool CSF_SKIP = sizeof(S) == 8;
+  unsigned char& s_csf = s_fl[0];
   __shared__ S s_buf[NBUF];
   S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
 
   const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
-  const CaseC& C = a.cases[tl.x];
+  const CaseC& C = CSF_SKIP ? case_at(a.cases, tl.x) : a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const SchemeC& SC = a.sc;
   const int x0 = tl.y * TX, y0 = tl.z * TY, z0 = tl.w * TZ;
   const int tid = threadIdx.x;
+  if (CSF_SKIP && tid == 0) s_csf = 0;
   const bool upd = a.stage >= 0;
   const long long step = upd ? dy.base + a.step_off : a.rhs_step;
   const long long T = a.total;
@@ -1052,6 +1061,11 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
     }
   }
   __syncthreads();
+  // FP64 kernels: tiles whose staged gas fractions are all equal skip the CSF
+  // term (exactly zero there); any thread that sees a difference marks the tile
+  if constexpr (CSF_SKIP) {
+    if (SC.sigma > 0.0 && staged_fractions_differ(YG, aG, NH, tid, NT)) s_csf = 1;
+  }
 
   const int st[3] = {1, HX, HXY};
   // ---- switching sensors (Ducros, gas and vapour volume fractions) on tile + one halo layer
@@ -1155,7 +1169,7 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
 
   // ---- CSF (Section 3.5): 3D binomial kernel /64 of xi, vertex normals, kappa = -div n,
   // force sigma kappa grad(alpha_G) on the momentum
-  if (SC.sigma > 0.0) {
+  if (SC.sigma > 0.0 && (!CSF_SKIP || s_csf)) {   // s_csf: marked before at least one barrier
     __syncthreads();
     S* s_H = s_buf;
     S* s_n = s_H + NFH;

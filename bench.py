@@ -52,22 +52,22 @@ def kernel_source_hash():
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
 MEASURED = {
-    ("liquid_jet_3d", "mixed", 4, "e830914dd0d0"): {"valu_per_cell_stage": 2075.5, "traffic_bytes": 7745482595},
-    ("liquid_jet_3d", "fp64", 15, "e830914dd0d0"): {"valu_per_cell_stage": 2505.0, "traffic_bytes": 13416964562},
-    ("liquid_jet_3d", "mixed", 7, "e830914dd0d0"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2474620571},
-    ("liquid_jet_3d", "fp64", 7, "e830914dd0d0"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5025964142},
-    ("shock_bubble_2d", "fp64", 10, "e830914dd0d0"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496584},
-    ("shock_bubble_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420095},
-    ("drop_2d", "mixed", 1, "e830914dd0d0"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
-    ("drop_2d", "fp64", 1, "e830914dd0d0"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879761},
-    ("bubble_collapse_batch", "mixed", 3, "e830914dd0d0"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432779979},
-    ("bubble_collapse_batch", "fp64", 3, "e830914dd0d0"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862827691},
-    ("vapour_bubble_wall_2d", "fp64", 9, "e830914dd0d0"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47634735},
-    ("vapour_bubble_wall_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23962347},
-    ("cube_to_sphere_3d", "fp64", 16, "e830914dd0d0"): {"valu_per_cell_stage": 1669.2, "traffic_bytes": 5517671173},
-    ("cube_to_sphere_3d", "mixed", 15, "e830914dd0d0"): {"valu_per_cell_stage": 1505.8, "traffic_bytes": 2656902674},
-    ("dual_gas_layer_2d", "fp64", 10, "e830914dd0d0"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71435863},
-    ("dual_gas_layer_2d", "mixed", 10, "e830914dd0d0"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798478},
+    ("liquid_jet_3d", "mixed", 4, "28f25f5cf36f"): {"valu_per_cell_stage": 2075.5, "traffic_bytes": 7504846242},
+    ("liquid_jet_3d", "fp64", 15, "28f25f5cf36f"): {"valu_per_cell_stage": 2275.9, "traffic_bytes": 13389913090},
+    ("liquid_jet_3d", "mixed", 7, "28f25f5cf36f"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2473916776},
+    ("liquid_jet_3d", "fp64", 7, "28f25f5cf36f"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5033976213},
+    ("shock_bubble_2d", "fp64", 10, "28f25f5cf36f"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496585},
+    ("shock_bubble_2d", "mixed", 10, "28f25f5cf36f"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420325},
+    ("drop_2d", "mixed", 1, "28f25f5cf36f"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050921},
+    ("drop_2d", "fp64", 1, "28f25f5cf36f"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879764},
+    ("bubble_collapse_batch", "mixed", 3, "28f25f5cf36f"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432794135},
+    ("bubble_collapse_batch", "fp64", 3, "28f25f5cf36f"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862868582},
+    ("vapour_bubble_wall_2d", "fp64", 9, "28f25f5cf36f"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47631826},
+    ("vapour_bubble_wall_2d", "mixed", 10, "28f25f5cf36f"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23969900},
+    ("cube_to_sphere_3d", "fp64", 16, "28f25f5cf36f"): {"valu_per_cell_stage": 1456.3, "traffic_bytes": 5510014840},
+    ("cube_to_sphere_3d", "mixed", 15, "28f25f5cf36f"): {"valu_per_cell_stage": 1505.8, "traffic_bytes": 2644223915},
+    ("dual_gas_layer_2d", "fp64", 10, "28f25f5cf36f"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71409925},
+    ("dual_gas_layer_2d", "mixed", 10, "28f25f5cf36f"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798585},
 }
 
 

@@ -31,6 +31,8 @@ struct fvm_batch {
   size_t esz = 8;
   void* q[3] = {nullptr, nullptr, nullptr};
   void* prim = nullptr;       // 3D: primitives of the stage input
+  void* fext = nullptr;       // 3D four-equation pair tiles: gas-fraction extremes per closure workgroup
+  unsigned char* czero = nullptr;   // and the per-tile marks of a zero CSF term
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   double* dpart = nullptr;
@@ -246,8 +248,21 @@ static int build_tiles(fvm_batch* b)
   }
   if (b->dtiles) (void)hipFree(b->dtiles);
   b->dtiles = nullptr;
+  if (b->fext) (void)hipFree(b->fext);
+  if (b->czero) (void)hipFree(b->czero);
+  b->fext = nullptr;
+  b->czero = nullptr;
   b->ntiles = (int)t.size();
   HIPCHECK(b, hipMalloc(&b->dtiles, sizeof(int4) * t.size()));
+  if (b->dim == 3 && !fvm_k_tile_is_m3(b->tile) && b->kind != FVM_KIND_BARO && b->kind != FVM_KIND_BARO2) {
+    // the closure + face pair of the four-equation model: (min, max) of both
+    // gas fractions per closure workgroup (256 cells; FP64-sized entries) and
+    // one mark per tile, from which the face kernel skips a CSF term that is
+    // exactly zero
+    const size_t pb = ((size_t)tx * ty * zc + 255) / 256;
+    HIPCHECK(b, hipMalloc(&b->fext, sizeof(double) * 4 * pb * t.size()));
+    HIPCHECK(b, hipMalloc((void**)&b->czero, t.size()));
+  }
   HIPCHECK(b, hipMemcpy(b->dtiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
   HIPCHECK(b, hipMemcpy(b->dc, b->hc.data(), sizeof(CaseC) * b->hc.size(), hipMemcpyHostToDevice));
   return FVM_OK;
@@ -280,6 +295,8 @@ static void batch_free(fvm_batch* b)
   for (int i = 0; i < 3; ++i)
     if (b->q[i]) (void)hipFree(b->q[i]);
   if (b->prim) (void)hipFree(b->prim);
+  if (b->fext) (void)hipFree(b->fext);
+  if (b->czero) (void)hipFree(b->czero);
   if (b->dc) (void)hipFree(b->dc);
   if (b->dd) (void)hipFree(b->dd);
   if (b->dtiles) (void)hipFree(b->dtiles);
@@ -509,6 +526,8 @@ static StageArgs stage_args(fvm_batch* b)
   a.total = b->total;
   a.prim = b->prim;
   a.sc = b->sc;
+  a.frac_ext = b->fext;
+  a.csf_zero = b->czero;
   return a;
 }
 

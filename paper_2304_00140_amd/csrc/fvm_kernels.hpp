@@ -18,6 +18,12 @@ struct StageArgs {
   int stage;                  // 0..3, or -1 for a bare right-hand side
   double ak;                  // stage coefficient
   fvm::SchemeC sc;
+  // 3D four-equation pair: per tile-table entry, 1 when the CSF term of the
+  // tile is exactly zero (its staged gas fractions are uniform), written each
+  // stage from the closure kernel's per-tile extremes (frac_ext); null: the
+  // face kernel evaluates the term everywhere
+  const unsigned char* csf_zero;
+  void* frac_ext;
 };
 
 // closure of a batch: stiffened-gas pair, Peng-Robinson component 1, a

@@ -41,7 +41,11 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
   const int cc = (bb % PB) * 256 + threadIdx.x;
   const int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
   const int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
-  if (cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2]) {
+  // this cell's total gas mass and volume fractions as the face kernel stages
+  // them (storage precision, the two gases summed there)
+  S yg = S(0), ag = S(0);
+  const bool in = cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2];
+  if (in) {
     long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
     double q[G2 ? 7 : 6], u[3], rho, Y, Y2 = 0.0;
     q[0] = (double)src[cell] + C.rref[0];
@@ -71,9 +75,13 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
     W[6 * T + cell] = S(Y);
     W[7 * T + cell] = S(pt.c);
     W[8 * T + cell] = S(pt.alpha);
+    yg = S(Y);
+    ag = S(pt.alpha);
     if constexpr (G2) {
       W[9 * T + cell] = S(Y2);
       W[10 * T + cell] = S(pt.alpha2);
+      yg = yg + S(Y2);
+      ag = ag + S(pt.alpha2);
     }
     if (first) {
       double l = cfl_rate<3, G2>(C, u, pt, rho, Y, Y2);
@@ -88,6 +96,75 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
     __syncthreads();
     if (threadIdx.x == 0) cfl_max(dy, (int)(step & 1), fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3])));
   }
+  // with surface tension: the extremes (min, max) of the two fractions over this
+  // workgroup's cells, from which the CSF mark of each face-kernel tile follows
+  // (a NaN widens them to the whole line)
+  if (a.frac_ext && a.sc.sigma > 0.0) {
+    __shared__ S s_ext[4][4];
+    const S inf = S(INFINITY);
+    S e[4] = {inf, -inf, inf, -inf};
+    if (in) {
+      if (yg != yg || ag != ag) {
+        e[0] = -inf; e[1] = inf; e[2] = -inf; e[3] = inf;
+      } else {
+        e[0] = yg; e[1] = yg; e[2] = ag; e[3] = ag;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      e[0] = fmin(e[0], __shfl_xor(e[0], o, 64));
+      e[1] = fmax(e[1], __shfl_xor(e[1], o, 64));
+      e[2] = fmin(e[2], __shfl_xor(e[2], o, 64));
+      e[3] = fmax(e[3], __shfl_xor(e[3], o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) s_ext[threadIdx.x >> 6][m] = e[m];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int m = threadIdx.x;
+      S r = s_ext[0][m];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) r = (m & 1) ? fmax(r, s_ext[w][m]) : fmin(r, s_ext[w][m]);
+      ((S*)a.frac_ext)[(long long)bb * 4 + m] = r;
+    }
+  }
+}
+
+// per tile-table entry of the face kernel: 1 when the tile's two-cell halo
+// lies inside its case and the 27 tiles around it (itself included) hold one
+// value of each gas fraction, so that the CSF term of the tile is exactly zero
+// (zero normals of a uniform smoothed fraction, zero volume-fraction
+// differences); PB closure workgroups per tile, each with its extremes
+template <class S, int TX, int TY, int TZ, int PB>
+__global__ __launch_bounds__(256) void k_csf_zero(StageArgs a, int ntiles, unsigned char* out)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= ntiles) return;
+  const int4 tl = a.tiles[e];
+  const CaseC& C = a.cases[tl.x];
+  unsigned char z = 0;
+  if (halo_inside3<S>(C, tl.y * TX, tl.z * TY, tl.w * TZ, TX, TY, TZ)) {
+    const S* ext = (const S*)a.frac_ext;
+    const S inf = S(INFINITY);
+    S ylo = inf, yhi = -inf, alo = inf, ahi = -inf;
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const long long n = C.tile0 + (tl.y + di) + (long long)C.tiles[0] * ((tl.z + dj) + (long long)C.tiles[1] * (tl.w + dk));
+#pragma unroll
+          for (int b = 0; b < PB; ++b) {
+            const S* x = ext + (n * PB + b) * 4;
+            ylo = fmin(ylo, x[0]);
+            yhi = fmax(yhi, x[1]);
+            alo = fmin(alo, x[2]);
+            ahi = fmax(ahi, x[3]);
+          }
+        }
+    z = (ylo == yhi && alo == ahi) ? 1 : 0;
+  }
+  out[e] = z;
 }
 
 // primitives of one (possibly ghost) cell

@@ -34,24 +34,15 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
 
   __shared__ S s_w[NW3][NH];
   __shared__ unsigned char s_fl[NH];
-  // FP64 kernels skip the CSF term on tiles where it is exactly zero; the tile's
-  // mark lives in s_fl[0], a corner of the two-cell halo that no sensor or face
-  // touches.  (In FP32 storage the test's code costs the face kernels more
-  // registers and time than the skip saves.)  The case table is then read
-  // through the constant address space, which keeps its field loads scalar
-  // past the mark's LDS store
-  constexpr bool CSF_SKIP = sizeof(S) == 8;
-  unsigned char& s_csf = s_fl[0];
   __shared__ S s_buf[NBUF];
   S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
 
   const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
-  const CaseC& C = CSF_SKIP ? case_at(a.cases, tl.x) : a.cases[tl.x];
+  const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const SchemeC& SC = a.sc;
   const int x0 = tl.y * TX, y0 = tl.z * TY, z0 = tl.w * TZ;
   const int tid = threadIdx.x;
-  if (CSF_SKIP && tid == 0) s_csf = 0;
   const bool upd = a.stage >= 0;
   const long long step = upd ? dy.base + a.step_off : a.rhs_step;
   const long long T = a.total;
@@ -123,11 +114,6 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
     }
   }
   __syncthreads();
-  // FP64 kernels: tiles whose staged gas fractions are all equal skip the CSF
-  // term (exactly zero there); any thread that sees a difference marks the tile
-  if constexpr (CSF_SKIP) {
-    if (SC.sigma > 0.0 && staged_fractions_differ(YG, aG, NH, tid, NT)) s_csf = 1;
-  }
 
   const int st[3] = {1, HX, HXY};
   // ---- switching sensors on tile + one halo layer
@@ -223,7 +209,9 @@ __global__ __launch_bounds__(NT, MINW) void k_face3(StageArgs a, const S* __rest
   }
 
   // ---- CSF (Section 3.5): 3D binomial kernel /64, vertex normals, kappa = -div n
-  if (SC.sigma > 0.0 && (!CSF_SKIP || s_csf)) {   // s_csf: marked before at least one barrier
+  // a tile whose staged gas fractions are all equal (marked by the closure
+  // kernel of this stage, with its neighbours) gets exactly zero from it
+  if (SC.sigma > 0.0 && !(a.csf_zero && a.frac_ext && a.csf_zero[xcd_block(blockIdx.x, gridDim.x)])) {
     __syncthreads();
     S* s_H = s_buf;
     S* s_n = s_H + NFH;    // [3][NV]
@@ -388,6 +376,12 @@ static hipError_t launch3(const StageArgs& a, int ntiles, hipStream_t st)
     hipLaunchKernelGGL((k_prim3<S, TX, TY, TZ, PRK, G2>), dim3(ntiles * PB), dim3(256), 0, st, a, W);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (a.csf_zero && a.frac_ext && a.sc.sigma > 0.0) {
+      hipLaunchKernelGGL((k_csf_zero<S, TX, TY, TZ, PB>), dim3((ntiles + 255) / 256), dim3(256), 0, st, a, ntiles,
+                         (unsigned char*)a.csf_zero);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_face3<S, TX, TY, TZ, NT, Wv, PRK, G2, LIM>), dim3(ntiles), dim3(NT), 0, st, a,
                        (const S*)W);
     return hipGetLastError();

@@ -136,3 +136,26 @@ def test_two_phase_2d_every_tile(dev, stream):
 def test_barotropic_2d_every_tile(dev, stream):
     case = W.random_state(2, [136, 72], 98, barotropic=True, switching=1, sigma=0.05)
     every_tile(case, 2, dev, stream, sens=True)
+
+
+def test_batch3d_equals_single_cases(dev, stream):
+    """two 3D jets of different sizes in one batch (one tile table, the CSF
+    marks built per case from its own tiles) against each case alone: the
+    same bits after three steps, on an 8 x 8 x 8 tile with inside tiles in
+    both cases"""
+    from paper_2304_00140_amd import fvm
+    cases = [W.liquid_jet_3d(nx=40, ny=20, nz=20, cells_per_D=8, steps=3),
+             W.liquid_jet_3d(nx=36, ny=28, nz=20, cells_per_D=8, steps=3)]
+    for prec in (fvm.FVM_FP64, fvm.FVM_MIXED):
+        b = fvm.Batch(cases, prec, stream=stream.cuda_stream)
+        b.set_tile(15)
+        for i in range(len(cases)):
+            b.init_primitive(i)
+        b.n_steps(3)
+        for i, c in enumerate(cases):
+            s = fvm.Context(c, prec, stream=stream.cuda_stream)
+            s.set_tile(15)
+            s.init_primitive()
+            s.n_steps(3)
+            np.testing.assert_array_equal(b.get_state(i), s.get_state())
+            s.close()

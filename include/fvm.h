@@ -191,7 +191,11 @@ typedef struct fvm_ctx fvm_ctx;
 
 /* Create a context for one case.  precision: FVM_FP64 or FVM_MIXED.
  * stream: hipStream_t to launch on (borrowed).  Allocates the state buffers
- * (3 x N_q x ncell words of the storage type) on the current device. */
+ * (3 x N_q x ncell words of the storage type) on the current device; in 3D
+ * also the primitive rows of the closure kernel (9 or 11 x ncell words) and,
+ * for the four-equation closure + face tiles, 32 bytes per 256 cells and one
+ * byte per tile for the surface-tension marks (tables of the tile set by
+ * fvm_set_tile, reallocated with it). */
 int fvm_create(fvm_ctx** out, const fvm_grid_desc* g, const fvm_eos_desc* e,
                const fvm_scheme_desc* s, int precision, void* stream);
 void fvm_destroy(fvm_ctx* ctx);

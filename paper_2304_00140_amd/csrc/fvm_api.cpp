@@ -31,7 +31,7 @@ struct fvm_batch {
   size_t esz = 8;
   void* q[3] = {nullptr, nullptr, nullptr};
   void* prim = nullptr;       // 3D: primitives of the stage input
-  void* fext = nullptr;       // 3D four-equation pair tiles: gas-fraction extremes per closure workgroup
+  void* fext = nullptr;       // 3D pair tiles: gas-fraction extremes per closure workgroup
   unsigned char* czero = nullptr;   // and the per-tile marks of a zero CSF term
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -254,8 +254,8 @@ static int build_tiles(fvm_batch* b)
   b->czero = nullptr;
   b->ntiles = (int)t.size();
   HIPCHECK(b, hipMalloc(&b->dtiles, sizeof(int4) * t.size()));
-  if (b->dim == 3 && !fvm_k_tile_is_m3(b->tile) && b->kind != FVM_KIND_BARO && b->kind != FVM_KIND_BARO2) {
-    // the closure + face pair of the four-equation model: (min, max) of both
+  if (b->dim == 3 && !fvm_k_tile_is_m3(b->tile)) {
+    // the closure + face pair (four-equation or barotropic): (min, max) of both
     // gas fractions per closure workgroup (256 cells; FP64-sized entries) and
     // one mark per tile, from which the face kernel skips a CSF term that is
     // exactly zero

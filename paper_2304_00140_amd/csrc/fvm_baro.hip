@@ -21,6 +21,7 @@
 #include "fvm_device.hpp"
 #include "fvm_kernels.hpp"
 #include "fvm_stage_common.hpp"
+#include "fvm_stage3_prim.hpp"   // k_csf_zero
 
 namespace fvm {
 
@@ -868,7 +869,11 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
   const int cc = (bb % NB) * 256 + threadIdx.x;
   const int i = cc % TX, j = (cc / TX) % TY, k = cc / (TX * TY);
   const int gx = tl.y * TX + i, gy = tl.z * TY + j, gz = tl.w * TZ + k;
-  if (cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2]) {
+  // this cell's total gas mass and volume fractions as the face kernel stages
+  // them (storage precision, the two gases summed there)
+  S yg = S(0), ag = S(0);
+  const bool in = cc < NC && gx < C.n[0] && gy < C.n[1] && gz < C.n[2];
+  if (in) {
     long long cell = C.off + gx + (long long)C.n[0] * (gy + (long long)C.n[1] * gz);
     constexpr int NQ = 5 + (G2 ? 1 : 0);
     double q[NQ], u[3], rho, Y, Y2;
@@ -886,9 +891,13 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
     W[6 * T + cell] = S(pb.aG);
     W[7 * T + cell] = S(pb.aV);
     if constexpr (sizeof(S) == 4) W[8 * T + cell] = S(pb.c);
+    yg = S(Y);
+    ag = S(pb.aG);
     if constexpr (G2) {
       W[(NW - 2) * T + cell] = S(Y2);
       W[(NW - 1) * T + cell] = S(pb.aG2);
+      yg = yg + S(Y2);
+      ag = ag + S(pb.aG2);
     }
     if (first) {
       double l = baro_cfl<3>(C, u, pb, rho);
@@ -903,6 +912,9 @@ __global__ __launch_bounds__(256) void k_bprim3(StageArgs a, S* __restrict__ W)
     __syncthreads();
     if (threadIdx.x == 0) cfl_max(dy, (int)(step & 1), fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3])));
   }
+  // with surface tension: this workgroup's (min, max) of both fractions, from
+  // which k_csf_zero marks the face-kernel tiles whose CSF term is zero
+  if (a.frac_ext && a.sc.sigma > 0.0) frac_extremes<S>(in, yg, ag, (S*)a.frac_ext + (long long)bb * 4);
 }
 
 template <class S, bool G2>
@@ -981,24 +993,15 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
 
   __shared__ S s_w[NWB3][NH];
   __shared__ unsigned char s_fl[NH];
-  // FP64 kernels skip the CSF term on tiles where it is exactly zero; the tile's
-  // mark lives in s_fl[0], a corner of the two-cell halo that no sensor or face
-  // touches.  (In FP32 storage the test's code costs the face kernels more
-  // registers and time than the skip saves.)  The case table is then read
-  // through the constant address space, which keeps its field loads scalar
-  // past the mark's LDS store
-  constexpr bool CSF_SKIP = sizeof(S) == 8;
-  unsigned char& s_csf = s_fl[0];
   __shared__ S s_buf[NBUF];
   S(*s_F)[NF] = reinterpret_cast<S(*)[NF]>(s_buf);
 
   const int4 tl = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
-  const CaseC& C = CSF_SKIP ? case_at(a.cases, tl.x) : a.cases[tl.x];
+  const CaseC& C = a.cases[tl.x];
   CaseDyn& dy = a.dyn[tl.x];
   const SchemeC& SC = a.sc;
   const int x0 = tl.y * TX, y0 = tl.z * TY, z0 = tl.w * TZ;
   const int tid = threadIdx.x;
-  if (CSF_SKIP && tid == 0) s_csf = 0;
   const bool upd = a.stage >= 0;
   const long long step = upd ? dy.base + a.step_off : a.rhs_step;
   const long long T = a.total;
@@ -1061,11 +1064,6 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
     }
   }
   __syncthreads();
-  // FP64 kernels: tiles whose staged gas fractions are all equal skip the CSF
-  // term (exactly zero there); any thread that sees a difference marks the tile
-  if constexpr (CSF_SKIP) {
-    if (SC.sigma > 0.0 && staged_fractions_differ(YG, aG, NH, tid, NT)) s_csf = 1;
-  }
 
   const int st[3] = {1, HX, HXY};
   // ---- switching sensors (Ducros, gas and vapour volume fractions) on tile + one halo layer
@@ -1169,7 +1167,9 @@ __global__ __launch_bounds__(NT, MINW) void k_bface3(StageArgs a, const S* __res
 
   // ---- CSF (Section 3.5): 3D binomial kernel /64 of xi, vertex normals, kappa = -div n,
   // force sigma kappa grad(alpha_G) on the momentum
-  if (SC.sigma > 0.0 && (!CSF_SKIP || s_csf)) {   // s_csf: marked before at least one barrier
+  // a tile whose staged gas fractions are all equal (marked by k_csf_zero from
+  // the closure kernel of this stage, with its neighbours) gets exactly zero
+  if (SC.sigma > 0.0 && !(a.csf_zero && a.frac_ext && a.csf_zero[xcd_block(blockIdx.x, gridDim.x)])) {
     __syncthreads();
     S* s_H = s_buf;
     S* s_n = s_H + NFH;
@@ -1307,6 +1307,12 @@ static hipError_t launch_b3(const StageArgs& a, int ntiles, hipStream_t st)
     hipLaunchKernelGGL((k_bprim3<S, TX, TY, TZ, G2>), dim3(ntiles * NB), dim3(256), 0, st, a, W);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (a.csf_zero && a.frac_ext && a.sc.sigma > 0.0) {
+      hipLaunchKernelGGL((k_csf_zero<S, TX, TY, TZ, NB>), dim3((ntiles + 255) / 256), dim3(256), 0, st, a, ntiles,
+                         (unsigned char*)a.csf_zero);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (fvm_default_limiters(a.sc))
       hipLaunchKernelGGL((k_bface3<S, TX, TY, TZ, NT, MINW, 1, G2>), dim3(ntiles), dim3(NT), 0, st, a, (const S*)W);
     else

@@ -14,6 +14,44 @@ namespace fvm {
 template <bool G2>
 constexpr int nw3() { return G2 ? 11 : 9; }
 
+// (min, max) of a 256-thread workgroup's gas mass fractions yg and volume
+// fractions ag (cells with in == false left out; a NaN widens them to the whole
+// line), stored as out[0..3] = (min yg, max yg, min ag, max ag).  Called by all
+// threads of the workgroup
+template <class S>
+__device__ inline void frac_extremes(bool in, S yg, S ag, S* out)
+{
+  __shared__ S s_ext[4][4];
+  const S inf = S(INFINITY);
+  S e[4] = {inf, -inf, inf, -inf};
+  if (in) {
+    if (yg != yg || ag != ag) {
+      e[0] = -inf; e[1] = inf; e[2] = -inf; e[3] = inf;
+    } else {
+      e[0] = yg; e[1] = yg; e[2] = ag; e[3] = ag;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    e[0] = fmin(e[0], __shfl_xor(e[0], o, 64));
+    e[1] = fmax(e[1], __shfl_xor(e[1], o, 64));
+    e[2] = fmin(e[2], __shfl_xor(e[2], o, 64));
+    e[3] = fmax(e[3], __shfl_xor(e[3], o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s_ext[threadIdx.x >> 6][m] = e[m];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int m = threadIdx.x;
+    S r = s_ext[0][m];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) r = (m & 1) ? fmax(r, s_ext[w][m]) : fmin(r, s_ext[w][m]);
+    out[m] = r;
+  }
+}
+
 // primitives of every owned cell of the tile (a Peng-Robinson closure starts
 // its Newton iterations from the cell's previous primitives, which the paper
 // suggests for convergence speed).  In the first stage of a step
@@ -98,38 +136,7 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
   }
   // with surface tension: the extremes (min, max) of the two fractions over this
   // workgroup's cells, from which the CSF mark of each face-kernel tile follows
-  // (a NaN widens them to the whole line)
-  if (a.frac_ext && a.sc.sigma > 0.0) {
-    __shared__ S s_ext[4][4];
-    const S inf = S(INFINITY);
-    S e[4] = {inf, -inf, inf, -inf};
-    if (in) {
-      if (yg != yg || ag != ag) {
-        e[0] = -inf; e[1] = inf; e[2] = -inf; e[3] = inf;
-      } else {
-        e[0] = yg; e[1] = yg; e[2] = ag; e[3] = ag;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      e[0] = fmin(e[0], __shfl_xor(e[0], o, 64));
-      e[1] = fmax(e[1], __shfl_xor(e[1], o, 64));
-      e[2] = fmin(e[2], __shfl_xor(e[2], o, 64));
-      e[3] = fmax(e[3], __shfl_xor(e[3], o, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) s_ext[threadIdx.x >> 6][m] = e[m];
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      const int m = threadIdx.x;
-      S r = s_ext[0][m];
-#pragma unroll
-      for (int w = 1; w < 4; ++w) r = (m & 1) ? fmax(r, s_ext[w][m]) : fmin(r, s_ext[w][m]);
-      ((S*)a.frac_ext)[(long long)bb * 4 + m] = r;
-    }
-  }
+  if (a.frac_ext && a.sc.sigma > 0.0) frac_extremes<S>(in, yg, ag, (S*)a.frac_ext + (long long)bb * 4);
 }
 
 // per tile-table entry of the face kernel: 1 when the tile's two-cell halo

@@ -98,29 +98,6 @@ __device__ inline bool halo_inside3(const CaseC& C, int x0, int y0, int z0, int 
          z0 + TZ + 2 <= C.n[2] && (long long)C.n[0] * C.n[1] * C.n[2] * (long long)sizeof(S) <= 0xffffffffLL;
 }
 
-// the case table is read-only while a stage kernel runs: reading it through
-// the constant address space lets every uniform field load stay a scalar load,
-// whatever the kernel stores to LDS before it
-__device__ inline const CaseC& case_at(const CaseC* cases, int i)
-{
-  typedef const __attribute__((address_space(4))) CaseC ConstCase;
-  return *(const CaseC*)((ConstCase*)cases + i);
-}
-
-// the CSF term of a tile is exactly zero when the gas fractions it stages are
-// all equal: the smoothed fraction is then uniform, its normals zero, and the
-// volume-fraction differences zero.  True when any of this thread's staged
-// cells h = tid, tid + nt, ... (of nh) differs from cell 0 in either fraction
-// (a NaN counts as a difference)
-template <class FY, class FA>
-__device__ inline bool staged_fractions_differ(FY YG, FA aG, int nh, int tid, int nt)
-{
-  const auto y0 = YG(0), a0 = aG(0);
-  bool d = false;
-  for (int h = tid; h < nh; h += nt) d |= !(YG(h) == y0) || !(aG(h) == a0);
-  return d;
-}
-
 // load one (possibly ghost) cell: physical partial densities, momentum, gauge
 // energy (and the second gas's partial density with G2)
 template <class S, int D, bool PRK, bool G2 = false>

@@ -1,9 +1,11 @@
 """GPU (gfx950) stage kernels on grids large enough that every tile shape has
 tiles whose two-cell halo lies inside the domain (those stage their halo
 without the boundary logic, at 32-bit offsets) next to boundary tiles (the
-per-cell ghost path), and tiles whose staged gas fractions are uniform (the
-FP64 3D face kernels skip the CSF term there, which is exactly zero) next to
-interface tiles.  One FP64 right-hand side on every tile against the oracle.
+per-cell ghost path), and tiles whose 27-tile neighbourhood is uniform in the
+gas fractions (the 3D face kernels skip the CSF term there, which is exactly
+zero, after the closure kernel's extremes and the mark kernel) next to
+interface tiles.  One FP64 right-hand side on every tile against the oracle,
+and a 3D batch against its cases alone in both precisions.
 
 Sizes: a 3D tile of TX x TY x TZ cells at x0 has an inside halo when
 x0 >= 2 and x0 + TX + 2 <= n (likewise y, z); the widest 3D tile row is

@@ -14,40 +14,53 @@ namespace fvm {
 template <bool G2>
 constexpr int nw3() { return G2 ? 11 : 9; }
 
+// the value of the lowest active lane of the wave
+template <class S>
+__device__ inline S first_lane(S v)
+{
+  if constexpr (sizeof(S) == 4) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+}
+
 // (min, max) of a 256-thread workgroup's gas mass fractions yg and volume
-// fractions ag (cells with in == false left out; a NaN widens them to the whole
-// line), stored as out[0..3] = (min yg, max yg, min ag, max ag).  Called by all
-// threads of the workgroup
+// fractions ag over its cells with in == true, stored as out[0..3] = (min yg,
+// max yg, min ag, max ag) where they are uniform; a workgroup whose cells
+// differ (a NaN counts) stores the whole line, one without cells the empty
+// interval.  Each wave compares its cells with its first one (a ballot, no
+// shuffles); called by all threads of the workgroup
 template <class S>
 __device__ inline void frac_extremes(bool in, S yg, S ag, S* out)
 {
   __shared__ S s_ext[4][4];
   const S inf = S(INFINITY);
-  S e[4] = {inf, -inf, inf, -inf};
-  if (in) {
-    if (yg != yg || ag != ag) {
-      e[0] = -inf; e[1] = inf; e[2] = -inf; e[3] = inf;
-    } else {
-      e[0] = yg; e[1] = yg; e[2] = ag; e[3] = ag;
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    e[0] = fmin(e[0], __shfl_xor(e[0], o, 64));
-    e[1] = fmax(e[1], __shfl_xor(e[1], o, 64));
-    e[2] = fmin(e[2], __shfl_xor(e[2], o, 64));
-    e[3] = fmax(e[3], __shfl_xor(e[3], o, 64));
-  }
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) s_ext[threadIdx.x >> 6][m] = e[m];
+    s_ext[w][0] = inf; s_ext[w][1] = -inf; s_ext[w][2] = inf; s_ext[w][3] = -inf;
+  }
+  if (in) {
+    const S y0 = first_lane(yg), a0 = first_lane(ag);
+    const unsigned long long diff = __ballot(!(yg == y0) || !(ag == a0));
+    const unsigned long long act = __ballot(1);
+    if (__lane_id() == __ffsll((long long)act) - 1) {
+      if (diff) {
+        s_ext[w][0] = -inf; s_ext[w][1] = inf; s_ext[w][2] = -inf; s_ext[w][3] = inf;
+      } else {
+        s_ext[w][0] = y0; s_ext[w][1] = y0; s_ext[w][2] = a0; s_ext[w][3] = a0;
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x < 4) {
     const int m = threadIdx.x;
     S r = s_ext[0][m];
 #pragma unroll
-    for (int w = 1; w < 4; ++w) r = (m & 1) ? fmax(r, s_ext[w][m]) : fmin(r, s_ext[w][m]);
+    for (int v = 1; v < 4; ++v) r = (m & 1) ? fmax(r, s_ext[v][m]) : fmin(r, s_ext[v][m]);
     out[m] = r;
   }
 }

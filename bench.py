@@ -52,22 +52,22 @@ def kernel_source_hash():
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
 MEASURED = {
-    ("liquid_jet_3d", "mixed", 4, "7614c1f0d989"): {"valu_per_cell_stage": 1917.8, "traffic_bytes": 7509416358},
-    ("liquid_jet_3d", "fp64", 15, "7614c1f0d989"): {"valu_per_cell_stage": 2383.2, "traffic_bytes": 13448679640},
-    ("liquid_jet_3d", "mixed", 7, "7614c1f0d989"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523525710},
-    ("liquid_jet_3d", "fp64", 7, "7614c1f0d989"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5142890786},
-    ("shock_bubble_2d", "fp64", 10, "7614c1f0d989"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496588},
-    ("shock_bubble_2d", "mixed", 10, "7614c1f0d989"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420370},
-    ("drop_2d", "mixed", 1, "7614c1f0d989"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
-    ("drop_2d", "fp64", 1, "7614c1f0d989"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879758},
-    ("bubble_collapse_batch", "mixed", 3, "7614c1f0d989"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432793701},
-    ("bubble_collapse_batch", "fp64", 3, "7614c1f0d989"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862827998},
-    ("vapour_bubble_wall_2d", "fp64", 9, "7614c1f0d989"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47624942},
-    ("vapour_bubble_wall_2d", "mixed", 10, "7614c1f0d989"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23957215},
-    ("cube_to_sphere_3d", "fp64", 16, "7614c1f0d989"): {"valu_per_cell_stage": 1575.5, "traffic_bytes": 5303847386},
-    ("cube_to_sphere_3d", "mixed", 15, "7614c1f0d989"): {"valu_per_cell_stage": 1374.5, "traffic_bytes": 2719492826},
-    ("dual_gas_layer_2d", "fp64", 10, "7614c1f0d989"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71382056},
-    ("dual_gas_layer_2d", "mixed", 10, "7614c1f0d989"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798513},
+    ("liquid_jet_3d", "mixed", 4, "8a49180734a5"): {"valu_per_cell_stage": 1849.8, "traffic_bytes": 7549845083},
+    ("liquid_jet_3d", "fp64", 15, "8a49180734a5"): {"valu_per_cell_stage": 2307.2, "traffic_bytes": 13469093469},
+    ("liquid_jet_3d", "mixed", 7, "8a49180734a5"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523164008},
+    ("liquid_jet_3d", "fp64", 7, "8a49180734a5"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5143180578},
+    ("shock_bubble_2d", "fp64", 10, "8a49180734a5"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496587},
+    ("shock_bubble_2d", "mixed", 10, "8a49180734a5"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420212},
+    ("drop_2d", "mixed", 1, "8a49180734a5"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
+    ("drop_2d", "fp64", 1, "8a49180734a5"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879769},
+    ("bubble_collapse_batch", "mixed", 3, "8a49180734a5"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432789469},
+    ("bubble_collapse_batch", "fp64", 3, "8a49180734a5"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862837776},
+    ("vapour_bubble_wall_2d", "fp64", 9, "8a49180734a5"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47623163},
+    ("vapour_bubble_wall_2d", "mixed", 10, "8a49180734a5"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23974729},
+    ("cube_to_sphere_3d", "fp64", 16, "8a49180734a5"): {"valu_per_cell_stage": 1495.5, "traffic_bytes": 5316364691},
+    ("cube_to_sphere_3d", "mixed", 15, "8a49180734a5"): {"valu_per_cell_stage": 1302.5, "traffic_bytes": 2723265861},
+    ("dual_gas_layer_2d", "fp64", 10, "8a49180734a5"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71387775},
+    ("dual_gas_layer_2d", "mixed", 10, "8a49180734a5"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798585},
 }
 
 

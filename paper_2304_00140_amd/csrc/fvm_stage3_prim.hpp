@@ -152,11 +152,14 @@ __global__ __launch_bounds__(256, 4) void k_prim3(StageArgs a, S* __restrict__ W
   if (a.frac_ext && a.sc.sigma > 0.0) frac_extremes<S>(in, yg, ag, (S*)a.frac_ext + (long long)bb * 4);
 }
 
-// per tile-table entry of the face kernel: 1 when the tile's two-cell halo
-// lies inside its case and the 27 tiles around it (itself included) hold one
-// value of each gas fraction, so that the CSF term of the tile is exactly zero
-// (zero normals of a uniform smoothed fraction, zero volume-fraction
-// differences); PB closure workgroups per tile, each with its extremes
+// per tile-table entry of the face kernel: 1 when the tiles around it (itself
+// included, at most 27) hold one value of each gas fraction, so that the CSF
+// term of the tile is exactly zero (zero normals of a uniform smoothed
+// fraction, zero volume-fraction differences).  Where the tile's two-cell halo
+// crosses a zero-gradient or slip-wall side, its ghost cells copy or mirror
+// cells of the tile and its neighbours, so the neighbours that exist decide;
+// across a periodic, inflow or far-field side (ghosts from elsewhere) the tile
+// keeps its CSF term.  PB closure workgroups per tile, each with its extremes
 template <class S, int TX, int TY, int TZ, int PB>
 __global__ __launch_bounds__(256) void k_csf_zero(StageArgs a, int ntiles, unsigned char* out)
 {
@@ -164,15 +167,27 @@ __global__ __launch_bounds__(256) void k_csf_zero(StageArgs a, int ntiles, unsig
   if (e >= ntiles) return;
   const int4 tl = a.tiles[e];
   const CaseC& C = a.cases[tl.x];
+  const int t[3] = {tl.y, tl.z, tl.w}, ext3[3] = {TX, TY, TZ};
+  int lo[3], hi[3];
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int x0 = t[d] * ext3[d];
+    lo[d] = (t[d] > 0) ? -1 : 0;
+    hi[d] = (t[d] < C.tiles[d] - 1) ? 1 : 0;
+    const bool below = x0 < 2, above = x0 + ext3[d] + 2 > C.n[d];
+    if (below && !(C.bc[d][0] == BC_ZEROGRAD || C.bc[d][0] == BC_WALL)) ok = false;
+    if (above && !(C.bc[d][1] == BC_ZEROGRAD || C.bc[d][1] == BC_WALL)) ok = false;
+  }
   unsigned char z = 0;
-  if (halo_inside3<S>(C, tl.y * TX, tl.z * TY, tl.w * TZ, TX, TY, TZ)) {
+  if (ok) {
     const S* ext = (const S*)a.frac_ext;
     const S inf = S(INFINITY);
     S ylo = inf, yhi = -inf, alo = inf, ahi = -inf;
-    for (int dk = -1; dk <= 1; ++dk)
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-          const long long n = C.tile0 + (tl.y + di) + (long long)C.tiles[0] * ((tl.z + dj) + (long long)C.tiles[1] * (tl.w + dk));
+    for (int dk = lo[2]; dk <= hi[2]; ++dk)
+      for (int dj = lo[1]; dj <= hi[1]; ++dj)
+        for (int di = lo[0]; di <= hi[0]; ++di) {
+          const long long n = C.tile0 + (t[0] + di) + (long long)C.tiles[0] * ((t[1] + dj) + (long long)C.tiles[1] * (t[2] + dk));
 #pragma unroll
           for (int b = 0; b < PB; ++b) {
             const S* x = ext + (n * PB + b) * 4;

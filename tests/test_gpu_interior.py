@@ -161,3 +161,21 @@ def test_batch3d_equals_single_cases(dev, stream):
             s.n_steps(3)
             np.testing.assert_array_equal(b.get_state(i), s.get_state())
             s.close()
+
+
+def test_walls_and_periodic_sides_every_3d_tile(dev, stream):
+    """the cube with slip walls on some sides and a periodic pair on another:
+    tiles at a wall are marked from their neighbours (mirror ghosts), tiles
+    at the periodic sides keep the CSF term; one RHS on every 3D tile"""
+    case = W.cube_to_sphere_3d(40, 10)
+    case["grid"] = dict(case["grid"], bc=[[W.BC_WALL, W.BC_ZEROGRAD], [W.BC_PERIODIC, W.BC_PERIODIC],
+                                          [W.BC_WALL, W.BC_WALL]])
+    every_tile(case, 3, dev, stream, sens=True)
+
+
+def test_jet_walls_every_3d_tile(dev, stream):
+    """the four-equation jet with slip walls on the y and z sides"""
+    case = W.liquid_jet_3d(nx=40, ny=20, nz=20, cells_per_D=8, steps=3)
+    bc = case["grid"]["bc"]
+    case["grid"] = dict(case["grid"], bc=[bc[0], [W.BC_WALL, W.BC_WALL], [W.BC_WALL, W.BC_ZEROGRAD]])
+    every_tile(case, 3, dev, stream)

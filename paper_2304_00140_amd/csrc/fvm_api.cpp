@@ -242,9 +242,18 @@ static int build_tiles(fvm_batch* b)
     C.tiles[1] = (b->dim >= 2) ? (C.n[1] + ty - 1) / ty : 1;
     C.tiles[2] = (b->dim >= 3) ? (C.n[2] + zc - 1) / zc : 1;
     C.tile0 = (int)t.size();
-    for (int k = 0; k < C.tiles[2]; ++k)
-      for (int j = 0; j < C.tiles[1]; ++j)
-        for (int i = 0; i < C.tiles[0]; ++i) t.push_back(make_int4(c, i, j, k));
+    // 3D: up to eight x slabs one after another, each in (z, y, x) order with
+    // x fastest, so that the contiguous run of the table each XCD takes is a
+    // slab across the whole y-z section (a jet along x lands on every XCD
+    // alike); a slab spans at least 64 cells in x, so that the tiles resident
+    // together still read rows of 64 cells or more
+    C.xslab = (b->dim == 3) ? std::max((C.tiles[0] + 7) / 8, (64 + tx - 1) / tx) : C.tiles[0];
+    for (int s0 = 0; s0 < C.tiles[0]; s0 += C.xslab) {
+      const int s1 = std::min(C.tiles[0], s0 + C.xslab);
+      for (int k = 0; k < C.tiles[2]; ++k)
+        for (int j = 0; j < C.tiles[1]; ++j)
+          for (int i = s0; i < s1; ++i) t.push_back(make_int4(c, i, j, k));
+    }
   }
   if (b->dtiles) (void)hipFree(b->dtiles);
   b->dtiles = nullptr;
@@ -1130,6 +1139,7 @@ extern "C" int fvm_rhs_noalloc(const fvm_grid_desc* g, const fvm_eos_desc* e, co
   C.tiles[1] = dim >= 2 ? (C.n[1] + ty - 1) / ty : 1;
   C.tiles[2] = dim >= 3 ? (C.n[2] + zc - 1) / zc : 1;
   C.tile0 = 0;
+  C.xslab = C.tiles[0];   // one slab: the table this path builds runs x fastest over the whole case
   const long long ntiles = (long long)C.tiles[0] * C.tiles[1] * C.tiles[2];
   const long long total = (C.ncell + 63) / 64 * 64;
   const size_t rows = (kind == FVM_KIND_THREE || kind == FVM_KIND_BARO2) ? 11 : 9;

@@ -67,6 +67,7 @@ struct CaseC {
   double rref[3];      // partial-density shifts (FP32-exact for FP32 storage)
   double Q[3];         // energy gauge: E' = rho E - sum_k rho_k Q_k
   int tile0, tiles[3];
+  int xslab;           // 3D tile table: tiles per x slab (the table runs slab by slab, x fastest in each)
   int diff;            // some component is viscous or conducting
   double sdx2;         // sum_d 1 / dx_d^2 over the used directions
   // barotropic model (Section 2.2; model = 1): saturated liquid density and

@@ -187,7 +187,9 @@ __global__ __launch_bounds__(256) void k_csf_zero(StageArgs a, int ntiles, unsig
     for (int dk = lo[2]; dk <= hi[2]; ++dk)
       for (int dj = lo[1]; dj <= hi[1]; ++dj)
         for (int di = lo[0]; di <= hi[0]; ++di) {
-          const long long n = C.tile0 + (t[0] + di) + (long long)C.tiles[0] * ((t[1] + dj) + (long long)C.tiles[1] * (t[2] + dk));
+          const int ni = t[0] + di, sl = ni / C.xslab, w = min(C.xslab, C.tiles[0] - sl * C.xslab);
+          const long long n = C.tile0 + (long long)sl * C.xslab * C.tiles[1] * C.tiles[2] +
+                              ((long long)(t[2] + dk) * C.tiles[1] + (t[1] + dj)) * w + (ni - sl * C.xslab);
 #pragma unroll
           for (int b = 0; b < PB; ++b) {
             const S* x = ext + (n * PB + b) * 4;

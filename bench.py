@@ -52,22 +52,22 @@ def kernel_source_hash():
 # precision, tile, hash of the kernel sources); a key that does not match the
 # built sources reports null instead of stale numbers.
 MEASURED = {
-    ("liquid_jet_3d", "mixed", 4, "f6a11c3afbf3"): {"valu_per_cell_stage": 1807.6, "traffic_bytes": 7538030877},
-    ("liquid_jet_3d", "fp64", 15, "f6a11c3afbf3"): {"valu_per_cell_stage": 2266.5, "traffic_bytes": 13470730128},
-    ("liquid_jet_3d", "mixed", 7, "f6a11c3afbf3"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 2523629947},
-    ("liquid_jet_3d", "fp64", 7, "f6a11c3afbf3"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5140579291},
-    ("shock_bubble_2d", "fp64", 10, "f6a11c3afbf3"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496584},
-    ("shock_bubble_2d", "mixed", 10, "f6a11c3afbf3"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420296},
-    ("drop_2d", "mixed", 1, "f6a11c3afbf3"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
-    ("drop_2d", "fp64", 1, "f6a11c3afbf3"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879764},
-    ("bubble_collapse_batch", "mixed", 3, "f6a11c3afbf3"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432779511},
-    ("bubble_collapse_batch", "fp64", 3, "f6a11c3afbf3"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862834518},
-    ("vapour_bubble_wall_2d", "fp64", 9, "f6a11c3afbf3"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47629352},
-    ("vapour_bubble_wall_2d", "mixed", 10, "f6a11c3afbf3"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23954248},
-    ("cube_to_sphere_3d", "fp64", 16, "f6a11c3afbf3"): {"valu_per_cell_stage": 1443.9, "traffic_bytes": 5349206310},
-    ("cube_to_sphere_3d", "mixed", 15, "f6a11c3afbf3"): {"valu_per_cell_stage": 1247.3, "traffic_bytes": 2707060282},
-    ("dual_gas_layer_2d", "fp64", 10, "f6a11c3afbf3"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71381508},
-    ("dual_gas_layer_2d", "mixed", 10, "f6a11c3afbf3"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798591},
+    ("liquid_jet_3d", "mixed", 4, "1194ec10b665"): {"valu_per_cell_stage": 1809.2, "traffic_bytes": 8254990131},
+    ("liquid_jet_3d", "fp64", 15, "1194ec10b665"): {"valu_per_cell_stage": 2268.1, "traffic_bytes": 14588750395},
+    ("liquid_jet_3d", "mixed", 7, "1194ec10b665"): {"valu_per_cell_stage": 1968.1, "traffic_bytes": 3098237986},
+    ("liquid_jet_3d", "fp64", 7, "1194ec10b665"): {"valu_per_cell_stage": 2320.7, "traffic_bytes": 5786164187},
+    ("shock_bubble_2d", "fp64", 10, "1194ec10b665"): {"valu_per_cell_stage": 821.6, "traffic_bytes": 30496587},
+    ("shock_bubble_2d", "mixed", 10, "1194ec10b665"): {"valu_per_cell_stage": 783.0, "traffic_bytes": 15420247},
+    ("drop_2d", "mixed", 1, "1194ec10b665"): {"valu_per_cell_stage": 1399.0, "traffic_bytes": 4050920},
+    ("drop_2d", "fp64", 1, "1194ec10b665"): {"valu_per_cell_stage": 1497.5, "traffic_bytes": 7879764},
+    ("bubble_collapse_batch", "mixed", 3, "1194ec10b665"): {"valu_per_cell_stage": 1049.7, "traffic_bytes": 432785685},
+    ("bubble_collapse_batch", "fp64", 3, "1194ec10b665"): {"valu_per_cell_stage": 1117.8, "traffic_bytes": 862843361},
+    ("vapour_bubble_wall_2d", "fp64", 9, "1194ec10b665"): {"valu_per_cell_stage": 926.5, "traffic_bytes": 47624930},
+    ("vapour_bubble_wall_2d", "mixed", 10, "1194ec10b665"): {"valu_per_cell_stage": 796.3, "traffic_bytes": 23957217},
+    ("cube_to_sphere_3d", "fp64", 16, "1194ec10b665"): {"valu_per_cell_stage": 1445.4, "traffic_bytes": 5560591824},
+    ("cube_to_sphere_3d", "mixed", 15, "1194ec10b665"): {"valu_per_cell_stage": 1248.8, "traffic_bytes": 3249863504},
+    ("dual_gas_layer_2d", "fp64", 10, "1194ec10b665"): {"valu_per_cell_stage": 1023.5, "traffic_bytes": 71383045},
+    ("dual_gas_layer_2d", "mixed", 10, "1194ec10b665"): {"valu_per_cell_stage": 907.9, "traffic_bytes": 35798626},
 }
 
 
